@@ -1,0 +1,150 @@
+"""The double-sweep domain-decomposition preconditioner P (oracle).
+
+Written step by step after Sec. 2.1-2.3 of the paper:
+  upward sweep   (eq. solve_upward):   A^(j) v^(j) = f^(j) - 2 delta(x - b_{j-1}) d_x v^(j-1)
+  residual                              g = f - A v   on the whole grid
+  downward sweep (eq. solve_downward): A~^(j) w^(j) = g^(j) + 2 delta(x - b~_j) d_x w^(j+1)
+  P f = v + w
+with the discrete derivative d_x u(x_{j+1/2}) = (u_{j+1} - u_j)/h and the discrete
+delta equal to 1/(2h) on the two grid columns next to the half-point (Sec. 2.2).
+The same padded strip operator serves both sweeps (Sec. 2.2: A~^(j) = A^(j) once the
+second boundary set is beta~_j = beta_j + 1).
+
+The reduced form (Sec. 2.3, Algorithms 2-4) keeps only the columns beta_j, beta_j+1
+(0-based) of each internal interface.
+
+Every subdomain solve is a SuperLU factorisation of the assembled strip matrix.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from .assemble import assemble_global, assemble_strip
+from .grid import Geometry
+
+
+class StripSolvers:
+    """SuperLU factorisations of all padded strip operators A^(j) (Algorithm 1)."""
+
+    def __init__(self, g: Geometry, k2=None):
+        self.g = g
+        k2 = g.k2() if k2 is None else k2
+        self.lu = []
+        for st in g.strips:
+            As = assemble_strip(g, st, k2).tocsc()
+            self.lu.append(spla.splu(As, permc_spec="COLAMD"))
+
+    def solve(self, s: int, rhs: np.ndarray) -> np.ndarray:
+        st = self.g.strips[s]
+        assert rhs.shape == (self.g.N_y, st.W)
+        return self.lu[s].solve(rhs.ravel().astype(np.complex128)).reshape(rhs.shape)
+
+
+def sweep(g: Geometry, S: StripSolvers, A, f: np.ndarray, up_from: int = 0, dn_from: int = None):
+    """Both sweeps for input f (N_y, N_x).  Returns (v, w, residual g).
+
+    up_from / dn_from: first strip of each sweep (0-based).  The full preconditioner
+    starts at strip 0 and at strip J-1; Algorithms 3 and 4 start at strip 1 and J-2
+    because their inputs vanish on the skipped subdomains."""
+    J, h = g.J, g.h
+    Ny, Nx = f.shape
+    if dn_from is None:
+        dn_from = J - 1
+
+    # ---- upward sweep, eq. solve_upward
+    v = np.zeros_like(f)
+    prev = None
+    for s in range(up_from, J):
+        st = g.strips[s]
+        rhs = np.zeros((Ny, st.W), dtype=np.complex128)
+        lo, hi = st.core
+        rhs[:, lo - st.a:hi - st.a] = f[:, lo:hi]               # f^(j): f restricted to D^(j)
+        if prev is not None:
+            b = g.beta[s]                                          # b_{j-1} between columns b-1 and b
+            pst, px = prev
+            dxv = (px[:, b - pst.a] - px[:, b - 1 - pst.a]) / h   # d_x v^(j-1)(b_{j-1})
+            delta = 1.0 / (2.0 * h)                                # discrete delta on columns b-1, b
+            rhs[:, b - 1 - st.a] += -2.0 * delta * dxv
+            rhs[:, b - st.a] += -2.0 * delta * dxv
+        x = S.solve(s, rhs)
+        v[:, lo:hi] = x[:, lo - st.a:hi - st.a]                   # v = v^(j) on D^(j)
+        prev = (st, x)
+
+    # ---- residual on the whole grid
+    res = f - (A @ v.ravel()).reshape(f.shape)
+
+    # ---- downward sweep, eq. solve_downward
+    w = np.zeros_like(f)
+    nxt = None
+    for s in range(dn_from, -1, -1):
+        st = g.strips[s]
+        rhs = np.zeros((Ny, st.W), dtype=np.complex128)
+        lo, hi = st.keep_dn
+        rhs[:, lo - st.a:hi - st.a] = res[:, lo:hi]             # g^(j): g restricted to D~^(j)
+        if nxt is not None:
+            b = g.beta[s + 1]                                      # b~_j between columns b and b+1
+            nst, nx_ = nxt
+            dxw = (nx_[:, b + 1 - nst.a] - nx_[:, b - nst.a]) / h  # d_x w^(j+1)(b~_j)
+            delta = 1.0 / (2.0 * h)
+            rhs[:, b - st.a] += 2.0 * delta * dxw
+            rhs[:, b + 1 - st.a] += 2.0 * delta * dxw
+        x = S.solve(s, rhs)
+        w[:, lo:hi] = x[:, lo - st.a:hi - st.a]                   # w = w^(j) on D~^(j)
+        nxt = (st, x)
+    return v, w, res
+
+
+def apply_P(g: Geometry, S: StripSolvers, A, f: np.ndarray) -> np.ndarray:
+    """P f = v + w (Sec. 2.1, end)."""
+    v, w, _ = sweep(g, S, A, f)
+    return v + w
+
+
+def apply_AP_full(g: Geometry, S: StripSolvers, A, f: np.ndarray) -> np.ndarray:
+    pf = apply_P(g, S, A, f)
+    return (A @ pf.ravel()).reshape(f.shape)
+
+
+# ------------------------------------------------------------------ reduced form
+
+def reduced_setup(g: Geometry, S: StripSolvers, A, f: np.ndarray):
+    """Algorithm 2: u~^(j) = A^(j)^{-1} f~^(j) with f~^(j) = f on D~^(j); u~ = u~^(j) on
+    D~^(j); returns (u~, phi = f - A u~)."""
+    Ny, Nx = f.shape
+    ut = np.zeros_like(f)
+    for s, st in enumerate(g.strips):
+        rhs = np.zeros((Ny, st.W), dtype=np.complex128)
+        lo, hi = st.keep_dn
+        rhs[:, lo - st.a:hi - st.a] = f[:, lo:hi]
+        x = S.solve(s, rhs)
+        ut[:, lo:hi] = x[:, lo - st.a:hi - st.a]
+    phi = f - (A @ ut.ravel()).reshape(f.shape)
+    return ut, phi
+
+
+def to_reduced(g: Geometry, field: np.ndarray) -> np.ndarray:
+    """Restriction of a field to the reduced columns, shape (N_y, 2(J-1))."""
+    return field[:, g.reduced_columns()].copy()
+
+
+def from_reduced(g: Geometry, red: np.ndarray) -> np.ndarray:
+    out = np.zeros((g.N_y, g.N_x), dtype=np.complex128)
+    out[:, g.reduced_columns()] = red
+    return out
+
+
+def apply_AP_reduced(g: Geometry, S: StripSolvers, A, psi_red: np.ndarray) -> np.ndarray:
+    """Algorithm 3 on a reduced vector: upward sweep j = 2..J, g = psi - A v, downward
+    sweep j = J-1..1, h = g - A w, output psi - h (restricted to the reduced columns)."""
+    psi = from_reduced(g, psi_red)
+    v, w, res = sweep(g, S, A, psi, up_from=1, dn_from=g.J - 2)
+    hres = res - (A @ w.ravel()).reshape(psi.shape)
+    return to_reduced(g, psi - hres)
+
+
+def apply_P_reduced(g: Geometry, S: StripSolvers, A, psi_red: np.ndarray, ut: np.ndarray) -> np.ndarray:
+    """Algorithm 4: v + w for input psi (sweeps as in Algorithm 3), plus u~."""
+    psi = from_reduced(g, psi_red)
+    v, w, _ = sweep(g, S, A, psi, up_from=1, dn_from=g.J - 2)
+    return v + w + ut

@@ -1,0 +1,352 @@
+"""Pins for the CPU oracle: each test checks the oracle against something other than
+itself (a textbook construction, a closed form, an invariant the paper states, brute
+force, or a planted mistake that must be caught)."""
+import json
+import math
+import os
+import types
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import grid as ogrid
+from oracle.assemble import assemble_5pt, assemble_global, assemble_strip, pml_scaling
+from oracle.dd import (StripSolvers, apply_AP_reduced, apply_P, reduced_setup, sweep,
+                       to_reduced, from_reduced)
+from oracle.gmres import gmres_right
+from oracle.greens import lattice_green
+from oracle.grid import make_geometry, geometry_from_workload
+from oracle.solve import solve_direct, solve_dd, solve_dd_reduced, relres
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _rand_field(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _geom(n=40, J=3, w_out=8, w=6, c=None, s0=10.0, ppw=10.0, seed=0):
+    h = 1.0 / n
+    if c is None:
+        rng = np.random.default_rng(seed)
+        c = 1.0 + 0.3 * rng.random((n, n))
+    om = 2 * math.pi / (ppw * h) * float(np.min(c))
+    return make_geometry(c, om, h, w_out, w, J, s0=s0)
+
+
+# ------------------------------------------------------------------ operator
+
+def test_textbook_stencil_when_alpha_is_one():
+    """alpha = 1 must give exactly the textbook 5-point Laplacian minus k^2 (Sec. 2.2),
+    built here independently as a Kronecker sum."""
+    Ny, Nx, h = 7, 9, 0.1
+    rng = np.random.default_rng(3)
+    k2 = 1.0 + rng.random((Ny, Nx))
+    A = assemble_5pt(np.ones(Nx), np.ones(Nx + 1), np.ones(Ny), np.ones(Ny + 1), k2, h)
+    T = lambda n: sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1])
+    L = (sp.kron(sp.eye(Ny), T(Nx)) + sp.kron(T(Ny), sp.eye(Nx))) / h ** 2
+    ref = (L - sp.diags(k2.ravel())).toarray()
+    assert np.max(np.abs(A.toarray() - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("which", ["global", "strip"])
+def test_pml_operator_is_D_times_symmetric(which):
+    """A = D S with D = diag(alpha_x alpha_y) and S complex symmetric: holds only if each
+    half-point alpha sits on the right side of its point (Sec. 2.2 PML formula)."""
+    g = _geom(n=20, J=3, w_out=6, w=5)
+    if which == "global":
+        A = assemble_global(g).toarray()
+        D = pml_scaling(g).ravel()
+    else:
+        st = g.strips[1]
+        A = assemble_strip(g, st).toarray()
+        ax = g.alpha_strip_x(st, False)
+        ay = g.alpha_outer(g.N_y, False)
+        D = (ay[:, None] * ax[None, :]).ravel()
+    S = A / D[:, None]
+    assert np.max(np.abs(S - S.T)) < 1e-12 * np.max(np.abs(S))
+    # and it is genuinely non-symmetric in paper form (the PML is active)
+    assert np.max(np.abs(A - A.T)) > 1e-3 * np.max(np.abs(A))
+
+
+def test_constant_alpha_matches_damped_lattice_green():
+    """With alpha constant in x and y the operator is alpha^2 (-Lap_h) - k^2, i.e. the
+    Helmholtz lattice with k_eff = k/alpha (Im > 0, exponentially decaying).  The
+    Dirichlet-box solution must equal the closed-form lattice Green's function."""
+    h, kh = 1.0, 2 * math.pi / 10
+    alpha = 1.0 / (1.0 + 1.0j)              # sigma/omega = 1
+    n = 81
+    A = assemble_5pt(np.full(n, alpha), np.full(n + 1, alpha), np.full(n, alpha),
+                     np.full(n + 1, alpha), np.full((n, n), kh ** 2), h)
+    f = np.zeros(n * n, complex)
+    c0 = n // 2
+    f[c0 * n + c0] = 1.0 / h ** 2
+    u = sp.linalg.spsolve(A.tocsc(), f).reshape(n, n)
+    for (m, q) in [(0, 0), (1, 0), (0, 3), (4, 2), (5, 5)]:
+        ref = lattice_green(m, q, kh / alpha) / alpha ** 2
+        assert abs(u[c0 + q, c0 + m] - ref) < 1e-9 * abs(lattice_green(0, 0, kh / alpha))
+
+
+def test_lattice_green_satisfies_recurrence():
+    """The closed form itself solves the discrete equation at the source and beside it."""
+    kh = 2 * math.pi / 10
+    G = {(m, n): lattice_green(m, n, kh) for m in range(-2, 3) for n in range(-2, 3)}
+    for (m, n) in [(0, 0), (1, 0), (1, 1)]:
+        lap = 4 * G[(m, n)] - G[(m + 1, n)] - G[(m - 1, n)] - G[(m, n + 1)] - G[(m, n - 1)]
+        val = lap - kh ** 2 * G[(m, n)]
+        assert abs(val - (1.0 if (m, n) == (0, 0) else 0.0)) < 1e-8
+
+
+def test_pml_absorbs_like_free_space():
+    """Homogeneous medium, point source: the PML-truncated direct solution matches the
+    infinite-lattice outgoing Green's function in the interior, and the mismatch (the
+    discrete PML reflection) drops as the layer widens.  Catches a wrong sign of the
+    stretching (incoming instead of outgoing) or of the time convention."""
+    n = 60
+    h = 1.0 / n
+    kh = 2 * math.pi / 10
+    errs = []
+    for w_out in (4, 8, 16):
+        g = make_geometry(np.ones((n, n)), kh / h, h, w_out, 4, 1)
+        f = np.zeros((g.N_y, g.N_x), complex)
+        i0 = w_out + n // 2
+        f[i0, i0] = 1.0 / h ** 2
+        u = solve_direct(g, f)
+        pts = [(0, 0), (3, 1), (10, 0), (7, 12), (20, 5)]
+        ref = np.array([lattice_green(m, q, kh) for m, q in pts])
+        got = np.array([u[i0 + q, i0 + m] for m, q in pts])
+        errs.append(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    assert errs[-1] < 0.01
+    assert errs[0] > errs[1] > errs[2]
+
+
+# ------------------------------------------------------------------ geometry
+
+def test_partition_matches_configs():
+    g = geometry_from_workload(W.cfg1())
+    assert list(g.beta) == [0, 35, 60, 85, 120]
+    assert [st.W for st in g.strips] == [44, 42, 42, 43]
+    g3 = ogrid.partition(2000, 16, 64, 14)
+    W3 = [(g3[s + 1] - g3[s]) + (14 if s > 0 else 0) + (15 if s < 63 else 0) for s in range(64)]
+    assert max(W3) == 62 and min(W3) >= 60
+    assert sum(W3) == 2032 + 63 * (2 * 14 + 1)        # the paper's count (Sec. 2.2)
+
+
+def test_strip_solve_matches_dense():
+    g = _geom(n=16, J=3, w_out=4, w=3)
+    S = StripSolvers(g)
+    rng = np.random.default_rng(5)
+    for s, st in enumerate(g.strips):
+        rhs = _rand_field(rng, (g.N_y, st.W))
+        x = S.solve(s, rhs)
+        xd = np.linalg.solve(assemble_strip(g, st).toarray(), rhs.ravel()).reshape(rhs.shape)
+        assert np.linalg.norm(x - xd) < 1e-11 * np.linalg.norm(xd)
+
+
+def test_direct_solve_matches_dense_and_residual():
+    g = _geom(n=14, J=2, w_out=4, w=3)
+    rng = np.random.default_rng(2)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    u = solve_direct(g, f)
+    A = assemble_global(g)
+    ud = np.linalg.solve(A.toarray(), f.ravel()).reshape(f.shape)
+    assert np.linalg.norm(u - ud) < 1e-11 * np.linalg.norm(ud)
+    assert relres(A, u, f) < 1e-12
+
+
+# ------------------------------------------------------------------ preconditioner
+
+def test_J1_preconditioner_is_exact_inverse():
+    """One subdomain: no pads, no transmission, g = 0 -> P = A^{-1}; GMRES needs one step."""
+    g = _geom(n=24, J=1, w_out=6, w=4)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    rng = np.random.default_rng(7)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    pf = apply_P(g, S, A, f)
+    assert np.linalg.norm(f - (A @ pf.ravel()).reshape(f.shape)) < 1e-12 * np.linalg.norm(f)
+    res = solve_dd(g, f, 1e-10, S=S, A=A)
+    assert res.iters == 1 and res.relres < 1e-10
+
+
+def test_support_of_residuals():
+    """Exact-arithmetic support properties (Sec. 2.1-2.3): f - A v lives on columns
+    beta_j - 1, beta_j; f - A P f and phi = f - A u~ live on beta_j, beta_j + 1."""
+    g = _geom(n=36, J=4, w_out=6, w=5)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    rng = np.random.default_rng(11)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    v, w, res = sweep(g, S, A, f)
+    mask_g = np.ones(g.N_x, bool); mask_g[g.residual_columns()] = False
+    mask_r = np.ones(g.N_x, bool); mask_r[g.reduced_columns()] = False
+    scale = np.linalg.norm(f)
+    assert np.linalg.norm(res[:, mask_g]) < 1e-12 * scale
+    assert np.linalg.norm(res[:, ~mask_g]) > 1e-3 * scale
+    r = f - (A @ (v + w).ravel()).reshape(f.shape)
+    assert np.linalg.norm(r[:, mask_r]) < 1e-12 * scale
+    ut, phi = reduced_setup(g, S, A, f)
+    assert np.linalg.norm(phi[:, mask_r]) < 1e-12 * scale
+
+
+def _thm1_error(w, layered=True, mutate=None):
+    n = 48
+    rng = np.random.default_rng(4)
+    cy = 1.0 + 0.5 * rng.random(n)
+    c = np.repeat(cy[:, None], n, 1) if layered else np.ones((n, n))
+    g = make_geometry(c, 2 * math.pi / (10 / n), 1.0 / n, 10, w, 4)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    f = np.zeros((g.N_y, g.N_x), complex)
+    f[g.N_y // 2, 15] = f[g.N_y // 3, 45] = n * n
+    sw = sweep if mutate is None else mutate
+    v, ww, _ = sw(g, S, A, f)
+    r = f - (A @ (v + ww).ravel()).reshape(f.shape)
+    return np.linalg.norm(r) / np.linalg.norm(f)
+
+
+def test_theorem1_x_invariant_medium():
+    """Theorem 1 (Sec. 3.2): for a medium independent of x and a perfect PML, A P = I.
+    With the discrete PML the defect is the PML reflection: small and falling with w."""
+    e = [_thm1_error(w) for w in (3, 6, 12)]
+    assert e[0] > e[1] > e[2]
+    assert e[2] < 0.01
+
+
+def _mutated_sweep(old, new):
+    """A copy of the oracle sweep with one planted mistake (source text edited)."""
+    import inspect
+    from oracle import dd
+    src = inspect.getsource(dd.sweep)
+    assert old in src
+    ns = dict(vars(dd))
+    exec(compile(src.replace(old, new), "mutant", "exec"), ns)
+    return ns["sweep"]
+
+
+@pytest.mark.parametrize("old,new", [
+    ("+= -2.0 * delta * dxv", "+= 2.0 * delta * dxv"),                       # wrong sign
+    ("rhs[:, b - 1 - st.a] += -2.0", "rhs[:, b - 2 - st.a] += -2.0"),         # wrong column
+    ("delta = 1.0 / (2.0 * h)                                # discrete", "delta = 1.0 / h  # discrete"),
+    ("px[:, b - 1 - pst.a]) / h", "px[:, b - 2 - pst.a]) / h"),                # wrong derivative
+    ("rhs[:, b + 1 - st.a] += 2.0", "rhs[:, b - 1 - st.a] += 2.0"),           # wrong downward column
+])
+def test_planted_transmission_mistakes_are_caught(old, new):
+    """The Theorem-1 pin has teeth: each plausible mistake in the transmission terms
+    makes A P far from the identity."""
+    e_good = _thm1_error(8)
+    e_bad = _thm1_error(8, mutate=_mutated_sweep(old, new))
+    assert e_bad > 20 * e_good
+
+
+def test_reduced_form_is_the_same_method():
+    """Algorithm 3 on the reduced columns equals (A P psi) restricted there, and the
+    reduced GMRES residual is the true residual of u = P psi + u~ (Sec. 2.3)."""
+    g = _geom(n=30, J=3, w_out=6, w=5)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    rng = np.random.default_rng(9)
+    psi_r = _rand_field(rng, (g.N_y, 2 * (g.J - 1)))
+    psi = from_reduced(g, psi_r)
+    full = (A @ apply_P(g, S, A, psi).ravel()).reshape(psi.shape)
+    red = apply_AP_reduced(g, S, A, psi_r)
+    assert np.linalg.norm(full[:, g.reduced_columns()] - red) < 1e-12 * np.linalg.norm(red)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    ut, phi = reduced_setup(g, S, A, f)
+    u = apply_P(g, S, A, psi) + ut
+    r_true = f - (A @ u.ravel()).reshape(f.shape)
+    r_red = to_reduced(g, phi) - red
+    assert abs(np.linalg.norm(r_true) - np.linalg.norm(r_red)) < 1e-10 * np.linalg.norm(f)
+
+
+# ------------------------------------------------------------------ GMRES and solves
+
+def test_gmres_is_minimal_residual():
+    """k-th GMRES residual = min over the Krylov space K_k(AP, f) (brute force: explicit
+    power basis + least squares)."""
+    g = _geom(n=14, J=3, w_out=4, w=3)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    rng = np.random.default_rng(13)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    op = lambda y: (A @ apply_P(g, S, A, y).ravel()).reshape(y.shape)
+    _, it, hist = gmres_right(op, f, 1e-12, 4)
+    K = [f.ravel()]
+    for k in range(1, 4):
+        K.append(op(K[-1].reshape(f.shape)).ravel())
+    for k in range(1, 4):
+        B = np.stack([op(K[i].reshape(f.shape)).ravel() for i in range(k)], 1)
+        z = np.linalg.lstsq(B, f.ravel(), rcond=None)[0]
+        best = np.linalg.norm(f.ravel() - B @ z) / np.linalg.norm(f)
+        assert abs(hist[k] - best) < 1e-8 * max(best, 1e-300) + 1e-13
+
+
+@pytest.mark.parametrize("mode", ["full", "reduced"])
+def test_dd_gmres_reaches_direct_solution(mode):
+    wl = W.small(n=40, J=4, w_out=8, w=6, c=1.0 + 0.3 * np.random.default_rng(1).random((40, 40)))
+    g = geometry_from_workload(wl)
+    f = wl.rhs()[0]
+    ud = solve_direct(g, f)
+    res = (solve_dd if mode == "full" else solve_dd_reduced)(g, f, 1e-10)
+    assert res.relres < 1e-9
+    assert np.linalg.norm(res.u - ud) < 1e-7 * np.linalg.norm(ud)
+    assert res.iters <= 12
+
+
+def test_paper_table4_iteration_counts_soft():
+    """Soft pin against Table 4 (Sec. 4.4), PML column: constant medium, J = n/10.
+    The paper's PML profile is unstated, so +-1 iteration is allowed."""
+    rows = json.load(open(os.path.join(HERE, "golden", "table4_pml_const2d.json")))["rows"]
+    for row in rows[:2]:
+        n, J = row["n"], row["J"]
+        h = 1.0 / n
+        g = make_geometry(np.ones((n, n)), 2 * math.pi / (10 * h), h, 10, 8, J)
+        f = np.zeros((g.N_y, g.N_x), complex)
+        f[g.N_y // 2, g.N_x // 2] = 1 / h ** 2
+        res = solve_dd_reduced(g, f, 1e-6)
+        assert abs(res.iters - row["iterations"]) <= 1, (n, res.iters)
+
+
+# ------------------------------------------------------------------ gradient
+
+def test_gradient_matches_finite_differences():
+    from oracle.grad import gradient, misfit
+    n = 16
+    h = 1.0 / n
+    rng = np.random.default_rng(21)
+    c = 1.0 + 0.2 * rng.random((n, n))
+    g0 = make_geometry(c, 2 * math.pi / (10 * h), h, 5, 4, 2)
+    m = 1.0 / c ** 2
+    f = np.zeros((2, g0.N_y, g0.N_x), complex)
+    f[0, 5, 8] = f[1, 5, 14] = 1 / h ** 2
+    rec = np.array([(g0.N_y - 7) * g0.N_x + i for i in range(5, 20)])
+    d = (rng.standard_normal((2, rec.size)) + 1j * rng.standard_normal((2, rec.size))) * 1e-3
+    Jv, G = gradient(g0, m, f, rec, d)
+    J2, _ = misfit(g0, m, f, rec, d)
+    assert abs(Jv - J2) < 1e-12 * abs(J2)
+    for (l, i) in [(0, 0), (3, 7), (8, 8), (15, 2), (12, 15)]:
+        eps = 1e-6
+        mp = m.copy(); mp[l, i] += eps
+        mm = m.copy(); mm[l, i] -= eps
+        fd = (misfit(g0, mp, f, rec, d)[0] - misfit(g0, mm, f, rec, d)[0]) / (2 * eps)
+        assert abs(fd - G[l, i]) < 1e-5 * np.max(np.abs(G)), (l, i, fd, G[l, i])
+
+
+def test_adjoint_identity_via_complex_symmetry():
+    """<A^{-1} a, b> = <a, A^{-H} b>, and A^{-H} b = conj(D^{-1} A^{-1} (D conj b)) from
+    A = D S with S symmetric: the identity the GPU adjoint relies on."""
+    g = _geom(n=18, J=2, w_out=5, w=4)
+    A = assemble_global(g)
+    D = pml_scaling(g).ravel()
+    rng = np.random.default_rng(8)
+    a = _rand_field(rng, (g.N_y, g.N_x)).ravel()
+    b = _rand_field(rng, (g.N_y, g.N_x)).ravel()
+    Ainv = lambda x: sp.linalg.spsolve(A.tocsc(), x)
+    AHinv_b = sp.linalg.spsolve(A.conj().T.tocsc(), b)
+    lhs = np.vdot(b, Ainv(a))
+    rhs = np.vdot(AHinv_b, a)
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    via_sym = np.conj(Ainv(D * np.conj(b)) / D)
+    assert np.linalg.norm(via_sym - AHinv_b) < 1e-10 * np.linalg.norm(AHinv_b)
