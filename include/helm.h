@@ -1,0 +1,163 @@
+/*
+ * helm.h -- C ABI of an MI355X (gfx950) solver for the 2-D heterogeneous Helmholtz
+ * equation  -u_xx - u_yy - k(x,y)^2 u = f,  k = omega / c  (paper Sec. 1, eq. helm1),
+ * discretised with the 5-point stencil and truncated by a PML (Sec. 2.1-2.2), solved by
+ * right-preconditioned GMRES (Sec. 2.3) with Stolk's double-sweep domain-decomposition
+ * preconditioner P: J strips along x, each padded with PML at its internal sides and
+ * coupled by single-layer-potential transmission sources (eqs. solve_upward and
+ * solve_downward), forward sweep j = 1..J, residual, backward sweep J..1.
+ *
+ * Grids and layouts
+ *   interior grid  n_x x n_y points, spacing h;  padded grid  N_x x N_y,
+ *   N = n + 2*pml_outer.  The unknowns of the discrete system are all padded-grid points;
+ *   an outer PML of pml_outer cells surrounds the interior on all four faces, with
+ *   homogeneous Dirichlet values beyond it.
+ *   Fields (rhs, u, P-apply input and output) are complex128, interleaved re/im doubles
+ *   (the layout of torch.complex128), indexed [rhs][y][x] on the PADDED grid, x fastest.
+ *   The medium c is real float64 on the INTERIOR grid, [y][x], x fastest; the padded
+ *   medium takes the value of the nearest interior point.
+ *
+ * Memory ownership
+ *   The caller owns every array it passes.  Arrays documented "device" live on the
+ *   handle's HIP device (normally torch tensors); arrays documented "host" are ordinary
+ *   host memory.  The handle owns the strip factors and all workspaces and frees them in
+ *   helm_destroy.  All device work is queued on opts.stream (a hipStream_t; NULL = the
+ *   default stream).  Calls that return scalars to the host (iteration counts, residuals)
+ *   synchronise that stream.
+ *
+ * Errors
+ *   Every entry point returns a helm_status; nothing is thrown across the ABI.  A
+ *   human-readable message for the last failure on a handle is in helm_last_error.
+ *   HELM_EINVAL leaves the handle usable; HELM_EHIP means a HIP runtime call failed.
+ *
+ * Threading: a handle may be used by one host thread at a time.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct helm_problem* helm_t;
+
+typedef enum {
+    HELM_OK = 0,
+    HELM_EINVAL = 1,     /* invalid argument or geometry                          */
+    HELM_ENOMEM = 2,     /* device allocation failed                              */
+    HELM_EHIP = 3,       /* HIP runtime error                                     */
+    HELM_ESTATE = 4,     /* call order: solve / apply before helm_factor          */
+    HELM_ESINGULAR = 5,  /* zero or non-finite pivot while factoring a strip      */
+    HELM_ENOCONV = 6     /* GMRES did not reach the tolerance within max_iter     */
+} helm_status;
+
+typedef enum { HELM_C128 = 0, HELM_MIXED_C64 = 1 } helm_precision;
+typedef enum { HELM_FULL = 0, HELM_REDUCED = 1 } helm_mode;
+
+typedef struct {
+    int dim;            /* 2 (the 3-D slab variant is not provided by this library)      */
+    int n[3];           /* interior points n_x, n_y (, n_z unused)                        */
+    int pml_outer;      /* outer PML width in cells, all faces (>= 1)                     */
+    int pml_iface;      /* interface PML width w: pads on internal strip sides (>= 1)     */
+    double pml_power;   /* profile sigma(xi) = sigma_max (xi / (w h))^power; default 2    */
+    double pml_s0;      /* sigma_max = pml_s0 * c_ref / (w h); default 10                */
+    double pml_cref;    /* c_ref; <= 0 selects max(c)                                     */
+    const int* beta;    /* host; NULL, or J-1 interface columns (0-based padded-grid
+                           column where strip j+1 starts, strictly increasing)           */
+    int beta_rule;      /* when beta == NULL: 0 = even split of the interior,
+                           1 = the paper's rule (eq. define_beta_j)                      */
+    int prec;           /* helm_precision: HELM_C128, or HELM_MIXED_C64 = strip factors and
+                           sweeps in complex64 (FP32), GMRES/residuals/outer field FP64  */
+    int mode;           /* helm_mode: HELM_FULL (GMRES on the whole grid) or HELM_REDUCED
+                           (Sec. 2.3 / Algorithms 2-5: GMRES on the interface columns)    */
+    int max_iter;       /* GMRES iteration cap; <= 0 selects 200                          */
+    int chunk;          /* rows per chunk of the y-partitioned strip solver; 0 = auto     */
+    void* stream;       /* hipStream_t for all device work; NULL = default stream        */
+} helm_opts;
+
+/* Default options for a 2-D problem of n_x x n_y interior points. */
+void helm_default_opts(helm_opts* o, int n_x, int n_y);
+
+/*
+ * Algorithm 1, first half (Sec. 2.3): validate the geometry, partition the x axis into J
+ * strips (interfaces at half-points, Sec. 2.2), build the PML tables (Sec. 2.1, 2.2) and
+ * upload the medium.
+ *   c      host, n_y*n_x float64 wave speed (> 0, finite), [y][x]
+ *   omega  angular frequency (> 0);  h  grid spacing (> 0);  J >= 1 strips
+ *   out    receives the new handle (NULL on failure)
+ * HELM_EINVAL: J < 1, a strip core narrower than 2 columns, an interface column with a
+ * neighbour inside the outer PML, a padded strip wider than 64 columns, c <= 0 or not
+ * finite, omega or h <= 0.
+ */
+helm_status helm_setup(const double* c, double omega, double h, const helm_opts* opts,
+                       int J, helm_t* out);
+
+/*
+ * Algorithm 1, second half: factor every padded strip operator A^(j) (Sec. 2.2, grid of
+ * eq. grid_A_j).  Each strip is block-tridiagonal along y with W x W blocks; it is cut
+ * into chunks of opts.chunk rows whose last row is a separator; every chunk is factored
+ * by block LU with explicit inverses and its two spikes, and the separators by block LU
+ * of their Schur complement.  Computed in FP64; stored in FP64 (HELM_C128) or FP32.
+ * HELM_ESINGULAR if a pivot is zero or not finite.
+ */
+helm_status helm_factor(helm_t H);
+
+/*
+ * Algorithm 5: solve A u = f for nrhs right-hand sides by right-preconditioned GMRES
+ * with the double-sweep preconditioner, starting from u = 0 (FULL) or u = u~ (REDUCED,
+ * Algorithm 2), stopping when the GMRES residual has dropped by `tol` relative to its
+ * start (Sec. 4: reduction by 1e-6), then checking the true residual ||f - A u|| / ||f||
+ * in FP64 and restarting once from u if it exceeds tol.
+ *   rhs     device, nrhs * N_y * N_x complex128 (padded grid)
+ *   u       device, same shape, output
+ *   iters   host, nrhs ints (may be NULL): GMRES iterations (applications of A P)
+ *   relres  host, nrhs doubles (may be NULL): explicit ||f - A u|| / ||f||
+ * HELM_ESTATE before helm_factor; HELM_ENOCONV if some right-hand side missed tol after
+ * max_iter (u and relres still hold the best iterate).
+ */
+helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
+                       int* iters, double* relres);
+
+/*
+ * The preconditioner alone (Sec. 2.1, end): out = P f = v + w for nrhs fields, computed
+ * in the handle's precision.  f, out: device, nrhs * N_y * N_x complex128.
+ */
+helm_status helm_apply_P(helm_t H, int nrhs, const void* f, void* out);
+
+/*
+ * Algorithm 3 on the reduced unknowns (Sec. 2.3): out = (A P psi) restricted to the
+ * columns beta_j, beta_j + 1 of every internal interface.  psi, out: device,
+ * nrhs * N_y * 2(J-1) complex128, [rhs][y][interface column], interface columns ordered
+ * beta_1, beta_1+1, beta_2, beta_2+1, ...
+ */
+helm_status helm_apply_AP_reduced(helm_t H, int nrhs, const void* psi, void* out);
+
+/*
+ * The FP64 PML stencil (Sec. 2.2): out = f - A u, or out = A u when f is NULL.
+ * u, f, out: device, nrhs * N_y * N_x complex128.
+ */
+helm_status helm_apply_A(helm_t H, int nrhs, const void* u, const void* f, void* out);
+
+/*
+ * One padded strip solve x = A^(j)^{-1} r with the stored factors (strip = 0..J-1).
+ * r, x: device, nrhs * N_y * W_j complex128, [rhs][y][strip-local column].
+ */
+helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void* x);
+
+/* Geometry queries: N_x, N_y; the J+1 interface columns beta (host, beta[0] = 0,
+ * beta[J] = N_x); the first global column and width of each padded strip (host, J each). */
+helm_status helm_get_dims(helm_t H, int* N_x, int* N_y, int* J);
+helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip_width);
+
+/* Counters of the last helm_solve: total A P applications and restarts (host). */
+helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* solve_ms);
+
+const char* helm_last_error(helm_t H);
+void helm_destroy(helm_t H);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

@@ -1,0 +1,170 @@
+"""ctypes binding of libhelm.so (the C ABI in include/helm.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  Loading
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhelm.so")
+
+HELM_OK, HELM_EINVAL, HELM_ENOMEM, HELM_EHIP, HELM_ESTATE, HELM_ESINGULAR, HELM_ENOCONV = range(7)
+HELM_C128, HELM_MIXED_C64 = 0, 1
+HELM_FULL, HELM_REDUCED = 0, 1
+STATUS_NAMES = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP",
+                4: "HELM_ESTATE", 5: "HELM_ESINGULAR", 6: "HELM_ENOCONV"}
+
+# every entry point declared in include/helm.h
+EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm_apply_P",
+           "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
+           "helm_get_partition", "helm_get_stats", "helm_last_error", "helm_destroy"]
+
+
+class HelmOpts(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("pml_outer", ctypes.c_int),
+        ("pml_iface", ctypes.c_int),
+        ("pml_power", ctypes.c_double),
+        ("pml_s0", ctypes.c_double),
+        ("pml_cref", ctypes.c_double),
+        ("beta", ctypes.POINTER(ctypes.c_int)),
+        ("beta_rule", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("mode", ctypes.c_int),
+        ("max_iter", ctypes.c_int),
+        ("chunk", ctypes.c_int),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class HelmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if libhelm.so is missing (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1208_3956_amd.build` "
+                          "(the solver has no non-HIP fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    pint, pdbl = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    L.helm_default_opts.argtypes = [ctypes.POINTER(HelmOpts), ci, ci]
+    L.helm_default_opts.restype = None
+    L.helm_setup.argtypes = [pdbl, cd, cd, ctypes.POINTER(HelmOpts), ci, ctypes.POINTER(vp)]
+    L.helm_factor.argtypes = [vp]
+    L.helm_solve.argtypes = [vp, ci, vp, vp, cd, pint, pdbl]
+    L.helm_apply_P.argtypes = [vp, ci, vp, vp]
+    L.helm_apply_AP_reduced.argtypes = [vp, ci, vp, vp]
+    L.helm_apply_A.argtypes = [vp, ci, vp, vp, vp]
+    L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
+    L.helm_get_dims.argtypes = [vp, pint, pint, pint]
+    L.helm_get_partition.argtypes = [vp, pint, pint, pint]
+    L.helm_get_stats.argtypes = [vp, pint, pint, pdbl]
+    L.helm_last_error.argtypes = [vp]
+    L.helm_last_error.restype = ctypes.c_char_p
+    L.helm_destroy.argtypes = [vp]
+    L.helm_destroy.restype = None
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("helm_default_opts", "helm_last_error", "helm_destroy"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status: int, handle=None) -> None:
+    if status != HELM_OK:
+        msg = lib().helm_last_error(handle)
+        raise HelmError(status, msg.decode() if msg else "")
+
+
+# ---------------------------------------------------------------- same-name wrappers
+
+def helm_default_opts(n_x: int, n_y: int) -> HelmOpts:
+    o = HelmOpts()
+    lib().helm_default_opts(ctypes.byref(o), int(n_x), int(n_y))
+    return o
+
+
+def helm_setup(c_ptr, omega: float, h: float, opts: HelmOpts, J: int):
+    """c_ptr: ctypes pointer to n_y*n_x float64 on the host.  Returns the handle."""
+    hdl = ctypes.c_void_p()
+    st = lib().helm_setup(c_ptr, float(omega), float(h), ctypes.byref(opts), int(J), ctypes.byref(hdl))
+    check(st, None)
+    return hdl
+
+
+def helm_factor(hdl) -> None:
+    check(lib().helm_factor(hdl), hdl)
+
+
+def helm_solve(hdl, nrhs: int, rhs_ptr: int, u_ptr: int, tol: float):
+    iters = (ctypes.c_int * nrhs)()
+    rel = (ctypes.c_double * nrhs)()
+    st = lib().helm_solve(hdl, int(nrhs), ctypes.c_void_p(rhs_ptr), ctypes.c_void_p(u_ptr),
+                          float(tol), iters, rel)
+    if st not in (HELM_OK, HELM_ENOCONV):
+        check(st, hdl)
+    return st, list(iters), list(rel)
+
+
+def helm_apply_P(hdl, nrhs: int, f_ptr: int, out_ptr: int) -> None:
+    check(lib().helm_apply_P(hdl, int(nrhs), ctypes.c_void_p(f_ptr), ctypes.c_void_p(out_ptr)), hdl)
+
+
+def helm_apply_AP_reduced(hdl, nrhs: int, psi_ptr: int, out_ptr: int) -> None:
+    check(lib().helm_apply_AP_reduced(hdl, int(nrhs), ctypes.c_void_p(psi_ptr),
+                                      ctypes.c_void_p(out_ptr)), hdl)
+
+
+def helm_apply_A(hdl, nrhs: int, u_ptr: int, f_ptr, out_ptr: int) -> None:
+    check(lib().helm_apply_A(hdl, int(nrhs), ctypes.c_void_p(u_ptr),
+                             ctypes.c_void_p(f_ptr) if f_ptr else None, ctypes.c_void_p(out_ptr)), hdl)
+
+
+def helm_strip_solve(hdl, strip: int, nrhs: int, r_ptr: int, x_ptr: int) -> None:
+    check(lib().helm_strip_solve(hdl, int(strip), int(nrhs), ctypes.c_void_p(r_ptr),
+                                 ctypes.c_void_p(x_ptr)), hdl)
+
+
+def helm_get_dims(hdl):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib().helm_get_dims(hdl, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), hdl)
+    return a.value, b.value, c.value
+
+
+def helm_get_partition(hdl, J: int):
+    beta = (ctypes.c_int * (J + 1))()
+    first = (ctypes.c_int * J)()
+    width = (ctypes.c_int * J)()
+    check(lib().helm_get_partition(hdl, beta, first, width), hdl)
+    return list(beta), list(first), list(width)
+
+
+def helm_get_stats(hdl):
+    a, r, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    check(lib().helm_get_stats(hdl, ctypes.byref(a), ctypes.byref(r), ctypes.byref(ms)), hdl)
+    return a.value, r.value, ms.value
+
+
+def helm_last_error(hdl) -> str:
+    m = lib().helm_last_error(hdl)
+    return m.decode() if m else ""
+
+
+def helm_destroy(hdl) -> None:
+    lib().helm_destroy(hdl)

@@ -1,0 +1,856 @@
+// Host core and C ABI: geometry and PML tables (Sec. 2.1-2.2), the strip factorisation
+// (Algorithm 1), the double sweep P (eqs. solve_upward / solve_downward), its reduced form
+// (Algorithms 2-4) and right-preconditioned GMRES (Algorithm 5, Sec. 2.3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "helm_internal.hpp"
+
+using helm::BLK;
+using helm::NSLOT;
+using helm::WP;
+using cd = std::complex<double>;
+
+struct Work {
+    int nrhs = 0;
+    void* Yw = nullptr;
+    double2 *V = nullptr, *G = nullptr, *PF = nullptr, *Psi = nullptr, *Wf = nullptr,
+            *Hf = nullptr, *Ut = nullptr, *R = nullptr, *Tup = nullptr, *Tdn = nullptr;
+    // GMRES
+    int mcap = 0;
+    long n = 0;
+    double2* basis = nullptr;
+    double2* w = nullptr;
+    double2* h1 = nullptr;
+    double2* h2 = nullptr;
+    double* nrm = nullptr;
+    double2* partial = nullptr;
+    double* npartial = nullptr;
+    double2* y = nullptr;
+    double2* red = nullptr;
+};
+
+struct helm_problem {
+    helm::Geom g;
+    helm::Chunks ch;
+    helm::DevTables t;
+    hipStream_t st = nullptr;
+    int prec = HELM_C128, mode = HELM_FULL, max_iter = 200;
+    std::string err;
+    void* F = nullptr;          // factors: double2 (C128) or float2 (MIXED)
+    bool factored = false;
+    int* d_err = nullptr;
+    Work wk;
+    int stat_ap = 0, stat_restarts = 0;
+    double stat_ms = 0.0;
+    std::vector<void*> owned;   // table allocations
+};
+
+namespace {
+
+thread_local std::string g_setup_err;   // message of the last failed helm_setup
+
+helm_status fail(helm_t H, helm_status code, const std::string& msg) {
+    if (H) H->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(H, e_ == hipErrorOutOfMemory ? HELM_ENOMEM : HELM_EHIP,            \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                \
+    } while (0)
+
+#define CHK(expr)                                 \
+    do {                                          \
+        helm_status s_ = (expr);                  \
+        if (s_ != HELM_OK) return s_;             \
+    } while (0)
+
+template <typename P>
+helm_status dmalloc(helm_t H, P** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e != hipSuccess)
+        return fail(H, HELM_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                                        hipGetErrorString(e));
+    return HELM_OK;
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+// ---------------------------------------------------------------- PML profile
+// sigma(xi) = sigma_max (xi / (w h))^power for depth xi = depth_cells * h inside a layer
+// of w cells; alpha = 1 / (1 + i sigma / omega)  (Sec. 2.1).
+double sigma_of(double depth_cells, int width, double smax, double power) {
+    if (depth_cells <= 0.0 || width <= 0) return 0.0;
+    return smax * std::pow(depth_cells / width, power);
+}
+cd alpha_of(double sigma, double omega) { return 1.0 / cd(1.0, sigma / omega); }
+
+double outer_depth(const helm::Geom& g, double pos, int N) {
+    const double lo = g.wout - 0.5, hi = N - g.wout - 0.5;
+    return std::max(std::max(lo - pos, pos - hi), 0.0);
+}
+double smax_of(const helm::Geom& g, int width) {
+    return width > 0 ? g.s0 * g.cref / (width * g.h) : 0.0;
+}
+cd alpha_outer(const helm::Geom& g, double pos, int N) {
+    return alpha_of(sigma_of(outer_depth(g, pos, N), g.wout, smax_of(g, g.wout), g.power), g.omega);
+}
+// alpha_x of the padded strip operator at global position pos (points integer, half-points
+// x.5): pad profile left of the left pad edge / right of the right pad edge, else global.
+cd alpha_strip(const helm::Geom& g, const helm::Strip& s, double pos) {
+    if (s.lpad && pos < s.core_lo - 0.5)
+        return alpha_of(sigma_of(s.core_lo - 0.5 - pos, g.w, smax_of(g, g.w), g.power), g.omega);
+    if (s.rpad && pos > s.dom_hi - 0.5)
+        return alpha_of(sigma_of(pos - (s.dom_hi - 0.5), g.w, smax_of(g, g.w), g.power), g.omega);
+    return alpha_outer(g, pos, g.Nx);
+}
+
+double2 d2(cd z) { return make_double2(z.real(), z.imag()); }
+
+helm_status upload(helm_t H, void** dptr, const void* src, size_t bytes) {
+    CHK(dmalloc(H, dptr, bytes));
+    H->owned.push_back(*dptr);
+    HIPCHK(hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice));
+    return HELM_OK;
+}
+
+// ---------------------------------------------------------------- workspaces
+void free_work(Work& w) {
+    void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
+                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red};
+    for (void* p : ps) dfree(p);
+    w = Work();
+}
+
+size_t field_bytes(helm_t H, int nrhs) { return (size_t)nrhs * H->g.Ny * H->g.Nx * sizeof(double2); }
+
+helm_status ensure_sweep_ws(helm_t H, int nrhs) {
+    Work& w = H->wk;
+    if (w.nrhs >= nrhs && w.V) return HELM_OK;
+    free_work(w);
+    const auto& g = H->g;
+    const size_t fb = field_bytes(H, nrhs);
+    CHK(dmalloc(H, &w.Yw, (size_t)nrhs * g.Ny * WP * sizeof(double2)));
+    double2** fields[] = {&w.V, &w.G, &w.PF, &w.Psi, &w.Wf, &w.Hf};
+    for (double2** f : fields) {
+        CHK(dmalloc(H, f, fb));
+        HIPCHK(hipMemsetAsync(*f, 0, fb, H->st));
+    }
+    const size_t tb = (size_t)std::max(1, g.J) * 2 * nrhs * g.Ny * sizeof(double2);
+    CHK(dmalloc(H, &w.Tup, tb));
+    CHK(dmalloc(H, &w.Tdn, tb));
+    HIPCHK(hipMemsetAsync(w.Tup, 0, tb, H->st));
+    HIPCHK(hipMemsetAsync(w.Tdn, 0, tb, H->st));
+    w.nrhs = nrhs;
+    return HELM_OK;
+}
+
+// ---------------------------------------------------------------- sweeps
+template <typename T>
+helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
+    const auto* F = static_cast<const helm::cplx<T>*>(H->F);
+    auto* Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
+    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Yw, nrhs, io, H->st));
+    return HELM_OK;
+}
+
+helm_status strip_solve_any(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
+    return H->prec == HELM_C128 ? strip_solve<double>(H, s, nrhs, io)
+                                : strip_solve<float>(H, s, nrhs, io);
+}
+
+double2* trace(double2* base, int s, int k, int nrhs, int Ny) {
+    return base + ((size_t)s * 2 + k) * nrhs * Ny;
+}
+
+helm::IOSpec field_io(helm_t H, int s) {
+    helm::IOSpec io;
+    const auto& g = H->g;
+    io.src_rs = (long)g.Ny * g.Nx; io.src_ls = g.Nx; io.src_off = g.strips[s].a;
+    io.dst_rs = (long)g.Ny * g.Nx; io.dst_ls = g.Nx; io.dst_off = g.strips[s].a;
+    return io;
+}
+
+// Upward sweep (eq. solve_upward) for strips s0..J-1.  full: keep v^(j) on its whole core;
+// otherwise only the columns the interface residuals read.  src = input field.
+helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
+                     const double2* red_src) {
+    const auto& g = H->g;
+    Work& w = H->wk;
+    const double ih2 = 1.0 / (g.h * g.h);
+    for (int s = s0; s < g.J; ++s) {
+        const auto& S = g.strips[s];
+        helm::IOSpec io = field_io(H, s);
+        if (red_src) {
+            // reduced input: columns beta_s, beta_s+1 of interface s (s >= 1)
+            const int nred = 2 * (g.J - 1);
+            io.src = red_src; io.src_rs = (long)g.Ny * nred; io.src_ls = nred;
+            io.src_lo = g.beta[s] - S.a; io.src_hi = io.src_lo + 2;
+            io.src_off = 2 * (s - 1) - io.src_lo;
+        } else {
+            io.src = src;
+            io.src_lo = S.core_lo - S.a; io.src_hi = S.core_hi - S.a;
+        }
+        if (s > s0) {
+            io.trA = trace(w.Tup, s - 1, 0, nrhs, g.Ny);
+            io.trB = trace(w.Tup, s - 1, 1, nrhs, g.Ny);
+            io.q_t = g.beta[s] - 1 - S.a;
+            io.coef = -ih2;                                   // -2 delta d_x v, delta = 1/(2h)
+        }
+        io.dst = w.V;
+        if (full) {
+            io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = S.core_hi - S.a;
+        } else {
+            io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = io.o_lo[0] + 2;
+            if (s < g.J - 1) { io.o_lo[1] = S.core_hi - 2 - S.a; io.o_hi[1] = S.core_hi - S.a; }
+        }
+        if (s < g.J - 1) {
+            io.tro0 = trace(w.Tup, s, 0, nrhs, g.Ny);
+            io.tro1 = trace(w.Tup, s, 1, nrhs, g.Ny);
+            io.qo0 = g.beta[s + 1] - 1 - S.a;
+            io.qo1 = g.beta[s + 1] - S.a;
+        }
+        CHK(strip_solve_any(H, s, nrhs, io));
+    }
+    return HELM_OK;
+}
+
+// Downward sweep (eq. solve_downward) for strips J-2..0 with right-hand side g = G on
+// the residual columns beta_j - 1, beta_j.  full: accumulate w^(j) on D~^(j) into dst;
+// otherwise write only the columns the interface residuals read into dst.
+helm_status sweep_down(helm_t H, int nrhs, double2* dst, bool full) {
+    const auto& g = H->g;
+    Work& w = H->wk;
+    const double ih2 = 1.0 / (g.h * g.h);
+    for (int s = g.J - 2; s >= 0; --s) {
+        const auto& S = g.strips[s];
+        helm::IOSpec io = field_io(H, s);
+        io.src = w.G;
+        io.src_lo = g.beta[s + 1] - 1 - S.a; io.src_hi = io.src_lo + 2;
+        if (s < g.J - 2) {
+            io.trA = trace(w.Tdn, s + 1, 0, nrhs, g.Ny);
+            io.trB = trace(w.Tdn, s + 1, 1, nrhs, g.Ny);
+            io.q_t = g.beta[s + 1] - S.a;
+            io.coef = ih2;                                     // +2 delta d_x w
+        }
+        io.dst = dst;
+        if (full) {
+            io.o_lo[0] = S.kdn_lo - S.a; io.o_hi[0] = S.kdn_hi - S.a;
+            io.accumulate = 1;
+        } else {
+            io.o_lo[0] = g.beta[s + 1] - 1 - S.a; io.o_hi[0] = io.o_lo[0] + 2;
+            if (s > 0) { io.o_lo[1] = g.beta[s] + 1 - S.a; io.o_hi[1] = io.o_lo[1] + 2; }
+        }
+        if (s > 0) {
+            io.tro0 = trace(w.Tdn, s, 0, nrhs, g.Ny);
+            io.tro1 = trace(w.Tdn, s, 1, nrhs, g.Ny);
+            io.qo0 = g.beta[s] - S.a;
+            io.qo1 = g.beta[s] + 1 - S.a;
+        }
+        CHK(strip_solve_any(H, s, nrhs, io));
+    }
+    return HELM_OK;
+}
+
+// out = P f = v + w  (full form, Sec. 2.1)
+helm_status apply_P_full(helm_t H, int nrhs, const double2* f, double2* out) {
+    CHK(ensure_sweep_ws(H, nrhs));
+    const auto& g = H->g;
+    Work& w = H->wk;
+    CHK(sweep_up(H, nrhs, f, 0, true, nullptr));
+    HIPCHK(helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, 2 * (g.J - 1), w.V, f, w.G, H->st));
+    HIPCHK(hipMemcpyAsync(out, w.V, field_bytes(H, nrhs), hipMemcpyDeviceToDevice, H->st));
+    CHK(sweep_down(H, nrhs, out, true));
+    return HELM_OK;
+}
+
+// Algorithm 3: out = (A P psi) on the reduced columns for reduced psi.
+helm_status apply_AP_reduced(helm_t H, int nrhs, const double2* psi, double2* out) {
+    CHK(ensure_sweep_ws(H, nrhs));
+    const auto& g = H->g;
+    Work& w = H->wk;
+    const int nred = 2 * (g.J - 1);
+    if (nred == 0) return HELM_OK;
+    HIPCHK(helm::launch_scatter_cols(psi, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st));
+    // v^(1) = 0 (Algorithm 3 starts at j = 2): clear the columns of V it would own
+    HIPCHK(helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, -1, H->st));
+    HIPCHK(helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, 0, H->st));
+    CHK(sweep_up(H, nrhs, nullptr, 1, false, psi));
+    HIPCHK(helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, nred, w.V, w.Psi, w.G, H->st));
+    CHK(sweep_down(H, nrhs, w.Wf, false));
+    // h = g - A w on the reduced columns; output psi - h
+    HIPCHK(helm::launch_apply_A_cols(H->t, g, nrhs, H->t.redcols, nred, w.Wf, w.G, w.Hf, H->st));
+    HIPCHK(helm::launch_axpby(w.Psi, w.Hf, w.Hf, 1.0, -1.0, (long)nrhs * g.Ny * g.Nx, H->st));
+    HIPCHK(helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, out, H->st));
+    return HELM_OK;
+}
+
+// Algorithm 2: u~ on D~^(j) from independent strip solves with f on D~^(j).
+helm_status reduced_setup(helm_t H, int nrhs, const double2* f, double2* ut) {
+    const auto& g = H->g;
+    for (int s = 0; s < g.J; ++s) {
+        const auto& S = g.strips[s];
+        helm::IOSpec io = field_io(H, s);
+        io.src = f;
+        io.src_lo = S.kdn_lo - S.a; io.src_hi = S.kdn_hi - S.a;
+        io.dst = ut;
+        io.o_lo[0] = io.src_lo; io.o_hi[0] = io.src_hi;
+        CHK(strip_solve_any(H, s, nrhs, io));
+    }
+    return HELM_OK;
+}
+
+// ---------------------------------------------------------------- GMRES
+struct Givens {
+    int m = 0;
+    std::vector<cd> R;      // m x m upper triangular, column-major
+    std::vector<double> c;
+    std::vector<cd> sn, gv;
+    int k = 0;
+    bool done = false;
+    double res = 0.0;
+    void init(int mm, double beta) {
+        m = mm; R.assign((size_t)m * m, 0.0); c.assign(m, 0.0); sn.assign(m, 0.0);
+        gv.assign(m + 1, 0.0); gv[0] = beta; k = 0; done = false; res = beta;
+    }
+    // add Hessenberg column k (entries 0..k from CGS, hk1 = ||w||)
+    void push(const cd* h, double hk1) {
+        std::vector<cd> col(k + 2);
+        for (int i = 0; i <= k; ++i) col[i] = h[i];
+        col[k + 1] = hk1;
+        for (int i = 0; i < k; ++i) {
+            const cd a = col[i], b = col[i + 1];
+            col[i] = c[i] * a + sn[i] * b;
+            col[i + 1] = -std::conj(sn[i]) * a + c[i] * b;
+        }
+        const cd a = col[k];
+        const double b = std::abs(col[k + 1]);
+        const double t = std::hypot(std::abs(a), b);
+        double ck;
+        cd sk;
+        if (std::abs(a) == 0.0) { ck = 0.0; sk = 1.0; }
+        else { ck = std::abs(a) / t; sk = (a / std::abs(a)) * std::conj(col[k + 1]) / t; }
+        c[k] = ck; sn[k] = sk;
+        col[k] = ck * a + sk * col[k + 1];
+        for (int i = 0; i <= k; ++i) R[(size_t)k * m + i] = col[i];
+        gv[k + 1] = -std::conj(sk) * gv[k];
+        gv[k] = ck * gv[k];
+        res = std::abs(gv[k + 1]);
+        ++k;
+    }
+    std::vector<cd> solve(int kk) const {
+        std::vector<cd> y(kk);
+        for (int i = kk - 1; i >= 0; --i) {
+            cd s = gv[i];
+            for (int j = i + 1; j < kk; ++j) s -= R[(size_t)j * m + i] * y[j];
+            const cd d = R[(size_t)i * m + i];
+            y[i] = (std::abs(d) > 0.0) ? s / d : 0.0;
+        }
+        return y;
+    }
+};
+
+helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
+    Work& w = H->wk;
+    if (w.basis && w.n == n && w.mcap >= mwant) return HELM_OK;
+    dfree(w.basis); dfree(w.w); dfree(w.h1); dfree(w.h2); dfree(w.nrm); dfree(w.partial);
+    dfree(w.npartial); dfree(w.y); dfree(w.red);
+    size_t freeb = 0, totb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totb));
+    const size_t vb = (size_t)nrhs * n * sizeof(double2);
+    size_t fit = vb ? (size_t)(0.8 * (double)freeb) / vb : (size_t)mwant + 3;
+    int m = (int)std::min<size_t>((size_t)mwant, fit > 3 ? fit - 3 : 1);
+    if (m < 1) return fail(H, HELM_ENOMEM, "not enough device memory for the GMRES basis");
+    CHK(dmalloc(H, &w.basis, vb * (m + 1)));
+    CHK(dmalloc(H, &w.w, vb));
+    CHK(dmalloc(H, &w.red, vb));
+    CHK(dmalloc(H, &w.h1, (size_t)nrhs * (m + 1) * sizeof(double2)));
+    CHK(dmalloc(H, &w.h2, (size_t)nrhs * (m + 1) * sizeof(double2)));
+    CHK(dmalloc(H, &w.y, (size_t)nrhs * (m + 1) * sizeof(double2)));
+    CHK(dmalloc(H, &w.nrm, (size_t)nrhs * sizeof(double)));
+    const int nb = helm::dots_blocks(std::max(n, (long)H->g.Ny * H->g.Nx));
+    CHK(dmalloc(H, &w.partial, (size_t)nb * nrhs * (m + 1) * sizeof(double2)));
+    CHK(dmalloc(H, &w.npartial, (size_t)nb * nrhs * sizeof(double)));
+    w.mcap = m;
+    w.n = n;
+    return HELM_OK;
+}
+
+// operator of the GMRES space: full = A P on the padded grid, reduced = Algorithm 3
+helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
+    H->stat_ap += 1;
+    if (H->mode == HELM_FULL) {
+        CHK(apply_P_full(H, nrhs, x, H->wk.PF));
+        HIPCHK(helm::launch_apply_A(H->t, H->g, nrhs, H->wk.PF, nullptr, out, H->st));
+        return HELM_OK;
+    }
+    return apply_AP_reduced(H, nrhs, x, out);
+}
+
+helm_status norms(helm_t H, const double2* v, int nrhs, long n, std::vector<double>& out) {
+    Work& w = H->wk;
+    const int nb = helm::dots_blocks(n);
+    HIPCHK(helm::launch_norms(v, nrhs, n, w.npartial, nb, w.nrm, H->st));
+    out.resize(nrhs);
+    HIPCHK(hipMemcpyAsync(out.data(), w.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    return HELM_OK;
+}
+
+// One GMRES(m) cycle on op(y) = b.  b is copied into the basis.  Each right-hand side
+// stops when its residual is <= target[r]; returns y (device, [nrhs][n]) and per-rhs
+// iteration counts.  active[r] == false rhs take no part (y = 0).
+helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std::vector<double>& bnorm,
+                        const std::vector<double>& target, int maxit, double2* yout,
+                        std::vector<int>& its, std::vector<double>& resid) {
+    Work& w = H->wk;
+    const int m = std::min(maxit, w.mcap);
+    const size_t vs = (size_t)nrhs * n;
+    std::vector<Givens> gv(nrhs);
+    std::vector<double> scale(nrhs);
+    its.assign(nrhs, 0);
+    resid.assign(nrhs, 0.0);
+    bool all = true;
+    for (int r = 0; r < nrhs; ++r) {
+        gv[r].init(m, bnorm[r]);
+        gv[r].done = !(bnorm[r] > target[r]);
+        resid[r] = bnorm[r];
+        all = all && gv[r].done;
+    }
+    // V_0 = b / ||b||
+    {
+        HIPCHK(hipMemcpyAsync(w.nrm, bnorm.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, H->st));
+        HIPCHK(helm::launch_scale(b, w.nrm, w.basis, nrhs, n, H->st));
+        HIPCHK(hipStreamSynchronize(H->st));
+    }
+    int k = 0;
+    std::vector<double2> hh1((size_t)nrhs * (m + 1)), hh2((size_t)nrhs * (m + 1));
+    std::vector<double> nr(nrhs);
+    const int nb = helm::dots_blocks(n);
+    while (!all && k < m) {
+        double2* vk = w.basis + (size_t)k * vs;
+        CHK(apply_op(H, nrhs, vk, w.w));
+        const int nv = k + 1;
+        // classical Gram-Schmidt, twice
+        HIPCHK(helm::launch_dots(w.basis, nv, w.w, nrhs, n, w.partial, nb, w.h1, H->st));
+        HIPCHK(helm::launch_update(w.basis, nv, w.h1, w.w, nrhs, n, H->st));
+        HIPCHK(helm::launch_dots(w.basis, nv, w.w, nrhs, n, w.partial, nb, w.h2, H->st));
+        HIPCHK(helm::launch_update(w.basis, nv, w.h2, w.w, nrhs, n, H->st));
+        HIPCHK(helm::launch_norms(w.w, nrhs, n, w.npartial, nb, w.nrm, H->st));
+        HIPCHK(helm::launch_scale(w.w, w.nrm, w.basis + (size_t)(k + 1) * vs, nrhs, n, H->st));
+        HIPCHK(hipMemcpyAsync(hh1.data(), w.h1, (size_t)nrhs * nv * sizeof(double2), hipMemcpyDeviceToHost, H->st));
+        HIPCHK(hipMemcpyAsync(hh2.data(), w.h2, (size_t)nrhs * nv * sizeof(double2), hipMemcpyDeviceToHost, H->st));
+        HIPCHK(hipMemcpyAsync(nr.data(), w.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, H->st));
+        HIPCHK(hipStreamSynchronize(H->st));
+        all = true;
+        for (int r = 0; r < nrhs; ++r) {
+            Givens& G = gv[r];
+            if (!G.done) {
+                std::vector<cd> col(nv);
+                for (int i = 0; i < nv; ++i) {
+                    const double2 a = hh1[(size_t)r * nv + i], c2 = hh2[(size_t)r * nv + i];
+                    col[i] = cd(a.x + c2.x, a.y + c2.y);
+                }
+                G.push(col.data(), nr[r]);
+                its[r] = G.k;
+                resid[r] = G.res;
+                if (G.res <= target[r] || !(nr[r] > 0.0)) G.done = true;
+            }
+            all = all && G.done;
+        }
+        ++k;
+    }
+    // y for each rhs from its own k, zero-padded to the k basis vectors built
+    const int nvec = std::max(k, 1);
+    std::vector<double2> yh((size_t)nrhs * nvec, make_double2(0, 0));
+    for (int r = 0; r < nrhs; ++r) {
+        std::vector<cd> y = gv[r].solve(gv[r].k);
+        for (int i = 0; i < (int)y.size(); ++i) yh[(size_t)r * nvec + i] = make_double2(y[i].real(), y[i].imag());
+    }
+    HIPCHK(hipMemcpyAsync(w.y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
+    HIPCHK(helm::launch_lincomb(w.basis, nvec, w.y, yout, nrhs, n, 0, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    return HELM_OK;
+}
+
+helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double tol,
+                       int* iters, double* relres) {
+    const auto& g = H->g;
+    CHK(ensure_sweep_ws(H, nrhs));
+    Work& w = H->wk;
+    const long nfull = (long)g.Ny * g.Nx;
+    const int nred = 2 * (g.J - 1);
+    const bool reduced = H->mode == HELM_REDUCED && nred > 0;
+    const long n = reduced ? (long)g.Ny * nred : nfull;
+    CHK(ensure_gmres_ws(H, nrhs, n, std::min(H->max_iter, reduced ? 60 : 30)));
+    if (!w.R) {
+        CHK(dmalloc(H, &w.R, field_bytes(H, nrhs)));
+        CHK(dmalloc(H, &w.Ut, field_bytes(H, nrhs)));
+    }
+    std::vector<double> fn, rn;
+    CHK(norms(H, f, nrhs, nfull, fn));
+    HIPCHK(hipMemsetAsync(u, 0, field_bytes(H, nrhs), H->st));
+    std::vector<int> total(nrhs, 0), its;
+    std::vector<double> resid;
+    int used = 0;
+    H->stat_restarts = -1;
+    bool ok = false;
+    for (int cycle = 0; used < H->max_iter; ++cycle) {
+        // explicit FP64 residual of the current iterate
+        HIPCHK(helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st));
+        CHK(norms(H, w.R, nrhs, nfull, rn));
+        bool conv = true;
+        for (int r = 0; r < nrhs; ++r) conv = conv && (rn[r] <= tol * fn[r] || fn[r] == 0.0);
+        if (cycle > 0 && conv) { ok = true; break; }
+        H->stat_restarts += 1;
+        std::vector<double> bn, target(nrhs);
+        const double2* b = w.R;
+        if (reduced) {
+            // Algorithm 2 on the current residual: u~ and phi = r - A u~ (reduced columns)
+            HIPCHK(hipMemsetAsync(w.Ut, 0, field_bytes(H, nrhs), H->st));
+            CHK(reduced_setup(H, nrhs, w.R, w.Ut));
+            HIPCHK(helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st));
+            HIPCHK(helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.red, H->st));
+            b = w.red;
+        }
+        CHK(norms(H, b, nrhs, n, bn));
+        for (int r = 0; r < nrhs; ++r) {
+            // first cycle: the paper's criterion (residual reduced by tol); later cycles:
+            // the true residual target tol ||f||
+            target[r] = (cycle == 0) ? tol * bn[r] : tol * fn[r];
+            if (rn[r] <= tol * fn[r] && cycle > 0) target[r] = bn[r];
+        }
+        double2* ycorr = reduced ? w.Psi : w.PF;
+        // GMRES on op(y) = b; the solution increment is P y (+ u~)
+        double2* ydev = reduced ? w.Hf : w.G;  // reuse as scratch for y
+        (void)ydev;
+        CHK(gmres_cycle(H, nrhs, n, b, bn, target, H->max_iter - used, w.w, its, resid));
+        int kmax = 0;
+        for (int r = 0; r < nrhs; ++r) { total[r] += its[r]; kmax = std::max(kmax, its[r]); }
+        used += std::max(kmax, 1);
+        if (reduced) {
+            // Algorithm 4: u += P psi + u~   (psi scattered onto the grid)
+            HIPCHK(hipMemsetAsync(w.Psi, 0, field_bytes(H, nrhs), H->st));
+            HIPCHK(helm::launch_scatter_cols(w.w, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st));
+            CHK(apply_P_full(H, nrhs, w.Psi, w.Hf));
+            HIPCHK(helm::launch_axpby(w.Hf, w.Ut, w.Hf, 1.0, 1.0, nrhs * nfull, H->st));
+        } else {
+            CHK(apply_P_full(H, nrhs, w.w, w.Hf));
+        }
+        (void)ycorr;
+        HIPCHK(helm::launch_axpby(u, w.Hf, u, 1.0, 1.0, nrhs * nfull, H->st));
+    }
+    if (!ok) {
+        HIPCHK(helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st));
+        CHK(norms(H, w.R, nrhs, nfull, rn));
+    }
+    bool conv = true;
+    for (int r = 0; r < nrhs; ++r) {
+        const double rr = fn[r] > 0 ? rn[r] / fn[r] : rn[r];
+        if (relres) relres[r] = rr;
+        if (iters) iters[r] = total[r];
+        conv = conv && (rr <= tol);
+    }
+    if (H->mode == HELM_REDUCED && nred > 0) HIPCHK(hipMemsetAsync(w.Psi, 0, field_bytes(H, nrhs), H->st));
+    if (!conv) return fail(H, HELM_ENOCONV, "GMRES did not reach the tolerance within max_iter");
+    return HELM_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+void helm_default_opts(helm_opts* o, int n_x, int n_y) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->dim = 2;
+    o->n[0] = n_x; o->n[1] = n_y; o->n[2] = 1;
+    o->pml_outer = 16; o->pml_iface = 8;
+    o->pml_power = 2.0; o->pml_s0 = 10.0; o->pml_cref = 0.0;
+    o->beta = nullptr; o->beta_rule = 0;
+    o->prec = HELM_C128; o->mode = HELM_FULL; o->max_iter = 200; o->chunk = 0;
+    o->stream = nullptr;
+}
+
+helm_status helm_setup(const double* c, double omega, double h, const helm_opts* opts, int J,
+                       helm_t* out) {
+    if (!out) return HELM_EINVAL;
+    *out = nullptr;
+    g_setup_err.clear();
+    if (!c || !opts) { g_setup_err = "null c or opts"; return HELM_EINVAL; }
+    helm_t H = new helm_problem();
+    auto bad = [&](const std::string& m) {
+        g_setup_err = m;
+        delete H;
+        return HELM_EINVAL;
+    };
+    if (opts->dim != 2) return bad("only dim = 2 is supported");
+    const int nx = opts->n[0], ny = opts->n[1];
+    if (nx < 2 || ny < 2) return bad("interior grid must be at least 2 x 2");
+    if (!(omega > 0) || !std::isfinite(omega)) return bad("omega must be positive and finite");
+    if (!(h > 0) || !std::isfinite(h)) return bad("h must be positive and finite");
+    if (J < 1) return bad("J must be >= 1");
+    if (opts->pml_outer < 1) return bad("pml_outer must be >= 1");
+    if (J > 1 && opts->pml_iface < 1) return bad("pml_iface must be >= 1");
+    double cmax = 0.0;
+    for (size_t i = 0; i < (size_t)nx * ny; ++i) {
+        if (!(c[i] > 0.0) || !std::isfinite(c[i])) return bad("c must be positive and finite");
+        cmax = std::max(cmax, c[i]);
+    }
+    helm::Geom& g = H->g;
+    g.nx = nx; g.ny = ny; g.wout = opts->pml_outer; g.w = opts->pml_iface; g.J = J;
+    g.Nx = nx + 2 * g.wout; g.Ny = ny + 2 * g.wout;
+    g.h = h; g.omega = omega;
+    g.power = opts->pml_power > 0 ? opts->pml_power : 2.0;
+    g.s0 = opts->pml_s0 >= 0 ? opts->pml_s0 : 10.0;
+    g.cref = opts->pml_cref > 0 ? opts->pml_cref : cmax;
+    // ---- partition (Sec. 2.2; eq. define_beta_j for rule 1)
+    g.beta.assign(J + 1, 0);
+    g.beta[J] = g.Nx;
+    for (int s = 1; s < J; ++s) {
+        if (opts->beta) g.beta[s] = opts->beta[s - 1];
+        else if (opts->beta_rule == 1)
+            g.beta[s] = (int)std::floor(g.w + s * (double)(g.Nx - 2 * g.w - 1) / J + 0.5);
+        else
+            g.beta[s] = g.wout + (int)std::floor(s * (double)nx / J + 0.5);
+    }
+    for (int s = 1; s <= J; ++s)
+        if (g.beta[s] - g.beta[s - 1] < 2) return bad("every strip core needs at least two columns");
+    for (int s = 1; s < J; ++s)
+        if (g.beta[s] - 1 < g.wout || g.beta[s] + 1 > g.wout + nx - 1)
+            return bad("interfaces must lie inside the interior, clear of the outer PML");
+    g.strips.resize(J);
+    for (int s = 0; s < J; ++s) {
+        helm::Strip& S = g.strips[s];
+        S.lpad = s > 0; S.rpad = s < J - 1;
+        S.core_lo = g.beta[s]; S.core_hi = g.beta[s + 1];
+        S.dom_lo = S.core_lo; S.dom_hi = S.core_hi + (S.rpad ? 1 : 0);
+        S.a = S.core_lo - (S.lpad ? g.w : 0);
+        S.W = S.dom_hi + (S.rpad ? g.w : 0) - S.a;
+        S.kdn_lo = S.core_lo + (S.lpad ? 1 : 0);
+        S.kdn_hi = S.core_hi + (S.rpad ? 1 : 0);
+        if (S.W > WP) return bad("padded strip " + std::to_string(s) + " is " + std::to_string(S.W) +
+                                 " columns wide; at most 64 are supported (use more strips)");
+    }
+    // ---- chunks along y
+    int m = opts->chunk > 0 ? opts->chunk : 32;
+    if (m < 2) m = 2;
+    H->ch.m = m;
+    H->ch.P = (g.Ny + m - 1) / m;
+    if (H->ch.P > 1 && (H->ch.P - 1) * m >= g.Ny) H->ch.P -= 1;
+    H->prec = opts->prec == HELM_MIXED_C64 ? HELM_MIXED_C64 : HELM_C128;
+    H->mode = opts->mode == HELM_REDUCED ? HELM_REDUCED : HELM_FULL;
+    H->max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
+    H->st = static_cast<hipStream_t>(opts->stream);
+
+    // ---- tables (FP64 complex), Sec. 2.1-2.2
+    const int Nx = g.Nx, Ny = g.Ny;
+    std::vector<double> k2((size_t)Nx * Ny);
+    for (int l = 0; l < Ny; ++l) {
+        const int li = std::min(std::max(l - g.wout, 0), ny - 1);
+        for (int i = 0; i < Nx; ++i) {
+            const int ii = std::min(std::max(i - g.wout, 0), nx - 1);
+            const double cc = c[(size_t)li * nx + ii];
+            k2[(size_t)l * Nx + i] = (omega / cc) * (omega / cc);
+        }
+    }
+    std::vector<double2> ax(Nx), axh(Nx + 1), ay(Ny), ayh(Ny + 1), cy(Ny), by(Ny);
+    for (int i = 0; i < Nx; ++i) ax[i] = d2(alpha_outer(g, i, Nx));
+    for (int i = 0; i <= Nx; ++i) axh[i] = d2(alpha_outer(g, i - 0.5, Nx));
+    for (int l = 0; l < Ny; ++l) ay[l] = d2(alpha_outer(g, l, Ny));
+    for (int l = 0; l <= Ny; ++l) ayh[l] = d2(alpha_outer(g, l - 0.5, Ny));
+    const double ih2 = 1.0 / (h * h);
+    for (int l = 0; l < Ny; ++l) {
+        const cd a = alpha_outer(g, l, Ny);
+        cy[l] = d2(-a * alpha_outer(g, l - 0.5, Ny) * ih2);
+        by[l] = d2(-a * alpha_outer(g, l + 0.5, Ny) * ih2);
+    }
+    std::vector<double2> sax((size_t)J * WP, make_double2(0, 0)), saxh((size_t)J * (WP + 1), make_double2(0, 0));
+    std::vector<int> scol((size_t)J * WP, 0), sW(J);
+    for (int s = 0; s < J; ++s) {
+        const auto& S = g.strips[s];
+        sW[s] = S.W;
+        for (int q = 0; q < S.W; ++q) {
+            sax[(size_t)s * WP + q] = d2(alpha_strip(g, S, S.a + q));
+            scol[(size_t)s * WP + q] = std::min(std::max(S.a + q, S.dom_lo), S.dom_hi - 1);
+        }
+        for (int q = 0; q <= S.W; ++q) saxh[(size_t)s * (WP + 1) + q] = d2(alpha_strip(g, S, S.a + q - 0.5));
+    }
+    std::vector<int> rcols, redcols;
+    for (int s = 1; s < J; ++s) {
+        rcols.push_back(g.beta[s] - 1); rcols.push_back(g.beta[s]);
+        redcols.push_back(g.beta[s]); redcols.push_back(g.beta[s] + 1);
+    }
+    rcols.push_back(0); redcols.push_back(0);   // never empty
+    auto& t = H->t;
+    helm_status st = HELM_OK;
+    struct Guard {
+        helm_t& H; helm_status& st; bool armed = true;
+        ~Guard() { if (armed && st != HELM_OK) { g_setup_err = H->err; helm_destroy(H); } }
+    } guard{H, st};
+    if ((st = upload(H, (void**)&t.k2, k2.data(), k2.size() * sizeof(double))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.ax, ax.data(), ax.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.axh, axh.data(), axh.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.ay, ay.data(), ay.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.ayh, ayh.data(), ayh.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.cy, cy.data(), cy.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.by, by.data(), by.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.sax, sax.data(), sax.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.saxh, saxh.data(), saxh.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.scol, scol.data(), scol.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.sW, sW.data(), sW.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.rcols, rcols.data(), rcols.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.redcols, redcols.data(), redcols.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = dmalloc(H, &H->d_err, sizeof(int))) != HELM_OK) return st;
+    H->err.clear();
+    *out = H;
+    return HELM_OK;
+}
+
+helm_status helm_factor(helm_t H) {
+    if (!H) return HELM_EINVAL;
+    if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
+    const auto& g = H->g;
+    dfree(H->F);
+    H->F = nullptr;
+    H->factored = false;
+    const size_t nel = (size_t)g.J * g.Ny * NSLOT * BLK;
+    double2* F64 = nullptr;
+    CHK(dmalloc(H, &F64, nel * sizeof(double2)));
+    HIPCHK(hipMemsetAsync(F64, 0, nel * sizeof(double2), H->st));
+    HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
+    HIPCHK(helm::launch_factor_chunks(H->t, g, H->ch, F64, H->d_err, H->st));
+    HIPCHK(helm::launch_factor_separators(H->t, g, H->ch, F64, H->d_err, H->st));
+    if (H->prec == HELM_C128) {
+        H->F = F64;
+    } else {
+        float2* F32 = nullptr;
+        helm_status s = dmalloc(H, &F32, nel * sizeof(float2));
+        if (s != HELM_OK) { dfree(F64); return s; }
+        HIPCHK(helm::launch_convert_factor(F64, F32, nel, H->st));
+        HIPCHK(hipStreamSynchronize(H->st));
+        dfree(F64);
+        H->F = F32;
+    }
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    if (herr) return fail(H, HELM_ESINGULAR, "zero or non-finite pivot in a strip factorisation");
+    H->factored = true;
+    return HELM_OK;
+}
+
+helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol, int* iters,
+                       double* relres) {
+    if (!H) return HELM_EINVAL;
+    if (!H->factored) return fail(H, HELM_ESTATE, "helm_solve before helm_factor");
+    if (nrhs < 1 || !rhs || !u) return fail(H, HELM_EINVAL, "nrhs >= 1 and non-null rhs, u required");
+    if (!(tol > 0)) return fail(H, HELM_EINVAL, "tol must be positive");
+    H->stat_ap = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    helm_status s = solve_impl(H, nrhs, static_cast<const double2*>(rhs), static_cast<double2*>(u),
+                               tol, iters, relres);
+    const auto t1 = std::chrono::steady_clock::now();
+    H->stat_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return s;
+}
+
+helm_status helm_apply_P(helm_t H, int nrhs, const void* f, void* out) {
+    if (!H) return HELM_EINVAL;
+    if (!H->factored) return fail(H, HELM_ESTATE, "helm_apply_P before helm_factor");
+    if (nrhs < 1 || !f || !out) return fail(H, HELM_EINVAL, "bad arguments");
+    return apply_P_full(H, nrhs, static_cast<const double2*>(f), static_cast<double2*>(out));
+}
+
+helm_status helm_apply_AP_reduced(helm_t H, int nrhs, const void* psi, void* out) {
+    if (!H) return HELM_EINVAL;
+    if (!H->factored) return fail(H, HELM_ESTATE, "helm_apply_AP_reduced before helm_factor");
+    if (nrhs < 1 || !psi || !out) return fail(H, HELM_EINVAL, "bad arguments");
+    if (H->g.J < 2) return fail(H, HELM_EINVAL, "the reduced space is empty for J = 1");
+    return apply_AP_reduced(H, nrhs, static_cast<const double2*>(psi), static_cast<double2*>(out));
+}
+
+helm_status helm_apply_A(helm_t H, int nrhs, const void* u, const void* f, void* out) {
+    if (!H) return HELM_EINVAL;
+    if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
+    if (nrhs < 1 || !u || !out) return fail(H, HELM_EINVAL, "bad arguments");
+    HIPCHK(helm::launch_apply_A(H->t, H->g, nrhs, static_cast<const double2*>(u),
+                                static_cast<const double2*>(f), static_cast<double2*>(out), H->st));
+    return HELM_OK;
+}
+
+helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void* x) {
+    if (!H) return HELM_EINVAL;
+    if (!H->factored) return fail(H, HELM_ESTATE, "helm_strip_solve before helm_factor");
+    if (strip < 0 || strip >= H->g.J || nrhs < 1 || !r || !x)
+        return fail(H, HELM_EINVAL, "bad arguments");
+    CHK(ensure_sweep_ws(H, nrhs));
+    const auto& g = H->g;
+    const int W = g.strips[strip].W;
+    helm::IOSpec io;
+    io.src = static_cast<const double2*>(r);
+    io.src_rs = (long)g.Ny * W; io.src_ls = W; io.src_off = 0;
+    io.src_lo = 0; io.src_hi = W;
+    io.dst = static_cast<double2*>(x);
+    io.dst_rs = (long)g.Ny * W; io.dst_ls = W; io.dst_off = 0;
+    io.o_lo[0] = 0; io.o_hi[0] = W;
+    return strip_solve_any(H, strip, nrhs, io);
+}
+
+helm_status helm_get_dims(helm_t H, int* N_x, int* N_y, int* J) {
+    if (!H) return HELM_EINVAL;
+    if (N_x) *N_x = H->g.Nx;
+    if (N_y) *N_y = H->g.Ny;
+    if (J) *J = H->g.J;
+    return HELM_OK;
+}
+
+helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip_width) {
+    if (!H || H->g.beta.empty()) return HELM_EINVAL;
+    for (int s = 0; s <= H->g.J; ++s) if (beta) beta[s] = H->g.beta[s];
+    for (int s = 0; s < H->g.J && s < (int)H->g.strips.size(); ++s) {
+        if (strip_first) strip_first[s] = H->g.strips[s].a;
+        if (strip_width) strip_width[s] = H->g.strips[s].W;
+    }
+    return HELM_OK;
+}
+
+helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* solve_ms) {
+    if (!H) return HELM_EINVAL;
+    if (ap_applies) *ap_applies = H->stat_ap;
+    if (restarts) *restarts = H->stat_restarts;
+    if (solve_ms) *solve_ms = H->stat_ms;
+    return HELM_OK;
+}
+
+const char* helm_last_error(helm_t H) { return H ? H->err.c_str() : g_setup_err.c_str(); }
+
+void helm_destroy(helm_t H) {
+    if (!H) return;
+    if (H->st) (void)hipStreamSynchronize(H->st);
+    else (void)hipDeviceSynchronize();
+    free_work(H->wk);
+    dfree(H->F);
+    dfree(H->d_err);
+    for (void* p : H->owned) dfree(p);
+    delete H;
+}
+
+}  // extern "C"

@@ -1,0 +1,148 @@
+// Internal declarations shared by the host core and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "helm.h"
+
+namespace helm {
+
+// Every padded strip is at most WP columns wide; its dense y-blocks are stored as
+// WP x WP column-major matrices (element (i,k) at k*WP + i), zero outside the leading
+// W x W corner.
+constexpr int WP = 64;
+constexpr int BLK = WP * WP;
+constexpr int NSLOT = 3;   // per row: G (or G'), top spike X~ (or L), bottom spike Y~ (or U')
+
+// ---------------------------------------------------------------- complex helpers
+template <typename T> struct cvec;
+template <> struct cvec<float> { using type = float2; };
+template <> struct cvec<double> { using type = double2; };
+template <typename T> using cplx = typename cvec<T>::type;
+
+template <typename V> __host__ __device__ inline V cmk(decltype(V{}.x) re, decltype(V{}.x) im) {
+    V r; r.x = re; r.y = im; return r;
+}
+template <typename V> __host__ __device__ inline V cadd(V a, V b) { return cmk<V>(a.x + b.x, a.y + b.y); }
+template <typename V> __host__ __device__ inline V csub(V a, V b) { return cmk<V>(a.x - b.x, a.y - b.y); }
+template <typename V> __host__ __device__ inline V cmul(V a, V b) {
+    return cmk<V>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename V> __host__ __device__ inline V cconjmul(V a, V b) {  // conj(a) * b
+    return cmk<V>(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+// acc += a * b
+template <typename V> __device__ inline void cfma(V& acc, V a, V b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+template <typename To, typename Ti> __host__ __device__ inline To ccast(Ti a) {
+    To r; r.x = a.x; r.y = a.y; return r;
+}
+
+// ---------------------------------------------------------------- geometry (host)
+struct Strip {
+    int a, W;              // first global column and width of the padded strip
+    int core_lo, core_hi;  // D^(j)
+    int dom_lo, dom_hi;    // non-pad columns (core + the extra column on the right)
+    int kdn_lo, kdn_hi;    // D~^(j), kept by the downward sweep
+    bool lpad, rpad;
+};
+
+struct Geom {
+    int nx = 0, ny = 0, Nx = 0, Ny = 0, wout = 0, w = 0, J = 0;
+    double h = 0, omega = 0, power = 2, s0 = 10, cref = 0;
+    std::vector<int> beta;       // J+1 entries
+    std::vector<Strip> strips;
+};
+
+// y-partition of every strip into chunks of m rows whose last row is a separator
+struct Chunks {
+    int m = 0, P = 0;            // rows per chunk, number of chunks
+    int first(int c) const { return c * m; }
+    int end(int c, int Ny) const { return c < P - 1 ? c * m + m - 1 : Ny; }   // interior end
+    int sep(int c) const { return c * m + m - 1; }                              // c < P-1
+};
+
+// Input gather / output scatter of one strip solve.  Strip-local column q of row l and
+// right-hand side r maps to element r*rs + l*ls + (q + off) of the buffer.
+struct IOSpec {
+    const double2* src = nullptr;  long src_rs = 0; int src_ls = 0; int src_off = 0;
+    int src_lo = 0, src_hi = 0;    // strip-local columns taken from src
+    // transmission source coef * (trB - trA) added at columns q_t and q_t + 1
+    const double2* trA = nullptr; const double2* trB = nullptr; int q_t = -1; double coef = 0;
+    // outputs: up to two strip-local column ranges written (or accumulated) into dst
+    double2* dst = nullptr;  long dst_rs = 0; int dst_ls = 0; int dst_off = 0;
+    int o_lo[2] = {0, 0}, o_hi[2] = {0, 0};
+    int accumulate = 0;
+    // outgoing traces: x[qo[0]] -> tro[0][r*Ny + l], x[qo[1]] -> tro[1][r*Ny + l]
+    double2* tro0 = nullptr; double2* tro1 = nullptr; int qo0 = -1, qo1 = -1;
+};
+
+// Device tables of one problem.
+struct DevTables {
+    double* k2 = nullptr;       // Ny*Nx
+    double2* ax = nullptr;      // Nx
+    double2* axh = nullptr;     // Nx+1
+    double2* ay = nullptr;      // Ny
+    double2* ayh = nullptr;     // Ny+1
+    double2* cy = nullptr;      // Ny: coupling of row l to row l-1 (same for every column)
+    double2* by = nullptr;      // Ny: coupling of row l to row l+1
+    double2* sax = nullptr;     // J*WP     strip alpha_x at points
+    double2* saxh = nullptr;    // J*(WP+1) strip alpha_x at half-points
+    int* scol = nullptr;        // J*WP     column whose medium each strip column uses
+    int* sW = nullptr;          // J        strip widths
+    int* rcols = nullptr;       // 2(J-1)   residual columns beta_j - 1, beta_j
+    int* redcols = nullptr;     // 2(J-1)   reduced columns beta_j, beta_j + 1
+};
+
+// ---------------------------------------------------------------- kernels (launchers)
+hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks& ch,
+                                double2* F64, int* err, hipStream_t st);
+hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chunks& ch,
+                                    double2* F64, int* err, hipStream_t st);
+hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipStream_t st);
+
+template <typename T>
+hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
+                              const cplx<T>* F, cplx<T>* Yw, int nrhs, const IOSpec& io,
+                              hipStream_t st);
+
+hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
+                          const double2* f, double2* out, hipStream_t st);
+hipError_t launch_apply_A_cols(const DevTables& t, const Geom& g, int nrhs, const int* cols,
+                               int ncols, const double2* u, const double2* f, double2* out,
+                               hipStream_t st);
+
+// Batched FP64 vector kernels for GMRES; vectors are [nrhs][n] complex, a basis is
+// kmax contiguous vectors of nrhs*n each.
+hipError_t launch_dots(const double2* V, int nvec, const double2* w, int nrhs, long n,
+                       double2* partial, int nblk, double2* out, hipStream_t st);
+hipError_t launch_update(const double2* V, int nvec, const double2* h, double2* w, int nrhs,
+                         long n, hipStream_t st);
+hipError_t launch_norms(const double2* w, int nrhs, long n, double* partial, int nblk,
+                        double* out, hipStream_t st);
+hipError_t launch_scale(const double2* w, const double* nrm, double2* out, int nrhs, long n,
+                        hipStream_t st);
+hipError_t launch_lincomb(const double2* V, int nvec, const double2* y, double2* out,
+                          int nrhs, long n, int accumulate, hipStream_t st);
+hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, int nrhs,
+                              int Ny, int Nx, double2* red, hipStream_t st);
+hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
+                               int Ny, int Nx, double2* field, hipStream_t st);
+// zero column cols[k] + shift of every row, k < ncols
+hipError_t launch_zero_cols(const int* cols, int ncols, int nrhs, int Ny, int Nx, double2* field,
+                            int shift, hipStream_t st);
+hipError_t launch_axpby(const double2* x, const double2* y, double2* out, double a, double b,
+                        long n, hipStream_t st);
+
+int dots_blocks(long n);
+
+}  // namespace helm

@@ -1,0 +1,358 @@
+// Strip factorisation (the subdomain factorisation of Algorithm 1, Sec. 2.3).
+//
+// A padded strip operator A^(j) (Sec. 2.2, grid of eq. grid_A_j) ordered row by row in y
+// is block tridiagonal: diagonal blocks T_l (W x W, tridiagonal in x: the x part of the
+// PML stencil plus the y diagonal and -k^2), and off-diagonal blocks that are scalar
+// multiples of the identity, c_l I (row l to row l-1) and b_l I (row l to row l+1),
+// because the y-PML coefficients do not depend on x.
+//
+// The y rows are cut into chunks of m rows; the last row of every chunk but the last is
+// a separator.  Per chunk (interior rows r0..r1-1), in FP64:
+//   block LU       S_r0 = T_r0,  S_l = T_l - c_l b_{l-1} S_{l-1}^{-1},  G_l = S_l^{-1}
+//   top spike      X~ = A_I^{-1} (coupling to the separator above) = c_r0 * A_I^{-1} E_first
+//   bottom spike   Y~ = A_I^{-1} (coupling to the separator below) = b_{r1-1} * A_I^{-1} E_last
+// and per strip the separators' block-tridiagonal Schur complement is factored by block
+// LU (G'_c, L_c, U'_c = G'_c S^_{c,c+1}).  Storage per row l: three WP x WP blocks
+// (slot 0: G or G', slot 1: X~ or L, slot 2: Y~ or U').
+//
+// Inverses are formed by Gauss-Jordan elimination with partial (row) pivoting in LDS.
+#include "helm_internal.hpp"
+
+namespace helm {
+
+namespace {
+
+constexpr int LDM = WP + 1;   // LDS leading dimension (bank spreading)
+constexpr int NT = 256;
+
+struct FactorArgs {
+    double2* F;
+    const double* k2;
+    const double2* ay;
+    const double2* ayh;
+    const double2* cy;
+    const double2* by;
+    const double2* sax;
+    const double2* saxh;
+    const int* scol;
+    const int* sW;
+    int* err;
+    int Nx, Ny, m, P;
+    double inv_h2;
+};
+
+__device__ inline double2 ld_scaled(const double2* p, double2 s) { return cmul(*p, s); }
+
+// Zero an LDS matrix and write the diagonal block T_l of strip s.
+__device__ void build_T(double2* M, const FactorArgs& a, int s, int l, int W) {
+    const int t = threadIdx.x;
+    for (int idx = t; idx < WP * LDM; idx += NT) M[idx] = cmk<double2>(0.0, 0.0);
+    __syncthreads();
+    if (t < W) {
+        const double2* sx = a.sax + (size_t)s * WP;
+        const double2* sxh = a.saxh + (size_t)s * (WP + 1);
+        const double2 axq = sx[t];
+        const double2 e = sxh[t + 1], wv = sxh[t];
+        const double2 ayl = a.ay[l];
+        const double2 n = a.ayh[l + 1], so = a.ayh[l];
+        double2 d = cmul(axq, cadd(e, wv));
+        d = cadd(d, cmul(ayl, cadd(n, so)));
+        d.x *= a.inv_h2; d.y *= a.inv_h2;
+        d.x -= a.k2[(size_t)l * a.Nx + a.scol[(size_t)s * WP + t]];
+        M[t + t * LDM] = d;
+        if (t + 1 < W) {
+            double2 o = cmul(axq, e);
+            M[t + (t + 1) * LDM] = cmk<double2>(-o.x * a.inv_h2, -o.y * a.inv_h2);
+        }
+        if (t >= 1) {
+            double2 o = cmul(axq, wv);
+            M[t + (t - 1) * LDM] = cmk<double2>(-o.x * a.inv_h2, -o.y * a.inv_h2);
+        }
+    }
+    __syncthreads();
+}
+
+// C = alpha * A * B (+ D), full WP x WP, column-major with leading dimensions.  Operands
+// may live in LDS or global memory; C may alias A, B or D.
+__device__ void gemm64(double2* C, int ldc, const double2* A, int lda, const double2* B, int ldb,
+                       double2 alpha, const double2* D, int ldd) {
+    const int t = threadIdx.x;
+    const int ti = t & 15, tj = t >> 4;
+    double2 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = cmk<double2>(0.0, 0.0);
+    for (int k = 0; k < WP; ++k) {
+        double2 av[4], bv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) av[r] = A[(4 * ti + r) + (size_t)k * lda];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bv[c] = B[k + (size_t)(4 * tj + c) * ldb];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cfma(acc[r][c], av[r], bv[c]);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double2 v = cmul(alpha, acc[r][c]);
+            if (D) v = cadd(v, D[(4 * ti + r) + (size_t)(4 * tj + c) * ldd]);
+            acc[r][c] = v;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) C[(4 * ti + r) + (size_t)(4 * tj + c) * ldc] = acc[r][c];
+    __syncthreads();
+}
+
+struct InvScratch {
+    double2 fcol[WP];
+    double2 rowk[WP];
+    int perm[WP];
+    int piv;
+};
+
+// In-place inverse of the leading n x n block of M (leading dimension LDM) by
+// Gauss-Jordan elimination with partial pivoting; columns are unscrambled at the end.
+__device__ void invert_inplace(double2* M, int n, InvScratch& sc, int* err) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < n; ++k) {
+        if (t < 64) {
+            double v = -1.0;
+            int idx = t;
+            if (t >= k && t < n) {
+                double2 q = M[t + k * LDM];
+                v = q.x * q.x + q.y * q.y;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                double ov = __shfl_xor(v, off);
+                int oi = __shfl_xor(idx, off);
+                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+            }
+            if (t == 0) {
+                sc.piv = idx;
+                sc.perm[k] = idx;
+                if (!(v > 0.0) || !isfinite(v)) atomicOr(err, 1);
+            }
+        }
+        __syncthreads();
+        const int p = sc.piv;
+        if (p != k && t < n) {
+            double2 x = M[k + t * LDM];
+            M[k + t * LDM] = M[p + t * LDM];
+            M[p + t * LDM] = x;
+        }
+        __syncthreads();
+        if (t < n) {
+            double2 q = M[k + k * LDM];
+            double den = q.x * q.x + q.y * q.y;
+            double2 inv = den > 0.0 ? cmk<double2>(q.x / den, -q.y / den) : cmk<double2>(0.0, 0.0);
+            double2 val = (t == k) ? cmk<double2>(1.0, 0.0) : M[k + t * LDM];
+            sc.rowk[t] = cmul(val, inv);
+            sc.fcol[t] = (t == k) ? cmk<double2>(0.0, 0.0) : M[t + k * LDM];
+        }
+        __syncthreads();
+        for (int idx = t; idx < n * n; idx += NT) {
+            const int i = idx % n, j = idx / n;
+            double2 r = sc.rowk[j];
+            if (i == k) {
+                M[i + j * LDM] = r;
+            } else {
+                double2 cur = (j == k) ? cmk<double2>(0.0, 0.0) : M[i + j * LDM];
+                M[i + j * LDM] = csub(cur, cmul(sc.fcol[i], r));
+            }
+        }
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = sc.perm[k];
+        if (p != k && t < n) {
+            double2 x = M[t + k * LDM];
+            M[t + k * LDM] = M[t + p * LDM];
+            M[t + p * LDM] = x;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ inline double2* slot(const FactorArgs& a, int s, int l, int sl) {
+    return a.F + (((size_t)s * a.Ny + l) * NSLOT + sl) * BLK;
+}
+
+// LDS (ld LDM) -> global (ld WP), optionally scaled.
+__device__ void store_blk(double2* dst, const double2* M, double2 scale) {
+    for (int idx = threadIdx.x; idx < BLK; idx += NT) {
+        const int i = idx & (WP - 1), k = idx / WP;
+        dst[idx] = cmul(M[i + k * LDM], scale);
+    }
+}
+__device__ void load_blk(double2* M, const double2* src) {
+    for (int idx = threadIdx.x; idx < BLK; idx += NT) {
+        const int i = idx & (WP - 1), k = idx / WP;
+        M[i + k * LDM] = src[idx];
+    }
+}
+
+__global__ void __launch_bounds__(NT) k_factor_chunks(FactorArgs a) {
+    __shared__ double2 bufA[WP * LDM];
+    __shared__ double2 bufB[WP * LDM];
+    __shared__ InvScratch sc;
+    const int c = blockIdx.x, s = blockIdx.y;
+    const int W = a.sW[s];
+    const int r0 = c * a.m;
+    const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
+    const double2 one = cmk<double2>(1.0, 0.0);
+    double2* Pm = bufA;
+    double2* Cm = bufB;
+
+    // ---- block LU of the chunk interior: G_l = (T_l - c_l b_{l-1} G_{l-1})^{-1}
+    for (int l = r0; l < r1; ++l) {
+        build_T(Cm, a, s, l, W);
+        if (l > r0) {
+            const double2 cb = cmul(a.cy[l], a.by[l - 1]);
+            for (int idx = threadIdx.x; idx < W * W; idx += NT) {
+                const int i = idx % W, k = idx / W;
+                Cm[i + k * LDM] = csub(Cm[i + k * LDM], cmul(cb, Pm[i + k * LDM]));
+            }
+            __syncthreads();
+        }
+        invert_inplace(Cm, W, sc, a.err);
+        store_blk(slot(a, s, l, 0), Cm, one);
+        double2* tmp = Pm; Pm = Cm; Cm = tmp;
+        __syncthreads();
+    }
+    __threadfence();
+    __syncthreads();
+
+    // ---- top spike: forward Z_r0 = G_r0, Z_l = -c_l G_l Z_{l-1}; backward
+    //      X_l = Z_l - b_l G_l X_{l+1};  stored scaled by c_r0
+    if (c > 0) {
+        load_blk(Pm, slot(a, s, r0, 0));
+        __syncthreads();
+        store_blk(slot(a, s, r0, 1), Pm, one);
+        for (int l = r0 + 1; l < r1; ++l) {
+            const double2 cl = a.cy[l];
+            gemm64(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-cl.x, -cl.y), nullptr, 0);
+            store_blk(slot(a, s, l, 1), Cm, one);
+            double2* tmp = Pm; Pm = Cm; Cm = tmp;
+        }
+        __threadfence();
+        __syncthreads();
+        const double2 ctop = a.cy[r0];
+        store_blk(slot(a, s, r1 - 1, 1), Pm, ctop);
+        for (int l = r1 - 2; l >= r0; --l) {
+            const double2 bl = a.by[l];
+            gemm64(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y),
+                   slot(a, s, l, 1), WP);
+            store_blk(slot(a, s, l, 1), Cm, ctop);
+            double2* tmp = Pm; Pm = Cm; Cm = tmp;
+        }
+        __syncthreads();
+    }
+
+    // ---- bottom spike: Y_{r1-1} = G_{r1-1}, Y_l = -b_l G_l Y_{l+1}; stored scaled by b_{r1-1}
+    if (c < a.P - 1) {
+        const double2 bbot = a.by[r1 - 1];
+        load_blk(Pm, slot(a, s, r1 - 1, 0));
+        __syncthreads();
+        store_blk(slot(a, s, r1 - 1, 2), Pm, bbot);
+        for (int l = r1 - 2; l >= r0; --l) {
+            const double2 bl = a.by[l];
+            gemm64(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y), nullptr, 0);
+            store_blk(slot(a, s, l, 2), Cm, bbot);
+            double2* tmp = Pm; Pm = Cm; Cm = tmp;
+        }
+    }
+}
+
+// Block LU of the separators' Schur complement, one workgroup per strip, sequential over
+// separators c = 0..P-2 (row s = sep(c)):
+//   S^_cc      = T_s - c_s Y~^(c)_{s-1} - b_s X~^(c+1)_{s+1}
+//   S^_{c,c-1} = -c_s X~^(c)_{s-1}           (stored as L_c in slot 1)
+//   S^_{c,c+1} = -b_s Y~^(c+1)_{s+1}
+//   S'_c = S^_cc - L_c U'_{c-1},  G'_c = S'_c^{-1} (slot 0),  U'_c = G'_c S^_{c,c+1} (slot 2)
+__global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
+    __shared__ double2 Am[WP * LDM];
+    __shared__ double2 Bm[WP * LDM];
+    __shared__ InvScratch sc;
+    const int s = blockIdx.x;
+    const int W = a.sW[s];
+    const double2 one = cmk<double2>(1.0, 0.0);
+    for (int c = 0; c + 1 < a.P; ++c) {
+        const int r = c * a.m + a.m - 1;
+        build_T(Bm, a, s, r, W);
+        const double2 cs = a.cy[r], bs = a.by[r];
+        {
+            const double2* Yc = slot(a, s, r - 1, 2);
+            const double2* Xn = slot(a, s, r + 1, 1);
+            for (int idx = threadIdx.x; idx < BLK; idx += NT) {
+                const int i = idx & (WP - 1), k = idx / WP;
+                double2 v = Bm[i + k * LDM];
+                v = csub(v, cmul(cs, Yc[idx]));
+                v = csub(v, cmul(bs, Xn[idx]));
+                Bm[i + k * LDM] = v;
+            }
+        }
+        __syncthreads();
+        if (c >= 1) {
+            const double2* Xc = slot(a, s, r - 1, 1);
+            double2* L = slot(a, s, r, 1);
+            for (int idx = threadIdx.x; idx < BLK; idx += NT)
+                L[idx] = cmul(cmk<double2>(-cs.x, -cs.y), Xc[idx]);
+            // Bm = Bm - L_c U'_{c-1} = Bm + c_s X~^(c)_{s-1} U'_{c-1}
+            gemm64(Bm, LDM, Xc, WP, Am, LDM, cs, Bm, LDM);
+        }
+        invert_inplace(Bm, W, sc, a.err);
+        store_blk(slot(a, s, r, 0), Bm, one);
+        __syncthreads();
+        if (c + 2 < a.P) {
+            gemm64(Am, LDM, Bm, LDM, slot(a, s, r + 1, 2), WP, cmk<double2>(-bs.x, -bs.y), nullptr, 0);
+            store_blk(slot(a, s, r, 2), Am, one);
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_convert(const double2* __restrict__ in, float2* __restrict__ out, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+FactorArgs make_args(const DevTables& t, const Geom& g, const Chunks& ch, double2* F, int* err) {
+    FactorArgs a;
+    a.F = F; a.k2 = t.k2; a.ay = t.ay; a.ayh = t.ayh; a.cy = t.cy; a.by = t.by;
+    a.sax = t.sax; a.saxh = t.saxh; a.scol = t.scol; a.sW = t.sW; a.err = err;
+    a.Nx = g.Nx; a.Ny = g.Ny; a.m = ch.m; a.P = ch.P; a.inv_h2 = 1.0 / (g.h * g.h);
+    return a;
+}
+
+}  // namespace
+
+hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks& ch,
+                                double2* F64, int* err, hipStream_t st) {
+    FactorArgs a = make_args(t, g, ch, F64, err);
+    dim3 grid(ch.P, g.J);
+    hipLaunchKernelGGL(k_factor_chunks, grid, dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chunks& ch,
+                                    double2* F64, int* err, hipStream_t st) {
+    if (ch.P < 2) return hipSuccess;
+    FactorArgs a = make_args(t, g, ch, F64, err);
+    hipLaunchKernelGGL(k_factor_separators, dim3(g.J), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_convert, dim3(2048), dim3(256), 0, st, F64, F32, n);
+    return hipGetLastError();
+}
+
+}  // namespace helm

@@ -1,0 +1,342 @@
+// FP64 kernels on whole fields: the PML stencil (Sec. 2.2) and the batched vector
+// operations of right-preconditioned GMRES (Sec. 2.3).
+//
+// Fields are [nrhs][Ny][Nx] complex128, x fastest.  Reductions are deterministic: every
+// block reduces in a fixed tree and the per-block partial sums are added in block order.
+#include "helm_internal.hpp"
+
+namespace helm {
+
+namespace {
+
+struct StencilArgs {
+    const double* k2;
+    const double2* ax;
+    const double2* axh;
+    const double2* ay;
+    const double2* ayh;
+    int Nx, Ny;
+    double inv_h2;
+};
+
+// (A u) at (l, i) in the paper form:
+//   -alpha_x(i)/h^2 [alpha_x(i+1/2)(u_{i+1}-u_i) - alpha_x(i-1/2)(u_i-u_{i-1})]
+//   -alpha_y(l)/h^2 [alpha_y(l+1/2)(u_{l+1}-u_l) - alpha_y(l-1/2)(u_l-u_{l-1})] - k^2 u
+// with zero Dirichlet ghosts.
+__device__ inline double2 stencil_at(const StencilArgs& s, const double2* __restrict__ u, int l, int i) {
+    const size_t p = (size_t)l * s.Nx + i;
+    const double2 uc = u[p];
+    const double2 ue = (i + 1 < s.Nx) ? u[p + 1] : cmk<double2>(0, 0);
+    const double2 uw = (i > 0) ? u[p - 1] : cmk<double2>(0, 0);
+    const double2 un = (l + 1 < s.Ny) ? u[p + s.Nx] : cmk<double2>(0, 0);
+    const double2 us = (l > 0) ? u[p - s.Nx] : cmk<double2>(0, 0);
+    const double2 ae = s.axh[i + 1], aw = s.axh[i];
+    const double2 an = s.ayh[l + 1], as = s.ayh[l];
+    // x part: alpha_x(i) [ae (uc - ue) + aw (uc - uw)]
+    double2 xp = cadd(cmul(ae, csub(uc, ue)), cmul(aw, csub(uc, uw)));
+    xp = cmul(s.ax[i], xp);
+    double2 yp = cadd(cmul(an, csub(uc, un)), cmul(as, csub(uc, us)));
+    yp = cmul(s.ay[l], yp);
+    double2 r = cadd(xp, yp);
+    r.x *= s.inv_h2; r.y *= s.inv_h2;
+    const double kk = s.k2[p];
+    r.x -= kk * uc.x;
+    r.y -= kk * uc.y;
+    return r;
+}
+
+__global__ void __launch_bounds__(256) k_apply_A(StencilArgs s, const double2* __restrict__ u,
+                                                 const double2* __restrict__ f,
+                                                 double2* __restrict__ out) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int l = blockIdx.y * 4 + threadIdx.y;
+    const size_t off = (size_t)blockIdx.z * s.Nx * s.Ny;
+    if (i >= s.Nx || l >= s.Ny) return;
+    double2 a = stencil_at(s, u + off, l, i);
+    const size_t p = off + (size_t)l * s.Nx + i;
+    out[p] = f ? csub(f[p], a) : a;
+}
+
+__global__ void __launch_bounds__(256) k_apply_A_cols(StencilArgs s, const int* __restrict__ cols,
+                                                      int ncols, const double2* __restrict__ u,
+                                                      const double2* __restrict__ f,
+                                                      double2* __restrict__ out) {
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    const int i = cols[blockIdx.y];
+    const size_t off = (size_t)blockIdx.z * s.Nx * s.Ny;
+    if (l >= s.Ny) return;
+    double2 a = stencil_at(s, u + off, l, i);
+    const size_t p = off + (size_t)l * s.Nx + i;
+    out[p] = f ? csub(f[p], a) : a;
+}
+
+StencilArgs stencil_args(const DevTables& t, const Geom& g) {
+    StencilArgs s;
+    s.k2 = t.k2; s.ax = t.ax; s.axh = t.axh; s.ay = t.ay; s.ayh = t.ayh;
+    s.Nx = g.Nx; s.Ny = g.Ny; s.inv_h2 = 1.0 / (g.h * g.h);
+    return s;
+}
+
+// ---------------------------------------------------------------- GMRES vectors
+constexpr int NV = 8;   // basis vectors per pass of the dot kernel
+
+__device__ inline double2 block_sum(double2 v, double2* sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (t < o) sh[t] = cadd(sh[t], sh[t + o]);
+        __syncthreads();
+    }
+    double2 r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[(b * nrhs + r) * nvec + i] = sum over block b's slice of conj(V_i[r]) w[r]
+__global__ void __launch_bounds__(256) k_dots(const double2* __restrict__ V, int nvec,
+                                              const double2* __restrict__ w, int nrhs, long n,
+                                              double2* __restrict__ partial) {
+    __shared__ double2 sh[256];
+    const int b = blockIdx.x, r = blockIdx.y, nb = gridDim.x;
+    const long per = (n + nb - 1) / nb;
+    const long lo = (long)b * per, hi = min(n, lo + per);
+    const size_t vs = (size_t)nrhs * n;
+    const double2* wr = w + (size_t)r * n;
+    for (int i0 = 0; i0 < nvec; i0 += NV) {
+        double2 acc[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) acc[q] = cmk<double2>(0, 0);
+        for (long p = lo + threadIdx.x; p < hi; p += 256) {
+            const double2 wv = wr[p];
+#pragma unroll
+            for (int q = 0; q < NV; ++q)
+                if (i0 + q < nvec) {
+                    const double2 v = V[(size_t)(i0 + q) * vs + (size_t)r * n + p];
+                    const double2 m = cconjmul(v, wv);
+                    acc[q] = cadd(acc[q], m);
+                }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            if (i0 + q >= nvec) break;
+            const double2 s = block_sum(acc[q], sh);
+            if (threadIdx.x == 0) partial[((size_t)b * nrhs + r) * nvec + i0 + q] = s;
+        }
+    }
+}
+
+__global__ void k_reduce_partials(const double2* __restrict__ partial, int nb, int m,
+                                  double2* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;   // j = r * nvec + i
+    if (j >= m) return;
+    double2 s = cmk<double2>(0, 0);
+    for (int b = 0; b < nb; ++b) s = cadd(s, partial[(size_t)b * m + j]);
+    out[j] = s;
+}
+
+// w[r] -= sum_i h[r][i] V_i[r]
+__global__ void k_update(const double2* __restrict__ V, int nvec, const double2* __restrict__ h,
+                         double2* __restrict__ w, int nrhs, long n) {
+    const size_t tot = (size_t)nrhs * n;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(q / n);
+        double2 acc = w[q];
+        for (int i = 0; i < nvec; ++i) acc = csub(acc, cmul(h[r * nvec + i], V[(size_t)i * tot + q]));
+        w[q] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_norms(const double2* __restrict__ w, int nrhs, long n,
+                                               double* __restrict__ partial) {
+    __shared__ double2 sh[256];
+    const int b = blockIdx.x, r = blockIdx.y, nb = gridDim.x;
+    const long per = (n + nb - 1) / nb;
+    const long lo = (long)b * per, hi = min(n, lo + per);
+    const double2* wr = w + (size_t)r * n;
+    double acc = 0.0;
+    for (long p = lo + threadIdx.x; p < hi; p += 256) {
+        const double2 v = wr[p];
+        acc = fma(v.x, v.x, acc);
+        acc = fma(v.y, v.y, acc);
+    }
+    const double2 s = block_sum(cmk<double2>(acc, 0.0), sh);
+    if (threadIdx.x == 0) partial[(size_t)b * nrhs + r] = s.x;
+}
+
+__global__ void k_reduce_norms(const double* __restrict__ partial, int nb, int nrhs,
+                               double* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += partial[(size_t)b * nrhs + r];
+    out[r] = sqrt(s);
+}
+
+__global__ void k_scale(const double2* __restrict__ w, const double* __restrict__ nrm,
+                        double2* __restrict__ out, int nrhs, long n) {
+    const size_t tot = (size_t)nrhs * n;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const double d = nrm[q / n];
+        const double2 v = w[q];
+        out[q] = d > 0.0 ? cmk<double2>(v.x / d, v.y / d) : cmk<double2>(0.0, 0.0);
+    }
+}
+
+__global__ void k_lincomb(const double2* __restrict__ V, int nvec, const double2* __restrict__ y,
+                          double2* __restrict__ out, int nrhs, long n, int accumulate) {
+    const size_t tot = (size_t)nrhs * n;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(q / n);
+        double2 acc = accumulate ? out[q] : cmk<double2>(0, 0);
+        for (int i = 0; i < nvec; ++i) acc = cadd(acc, cmul(y[r * nvec + i], V[(size_t)i * tot + q]));
+        out[q] = acc;
+    }
+}
+
+__global__ void k_gather_cols(const double2* __restrict__ field, const int* __restrict__ cols,
+                              int ncols, int nrhs, int Ny, int Nx, double2* __restrict__ red) {
+    const size_t tot = (size_t)nrhs * Ny * ncols;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q % ncols);
+        const size_t rl = q / ncols;          // r * Ny + l
+        red[q] = field[rl * Nx + cols[k]];
+    }
+}
+
+__global__ void k_scatter_cols(const double2* __restrict__ red, const int* __restrict__ cols,
+                               int ncols, int nrhs, int Ny, int Nx, double2* __restrict__ field) {
+    const size_t tot = (size_t)nrhs * Ny * ncols;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q % ncols);
+        const size_t rl = q / ncols;
+        field[rl * Nx + cols[k]] = red[q];
+    }
+}
+
+__global__ void k_zero_cols(const int* __restrict__ cols, int ncols, int nrhs, int Ny, int Nx,
+                            double2* __restrict__ field, int shift) {
+    const size_t tot = (size_t)nrhs * Ny * ncols;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q % ncols);
+        const size_t rl = q / ncols;
+        field[rl * Nx + cols[k] + shift] = cmk<double2>(0, 0);
+    }
+}
+
+__global__ void k_axpby(const double2* __restrict__ x, const double2* __restrict__ y,
+                        double2* __restrict__ out, double a, double b, long n) {
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const double2 xv = x[q];
+        const double2 yv = y ? y[q] : cmk<double2>(0, 0);
+        out[q] = cmk<double2>(a * xv.x + b * yv.x, a * xv.y + b * yv.y);
+    }
+}
+
+inline unsigned grid_for(size_t tot) {
+    size_t b = (tot + 255) / 256;
+    return (unsigned)(b > 8192 ? 8192 : (b < 1 ? 1 : b));
+}
+
+}  // namespace
+
+int dots_blocks(long n) {
+    long nb = (n + 8191) / 8192;
+    if (nb < 1) nb = 1;
+    if (nb > 256) nb = 256;
+    return (int)nb;
+}
+
+hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
+                          const double2* f, double2* out, hipStream_t st) {
+    StencilArgs s = stencil_args(t, g);
+    dim3 grid((g.Nx + 63) / 64, (g.Ny + 3) / 4, nrhs);
+    hipLaunchKernelGGL(k_apply_A, grid, dim3(64, 4), 0, st, s, u, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_A_cols(const DevTables& t, const Geom& g, int nrhs, const int* cols,
+                               int ncols, const double2* u, const double2* f, double2* out,
+                               hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    StencilArgs s = stencil_args(t, g);
+    dim3 grid((g.Ny + 255) / 256, ncols, nrhs);
+    hipLaunchKernelGGL(k_apply_A_cols, grid, dim3(256), 0, st, s, cols, ncols, u, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dots(const double2* V, int nvec, const double2* w, int nrhs, long n,
+                       double2* partial, int nblk, double2* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_dots, dim3(nblk, nrhs), dim3(256), 0, st, V, nvec, w, nrhs, n, partial);
+    const int m = nrhs * nvec;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((m + 255) / 256), dim3(256), 0, st, partial, nblk,
+                       m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const double2* V, int nvec, const double2* h, double2* w, int nrhs,
+                         long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_update, dim3(grid_for((size_t)nrhs * n)), dim3(256), 0, st, V, nvec, h,
+                       w, nrhs, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_norms(const double2* w, int nrhs, long n, double* partial, int nblk,
+                        double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_norms, dim3(nblk, nrhs), dim3(256), 0, st, w, nrhs, n, partial);
+    hipLaunchKernelGGL(k_reduce_norms, dim3((nrhs + 255) / 256), dim3(256), 0, st, partial, nblk,
+                       nrhs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const double2* w, const double* nrm, double2* out, int nrhs, long n,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_scale, dim3(grid_for((size_t)nrhs * n)), dim3(256), 0, st, w, nrm, out,
+                       nrhs, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(const double2* V, int nvec, const double2* y, double2* out,
+                          int nrhs, long n, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for((size_t)nrhs * n)), dim3(256), 0, st, V, nvec, y,
+                       out, nrhs, n, accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, int nrhs,
+                              int Ny, int Nx, double2* red, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_cols, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
+                       field, cols, ncols, nrhs, Ny, Nx, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
+                               int Ny, int Nx, double2* field, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_cols, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
+                       red, cols, ncols, nrhs, Ny, Nx, field);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_cols(const int* cols, int ncols, int nrhs, int Ny, int Nx, double2* field,
+                            int shift, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
+                       cols, ncols, nrhs, Ny, Nx, field, shift);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpby(const double2* x, const double2* y, double2* out, double a, double b,
+                        long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for((size_t)n)), dim3(256), 0, st, x, y, out, a, b, n);
+    return hipGetLastError();
+}
+
+}  // namespace helm

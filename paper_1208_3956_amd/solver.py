@@ -1,0 +1,159 @@
+"""Torch-facing wrapper of the HIP Helmholtz library.
+
+PyTorch supplies device memory and the HIP stream; every computation runs in
+libhelm.so.  Shapes and dtypes are checked here before anything is launched.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class SolveResult:
+    u: torch.Tensor
+    iters: list
+    relres: list
+    status: int
+    ap_applies: int
+    restarts: int
+    ms: float
+
+
+class Helmholtz:
+    """One discretised 2-D Helmholtz problem with its strip factors.
+
+    c          interior wave speed, (n_y, n_x) float64 (numpy or torch; copied to the host)
+    omega, h   angular frequency and grid spacing
+    J          number of strips along x
+    pml_outer  outer PML width (cells); pml_iface: interface PML width w
+    prec       "c128" or "mixed" (complex64 strip factors and sweeps, FP64 GMRES)
+    mode       "full" or "reduced" (GMRES on the interface columns, Algorithms 2-5)
+    chunk      rows per chunk of the y-partitioned strip solver (0 = library default)
+    """
+
+    def __init__(self, c, omega: float, h: float, J: int, pml_outer: int = 16,
+                 pml_iface: int = 8, pml_power: float = 2.0, pml_s0: float = 10.0,
+                 pml_cref: float = 0.0, prec: str = "c128", mode: str = "full",
+                 max_iter: int = 200, chunk: int = 0, beta: Optional[Sequence[int]] = None,
+                 device="cuda:0"):
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on a HIP device (cuda:N in torch)")
+        c = c.detach().cpu().numpy() if isinstance(c, torch.Tensor) else np.asarray(c)
+        self._c = np.ascontiguousarray(c, dtype=np.float64)
+        if self._c.ndim != 2:
+            raise ValueError("c must be a 2-D (n_y, n_x) array")
+        n_y, n_x = self._c.shape
+        o = L.helm_default_opts(n_x, n_y)
+        o.pml_outer, o.pml_iface = int(pml_outer), int(pml_iface)
+        o.pml_power, o.pml_s0, o.pml_cref = float(pml_power), float(pml_s0), float(pml_cref)
+        o.prec = {"c128": L.HELM_C128, "mixed": L.HELM_MIXED_C64, "c64": L.HELM_MIXED_C64}[prec]
+        o.mode = {"full": L.HELM_FULL, "reduced": L.HELM_REDUCED}[mode]
+        o.max_iter = int(max_iter)
+        o.chunk = int(chunk)
+        self._beta = None
+        if beta is not None:
+            self._beta = (ctypes.c_int * len(beta))(*[int(b) for b in beta])
+            o.beta = ctypes.cast(self._beta, ctypes.POINTER(ctypes.c_int))
+        with torch.cuda.device(self.device):
+            o.stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            self._opts = o
+            self.h = L.helm_setup(self._c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  omega, h, o, J)
+        self.N_x, self.N_y, self.J = L.helm_get_dims(self.h)
+        self.beta, self.strip_first, self.strip_width = L.helm_get_partition(self.h, self.J)
+        self.prec, self.mode = prec, mode
+        self.omega, self.grid_h = float(omega), float(h)
+        self.factored = False
+
+    # ------------------------------------------------------------------ helpers
+    def _field(self, x: torch.Tensor, name: str, cols: Optional[int] = None) -> torch.Tensor:
+        cols = self.N_x if cols is None else cols
+        if not isinstance(x, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if x.dtype != torch.complex128:
+            raise TypeError(f"{name} must be complex128")
+        if x.device != self.device:
+            raise ValueError(f"{name} must live on {self.device}")
+        if x.dim() == 2:
+            x = x.unsqueeze(0)
+        if x.dim() != 3 or x.shape[1] != self.N_y or x.shape[2] != cols:
+            raise ValueError(f"{name} must have shape (nrhs, {self.N_y}, {cols}), got {tuple(x.shape)}")
+        return x.contiguous()
+
+    def _sync(self):
+        torch.cuda.current_stream(self.device).synchronize()
+
+    # ------------------------------------------------------------------ API
+    def factor(self) -> "Helmholtz":
+        with torch.cuda.device(self.device):
+            L.helm_factor(self.h)
+        self.factored = True
+        return self
+
+    def solve(self, rhs: torch.Tensor, tol: float = 1e-6) -> SolveResult:
+        f = self._field(rhs, "rhs")
+        u = torch.empty_like(f)
+        with torch.cuda.device(self.device):
+            st, it, rel = L.helm_solve(self.h, f.shape[0], f.data_ptr(), u.data_ptr(), tol)
+            ap, rs, ms = L.helm_get_stats(self.h)
+        return SolveResult(u, it, rel, st, ap, rs, ms)
+
+    def apply_P(self, f: torch.Tensor) -> torch.Tensor:
+        f = self._field(f, "f")
+        out = torch.empty_like(f)
+        with torch.cuda.device(self.device):
+            L.helm_apply_P(self.h, f.shape[0], f.data_ptr(), out.data_ptr())
+        return out
+
+    def apply_AP_reduced(self, psi: torch.Tensor) -> torch.Tensor:
+        psi = self._field(psi, "psi", cols=2 * (self.J - 1))
+        out = torch.empty_like(psi)
+        with torch.cuda.device(self.device):
+            L.helm_apply_AP_reduced(self.h, psi.shape[0], psi.data_ptr(), out.data_ptr())
+        return out
+
+    def apply_A(self, u: torch.Tensor, f: Optional[torch.Tensor] = None) -> torch.Tensor:
+        u = self._field(u, "u")
+        if f is not None:
+            f = self._field(f, "f")
+            if f.shape != u.shape:
+                raise ValueError("u and f must have the same shape")
+        out = torch.empty_like(u)
+        with torch.cuda.device(self.device):
+            L.helm_apply_A(self.h, u.shape[0], u.data_ptr(), f.data_ptr() if f is not None else 0,
+                           out.data_ptr())
+        return out
+
+    def strip_solve(self, strip: int, r: torch.Tensor) -> torch.Tensor:
+        if not 0 <= strip < self.J:
+            raise ValueError("strip out of range")
+        r = self._field(r, "r", cols=self.strip_width[strip])
+        x = torch.empty_like(r)
+        with torch.cuda.device(self.device):
+            L.helm_strip_solve(self.h, strip, r.shape[0], r.data_ptr(), x.data_ptr())
+        return x
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            L.helm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
