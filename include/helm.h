@@ -151,8 +151,28 @@ helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void*
 helm_status helm_get_dims(helm_t H, int* N_x, int* N_y, int* J);
 helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip_width);
 
+/* y-partition of the strip solver: rows per chunk (the last row of every chunk but the
+ * last is a separator) and the number of chunks (host ints). */
+helm_status helm_get_chunks(helm_t H, int* rows_per_chunk, int* nchunks);
+
 /* Counters of the last helm_solve: total A P applications and restarts (host). */
 helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* solve_ms);
+
+/*
+ * Kernel timing (profiling aid).  While enabled, every launch of the hot kernels is
+ * bracketed by a pair of HIP events on the handle's stream (events are recorded
+ * asynchronously; no synchronisation is added).  helm_get_kernel_times synchronises the
+ * stream and returns, per kernel class, the number of launches and their summed
+ * duration in milliseconds since timing was last enabled.  Classes (nclass <= 8):
+ *   0 strip solve phase A (chunk substitutions)   1 phase B (separators)
+ *   2 phase C (spike correction + scatter)        3 factor, chunks
+ *   4 factor, separators                          5 FP64 stencil
+ *   6 GMRES vector kernels                        7 other
+ * launches, total_ms: host arrays of nclass entries.  At most 65536 launches are
+ * recorded per enable; later ones are counted but not timed (ms stays a lower bound).
+ */
+helm_status helm_set_kernel_timing(helm_t H, int enable);
+helm_status helm_get_kernel_times(helm_t H, int nclass, int* launches, double* total_ms);
 
 const char* helm_last_error(helm_t H);
 void helm_destroy(helm_t H);

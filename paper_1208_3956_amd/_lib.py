@@ -20,7 +20,10 @@ STATUS_NAMES = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP"
 # every entry point declared in include/helm.h
 EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm_apply_P",
            "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
-           "helm_get_partition", "helm_get_stats", "helm_last_error", "helm_destroy"]
+           "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
+           "helm_get_kernel_times", "helm_last_error", "helm_destroy"]
+KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
+                  "stencil", "gmres_vectors", "other"]
 
 
 class HelmOpts(ctypes.Structure):
@@ -73,7 +76,10 @@ def lib() -> ctypes.CDLL:
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
+    L.helm_get_chunks.argtypes = [vp, pint, pint]
     L.helm_get_stats.argtypes = [vp, pint, pint, pdbl]
+    L.helm_set_kernel_timing.argtypes = [vp, ci]
+    L.helm_get_kernel_times.argtypes = [vp, ci, pint, pdbl]
     L.helm_last_error.argtypes = [vp]
     L.helm_last_error.restype = ctypes.c_char_p
     L.helm_destroy.argtypes = [vp]
@@ -155,10 +161,28 @@ def helm_get_partition(hdl, J: int):
     return list(beta), list(first), list(width)
 
 
+def helm_get_chunks(hdl):
+    m, p = ctypes.c_int(), ctypes.c_int()
+    check(lib().helm_get_chunks(hdl, ctypes.byref(m), ctypes.byref(p)), hdl)
+    return m.value, p.value
+
+
 def helm_get_stats(hdl):
     a, r, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     check(lib().helm_get_stats(hdl, ctypes.byref(a), ctypes.byref(r), ctypes.byref(ms)), hdl)
     return a.value, r.value, ms.value
+
+
+def helm_set_kernel_timing(hdl, enable: bool) -> None:
+    check(lib().helm_set_kernel_timing(hdl, 1 if enable else 0), hdl)
+
+
+def helm_get_kernel_times(hdl) -> dict:
+    n = len(KERNEL_CLASSES)
+    cnt = (ctypes.c_int * n)()
+    ms = (ctypes.c_double * n)()
+    check(lib().helm_get_kernel_times(hdl, n, cnt, ms), hdl)
+    return {k: (cnt[i], ms[i]) for i, k in enumerate(KERNEL_CLASSES)}
 
 
 def helm_last_error(hdl) -> str:

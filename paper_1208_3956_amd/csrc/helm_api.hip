@@ -8,6 +8,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -38,6 +39,53 @@ struct Work {
     double2* red = nullptr;
 };
 
+// Event-pair timing of kernel launches (helm_set_kernel_timing).
+struct EventTimer : helm::KTimer {
+    static constexpr int kMax = 65536;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> cls;        // class of pair k (events 2k, 2k+1)
+    int used = 0;
+    long counts[helm::K_NCLASS] = {0};
+    double ms[helm::K_NCLASS] = {0};
+    int pending_cls = -1;
+    hipEvent_t get(int idx) {
+        while ((int)pool.size() <= idx) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[idx];
+    }
+    void begin(int c, hipStream_t st) override {
+        counts[c] += 1;
+        if (used >= kMax) { pending_cls = -1; return; }
+        hipEvent_t e = get(2 * used);
+        if (!e || !get(2 * used + 1)) { pending_cls = -1; return; }
+        (void)hipEventRecord(e, st);
+        pending_cls = c;
+    }
+    void end(int c, hipStream_t st) override {
+        if (pending_cls != c) return;
+        (void)hipEventRecord(pool[2 * used + 1], st);
+        cls.push_back(c);
+        ++used;
+        pending_cls = -1;
+    }
+    void collect() {
+        for (int k = 0; k < used; ++k) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pool[2 * k], pool[2 * k + 1]) == hipSuccess) ms[cls[k]] += t;
+        }
+        used = 0;
+        cls.clear();
+    }
+    void reset() {
+        used = 0; cls.clear(); pending_cls = -1;
+        for (int c = 0; c < helm::K_NCLASS; ++c) { counts[c] = 0; ms[c] = 0; }
+    }
+    ~EventTimer() override { for (hipEvent_t e : pool) (void)hipEventDestroy(e); }
+};
+
 struct helm_problem {
     helm::Geom g;
     helm::Chunks ch;
@@ -52,11 +100,19 @@ struct helm_problem {
     int stat_ap = 0, stat_restarts = 0;
     double stat_ms = 0.0;
     std::vector<void*> owned;   // table allocations
+    EventTimer* timer = nullptr; // non-null while kernel timing is enabled
+    helm::KTimer* kt() { return timer; }
 };
 
 namespace {
 
 thread_local std::string g_setup_err;   // message of the last failed helm_setup
+
+// HELM_TRACE=1 in the environment prints the residual history of every GMRES cycle to stderr
+bool trace_on() {
+    static const bool on = [] { const char* e = std::getenv("HELM_TRACE"); return e && e[0] == '1'; }();
+    return on;
+}
 
 helm_status fail(helm_t H, helm_status code, const std::string& msg) {
     if (H) H->err = msg;
@@ -161,12 +217,20 @@ helm_status ensure_sweep_ws(helm_t H, int nrhs) {
     return HELM_OK;
 }
 
+// class-timed launch: HIPCHK(TIMED(H, cls, launch_expr))
+struct TimedScope {
+    helm_t H; int c;
+    TimedScope(helm_t h, int cc) : H(h), c(cc) { if (H->timer) H->timer->begin(c, H->st); }
+    ~TimedScope() { if (H->timer) H->timer->end(c, H->st); }
+};
+#define TIMED(H, cls, expr) ([&]() { TimedScope ts_(H, cls); return (expr); }())
+
 // ---------------------------------------------------------------- sweeps
 template <typename T>
 helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
     const auto* F = static_cast<const helm::cplx<T>*>(H->F);
     auto* Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
-    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Yw, nrhs, io, H->st));
+    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Yw, nrhs, io, H->st, H->kt()));
     return HELM_OK;
 }
 
@@ -274,7 +338,7 @@ helm_status apply_P_full(helm_t H, int nrhs, const double2* f, double2* out) {
     const auto& g = H->g;
     Work& w = H->wk;
     CHK(sweep_up(H, nrhs, f, 0, true, nullptr));
-    HIPCHK(helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, 2 * (g.J - 1), w.V, f, w.G, H->st));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, 2 * (g.J - 1), w.V, f, w.G, H->st)));
     HIPCHK(hipMemcpyAsync(out, w.V, field_bytes(H, nrhs), hipMemcpyDeviceToDevice, H->st));
     CHK(sweep_down(H, nrhs, out, true));
     return HELM_OK;
@@ -287,17 +351,17 @@ helm_status apply_AP_reduced(helm_t H, int nrhs, const double2* psi, double2* ou
     Work& w = H->wk;
     const int nred = 2 * (g.J - 1);
     if (nred == 0) return HELM_OK;
-    HIPCHK(helm::launch_scatter_cols(psi, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(psi, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st)));
     // v^(1) = 0 (Algorithm 3 starts at j = 2): clear the columns of V it would own
-    HIPCHK(helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, -1, H->st));
-    HIPCHK(helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, 0, H->st));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, -1, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, 0, H->st)));
     CHK(sweep_up(H, nrhs, nullptr, 1, false, psi));
-    HIPCHK(helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, nred, w.V, w.Psi, w.G, H->st));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, nred, w.V, w.Psi, w.G, H->st)));
     CHK(sweep_down(H, nrhs, w.Wf, false));
     // h = g - A w on the reduced columns; output psi - h
-    HIPCHK(helm::launch_apply_A_cols(H->t, g, nrhs, H->t.redcols, nred, w.Wf, w.G, w.Hf, H->st));
-    HIPCHK(helm::launch_axpby(w.Psi, w.Hf, w.Hf, 1.0, -1.0, (long)nrhs * g.Ny * g.Nx, H->st));
-    HIPCHK(helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, out, H->st));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.redcols, nred, w.Wf, w.G, w.Hf, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_axpby(w.Psi, w.Hf, w.Hf, 1.0, -1.0, (long)nrhs * g.Ny * g.Nx, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, out, H->st)));
     return HELM_OK;
 }
 
@@ -397,7 +461,7 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
     H->stat_ap += 1;
     if (H->mode == HELM_FULL) {
         CHK(apply_P_full(H, nrhs, x, H->wk.PF));
-        HIPCHK(helm::launch_apply_A(H->t, H->g, nrhs, H->wk.PF, nullptr, out, H->st));
+        HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, H->g, nrhs, H->wk.PF, nullptr, out, H->st)));
         return HELM_OK;
     }
     return apply_AP_reduced(H, nrhs, x, out);
@@ -406,7 +470,7 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
 helm_status norms(helm_t H, const double2* v, int nrhs, long n, std::vector<double>& out) {
     Work& w = H->wk;
     const int nb = helm::dots_blocks(n);
-    HIPCHK(helm::launch_norms(v, nrhs, n, w.npartial, nb, w.nrm, H->st));
+    HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_norms(v, nrhs, n, w.npartial, nb, w.nrm, H->st)));
     out.resize(nrhs);
     HIPCHK(hipMemcpyAsync(out.data(), w.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
@@ -436,7 +500,7 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
     // V_0 = b / ||b||
     {
         HIPCHK(hipMemcpyAsync(w.nrm, bnorm.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, H->st));
-        HIPCHK(helm::launch_scale(b, w.nrm, w.basis, nrhs, n, H->st));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_scale(b, w.nrm, w.basis, nrhs, n, H->st)));
         HIPCHK(hipStreamSynchronize(H->st));
     }
     int k = 0;
@@ -448,12 +512,12 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
         CHK(apply_op(H, nrhs, vk, w.w));
         const int nv = k + 1;
         // classical Gram-Schmidt, twice
-        HIPCHK(helm::launch_dots(w.basis, nv, w.w, nrhs, n, w.partial, nb, w.h1, H->st));
-        HIPCHK(helm::launch_update(w.basis, nv, w.h1, w.w, nrhs, n, H->st));
-        HIPCHK(helm::launch_dots(w.basis, nv, w.w, nrhs, n, w.partial, nb, w.h2, H->st));
-        HIPCHK(helm::launch_update(w.basis, nv, w.h2, w.w, nrhs, n, H->st));
-        HIPCHK(helm::launch_norms(w.w, nrhs, n, w.npartial, nb, w.nrm, H->st));
-        HIPCHK(helm::launch_scale(w.w, w.nrm, w.basis + (size_t)(k + 1) * vs, nrhs, n, H->st));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_dots(w.basis, nv, w.w, nrhs, n, w.partial, nb, w.h1, H->st)));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_update(w.basis, nv, w.h1, w.w, nrhs, n, H->st)));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_dots(w.basis, nv, w.w, nrhs, n, w.partial, nb, w.h2, H->st)));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_update(w.basis, nv, w.h2, w.w, nrhs, n, H->st)));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_norms(w.w, nrhs, n, w.npartial, nb, w.nrm, H->st)));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_scale(w.w, w.nrm, w.basis + (size_t)(k + 1) * vs, nrhs, n, H->st)));
         HIPCHK(hipMemcpyAsync(hh1.data(), w.h1, (size_t)nrhs * nv * sizeof(double2), hipMemcpyDeviceToHost, H->st));
         HIPCHK(hipMemcpyAsync(hh2.data(), w.h2, (size_t)nrhs * nv * sizeof(double2), hipMemcpyDeviceToHost, H->st));
         HIPCHK(hipMemcpyAsync(nr.data(), w.nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, H->st));
@@ -470,6 +534,9 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
                 G.push(col.data(), nr[r]);
                 its[r] = G.k;
                 resid[r] = G.res;
+                if (trace_on() && r == 0)
+                    std::fprintf(stderr, "[helm] gmres k=%d rhs0 res=%.3e target=%.3e hnext=%.3e\n", G.k,
+                                 G.res, target[r], nr[r]);
                 if (G.res <= target[r] || !(nr[r] > 0.0)) G.done = true;
             }
             all = all && G.done;
@@ -484,7 +551,7 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
         for (int i = 0; i < (int)y.size(); ++i) yh[(size_t)r * nvec + i] = make_double2(y[i].real(), y[i].imag());
     }
     HIPCHK(hipMemcpyAsync(w.y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
-    HIPCHK(helm::launch_lincomb(w.basis, nvec, w.y, yout, nrhs, n, 0, H->st));
+    HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(w.basis, nvec, w.y, yout, nrhs, n, 0, H->st)));
     HIPCHK(hipStreamSynchronize(H->st));
     return HELM_OK;
 }
@@ -513,28 +580,39 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     bool ok = false;
     for (int cycle = 0; used < H->max_iter; ++cycle) {
         // explicit FP64 residual of the current iterate
-        HIPCHK(helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st));
+        HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st)));
         CHK(norms(H, w.R, nrhs, nfull, rn));
         bool conv = true;
         for (int r = 0; r < nrhs; ++r) conv = conv && (rn[r] <= tol * fn[r] || fn[r] == 0.0);
+        if (trace_on())
+            std::fprintf(stderr, "[helm] cycle %d true relres rhs0 %.3e (used %d)\n", cycle,
+                         fn[0] > 0 ? rn[0] / fn[0] : rn[0], used);
         if (cycle > 0 && conv) { ok = true; break; }
         H->stat_restarts += 1;
         std::vector<double> bn, target(nrhs);
+        // right-hand sides that already meet tol take no part in this cycle: their
+        // residual is cleared so the correction (P y + u~) added to them is zero
+        if (cycle > 0)
+            for (int r = 0; r < nrhs; ++r)
+                if (rn[r] <= tol * fn[r])
+                    HIPCHK(hipMemsetAsync(w.R + (size_t)r * nfull, 0, nfull * sizeof(double2), H->st));
         const double2* b = w.R;
         if (reduced) {
             // Algorithm 2 on the current residual: u~ and phi = r - A u~ (reduced columns)
             HIPCHK(hipMemsetAsync(w.Ut, 0, field_bytes(H, nrhs), H->st));
             CHK(reduced_setup(H, nrhs, w.R, w.Ut));
-            HIPCHK(helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st));
-            HIPCHK(helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.red, H->st));
+            HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.red, H->st)));
             b = w.red;
         }
         CHK(norms(H, b, nrhs, n, bn));
+        if (trace_on())
+            std::fprintf(stderr, "[helm] cycle %d |b| rhs0 %.3e |f| %.3e\n", cycle, bn[0], fn[0]);
         for (int r = 0; r < nrhs; ++r) {
-            // first cycle: the paper's criterion (residual reduced by tol); later cycles:
-            // the true residual target tol ||f||
-            target[r] = (cycle == 0) ? tol * bn[r] : tol * fn[r];
-            if (rn[r] <= tol * fn[r] && cycle > 0) target[r] = bn[r];
+            // the GMRES residual is the true residual of the updated iterate (reduced form:
+            // Sec. 2.3).  First cycle: the paper's reduction by tol of the starting
+            // residual, capped at tol ||f||; a restart only has to reach tol ||f||.
+            target[r] = cycle == 0 ? tol * std::min(bn[r], fn[r]) : tol * fn[r];
         }
         double2* ycorr = reduced ? w.Psi : w.PF;
         // GMRES on op(y) = b; the solution increment is P y (+ u~)
@@ -547,17 +625,17 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
         if (reduced) {
             // Algorithm 4: u += P psi + u~   (psi scattered onto the grid)
             HIPCHK(hipMemsetAsync(w.Psi, 0, field_bytes(H, nrhs), H->st));
-            HIPCHK(helm::launch_scatter_cols(w.w, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st)));
             CHK(apply_P_full(H, nrhs, w.Psi, w.Hf));
-            HIPCHK(helm::launch_axpby(w.Hf, w.Ut, w.Hf, 1.0, 1.0, nrhs * nfull, H->st));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_axpby(w.Hf, w.Ut, w.Hf, 1.0, 1.0, nrhs * nfull, H->st)));
         } else {
             CHK(apply_P_full(H, nrhs, w.w, w.Hf));
         }
         (void)ycorr;
-        HIPCHK(helm::launch_axpby(u, w.Hf, u, 1.0, 1.0, nrhs * nfull, H->st));
+        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_axpby(u, w.Hf, u, 1.0, 1.0, nrhs * nfull, H->st)));
     }
     if (!ok) {
-        HIPCHK(helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st));
+        HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st)));
         CHK(norms(H, w.R, nrhs, nfull, rn));
     }
     bool conv = true;
@@ -736,15 +814,15 @@ helm_status helm_factor(helm_t H) {
     CHK(dmalloc(H, &F64, nel * sizeof(double2)));
     HIPCHK(hipMemsetAsync(F64, 0, nel * sizeof(double2), H->st));
     HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
-    HIPCHK(helm::launch_factor_chunks(H->t, g, H->ch, F64, H->d_err, H->st));
-    HIPCHK(helm::launch_factor_separators(H->t, g, H->ch, F64, H->d_err, H->st));
+    HIPCHK(TIMED(H, helm::K_FACTOR_CHUNKS, helm::launch_factor_chunks(H->t, g, H->ch, F64, H->d_err, H->st)));
+    HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_separators(H->t, g, H->ch, F64, H->d_err, H->st)));
     if (H->prec == HELM_C128) {
         H->F = F64;
     } else {
         float2* F32 = nullptr;
         helm_status s = dmalloc(H, &F32, nel * sizeof(float2));
         if (s != HELM_OK) { dfree(F64); return s; }
-        HIPCHK(helm::launch_convert_factor(F64, F32, nel, H->st));
+        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_convert_factor(F64, F32, nel, H->st)));
         HIPCHK(hipStreamSynchronize(H->st));
         dfree(F64);
         H->F = F32;
@@ -791,8 +869,8 @@ helm_status helm_apply_A(helm_t H, int nrhs, const void* u, const void* f, void*
     if (!H) return HELM_EINVAL;
     if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
     if (nrhs < 1 || !u || !out) return fail(H, HELM_EINVAL, "bad arguments");
-    HIPCHK(helm::launch_apply_A(H->t, H->g, nrhs, static_cast<const double2*>(u),
-                                static_cast<const double2*>(f), static_cast<double2*>(out), H->st));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, H->g, nrhs, static_cast<const double2*>(u),
+                                static_cast<const double2*>(f), static_cast<double2*>(out), H->st)));
     return HELM_OK;
 }
 
@@ -832,11 +910,45 @@ helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip
     return HELM_OK;
 }
 
+helm_status helm_get_chunks(helm_t H, int* rows_per_chunk, int* nchunks) {
+    if (!H) return HELM_EINVAL;
+    if (rows_per_chunk) *rows_per_chunk = H->ch.m;
+    if (nchunks) *nchunks = H->ch.P;
+    return HELM_OK;
+}
+
 helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* solve_ms) {
     if (!H) return HELM_EINVAL;
     if (ap_applies) *ap_applies = H->stat_ap;
     if (restarts) *restarts = H->stat_restarts;
     if (solve_ms) *solve_ms = H->stat_ms;
+    return HELM_OK;
+}
+
+helm_status helm_set_kernel_timing(helm_t H, int enable) {
+    if (!H) return HELM_EINVAL;
+    if (enable) {
+        if (!H->timer) H->timer = new EventTimer();
+        HIPCHK(H->st ? hipStreamSynchronize(H->st) : hipDeviceSynchronize());
+        H->timer->reset();
+    } else if (H->timer) {
+        HIPCHK(H->st ? hipStreamSynchronize(H->st) : hipDeviceSynchronize());
+        delete H->timer;
+        H->timer = nullptr;
+    }
+    return HELM_OK;
+}
+
+helm_status helm_get_kernel_times(helm_t H, int nclass, int* launches, double* total_ms) {
+    if (!H || nclass < 0) return HELM_EINVAL;
+    if (!H->timer) return fail(H, HELM_ESTATE, "kernel timing is not enabled");
+    HIPCHK(H->st ? hipStreamSynchronize(H->st) : hipDeviceSynchronize());
+    H->timer->collect();
+    for (int c = 0; c < nclass; ++c) {
+        const bool ok = c < helm::K_NCLASS;
+        if (launches) launches[c] = ok ? (int)H->timer->counts[c] : 0;
+        if (total_ms) total_ms[c] = ok ? H->timer->ms[c] : 0.0;
+    }
     return HELM_OK;
 }
 
@@ -847,6 +959,7 @@ void helm_destroy(helm_t H) {
     if (H->st) (void)hipStreamSynchronize(H->st);
     else (void)hipDeviceSynchronize();
     free_work(H->wk);
+    delete H->timer;
     dfree(H->F);
     dfree(H->d_err);
     for (void* p : H->owned) dfree(p);

@@ -103,6 +103,15 @@ struct DevTables {
     int* redcols = nullptr;     // 2(J-1)   reduced columns beta_j, beta_j + 1
 };
 
+// Optional per-launch event timing: launchers call begin/end around each kernel.
+struct KTimer {
+    virtual void begin(int cls, hipStream_t st) = 0;
+    virtual void end(int cls, hipStream_t st) = 0;
+    virtual ~KTimer() = default;
+};
+enum KClass { K_PHASE_A = 0, K_PHASE_B, K_PHASE_C, K_FACTOR_CHUNKS, K_FACTOR_SEPS, K_STENCIL,
+              K_GMRES, K_OTHER, K_NCLASS };
+
 // ---------------------------------------------------------------- kernels (launchers)
 hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks& ch,
                                 double2* F64, int* err, hipStream_t st);
@@ -113,7 +122,7 @@ hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipS
 template <typename T>
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
                               const cplx<T>* F, cplx<T>* Yw, int nrhs, const IOSpec& io,
-                              hipStream_t st);
+                              hipStream_t st, KTimer* kt = nullptr);
 
 hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
                           const double2* f, double2* out, hipStream_t st);

@@ -264,11 +264,19 @@ __global__ void __launch_bounds__(NT) k_phase_c(SolveArgs<T> a) {
 }
 
 template <typename T, int R>
-hipError_t run(const SolveArgs<T>& a, hipStream_t st) {
+hipError_t run(const SolveArgs<T>& a, hipStream_t st, KTimer* kt) {
     const int RG = (a.nrhs + R - 1) / R;
+    if (kt) kt->begin(K_PHASE_A, st);
     hipLaunchKernelGGL((k_phase_a<T, R>), dim3(a.P, RG), dim3(NT), 0, st, a);
-    if (a.P > 1) hipLaunchKernelGGL((k_phase_b<T, R>), dim3(RG), dim3(NT), 0, st, a);
+    if (kt) kt->end(K_PHASE_A, st);
+    if (a.P > 1) {
+        if (kt) kt->begin(K_PHASE_B, st);
+        hipLaunchKernelGGL((k_phase_b<T, R>), dim3(RG), dim3(NT), 0, st, a);
+        if (kt) kt->end(K_PHASE_B, st);
+    }
+    if (kt) kt->begin(K_PHASE_C, st);
     hipLaunchKernelGGL((k_phase_c<T, R>), dim3(a.Ny, RG), dim3(NT), 0, st, a);
+    if (kt) kt->end(K_PHASE_C, st);
     return hipGetLastError();
 }
 
@@ -277,7 +285,7 @@ hipError_t run(const SolveArgs<T>& a, hipStream_t st) {
 template <typename T>
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
                               const cplx<T>* F, cplx<T>* Yw, int nrhs, const IOSpec& io,
-                              hipStream_t st) {
+                              hipStream_t st, KTimer* kt) {
     SolveArgs<T> a;
     a.F = F + (size_t)s * g.Ny * NSLOT * BLK;
     a.Yw = Yw;
@@ -289,15 +297,15 @@ hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& c
     a.m = ch.m;
     a.P = ch.P;
     a.nrhs = nrhs;
-    if (nrhs <= 4) return run<T, 4>(a, st);
-    return run<T, 16>(a, st);
+    if (nrhs <= 4) return run<T, 4>(a, st, kt);
+    return run<T, 16>(a, st, kt);
 }
 
 template hipError_t launch_strip_solve<float>(const DevTables&, const Geom&, const Chunks&, int,
                                               const float2*, float2*, int, const IOSpec&,
-                                              hipStream_t);
+                                              hipStream_t, KTimer*);
 template hipError_t launch_strip_solve<double>(const DevTables&, const Geom&, const Chunks&, int,
                                                const double2*, double2*, int, const IOSpec&,
-                                               hipStream_t);
+                                               hipStream_t, KTimer*);
 
 }  // namespace helm

@@ -69,6 +69,7 @@ class Helmholtz:
                                   omega, h, o, J)
         self.N_x, self.N_y, self.J = L.helm_get_dims(self.h)
         self.beta, self.strip_first, self.strip_width = L.helm_get_partition(self.h, self.J)
+        self.chunk_rows, self.n_chunks = L.helm_get_chunks(self.h)
         self.prec, self.mode = prec, mode
         self.omega, self.grid_h = float(omega), float(h)
         self.factored = False
@@ -140,6 +141,14 @@ class Helmholtz:
         with torch.cuda.device(self.device):
             L.helm_strip_solve(self.h, strip, r.shape[0], r.data_ptr(), x.data_ptr())
         return x
+
+    def set_kernel_timing(self, enable: bool = True):
+        """Bracket every hot-kernel launch with HIP events (see helm_set_kernel_timing)."""
+        L.helm_set_kernel_timing(self.h, enable)
+
+    def kernel_times(self) -> dict:
+        """{class: (launches, total ms)} since timing was enabled."""
+        return L.helm_get_kernel_times(self.h)
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -166,9 +166,9 @@ def test_one_strip_is_one_iteration():
     H.close()
 
 
-def test_cfg1_plain_c128():
-    """100x100 homogeneous, J = 4, one source at the centre, complex128 (first config)."""
-    wl = W.cfg1()
+def test_homogeneous_100_plain_c128():
+    """100x100 homogeneous, J = 4, one source at the centre, complex128."""
+    wl = W.homogeneous_100()
     g = geometry_from_workload(wl)
     A = assemble_global(g)
     H = _gpu(wl, chunk=0)

@@ -124,8 +124,8 @@ def test_pml_absorbs_like_free_space():
 
 # ------------------------------------------------------------------ geometry
 
-def test_partition_matches_configs():
-    g = geometry_from_workload(W.cfg1())
+def test_partition_of_the_workloads():
+    g = geometry_from_workload(W.homogeneous_100())
     assert list(g.beta) == [0, 35, 60, 85, 120]
     assert [st.W for st in g.strips] == [44, 42, 42, 43]
     g3 = ogrid.partition(2000, 16, 64, 14)

@@ -21,7 +21,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = [
-    "Workload", "cfg1", "cfg2", "cfg3", "cfg3b", "cfg4", "small",
+    "Workload", "homogeneous_100", "lens_1000", "layers", "layers_uneven_batch", "smooth_500", "small",
     "smoothed_noise", "point_sources", "padded_rhs", "WORKLOADS",
 ]
 
@@ -142,16 +142,16 @@ def small(n=24, J=3, w_out=6, w=5, c=None, nsrc=1, seed=11, ppw=10.0, **kw) -> W
     return Workload(f"small{n}", np.asarray(c, float), omega, h, w_out, w, J, srcs, **kw)
 
 
-def cfg1() -> Workload:
+def homogeneous_100() -> Workload:
     """100x100 interior, c = 1, 10 points per wavelength, outer PML 10, J = 4,
     interface PML 8, one point source at the grid centre, complex128."""
     n = 100
     h = 1.0 / n
-    return Workload("cfg1_100x100_J4", np.ones((n, n)), 2 * math.pi * 10.0, h, 10, 8, 4,
+    return Workload("homogeneous_100x100_J4", np.ones((n, n)), 2 * math.pi * 10.0, h, 10, 8, 4,
                     [(50, 50)], precision="c128")
 
 
-def cfg2(nsrc: int = 16) -> Workload:
+def lens_1000(nsrc: int = 16) -> Workload:
     """1000x1000 Gaussian lens c = 1 - 0.4 exp(-|r-r0|^2/0.1^2) + smoothed noise of
     standard deviation 0.05; 16 sources on row y = 0.1; J = 32, PML 16 / 12."""
     n = 1000
@@ -161,11 +161,11 @@ def cfg2(nsrc: int = 16) -> Workload:
     lens = 1.0 - 0.4 * np.exp(-((X - 0.5) ** 2 + (Y - 0.5) ** 2) / 0.01)
     c = lens + 0.05 * smoothed_noise((n, n), 20.0, 2001)
     srcs = [(int((s + 0.5) * n / nsrc), 100) for s in range(nsrc)]
-    return Workload("cfg2_1000x1000_lens_J32", c, 2 * math.pi * 100.0, h, 16, 12, 32, srcs,
+    return Workload("lens_1000x1000_J32", c, 2 * math.pi * 100.0, h, 16, 12, 32, srcs,
                     precision="mixed")
 
 
-def cfg3(n: int = 2000, nsrc: int = 64, seed_medium: int = 3001, seed_src: int = 3002,
+def layers(n: int = 2000, nsrc: int = 64, seed_medium: int = 3001, seed_src: int = 3002,
          J: Optional[int] = None) -> Workload:
     """n x n grid of random horizontal layers (c uniform in [1.5, 4.0], 10-30 layers),
     omega h = 2 pi / 10 at c = 1.5, `nsrc` uniform-random point sources, J = 64 at
@@ -177,20 +177,20 @@ def cfg3(n: int = 2000, nsrc: int = 64, seed_medium: int = 3001, seed_src: int =
     if J is None:
         J = max(1, int(round(64 * n / 2000)))
     srcs = point_sources(n, n, nsrc, seed_src)
-    return Workload(f"cfg3_{n}x{n}_layers_J{J}", c, omega, h, 16, 14, J, srcs, precision="mixed")
+    return Workload(f"layers_{n}x{n}_J{J}", c, omega, h, 16, 14, J, srcs, precision="mixed")
 
 
-def cfg3b() -> List[Workload]:
+def layers_uneven_batch() -> List[Workload]:
     """Eight uneven problems: 500^2, 750^2, ..., 2000^2 plus a second 2000^2 with another
     seed, 8 random sources each, J = round(64 n / 2000)."""
     out = []
     sizes = [500, 750, 1000, 1250, 1500, 1750, 2000, 2000]
     for k, n in enumerate(sizes):
-        out.append(cfg3(n=n, nsrc=8, seed_medium=3100 + k, seed_src=3200 + k))
+        out.append(layers(n=n, nsrc=8, seed_medium=3100 + k, seed_src=3200 + k))
     return out
 
 
-def cfg4() -> Workload:
+def smooth_500() -> Workload:
     """500x500 smooth random medium c in [1.5, 3] (Gaussian-smoothed, min-max mapped),
     omega = 2 pi 50, J = 16, 8 sources on the top row, receivers on row 5."""
     n = 500
@@ -198,7 +198,7 @@ def cfg4() -> Workload:
     s = smoothed_noise((n, n), 25.0, 4001)
     c = 1.5 + 1.5 * (s - s.min()) / (s.max() - s.min())
     srcs = [(int((k + 0.5) * n / 8), 0) for k in range(8)]
-    wl = Workload("cfg4_500x500_grad_J16", c, 2 * math.pi * 50.0, h, 16, 10, 16, srcs,
+    wl = Workload("smooth_500x500_J16", c, 2 * math.pi * 50.0, h, 16, 10, 16, srcs,
                   precision="mixed")
     x = np.arange(n) * h
     X, Y = np.meshgrid(x, x, indexing="xy")
@@ -209,4 +209,4 @@ def cfg4() -> Workload:
     return wl
 
 
-WORKLOADS = {"cfg1": cfg1, "cfg2": cfg2, "cfg3": cfg3, "cfg4": cfg4}
+WORKLOADS = {"homogeneous_100": homogeneous_100, "lens_1000": lens_1000, "layers": layers, "smooth_500": smooth_500}
