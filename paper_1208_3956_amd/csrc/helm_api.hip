@@ -94,6 +94,7 @@ struct helm_problem {
     int prec = HELM_C128, mode = HELM_FULL, max_iter = 200;
     std::string err;
     void* F = nullptr;          // factors: double2 (C128) or float2 (MIXED)
+    void* Fc = nullptr;         // compact spike rows at the target columns, same precision
     bool factored = false;
     int* d_err = nullptr;
     Work wk;
@@ -229,8 +230,9 @@ struct TimedScope {
 template <typename T>
 helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
     const auto* F = static_cast<const helm::cplx<T>*>(H->F);
+    const auto* Fc = static_cast<const helm::cplx<T>*>(H->Fc);
     auto* Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
-    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Yw, nrhs, io, H->st, H->kt()));
+    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Fc, Yw, nrhs, io, H->st, H->kt()));
     return HELM_OK;
 }
 
@@ -278,6 +280,7 @@ helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
             io.coef = -ih2;                                   // -2 delta d_x v, delta = 1/(2h)
         }
         io.dst = w.V;
+        io.targets_only = full ? 0 : 1;
         if (full) {
             io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = S.core_hi - S.a;
         } else {
@@ -314,6 +317,7 @@ helm_status sweep_down(helm_t H, int nrhs, double2* dst, bool full) {
             io.coef = ih2;                                     // +2 delta d_x w
         }
         io.dst = dst;
+        io.targets_only = full ? 0 : 1;
         if (full) {
             io.o_lo[0] = S.kdn_lo - S.a; io.o_hi[0] = S.kdn_hi - S.a;
             io.accumulate = 1;
@@ -360,8 +364,7 @@ helm_status apply_AP_reduced(helm_t H, int nrhs, const double2* psi, double2* ou
     CHK(sweep_down(H, nrhs, w.Wf, false));
     // h = g - A w on the reduced columns; output psi - h
     HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.redcols, nred, w.Wf, w.G, w.Hf, H->st)));
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_axpby(w.Psi, w.Hf, w.Hf, 1.0, -1.0, (long)nrhs * g.Ny * g.Nx, H->st)));
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, out, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols_sub(w.Psi, w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, out, H->st)));
     return HELM_OK;
 }
 
@@ -777,6 +780,16 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         redcols.push_back(g.beta[s]); redcols.push_back(g.beta[s] + 1);
     }
     rcols.push_back(0); redcols.push_back(0);   // never empty
+    // per strip, the strip-local columns the reduced sweeps read: beta_s .. beta_s+2 on the
+    // left interface, beta_{s+1}-2 .. beta_{s+1} on the right one
+    std::vector<int> tcol((size_t)J * 8, -1);
+    for (int s = 0; s < J; ++s) {
+        const auto& S = g.strips[s];
+        if (S.lpad)
+            for (int k = 0; k < 3; ++k) tcol[(size_t)s * 8 + k] = g.beta[s] + k - S.a;
+        if (S.rpad)
+            for (int k = 0; k < 3; ++k) tcol[(size_t)s * 8 + 3 + k] = g.beta[s + 1] - 2 + k - S.a;
+    }
     auto& t = H->t;
     helm_status st = HELM_OK;
     struct Guard {
@@ -796,6 +809,7 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if ((st = upload(H, (void**)&t.sW, sW.data(), sW.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.rcols, rcols.data(), rcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.redcols, redcols.data(), redcols.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.tcol, tcol.data(), tcol.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = dmalloc(H, &H->d_err, sizeof(int))) != HELM_OK) return st;
     H->err.clear();
     *out = H;
@@ -816,8 +830,15 @@ helm_status helm_factor(helm_t H) {
     HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
     HIPCHK(TIMED(H, helm::K_FACTOR_CHUNKS, helm::launch_factor_chunks(H->t, g, H->ch, F64, H->d_err, H->st)));
     HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_separators(H->t, g, H->ch, F64, H->d_err, H->st)));
+    dfree(H->Fc);
+    H->Fc = nullptr;
+    const size_t ncomp = (size_t)g.J * g.Ny * 2 * 8 * WP;
     if (H->prec == HELM_C128) {
         H->F = F64;
+        double2* Fc = nullptr;
+        CHK(dmalloc(H, &Fc, ncomp * sizeof(double2)));
+        H->Fc = Fc;
+        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<double2>(F64, Fc, H->t.tcol, g, H->ch, H->st)));
     } else {
         float2* F32 = nullptr;
         helm_status s = dmalloc(H, &F32, nel * sizeof(float2));
@@ -826,6 +847,10 @@ helm_status helm_factor(helm_t H) {
         HIPCHK(hipStreamSynchronize(H->st));
         dfree(F64);
         H->F = F32;
+        float2* Fc = nullptr;
+        CHK(dmalloc(H, &Fc, ncomp * sizeof(float2)));
+        H->Fc = Fc;
+        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<float2>(F32, Fc, H->t.tcol, g, H->ch, H->st)));
     }
     int herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
@@ -961,6 +986,7 @@ void helm_destroy(helm_t H) {
     free_work(H->wk);
     delete H->timer;
     dfree(H->F);
+    dfree(H->Fc);
     dfree(H->d_err);
     for (void* p : H->owned) dfree(p);
     delete H;

@@ -84,6 +84,9 @@ struct IOSpec {
     int accumulate = 0;
     // outgoing traces: x[qo[0]] -> tro[0][r*Ny + l], x[qo[1]] -> tro[1][r*Ny + l]
     double2* tro0 = nullptr; double2* tro1 = nullptr; int qo0 = -1, qo1 = -1;
+    // every requested column is one of the strip's 8 compact target columns: phase C may
+    // compute only those (reduced form)
+    int targets_only = 0;
 };
 
 // Device tables of one problem.
@@ -101,6 +104,7 @@ struct DevTables {
     int* sW = nullptr;          // J        strip widths
     int* rcols = nullptr;       // 2(J-1)   residual columns beta_j - 1, beta_j
     int* redcols = nullptr;     // 2(J-1)   reduced columns beta_j, beta_j + 1
+    int* tcol = nullptr;        // J*8      strip-local columns whose spike rows are kept compact
 };
 
 // Optional per-launch event timing: launchers call begin/end around each kernel.
@@ -118,11 +122,15 @@ hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks&
 hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chunks& ch,
                                     double2* F64, int* err, hipStream_t st);
 hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipStream_t st);
+// copies of the spike rows at the 8 target columns tcol[s*8 + t] (-1 = unused) of each strip
+template <typename V>
+hipError_t launch_extract_targets(const V* F, V* Fc, const int* tcol, const Geom& g,
+                                  const Chunks& ch, hipStream_t st);
 
 template <typename T>
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
-                              const cplx<T>* F, cplx<T>* Yw, int nrhs, const IOSpec& io,
-                              hipStream_t st, KTimer* kt = nullptr);
+                              const cplx<T>* F, const cplx<T>* Fc, cplx<T>* Yw, int nrhs,
+                              const IOSpec& io, hipStream_t st, KTimer* kt = nullptr);
 
 hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
                           const double2* f, double2* out, hipStream_t st);
@@ -144,6 +152,8 @@ hipError_t launch_lincomb(const double2* V, int nvec, const double2* y, double2*
                           int nrhs, long n, int accumulate, hipStream_t st);
 hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, int nrhs,
                               int Ny, int Nx, double2* red, hipStream_t st);
+hipError_t launch_gather_cols_sub(const double2* fa, const double2* fb, const int* cols, int ncols,
+                                  int nrhs, int Ny, int Nx, double2* red, hipStream_t st);
 hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
                                int Ny, int Nx, double2* field, hipStream_t st);
 // zero column cols[k] + shift of every row, k < ncols

@@ -12,8 +12,8 @@
 //   top spike      X~ = A_I^{-1} (coupling to the separator above) = c_r0 * A_I^{-1} E_first
 //   bottom spike   Y~ = A_I^{-1} (coupling to the separator below) = b_{r1-1} * A_I^{-1} E_last
 // and per strip the separators' block-tridiagonal Schur complement is factored by block
-// LU (G'_c, L_c, U'_c = G'_c S^_{c,c+1}).  Storage per row l: three WP x WP blocks
-// (slot 0: G or G', slot 1: X~ or L, slot 2: Y~ or U').
+// LU (G'_c, K_c = G'_c L_c, U'_c = G'_c S^_{c,c+1}).  Storage per row l: three WP x WP blocks
+// (slot 0: G or G', slot 1: X~ or K, slot 2: Y~ or U').
 //
 // Inverses are formed by Gauss-Jordan elimination with partial (row) pivoting in LDS.
 #include "helm_internal.hpp"
@@ -275,7 +275,8 @@ __global__ void __launch_bounds__(NT) k_factor_chunks(FactorArgs a) {
 //   S^_cc      = T_s - c_s Y~^(c)_{s-1} - b_s X~^(c+1)_{s+1}
 //   S^_{c,c-1} = -c_s X~^(c)_{s-1}           (stored as L_c in slot 1)
 //   S^_{c,c+1} = -b_s Y~^(c+1)_{s+1}
-//   S'_c = S^_cc - L_c U'_{c-1},  G'_c = S'_c^{-1} (slot 0),  U'_c = G'_c S^_{c,c+1} (slot 2)
+//   S'_c = S^_cc - L_c U'_{c-1},  G'_c = S'_c^{-1} (slot 0),  K_c = G'_c L_c (slot 1),
+//   U'_c = G'_c S^_{c,c+1} (slot 2)
 __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
     __shared__ double2 Am[WP * LDM];
     __shared__ double2 Bm[WP * LDM];
@@ -300,21 +301,40 @@ __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
         }
         __syncthreads();
         if (c >= 1) {
-            const double2* Xc = slot(a, s, r - 1, 1);
-            double2* L = slot(a, s, r, 1);
-            for (int idx = threadIdx.x; idx < BLK; idx += NT)
-                L[idx] = cmul(cmk<double2>(-cs.x, -cs.y), Xc[idx]);
-            // Bm = Bm - L_c U'_{c-1} = Bm + c_s X~^(c)_{s-1} U'_{c-1}
-            gemm64(Bm, LDM, Xc, WP, Am, LDM, cs, Bm, LDM);
+            // Bm = Bm - L_c U'_{c-1},  L_c = S^_{c,c-1} = -c_s X~^(c)_{s-1}
+            gemm64(Bm, LDM, slot(a, s, r - 1, 1), WP, Am, LDM, cs, Bm, LDM);
         }
         invert_inplace(Bm, W, sc, a.err);
         store_blk(slot(a, s, r, 0), Bm, one);
         __syncthreads();
+        if (c >= 1) {
+            // K_c = G'_c L_c = -c_s G'_c X~^(c)_{s-1} replaces L_c in slot 1, so that the
+            // forward separator recurrence is z'_c = G'_c r^_c - K_c z'_{c-1}
+            gemm64(Am, LDM, Bm, LDM, slot(a, s, r - 1, 1), WP, cmk<double2>(-cs.x, -cs.y), nullptr, 0);
+            store_blk(slot(a, s, r, 1), Am, one);
+            __syncthreads();
+        }
         if (c + 2 < a.P) {
             gemm64(Am, LDM, Bm, LDM, slot(a, s, r + 1, 2), WP, cmk<double2>(-bs.x, -bs.y), nullptr, 0);
             store_blk(slot(a, s, r, 2), Am, one);
             __syncthreads();
         }
+    }
+}
+
+// Fc[((s*Ny + l)*2 + side)*8*WP + t*WP + k] = (side ? Y~ : X~)_l(tcol[s*8+t], k), interior rows
+template <typename V>
+__global__ void k_extract_targets(const V* __restrict__ F, V* __restrict__ Fc,
+                                  const int* __restrict__ tcol, int Ny, int m, int P) {
+    const int l = blockIdx.x, s = blockIdx.y;
+    const int c = l / m;
+    const bool sep = (c < P - 1) && (l == c * m + m - 1);
+    for (int idx = threadIdx.x; idx < 2 * 8 * WP; idx += blockDim.x) {
+        const int k = idx % WP, t = (idx / WP) % 8, side = idx / (8 * WP);
+        const int q = tcol[s * 8 + t];
+        V v; v.x = 0; v.y = 0;
+        if (!sep && q >= 0) v = F[(((size_t)s * Ny + l) * NSLOT + 1 + side) * BLK + (size_t)k * WP + q];
+        Fc[(((size_t)s * Ny + l) * 2 + side) * 8 * WP + t * WP + k] = v;
     }
 }
 
@@ -349,6 +369,18 @@ hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chu
     hipLaunchKernelGGL(k_factor_separators, dim3(g.J), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
+
+template <typename V>
+hipError_t launch_extract_targets(const V* F, V* Fc, const int* tcol, const Geom& g,
+                                  const Chunks& ch, hipStream_t st) {
+    hipLaunchKernelGGL((k_extract_targets<V>), dim3(g.Ny, g.J), dim3(256), 0, st, F, Fc, tcol,
+                       g.Ny, ch.m, ch.P);
+    return hipGetLastError();
+}
+template hipError_t launch_extract_targets<float2>(const float2*, float2*, const int*, const Geom&,
+                                                   const Chunks&, hipStream_t);
+template hipError_t launch_extract_targets<double2>(const double2*, double2*, const int*,
+                                                    const Geom&, const Chunks&, hipStream_t);
 
 hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_convert, dim3(2048), dim3(256), 0, st, F64, F32, n);

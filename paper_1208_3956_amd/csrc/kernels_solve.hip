@@ -2,14 +2,19 @@
 // eqs. solve_upward / solve_downward, Sec. 2.1-2.2), for a panel of right-hand sides.
 //
 // With chunks I_c (interior rows) and separators s_c (see kernels_factor.hip):
-//   phase A  (all chunks in parallel)  y_I = A_I^{-1} r_I by forward / backward block
-//            substitution  z_l = G_l (r_l - c_l z_{l-1}),  y_l = z_l - b_l G_l y_{l+1}
-//   phase B  (one sweep over separators) r^_c = r_s - c_s y_{s-1} - b_s y_{s+1};
-//            z'_c = G'_c (r^_c - L_c z'_{c-1});  x_s = z'_c - U'_c x_{s'}
-//   phase C  (all rows in parallel)     x_l = y_l - X~_l x_{s above} - Y~_l x_{s below}
-// Phase A gathers the right-hand side (restriction of a field to the strip plus the
-// two-column transmission source of Sec. 2.2); phase C scatters the requested columns of
-// x into the output field and writes the two trace columns the next strip needs.
+//   phase A   (chunks x rhs groups)  y_I = A_I^{-1} r_I by forward / backward block
+//             substitution  z_l = G_l (r_l - c_l z_{l-1}),  y_l = z_l - b_l G_l y_{l+1}
+//   phase B0  (separators x rhs)     a_c = G'_c r^_c,  r^_c = r_s - c_s y_{s-1} - b_s y_{s+1}
+//   phase B   (one workgroup per rhs) z'_c = a_c - K_c z'_{c-1};  x_s = z'_c - U'_c x_{s'}
+//   phase C   (rows x rhs groups)    x_l = y_l - X~_l x_{s above} - Y~_l x_{s below}
+// Phase A (and B0) gather the right-hand side (a field restricted to the strip plus the
+// two-column transmission source of Sec. 2.2); phase C scatters the requested columns of x
+// and the two trace columns the next strip needs.  When only a few columns are requested
+// (the reduced form), phase C computes just those from compact copies of the spike rows.
+//
+// The chains of phases A and B read the next factor block from global memory into
+// registers while the current block (in LDS) is applied, then store it to the other LDS
+// buffer: the latency of the block loads stays off the dependency chain.
 //
 // Arithmetic is in T (float or double complex); gathered and scattered fields are FP64.
 #include "helm_internal.hpp"
@@ -23,6 +28,8 @@ constexpr int NT = 256;
 template <typename T>
 struct SolveArgs {
     const cplx<T>* F;     // factors of the strip: [Ny][NSLOT][WP*WP]
+    const cplx<T>* Fc;    // compact spike rows of the strip: [Ny][2][8][WP] (reduced phase C)
+    const int* tcol;      // 8 strip-local columns of the compact rows (-1 = unused)
     cplx<T>* Yw;          // workspace [nrhs][Ny][WP]
     const double2* cy;
     const double2* by;
@@ -43,177 +50,416 @@ __device__ inline cplx<T> gather(const IOSpec& io, int r, int l, int q, int Ny) 
     return ccast<cplx<T>>(v);
 }
 
+// Branch-free gather in two halves: load_raw issues the loads (clamped addresses; lanes
+// outside the source or transmission columns read element 0 and discard it), combine
+// forms the right-hand-side value.  Keeping the uses apart from the loads lets the loads
+// of the next step overlap the current one.  io.src, io.trA and io.trB must be valid
+// pointers (the host points unused transmission traces at the source).
+struct RawRhs {
+    double2 v, ta, tb;
+};
+__device__ inline RawRhs load_raw(const IOSpec& io, int r, int l, int q, int Ny, int nrhs, int W) {
+    const bool ok = r < nrhs && q < W;
+    const bool in_src = ok && q >= io.src_lo && q < io.src_hi;
+    const bool in_tr = ok && io.q_t >= 0 && (q == io.q_t || q == io.q_t + 1);
+    const size_t ps = in_src ? (size_t)r * io.src_rs + (size_t)l * io.src_ls + (q + io.src_off) : 0;
+    const size_t pt = in_tr ? (size_t)r * Ny + l : 0;
+    RawRhs x;
+    x.v = io.src[ps];
+    x.ta = io.trA[pt];
+    x.tb = io.trB[pt];
+    if (!in_src) x.v = cmk<double2>(0.0, 0.0);
+    if (!in_tr) { x.ta = cmk<double2>(0.0, 0.0); x.tb = x.ta; }
+    return x;
+}
+template <typename T>
+__device__ inline cplx<T> combine(const IOSpec& io, const RawRhs& x) {
+    double2 v = x.v;
+    v.x += io.coef * (x.tb.x - x.ta.x);
+    v.y += io.coef * (x.tb.y - x.ta.y);
+    return ccast<cplx<T>>(v);
+}
+
 template <typename T>
 __device__ inline const cplx<T>* fslot(const SolveArgs<T>& a, int l, int sl) {
     return a.F + ((size_t)l * NSLOT + sl) * BLK;
 }
 
-// acc[u] += sum_k M(i,k) vin[k][g + 4u] over k < W  (M column-major, ld WP)
-template <typename T, int R>
-__device__ inline void matvec_acc(cplx<T> (&acc)[R / 4], const cplx<T>* __restrict__ M,
-                                  const cplx<T> (*vin)[R], int W, int i, int g) {
-    constexpr int U = R / 4;
-    for (int k = 0; k < W; ++k) {
-        const cplx<T> mk = M[(size_t)k * WP + i];
+template <typename T>
+__device__ inline void scatter(const SolveArgs<T>& a, int r, int l, int i, cplx<T> x) {
+    const IOSpec& io = a.io;
+    const double2 xv = ccast<double2>(x);
+    const bool o = (i >= io.o_lo[0] && i < io.o_hi[0]) || (i >= io.o_lo[1] && i < io.o_hi[1]);
+    if (o && io.dst) {
+        double2* p = io.dst + (size_t)r * io.dst_rs + (size_t)l * io.dst_ls + (i + io.dst_off);
+        *p = io.accumulate ? cadd(*p, xv) : xv;
+    }
+    if (i == io.qo0 && io.tro0) io.tro0[(size_t)r * a.Ny + l] = xv;
+    if (i == io.qo1 && io.tro1) io.tro1[(size_t)r * a.Ny + l] = xv;
+}
+
+// A factor block staged through registers into LDS.  Thread t owns elements
+// t + NT*j, j < BLK/NT, of the column-major block.
+template <typename T>
+struct BlockPipe {
+    static constexpr int PER = BLK / NT;
+    cplx<T> reg[PER];
+    __device__ void load(const cplx<T>* __restrict__ g) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) cfma(acc[u], mk, vin[k][g + 4 * u]);
+        for (int j = 0; j < PER; ++j) reg[j] = g[threadIdx.x + NT * j];
+    }
+    __device__ void store(cplx<T>* s) const {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) s[threadIdx.x + NT * j] = reg[j];
+    }
+};
+
+// acc[u] += sum_{k<W} M(i,k) vin[k][g + G*u]   (M column-major WP x WP)
+template <typename T, int R, int G>
+__device__ inline void matvec(cplx<T> (&acc)[R / G], const cplx<T>* M, const cplx<T> (*vin)[R],
+                              int W, int i, int g) {
+    constexpr int U = R / G;
+#pragma unroll 4
+    for (int k = 0; k < W; ++k) {
+        const cplx<T> mk = M[k * WP + i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) cfma(acc[u], mk, vin[k][g + G * u]);
     }
 }
 
 // ---------------------------------------------------------------- phase A
+// R right-hand sides per workgroup; thread (i = t % 64, g = t / 64) owns row i of the
+// block and right-hand sides g, g+4, ...
 template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_phase_a(SolveArgs<T> a) {
     using V = cplx<T>;
-    constexpr int U = R / 4;
+    constexpr int G = 4, U = R / G;
+    __shared__ V Gs[2][BLK];
     __shared__ V vin[WP][R];
     const int t = threadIdx.x, i = t & (WP - 1), g = t >> 6;
     const int c = blockIdx.x, rbase = blockIdx.y * R;
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
+    const int n = r1 - r0;
+    const int steps = 2 * n - 1;                 // forward r0..r1-1, backward r1-2..r0
+    auto row_of = [&](int k) { return k < n ? r0 + k : r1 - 2 - (k - n); };
     const V zero = cmk<V>(0, 0);
     V z[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) z[u] = zero;
 
-    for (int l = r0; l < r1; ++l) {
-        const V cl = ccast<V>(a.cy[l]);
+    BlockPipe<T> pipe;
+    pipe.load(fslot(a, row_of(0), 0));
+    pipe.store(Gs[0]);
+    int cur = 0;
+    for (int k = 0; k < steps; ++k) {
+        const int l = row_of(k);
+        const bool fwd = k < n;
+        if (k + 1 < steps) pipe.load(fslot(a, row_of(k + 1), 0));
+        if (fwd) {
+            const V cl = ccast<V>(a.cy[l]);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = rbase + g + 4 * u;
-            V v = zero;
-            if (r < a.nrhs && i < a.W) {
-                v = gather<T>(a.io, r, l, i, a.Ny);
-                if (l > r0) v = csub(v, cmul(cl, z[u]));
+            for (int u = 0; u < U; ++u) {
+                const int r = rbase + g + G * u;
+                V v = zero;
+                if (r < a.nrhs && i < a.W) {
+                    v = gather<T>(a.io, r, l, i, a.Ny);
+                    if (l > r0) v = csub(v, cmul(cl, z[u]));
+                }
+                vin[i][g + G * u] = v;
             }
-            vin[i][g + 4 * u] = v;
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) vin[i][g + G * u] = z[u];
         }
         __syncthreads();
         V acc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u] = zero;
-        matvec_acc<T, R>(acc, fslot(a, l, 0), vin, a.W, i, g);
+        matvec<T, R, G>(acc, Gs[cur], vin, a.W, i, g);
+        if (fwd) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = rbase + g + 4 * u;
-            z[u] = acc[u];
-            if (r < a.nrhs) a.Yw[((size_t)r * a.Ny + l) * WP + i] = acc[u];
+            for (int u = 0; u < U; ++u) {
+                const int r = rbase + g + G * u;
+                z[u] = acc[u];
+                if (r < a.nrhs) a.Yw[((size_t)r * a.Ny + l) * WP + i] = acc[u];
+            }
+        } else {
+            const V bl = ccast<V>(a.by[l]);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int r = rbase + g + G * u;
+                if (r < a.nrhs) {
+                    V* p = a.Yw + ((size_t)r * a.Ny + l) * WP + i;
+                    const V y = csub(*p, cmul(bl, acc[u]));
+                    *p = y;
+                    z[u] = y;
+                } else {
+                    z[u] = zero;
+                }
+            }
         }
+        if (k + 1 < steps) pipe.store(Gs[cur ^ 1]);
         __syncthreads();
+        cur ^= 1;
     }
-    // backward: y_{r1-1} = z_{r1-1};  y_l = z_l - b_l G_l y_{l+1}
-    for (int l = r1 - 2; l >= r0; --l) {
+}
+
+// ---------------------------------------------------------------- phase A, MFMA
+// complex64, 16 right-hand sides per workgroup.  The block product Z = G V (64 x 64 times
+// 64 x 16, complex) runs on v_mfma_f32_16x16x4f32 as four real products
+// (Zr += Gr Vr - Gi Vi, Zi += Gr Vi + Gi Vr); wave w owns output rows 16w..16w+15.
+// MFMA lane layout (16x16x4, one block): A[l % 16][l / 16], B[l / 16][l % 16],
+// C[4 (l / 16) + j][l % 16] in component j.
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
+    using V = float2;
+    constexpr int R = 16;
+    __shared__ V Gs[2][BLK];
+    __shared__ V Vs[WP][R];
+    __shared__ V Rs[WP][R];
+    __shared__ unsigned char tmask[WP];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int n = lane & 15, q4 = lane >> 4;            // MFMA column (rhs), row quad
+    const int gi = t & (WP - 1), gr = t >> 6;            // gather: row gi, rhs gr + 4u
+    const int c = blockIdx.x, rbase = blockIdx.y * R;
+    const int r0 = c * a.m;
+    const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
+    const int nr = r1 - r0;
+    const V zero = make_float2(0.f, 0.f);
+    const int rn = rbase + n;                            // rhs of this lane's MFMA column
+    const bool rn_ok = rn < a.nrhs;
+    const size_t ybase = (size_t)(rn_ok ? rn : 0) * a.Ny * WP + 16 * w + 4 * q4;
+    // targets-only solves read y at the compact target columns (phase C) and on the first
+    // and last interior row (the separators' right-hand sides); full solves read it all
+    if (t < WP) {
+        bool on = false;
+        for (int k = 0; k < 8; ++k) on = on || (a.tcol[k] == t);
+        tmask[t] = on ? 1 : 0;
+    }
+    V z[4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) vin[i][g + 4 * u] = z[u];
-        __syncthreads();
-        V acc[U];
+    for (int j = 0; j < 4; ++j) z[j] = zero;
+    RawRhs raw[4];
+    auto load_rows = [&](int l) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = zero;
-        matvec_acc<T, R>(acc, fslot(a, l, 0), vin, a.W, i, g);
-        const V bl = ccast<V>(a.by[l]);
+        for (int u = 0; u < 4; ++u) raw[u] = load_raw(a.io, rbase + gr + 4 * u, l, gi, a.Ny, a.nrhs, a.W);
+    };
+    auto store_rows = [&]() {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = rbase + g + 4 * u;
-            if (r < a.nrhs) {
-                V* p = a.Yw + ((size_t)r * a.Ny + l) * WP + i;
-                const V y = csub(*p, cmul(bl, acc[u]));
-                *p = y;
-                z[u] = y;
-            } else {
-                z[u] = zero;
-            }
+        for (int u = 0; u < 4; ++u) Rs[gi][gr + 4 * u] = combine<float>(a.io, raw[u]);
+    };
+    BlockPipe<float> pipe;
+    auto mfma_block = [&](const V* Gb, V (&out)[4]) {
+        mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+#pragma unroll
+        for (int k0 = 0; k0 < WP; k0 += 8) {
+            const V g0 = Gb[(k0 + q4) * WP + 16 * w + n];
+            const V v0 = Vs[k0 + q4][n];
+            const V g1 = Gb[(k0 + 4 + q4) * WP + 16 * w + n];
+            const V v1 = Vs[k0 + 4 + q4][n];
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.y, aI1, 0, 0, 0);
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g0.y, v0.y, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.x, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g1.y, v1.y, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.x, aI1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[j] = make_float2(aR0[j] + aR1[j], aI0[j] + aI1[j]);
+    };
+
+    // prologue: block and right-hand side of row r0
+    load_rows(r0);
+    pipe.load(fslot(a, r0, 0));
+    store_rows();
+    pipe.store(Gs[0]);
+    __syncthreads();
+    int cur = 0;
+
+    // ---- forward:  z_l = G_l (r_l - c_l z_{l-1})
+    // (vmcnt retires loads in issue order: every value used inside a step is loaded one
+    // step earlier and issued before the large prefetches)
+    double2 cnext = a.cy[r0];
+    for (int l = r0; l < r1; ++l) {
+        const V cl = ccast<V>(cnext);
+        // next step's loads, all issued here: coupling, right-hand side of row l+1, then
+        // its block (the last forward step prefetches the block of the first backward row)
+        const int ln = l + 1 < r1 ? l + 1 : l;
+        const int lb = l + 1 < r1 ? l + 1 : (r1 - 2 >= r0 ? r1 - 2 : l);
+        cnext = a.cy[ln];
+        load_rows(ln);
+        pipe.load(fslot(a, lb, 0));
+        const bool first = l == r0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 16 * w + 4 * q4 + j;
+            V v = Rs[i][n];
+            if (!first) v = csub(v, cmul(cl, z[j]));
+            Vs[i][n] = v;
         }
         __syncthreads();
+        V acc[4];
+        mfma_block(Gs[cur], acc);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            z[j] = rn_ok ? acc[j] : zero;
+            if (rn_ok) a.Yw[ybase + (size_t)l * WP + j] = acc[j];
+        }
+        __syncthreads();            // everyone is done with Rs and Gs[cur ^ 1]
+        store_rows();
+        pipe.store(Gs[cur ^ 1]);
+        __syncthreads();
+        cur ^= 1;
+    }
+    // ---- backward:  y_l = z_l - b_l G_l y_{l+1},  l = r1-2 .. r0
+    V zn[4];
+    double2 bnext = a.by[r1 - 2 >= r0 ? r1 - 2 : r0];
+    if (r1 - 2 >= r0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) zn[j] = rn_ok ? a.Yw[ybase + (size_t)(r1 - 2) * WP + j] : zero;
+    }
+    for (int l = r1 - 2; l >= r0; --l) {
+        V zl[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) zl[j] = zn[j];
+        const V bl = ccast<V>(bnext);
+        const int lb = l - 1 >= r0 ? l - 1 : l;
+        // next step's loads: coupling and z of row l-1 (stored by the forward pass), then
+        // its block
+        bnext = a.by[lb];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) zn[j] = rn_ok ? a.Yw[ybase + (size_t)lb * WP + j] : zero;
+        pipe.load(fslot(a, lb, 0));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) Vs[16 * w + 4 * q4 + j][n] = z[j];
+        __syncthreads();
+        V acc[4];
+        mfma_block(Gs[cur], acc);
+        const bool store_y = !a.io.targets_only || l == r0 || l == r1 - 1;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const V y = csub(zl[j], cmul(bl, acc[j]));
+            z[j] = rn_ok ? y : zero;
+            if (rn_ok && (store_y || tmask[16 * w + 4 * q4 + j])) a.Yw[ybase + (size_t)l * WP + j] = y;
+        }
+        __syncthreads();
+        pipe.store(Gs[cur ^ 1]);
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
+// ---------------------------------------------------------------- phase B0
+// a_c = G'_c r^_c for every separator (grid: separators x rhs groups), stored at row s_c.
+template <typename T, int R>
+__global__ void __launch_bounds__(NT) k_phase_b0(SolveArgs<T> a) {
+    using V = cplx<T>;
+    constexpr int G = 4, U = R / G;
+    __shared__ V vin[WP][R];
+    const int t = threadIdx.x, i = t & (WP - 1), g = t >> 6;
+    const int c = blockIdx.x, rbase = blockIdx.y * R;
+    const int s = c * a.m + a.m - 1;
+    const V cs = ccast<V>(a.cy[s]), bs = ccast<V>(a.by[s]);
+    const V zero = cmk<V>(0, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = rbase + g + G * u;
+        V v = zero;
+        if (r < a.nrhs && i < a.W) {
+            v = gather<T>(a.io, r, s, i, a.Ny);
+            v = csub(v, cmul(cs, a.Yw[((size_t)r * a.Ny + (s - 1)) * WP + i]));
+            v = csub(v, cmul(bs, a.Yw[((size_t)r * a.Ny + (s + 1)) * WP + i]));
+        }
+        vin[i][g + G * u] = v;
+    }
+    __syncthreads();
+    V acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] = zero;
+    matvec<T, R, G>(acc, fslot(a, s, 0), vin, a.W, i, g);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int r = rbase + g + G * u;
+        if (r < a.nrhs) a.Yw[((size_t)r * a.Ny + s) * WP + i] = acc[u];
     }
 }
 
 // ---------------------------------------------------------------- phase B
-template <typename T, int R>
+// One right-hand side per workgroup; the k-sum of every matvec is split over the 4 waves
+// and combined through LDS.  Forward z'_0 = a_0, z'_c = a_c - K_c z'_{c-1}; backward
+// x_{P-2} = z'_{P-2}, x_c = z'_c - U'_c x_{c+1}.  The blocks of the next D steps are in
+// flight in registers while a step runs (ring of D+1 LDS buffers).
+template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_phase_b(SolveArgs<T> a) {
     using V = cplx<T>;
-    constexpr int U = R / 4;
-    __shared__ V vin[WP][R];
-    const int t = threadIdx.x, i = t & (WP - 1), g = t >> 6;
-    const int rbase = blockIdx.x * R;
-    const V zero = cmk<V>(0, 0);
-    V z[U];
+    __shared__ V Gs[D + 1][BLK];
+    __shared__ V vec[WP];
+    __shared__ V part[4][WP];
+    const int t = threadIdx.x, i = t & (WP - 1), w = t >> 6;
+    const int r = blockIdx.x;
+    const int ns = a.P - 1;                  // separators
+    const int nf = ns - 1;                   // forward steps (c = 1..ns-1)
+    const int steps = nf + (ns - 1);         // + backward steps (c = ns-2..0)
+    if (steps <= 0) return;
+    auto sep = [&](int c) { return c * a.m + a.m - 1; };
+    // separator row and factor block of step k (clamped to the last step: loads past the
+    // end re-read the last block and are never used)
+    auto sep_of = [&](int k) {
+        k = k < steps ? k : steps - 1;
+        return sep(k < nf ? k + 1 : ns - 2 - (k - nf));
+    };
+    auto blk = [&](int k) {
+        k = k < steps ? k : steps - 1;
+        return k < nf ? fslot(a, sep(k + 1), 1) : fslot(a, sep(ns - 2 - (k - nf)), 2);
+    };
+    V* Yr = a.Yw + (size_t)r * a.Ny * WP;
+    // every thread keeps the value of its row i; the four waves hold identical copies
+    vec[i] = Yr[(size_t)sep(0) * WP + i];    // z'_0 = a_0
+    V nextv = Yr[(size_t)sep_of(0) * WP + i];
+    BlockPipe<T> pipe[D];
 #pragma unroll
-    for (int u = 0; u < U; ++u) z[u] = zero;
-
-    for (int c = 0; c + 1 < a.P; ++c) {
-        const int s = c * a.m + a.m - 1;
-        const V cs = ccast<V>(a.cy[s]), bs = ccast<V>(a.by[s]);
-        V rh[U];
+    for (int d = 0; d < D; ++d) pipe[d].load(blk(d));
+    pipe[0].store(Gs[0]);
+    pipe[0].load(blk(D));
+    __syncthreads();
+    const int k0 = w * 16;
+    auto step = [&](int k, BlockPipe<T>& nxt) {
+        const int s = sep_of(k);
+        const V curv = nextv;                           // a_c (forward) or z'_c (backward)
+        nextv = Yr[(size_t)sep_of(k + 1) * WP + i];
+        V acc = cmk<V>(0, 0);
+        const V* M = Gs[k % (D + 1)] + k0 * WP + i;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = rbase + g + 4 * u;
-            V v = zero;
-            if (r < a.nrhs && i < a.W) {
-                v = gather<T>(a.io, r, s, i, a.Ny);
-                const V yu = a.Yw[((size_t)r * a.Ny + (s - 1)) * WP + i];
-                const V yd = a.Yw[((size_t)r * a.Ny + (s + 1)) * WP + i];
-                v = csub(v, cmul(cs, yu));
-                v = csub(v, cmul(bs, yd));
-            }
-            rh[u] = v;
-        }
-        if (c >= 1) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) vin[i][g + 4 * u] = z[u];
-            __syncthreads();
-            V acc[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) acc[u] = zero;
-            matvec_acc<T, R>(acc, fslot(a, s, 1), vin, a.W, i, g);
-#pragma unroll
-            for (int u = 0; u < U; ++u) rh[u] = csub(rh[u], acc[u]);
-            __syncthreads();
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) vin[i][g + 4 * u] = rh[u];
+        for (int kk = 0; kk < 16; ++kk) cfma(acc, M[kk * WP], vec[k0 + kk]);
+        part[w][i] = acc;
         __syncthreads();
-        V acc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = zero;
-        matvec_acc<T, R>(acc, fslot(a, s, 0), vin, a.W, i, g);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = rbase + g + 4 * u;
-            z[u] = acc[u];
-            if (r < a.nrhs) a.Yw[((size_t)r * a.Ny + s) * WP + i] = acc[u];
-        }
+        const V sum = cadd(cadd(part[0][i], part[1][i]), cadd(part[2][i], part[3][i]));
+        const V v = csub(curv, sum);            // a_c - K_c z'  or  z'_c - U'_c x
+        Yr[(size_t)s * WP + i] = v;
+        vec[i] = v;
+        nxt.store(Gs[(k + 1) % (D + 1)]);       // block k+1, in flight since step k+1-D
+        nxt.load(blk(k + 1 + D));
         __syncthreads();
+    };
+    int k = 0;
+    for (; k + D <= steps; k += D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) step(k + j, pipe[(j + 1) % D]);
     }
-    // backward over separators: x_c = z'_c - U'_c x_{c+1}
-    for (int c = a.P - 3; c >= 0; --c) {
-        const int s = c * a.m + a.m - 1;
 #pragma unroll
-        for (int u = 0; u < U; ++u) vin[i][g + 4 * u] = z[u];
-        __syncthreads();
-        V acc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] = zero;
-        matvec_acc<T, R>(acc, fslot(a, s, 2), vin, a.W, i, g);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = rbase + g + 4 * u;
-            if (r < a.nrhs) {
-                V* p = a.Yw + ((size_t)r * a.Ny + s) * WP + i;
-                const V x = csub(*p, acc[u]);
-                *p = x;
-                z[u] = x;
-            } else {
-                z[u] = zero;
-            }
-        }
-        __syncthreads();
-    }
+    for (int j = 0; j < D; ++j)
+        if (k + j < steps) step(k + j, pipe[(j + 1) % D]);
 }
 
-// ---------------------------------------------------------------- phase C
+// ---------------------------------------------------------------- phase C (all columns)
 template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_phase_c(SolveArgs<T> a) {
     using V = cplx<T>;
-    constexpr int U = R / 4;
+    constexpr int G = 4, U = R / G;
     __shared__ V va[WP][R];
     __shared__ V vb[WP][R];
     const int t = threadIdx.x, i = t & (WP - 1), g = t >> 6;
@@ -226,56 +472,121 @@ __global__ void __launch_bounds__(NT) k_phase_c(SolveArgs<T> a) {
     V x[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int r = rbase + g + 4 * u;
+        const int r = rbase + g + G * u;
         x[u] = (r < a.nrhs) ? a.Yw[((size_t)r * a.Ny + l) * WP + i] : zero;
         V xa = zero, xb = zero;
         if (r < a.nrhs) {
             if (top) xa = a.Yw[((size_t)r * a.Ny + (c * a.m - 1)) * WP + i];
             if (bot) xb = a.Yw[((size_t)r * a.Ny + (c * a.m + a.m - 1)) * WP + i];
         }
-        va[i][g + 4 * u] = xa;
-        vb[i][g + 4 * u] = xb;
+        va[i][g + G * u] = xa;
+        vb[i][g + G * u] = xb;
     }
     __syncthreads();
     if (top || bot) {
         V acc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u] = zero;
-        if (top) matvec_acc<T, R>(acc, fslot(a, l, 1), va, a.W, i, g);
-        if (bot) matvec_acc<T, R>(acc, fslot(a, l, 2), vb, a.W, i, g);
+        if (top) matvec<T, R, G>(acc, fslot(a, l, 1), va, a.W, i, g);
+        if (bot) matvec<T, R, G>(acc, fslot(a, l, 2), vb, a.W, i, g);
 #pragma unroll
         for (int u = 0; u < U; ++u) x[u] = csub(x[u], acc[u]);
     }
-    const IOSpec& io = a.io;
-    const bool o0 = i >= io.o_lo[0] && i < io.o_hi[0];
-    const bool o1 = i >= io.o_lo[1] && i < io.o_hi[1];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int r = rbase + g + 4 * u;
-        if (r >= a.nrhs || i >= a.W) continue;
-        const double2 xv = ccast<double2>(x[u]);
-        if ((o0 || o1) && io.dst) {
-            double2* p = io.dst + (size_t)r * io.dst_rs + (size_t)l * io.dst_ls + (i + io.dst_off);
-            *p = io.accumulate ? cadd(*p, xv) : xv;
-        }
-        if (i == io.qo0 && io.tro0) io.tro0[(size_t)r * a.Ny + l] = xv;
-        if (i == io.qo1 && io.tro1) io.tro1[(size_t)r * a.Ny + l] = xv;
+        const int r = rbase + g + G * u;
+        if (r < a.nrhs && i < a.W) scatter<T>(a, r, l, i, x[u]);
     }
 }
 
+// ---------------------------------------------------------------- phase C (target columns)
+// Only the 8 compact columns tcol[] of the strip; thread = (slot = t / 32, rhs = t % 32);
+// ROWS consecutive rows per workgroup share the separator vectors of their chunk.
+constexpr int CT_ROWS = 8;
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_phase_c_targets(SolveArgs<T> a) {
+    using V = cplx<T>;
+    constexpr int RC = 32;
+    __shared__ V va[WP][RC];
+    __shared__ V vb[WP][RC];
+    __shared__ V fr[16][WP];
+    const int t = threadIdx.x, rbase = blockIdx.y * RC;
+    const int sl = t / RC, rr = t % RC, r = rbase + rr;
+    const int q = a.tcol[sl];
+    const V zero = cmk<V>(0, 0);
+    const int l0 = blockIdx.x * CT_ROWS, l1 = min(a.Ny, l0 + CT_ROWS);
+    int loaded = -1;
+    for (int l = l0; l < l1; ++l) {
+        const int c = l / a.m;
+        if (c != loaded) {                       // uniform over the workgroup
+            __syncthreads();
+            for (int idx = t; idx < WP * RC; idx += NT) {
+                const int k = idx / RC, q2 = idx % RC, r2 = rbase + q2;
+                V xa = zero, xb = zero;
+                if (r2 < a.nrhs && k < a.W) {
+                    if (c > 0) xa = a.Yw[((size_t)r2 * a.Ny + (c * a.m - 1)) * WP + k];
+                    if (c < a.P - 1) xb = a.Yw[((size_t)r2 * a.Ny + (c * a.m + a.m - 1)) * WP + k];
+                }
+                va[k][q2] = xa;
+                vb[k][q2] = xb;
+            }
+            __syncthreads();
+            loaded = c;
+        }
+        const bool is_sep = (c < a.P - 1) && (l == c * a.m + a.m - 1);
+        // the 2 x 8 compact spike rows of row l (zero outside the strip width)
+        const V* src = a.Fc + (size_t)l * 2 * 8 * WP;
+        for (int idx = t; idx < 2 * 8 * WP; idx += NT) fr[idx / WP][idx % WP] = src[idx];
+        __syncthreads();
+        if (q >= 0 && r < a.nrhs) {
+            V x = a.Yw[((size_t)r * a.Ny + l) * WP + q];
+            if (!is_sep) {
+                V acc = zero;
+#pragma unroll 16
+                for (int k = 0; k < WP; ++k) {
+                    cfma(acc, fr[sl][k], va[k][rr]);
+                    cfma(acc, fr[8 + sl][k], vb[k][rr]);
+                }
+                x = csub(x, acc);
+            }
+            scatter<T>(a, r, l, q, x);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T> struct Depth { static constexpr int D = 1; };
+template <> struct Depth<float> { static constexpr int D = 3; };
+
 template <typename T, int R>
-hipError_t run(const SolveArgs<T>& a, hipStream_t st, KTimer* kt) {
+void launch_phase_a(const SolveArgs<T>& a, int RG, hipStream_t st) {
+    hipLaunchKernelGGL((k_phase_a<T, R>), dim3(a.P, RG), dim3(NT), 0, st, a);
+}
+template <>
+void launch_phase_a<float, 16>(const SolveArgs<float>& a, int RG, hipStream_t st) {
+    hipLaunchKernelGGL(k_phase_a_mfma, dim3(a.P, RG), dim3(NT), 0, st, a);
+}
+
+template <typename T, int R>
+hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) {
     const int RG = (a.nrhs + R - 1) / R;
     if (kt) kt->begin(K_PHASE_A, st);
-    hipLaunchKernelGGL((k_phase_a<T, R>), dim3(a.P, RG), dim3(NT), 0, st, a);
+    launch_phase_a<T, R>(a, RG, st);
     if (kt) kt->end(K_PHASE_A, st);
     if (a.P > 1) {
         if (kt) kt->begin(K_PHASE_B, st);
-        hipLaunchKernelGGL((k_phase_b<T, R>), dim3(RG), dim3(NT), 0, st, a);
+        hipLaunchKernelGGL((k_phase_b0<T, R>), dim3(a.P - 1, RG), dim3(NT), 0, st, a);
+        if (a.P > 2)
+            hipLaunchKernelGGL((k_phase_b<T, Depth<T>::D>), dim3(a.nrhs), dim3(NT), 0, st, a);
         if (kt) kt->end(K_PHASE_B, st);
     }
     if (kt) kt->begin(K_PHASE_C, st);
-    hipLaunchKernelGGL((k_phase_c<T, R>), dim3(a.Ny, RG), dim3(NT), 0, st, a);
+    if (targets)
+        hipLaunchKernelGGL((k_phase_c_targets<T>), dim3((a.Ny + CT_ROWS - 1) / CT_ROWS, (a.nrhs + 31) / 32),
+                           dim3(NT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_phase_c<T, R>), dim3(a.Ny, RG), dim3(NT), 0, st, a);
     if (kt) kt->end(K_PHASE_C, st);
     return hipGetLastError();
 }
@@ -284,28 +595,37 @@ hipError_t run(const SolveArgs<T>& a, hipStream_t st, KTimer* kt) {
 
 template <typename T>
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
-                              const cplx<T>* F, cplx<T>* Yw, int nrhs, const IOSpec& io,
-                              hipStream_t st, KTimer* kt) {
+                              const cplx<T>* F, const cplx<T>* Fc, cplx<T>* Yw, int nrhs,
+                              const IOSpec& io, hipStream_t st, KTimer* kt) {
     SolveArgs<T> a;
     a.F = F + (size_t)s * g.Ny * NSLOT * BLK;
+    a.Fc = Fc ? Fc + (size_t)s * g.Ny * 2 * 8 * WP : nullptr;
+    a.tcol = t.tcol + s * 8;
     a.Yw = Yw;
     a.cy = t.cy;
     a.by = t.by;
     a.io = io;
+    if (!Fc) a.io.targets_only = 0;     // without compact rows phase C reads every column
+    if (!a.io.trA || !a.io.trB || a.io.q_t < 0) {   // the gather always dereferences them
+        a.io.trA = a.io.trB = a.io.src;
+        a.io.q_t = -1;
+        a.io.coef = 0.0;
+    }
     a.Ny = g.Ny;
     a.W = g.strips[s].W;
     a.m = ch.m;
     a.P = ch.P;
     a.nrhs = nrhs;
-    if (nrhs <= 4) return run<T, 4>(a, st, kt);
-    return run<T, 16>(a, st, kt);
+    const bool targets = a.io.targets_only != 0;
+    if (nrhs <= 4) return run<T, 4>(a, targets, st, kt);
+    return run<T, 16>(a, targets, st, kt);
 }
 
 template hipError_t launch_strip_solve<float>(const DevTables&, const Geom&, const Chunks&, int,
-                                              const float2*, float2*, int, const IOSpec&,
-                                              hipStream_t, KTimer*);
+                                              const float2*, const float2*, float2*, int,
+                                              const IOSpec&, hipStream_t, KTimer*);
 template hipError_t launch_strip_solve<double>(const DevTables&, const Geom&, const Chunks&, int,
-                                               const double2*, double2*, int, const IOSpec&,
-                                               hipStream_t, KTimer*);
+                                               const double2*, const double2*, double2*, int,
+                                               const IOSpec&, hipStream_t, KTimer*);
 
 }  // namespace helm

@@ -208,6 +208,19 @@ __global__ void k_gather_cols(const double2* __restrict__ field, const int* __re
     }
 }
 
+// red[r][l][k] = a[r][l][cols[k]] - b[r][l][cols[k]]
+__global__ void k_gather_cols_sub(const double2* __restrict__ fa, const double2* __restrict__ fb,
+                                  const int* __restrict__ cols, int ncols, int nrhs, int Ny, int Nx,
+                                  double2* __restrict__ red) {
+    const size_t tot = (size_t)nrhs * Ny * ncols;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q % ncols);
+        const size_t p = (q / ncols) * Nx + cols[k];
+        red[q] = csub(fa[p], fb[p]);
+    }
+}
+
 __global__ void k_scatter_cols(const double2* __restrict__ red, const int* __restrict__ cols,
                                int ncols, int nrhs, int Ny, int Nx, double2* __restrict__ field) {
     const size_t tot = (size_t)nrhs * Ny * ncols;
@@ -314,6 +327,14 @@ hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, 
     if (ncols <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_cols, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
                        field, cols, ncols, nrhs, Ny, Nx, red);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_cols_sub(const double2* fa, const double2* fb, const int* cols, int ncols,
+                                  int nrhs, int Ny, int Nx, double2* red, hipStream_t st) {
+    if (ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_cols_sub, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
+                       fa, fb, cols, ncols, nrhs, Ny, Nx, red);
     return hipGetLastError();
 }
 
