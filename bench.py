@@ -39,6 +39,11 @@ def parse():
     p.add_argument("--chunk", type=int, default=0)
     p.add_argument("--tol", type=float, default=1e-6)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-c128-leg", action="store_true",
+                   help="skip the complex128 comparison legs (batched and one RHS per solve)")
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of MIB MiB three times and exit "
+                        "(reference dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     return p.parse_args()
 
 
@@ -130,11 +135,110 @@ def cpu_baseline(wl, iters_mean, budget_s=10.0):
     }
 
 
+KERNEL_SOURCES = ("paper_1208_3956_amd/csrc/kernels_solve.hip",
+                  "paper_1208_3956_amd/csrc/kernels_factor.hip",
+                  "paper_1208_3956_amd/csrc/helm_internal.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(cls, wl, nrhs, prec):
+    """HBM bytes per launch of kernel class `cls` from the committed counter summary of this
+    workload, or None when there is none or the kernel sources changed since it was taken.
+    The summary holds FETCH_SIZE and WRITE_SIZE per dispatch already scaled by the copy
+    calibration, and the sha256 of the kernel sources it was measured on."""
+    import re
+    path = os.path.join(ROOT, "profiles", f"{cls}_hbm_traffic_{wl.name}_nrhs{nrhs}_{prec}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    want = {}
+    for key in ("source_sha256", "fetch_bytes_per_launch", "write_bytes_per_launch"):
+        m = re.search(rf"^{key}:\s*(\S+)\s*$", text, re.M)
+        if not m:
+            return None
+        want[key] = m.group(1)
+    if want["source_sha256"] != kernel_source_hash():
+        return None
+    return float(want["fetch_bytes_per_launch"]) + float(want["write_bytes_per_launch"])
+
+
+def algorithmic_bytes(H, nrhs, prec):
+    """HBM bytes that one phase-A launch must move at least: the factor blocks G_l of every
+    interior row read once per direction, the right-hand side read once, the chunk result
+    written once (complex64: 8 B, complex128: 16 B per value)."""
+    b = 8 if prec == "mixed" else 16
+    Ny, m = H.N_y, H.chunk_rows
+    P = -(-Ny // m)
+    n_int = Ny - (P - 1)
+    W = sum(H.strip_width) / len(H.strip_width)
+    return b * (2.0 * W * W * n_int + 2.0 * W * Ny * nrhs)
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "copy_calibration_bytes_written": n * 4,
+                      "dispatches": 3}), flush=True)
+
+
+def c128_legs(wl, f, tol, plain_rhs=2):
+    """Complex128 comparison on the same workload: the batched solve (all right-hand sides in
+    one helm_solve) and the plain path (one right-hand side per helm_solve), each after a
+    factorisation, one timed pass; the plain path is timed on `plain_rhs` right-hand sides and
+    scaled per right-hand side (the metric is additive over independent right-hand sides)."""
+    import numpy as np
+    import torch
+    from paper_1208_3956_amd import Helmholtz
+    H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                  prec="c128", mode="reduced", device="cuda:0")
+    H.factor()
+    torch.cuda.synchronize()
+    pts_rhs = wl.n_x * wl.n_y
+    ta = time.perf_counter()
+    res = H.solve(f, tol)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - ta
+    t_plain = 0.0
+    it_plain = []
+    for k in range(plain_rhs):
+        ta = time.perf_counter()
+        r1 = H.solve(f[k:k + 1], tol)
+        torch.cuda.synchronize()
+        t_plain += time.perf_counter() - ta
+        it_plain.append(r1.iters[0])
+    H.close()
+    print(f"# c128: batched {t_batch * 1e3:.0f} ms, plain {t_plain / plain_rhs * 1e3:.0f} ms per RHS",
+          file=sys.stderr, flush=True)
+    return {
+        "batched": {"solve_only_value": f.shape[0] * pts_rhs / t_batch, "solve_ms": t_batch * 1e3,
+                    "iters_mean": float(np.mean(res.iters)), "relres_max": max(res.relres)},
+        "plain_one_rhs_per_solve": {"solve_only_value": pts_rhs * plain_rhs / t_plain,
+                                    "ms_per_rhs": t_plain / plain_rhs * 1e3,
+                                    "rhs_timed": plain_rhs, "iters": it_plain},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 (no multi-GPU path)"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import numpy as np
     import torch
     from paper_1208_3956_amd import Helmholtz
@@ -184,8 +288,10 @@ def main():
     ach = fl[dom] / avg_s / 1e12 if avg_s > 0 else 0.0
     peak = PEAK[dtype if dom.startswith("phase") else "c128"]
     roof = {"kernel": dom, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-            "frac": ach / peak, "traffic": None, "launches": cnt, "avg_launch_us": avg_s * 1e6,
-            "flops_per_launch": fl[dom]}
+            "frac": ach / peak, "traffic": profiled_traffic(dom, wl, nrhs, args.prec),
+            "launches": cnt, "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl[dom]}
+    if dom == "phase_a":
+        roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(H, nrhs, args.prec)
     out = {
         "metric": METRIC, "value": value, "unit": "RHS*gridpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -204,6 +310,11 @@ def main():
         "roofline": roof,
     }
     H.close()
+    if args.prec == "mixed" and not args.no_c128_leg:
+        out["c128"] = c128_legs(wl, f, args.tol)
+        out["mixed_vs_c128_batched"] = out["solve_only_value"] / out["c128"]["batched"]["solve_only_value"]
+        out["mixed_vs_c128_plain"] = (out["solve_only_value"]
+                                      / out["c128"]["plain_one_rhs_per_solve"]["solve_only_value"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, float(np.mean(res.iters)))
     print(json.dumps(out), flush=True)
