@@ -108,8 +108,10 @@ helm_status helm_factor(helm_t H);
  * Algorithm 5: solve A u = f for nrhs right-hand sides by right-preconditioned GMRES
  * with the double-sweep preconditioner, starting from u = 0 (FULL) or u = u~ (REDUCED,
  * Algorithm 2), stopping when the GMRES residual has dropped by `tol` relative to its
- * start (Sec. 4: reduction by 1e-6), then checking the true residual ||f - A u|| / ||f||
- * in FP64 and restarting once from u if it exceeds tol.
+ * start (Sec. 4: reduction by 1e-6, capped at tol ||f||), then checking the true
+ * residual ||f - A u|| / ||f|| in FP64 and, while it exceeds tol, running another GMRES
+ * cycle on that residual (iterative refinement; right-hand sides that already meet tol
+ * take no part), up to max_iter applications of A P in total.
  *   rhs     device, nrhs * N_y * N_x complex128 (padded grid)
  *   u       device, same shape, output
  *   iters   host, nrhs ints (may be NULL): GMRES iterations (applications of A P)
@@ -119,6 +121,33 @@ helm_status helm_factor(helm_t H);
  */
 helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
                        int* iters, double* relres);
+
+/*
+ * Misfit and its gradient with respect to the squared slowness m = 1/c^2 on the interior
+ * grid (the adjoint-state method; the paper has no gradient, this is the differentiation
+ * form of its solver).  For sources f_s, receivers R and data d_s:
+ *   J = 1/2 sum_s ||R u_s - d_s||^2,      A u_s = f_s,
+ *   dJ/dm_p = omega^2 Re sum_s sum_{q -> p} conj(lambda_s[q]) u_s[q],
+ *   A^H lambda_s = R^T (R u_s - d_s),
+ * where q runs over the padded points whose medium is that of interior point p (p itself,
+ * plus the outer-PML points behind an edge point).  Only the -k^2 u term of A depends on m.
+ * The adjoint systems use the same factors: the PML operator is A = D S with
+ * D = alpha_x(x) alpha_y(y) and S complex symmetric (Sec. 2.2), so
+ * conj(lambda) = A^{-1}(D conj(q)) / D.  The PML itself (its reference speed fixed at
+ * helm_setup) is held constant.  Both solves follow helm_solve with tolerance tol.
+ *   src     device, nsrc * N_y * N_x complex128, [source][y][x] (padded grid)
+ *   rec     device, nrec int64: flat padded-grid indices y * N_x + x of the receivers
+ *           (a receiver listed twice counts twice)
+ *   d       device, nsrc * nrec complex128, [source][receiver]
+ *   misfit  host, one double (output)
+ *   grad    device, n_y * n_x doubles, [y][x] interior grid (output, overwritten)
+ *   iters   host, 2 * nsrc ints (may be NULL): forward then adjoint GMRES iterations
+ * The call allocates and frees its own work arrays (3 * nsrc fields).  HELM_EINVAL for a
+ * receiver index outside [0, N_x N_y) or nsrc, nrec < 1; HELM_ESTATE before helm_factor;
+ * HELM_ENOCONV if a solve misses tol (misfit and grad are still written).
+ */
+helm_status helm_grad(helm_t H, int nsrc, const void* src, int nrec, const int64_t* rec,
+                      const void* d, double tol, double* misfit, double* grad, int* iters);
 
 /*
  * The preconditioner alone (Sec. 2.1, end): out = P f = v + w for nrhs fields, computed

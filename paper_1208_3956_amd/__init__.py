@@ -5,13 +5,16 @@ binding with the same names and `solver.Helmholtz` a torch-facing wrapper.  Impo
 this package does not load the library; the first call does, and fails loudly if it
 has not been built (`python -m paper_1208_3956_amd.build`).
 """
-__all__ = ["Helmholtz", "SolveResult", "build"]
+__all__ = ["Helmholtz", "SolveResult", "HelmMisfit", "misfit", "build"]
 
 
 def __getattr__(name):
     if name in ("Helmholtz", "SolveResult"):
         from . import solver
         return getattr(solver, name)
+    if name in ("HelmMisfit", "misfit"):
+        from . import autograd
+        return getattr(autograd, name)
     if name == "build":
         from .build import build
         return build

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP"
 EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm_apply_P",
            "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
-           "helm_get_kernel_times", "helm_last_error", "helm_destroy"]
+           "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
     L.helm_apply_P.argtypes = [vp, ci, vp, vp]
     L.helm_apply_AP_reduced.argtypes = [vp, ci, vp, vp]
     L.helm_apply_A.argtypes = [vp, ci, vp, vp, vp]
+    L.helm_grad.argtypes = [vp, ci, vp, ci, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                            vp, pint]
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
@@ -135,6 +137,19 @@ def helm_apply_P(hdl, nrhs: int, f_ptr: int, out_ptr: int) -> None:
 def helm_apply_AP_reduced(hdl, nrhs: int, psi_ptr: int, out_ptr: int) -> None:
     check(lib().helm_apply_AP_reduced(hdl, int(nrhs), ctypes.c_void_p(psi_ptr),
                                       ctypes.c_void_p(out_ptr)), hdl)
+
+
+def helm_grad(hdl, nsrc: int, src_ptr: int, nrec: int, rec_ptr: int, d_ptr: int, tol: float,
+              grad_ptr: int):
+    """Returns (status, misfit, iterations [forward..., adjoint...])."""
+    mis = ctypes.c_double(0.0)
+    its = (ctypes.c_int * (2 * nsrc))()
+    st = lib().helm_grad(hdl, int(nsrc), ctypes.c_void_p(src_ptr), int(nrec), ctypes.c_void_p(rec_ptr),
+                         ctypes.c_void_p(d_ptr), float(tol), ctypes.byref(mis), ctypes.c_void_p(grad_ptr),
+                         its)
+    if st not in (HELM_OK, HELM_ENOCONV):
+        check(st, hdl)
+    return st, mis.value, list(its)
 
 
 def helm_apply_A(hdl, nrhs: int, u_ptr: int, f_ptr, out_ptr: int) -> None:

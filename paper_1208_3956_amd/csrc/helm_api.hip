@@ -875,6 +875,88 @@ helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
     return s;
 }
 
+helm_status helm_grad(helm_t H, int nsrc, const void* src, int nrec, const int64_t* rec,
+                      const void* d, double tol, double* misfit, double* grad, int* iters) {
+    if (!H) return HELM_EINVAL;
+    if (!H->factored) return fail(H, HELM_ESTATE, "helm_grad before helm_factor");
+    if (nsrc < 1 || nrec < 1 || !src || !rec || !d || !misfit || !grad)
+        return fail(H, HELM_EINVAL, "nsrc, nrec >= 1 and non-null src, rec, d, misfit, grad required");
+    if (!(tol > 0)) return fail(H, HELM_EINVAL, "tol must be positive");
+    const auto& g = H->g;
+    const long field = (long)g.Nx * g.Ny;
+    // receivers: validated on the host, grouped by point (repeated receivers add up)
+    std::vector<int64_t> hrec(nrec);
+    HIPCHK(hipMemcpyAsync(hrec.data(), rec, nrec * sizeof(int64_t), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    std::vector<int> order(nrec);
+    for (int k = 0; k < nrec; ++k) {
+        if (hrec[k] < 0 || hrec[k] >= field)
+            return fail(H, HELM_EINVAL, "receiver index " + std::to_string(hrec[k]) +
+                                            " outside the padded grid [0, N_x N_y)");
+        order[k] = k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hrec[a] < hrec[b]; });
+    std::vector<long> upt;
+    std::vector<int> ustart;
+    for (int t = 0; t < nrec; ++t) {
+        if (t == 0 || hrec[order[t]] != hrec[order[t - 1]]) {
+            upt.push_back((long)hrec[order[t]]);
+            ustart.push_back(t);
+        }
+    }
+    ustart.push_back(nrec);
+    const int nu = (int)upt.size();
+
+    struct Bufs {
+        std::vector<void*> p;
+        ~Bufs() { for (void* q : p) dfree(q); }
+    } bufs;
+    auto alloc = [&](void** q, size_t bytes) -> helm_status {
+        CHK(dmalloc(H, q, bytes));
+        bufs.p.push_back(*q);
+        return HELM_OK;
+    };
+    double2 *U, *Q, *Z, *r;
+    long *dupt;
+    int *dustart, *duidx;
+    double* dmis;
+    CHK(alloc((void**)&U, field_bytes(H, nsrc)));
+    CHK(alloc((void**)&Q, field_bytes(H, nsrc)));
+    CHK(alloc((void**)&Z, field_bytes(H, nsrc)));
+    CHK(alloc((void**)&r, (size_t)nsrc * nrec * sizeof(double2)));
+    CHK(alloc((void**)&dupt, nu * sizeof(long)));
+    CHK(alloc((void**)&dustart, (nu + 1) * sizeof(int)));
+    CHK(alloc((void**)&duidx, nrec * sizeof(int)));
+    CHK(alloc((void**)&dmis, sizeof(double)));
+    HIPCHK(hipMemcpyAsync(dupt, upt.data(), nu * sizeof(long), hipMemcpyHostToDevice, H->st));
+    HIPCHK(hipMemcpyAsync(dustart, ustart.data(), (nu + 1) * sizeof(int), hipMemcpyHostToDevice, H->st));
+    HIPCHK(hipMemcpyAsync(duidx, order.data(), nrec * sizeof(int), hipMemcpyHostToDevice, H->st));
+
+    std::vector<int> it1(nsrc), it2(nsrc);
+    std::vector<double> rr1(nsrc), rr2(nsrc);
+    // forward fields u_s = A^{-1} f_s
+    helm_status s1 = solve_impl(H, nsrc, static_cast<const double2*>(src), U, tol, it1.data(), rr1.data());
+    if (s1 != HELM_OK && s1 != HELM_ENOCONV) return s1;
+    // r = R u - d, misfit, adjoint right-hand side D conj(R^T r)
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_rec_residual(U, field, reinterpret_cast<const long*>(rec), nrec,
+                                                             static_cast<const double2*>(d), nsrc, r, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_half_sumsq(r, (long)nsrc * nrec, dmis, H->st)));
+    HIPCHK(hipMemsetAsync(Q, 0, field_bytes(H, nsrc), H->st));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_adjoint_rhs(r, nrec, nsrc, dupt, dustart, duidx, nu, H->t, g, Q,
+                                                            H->st)));
+    // z = A^{-1} D conj(q), conj(lambda) = z / D
+    helm_status s2 = solve_impl(H, nsrc, Q, Z, tol, it2.data(), rr2.data());
+    if (s2 != HELM_OK && s2 != HELM_ENOCONV) return s2;
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_grad_m(U, Z, nsrc, H->t, g, grad, H->st)));
+    HIPCHK(hipMemcpyAsync(misfit, dmis, sizeof(double), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    if (iters)
+        for (int k = 0; k < nsrc; ++k) { iters[k] = it1[k]; iters[nsrc + k] = it2[k]; }
+    if (s1 != HELM_OK || s2 != HELM_OK)
+        return fail(H, HELM_ENOCONV, "a forward or adjoint solve did not reach the tolerance");
+    return HELM_OK;
+}
+
 helm_status helm_apply_P(helm_t H, int nrhs, const void* f, void* out) {
     if (!H) return HELM_EINVAL;
     if (!H->factored) return fail(H, HELM_ESTATE, "helm_apply_P before helm_factor");

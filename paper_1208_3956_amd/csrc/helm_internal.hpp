@@ -164,4 +164,14 @@ hipError_t launch_axpby(const double2* x, const double2* y, double2* out, double
 
 int dots_blocks(long n);
 
+// ---- misfit and adjoint gradient (kernels_grad.hip)
+hipError_t launch_rec_residual(const double2* u, long field, const long* rec, int nrec,
+                               const double2* d, int nsrc, double2* r, hipStream_t st);
+hipError_t launch_half_sumsq(const double2* r, long n, double* out, hipStream_t st);
+hipError_t launch_adjoint_rhs(const double2* r, int nrec, int nsrc, const long* upt, const int* ustart,
+                              const int* uidx, int nu, const DevTables& t, const Geom& g, double2* Q,
+                              hipStream_t st);
+hipError_t launch_grad_m(const double2* u, const double2* z, int nsrc, const DevTables& t,
+                         const Geom& g, double* grad, hipStream_t st);
+
 }  // namespace helm

@@ -107,6 +107,27 @@ class Helmholtz:
             ap, rs, ms = L.helm_get_stats(self.h)
         return SolveResult(u, it, rel, st, ap, rs, ms)
 
+    def grad(self, src: torch.Tensor, rec, d: torch.Tensor, tol: float = 1e-6):
+        """Misfit 1/2 sum_s |R u_s - d_s|^2 and its gradient with respect to m = 1/c^2 on
+        the interior grid (adjoint state, see helm_grad).  src: (nsrc, N_y, N_x) complex128;
+        rec: flat padded-grid receiver indices (int64 tensor or sequence); d: (nsrc, nrec)
+        complex128.  Returns (misfit, grad (n_y, n_x) float64 tensor, iterations)."""
+        f = self._field(src, "src")
+        nsrc = f.shape[0]
+        rec_t = torch.as_tensor(rec, dtype=torch.int64).to(self.device).contiguous().reshape(-1)
+        nrec = rec_t.numel()
+        if not isinstance(d, torch.Tensor) or d.dtype != torch.complex128 or d.device != self.device:
+            raise TypeError("d must be a complex128 tensor on the solver's device")
+        if tuple(d.shape) != (nsrc, nrec):
+            raise ValueError(f"d must have shape ({nsrc}, {nrec}), got {tuple(d.shape)}")
+        d = d.contiguous()
+        n_y, n_x = self._c.shape
+        g = torch.empty((n_y, n_x), dtype=torch.float64, device=self.device)
+        with torch.cuda.device(self.device):
+            st, mis, its = L.helm_grad(self.h, nsrc, f.data_ptr(), nrec, rec_t.data_ptr(), d.data_ptr(),
+                                       tol, g.data_ptr())
+        return mis, g, its
+
     def apply_P(self, f: torch.Tensor) -> torch.Tensor:
         f = self._field(f, "f")
         out = torch.empty_like(f)

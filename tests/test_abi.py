@@ -75,3 +75,7 @@ def test_interface_inside_outer_pml_rejected():
 
 def test_destroy_null_is_noop():
     L.lib().helm_destroy(None)
+
+
+def test_grad_null_handle_is_einval():
+    assert L.lib().helm_grad(None, 1, None, 1, None, None, 1e-6, None, None, None) == L.HELM_EINVAL
