@@ -31,7 +31,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--workload", default="layers", choices=["homogeneous_100", "lens_1000", "layers"])
+    p.add_argument("--workload", default="layers",
+                   choices=["homogeneous_100", "lens_1000", "layers", "layers_uneven_batch"])
     p.add_argument("--n", type=int, default=None, help="grid size for the layers family")
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--prec", default="mixed", choices=["mixed", "c128"])
@@ -231,6 +232,68 @@ def c128_legs(wl, f, tol, plain_rhs=2):
     }
 
 
+def batch_main(args):
+    """Eight uneven layered problems (500^2 ... 2000^2, 8 RHS each): one step = factor all +
+    solve all concurrently (helm_solve_batch, one stream per problem); the same handles are
+    also solved one after another for comparison."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1208_3956_amd import Helmholtz, solve_batch
+    wls = W.layers_uneven_batch()
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    fs = [torch.from_numpy(wl.rhs()).to(dev) for wl in wls]
+    streams = [torch.cuda.Stream(dev) for _ in wls]
+    Hs = [Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                    prec=args.prec, mode=args.mode, chunk=args.chunk, device=dev, stream=s)
+          for wl, s in zip(wls, streams)]
+    pts = sum(f.shape[0] * wl.n_x * wl.n_y for wl, f in zip(wls, fs))
+
+    def step(concurrent):
+        for H in Hs:
+            H.factor()
+        for H in Hs:
+            H.stream.synchronize()
+        if concurrent:
+            return solve_batch(Hs, fs, args.tol)
+        return [H.solve(f, args.tol) for H, f in zip(Hs, fs)]
+
+    for k in range(args.warmup):
+        print(f"# batch warmup {k}: concurrent", file=sys.stderr, flush=True)
+        step(True)
+        print(f"# batch warmup {k}: sequential", file=sys.stderr, flush=True)
+        step(False)
+    torch.cuda.synchronize()
+    print("# batch timed: concurrent", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step(True)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / args.steps
+    print("# batch timed: sequential", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res_s = step(False)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / args.steps
+    for H in Hs:
+        H.close()
+    out = {
+        "metric": "RHS*gridpts/s to 1e-6 residual, uneven batch of 8 layered 2-D problems (500^2..2000^2, 8 RHS each)",
+        "value": pts / t_b, "unit": "RHS*gridpts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_b * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64" if args.prec == "mixed" else "c128", "data": "synthetic",
+        "config": {"workload": "layers_uneven_batch", "sizes": [wl.n_x for wl in wls],
+                   "J": [wl.J for wl in wls], "nrhs_each": 8, "prec": args.prec, "mode": args.mode,
+                   "step": "helm_factor (each) + helm_solve_batch"},
+        "sequential_value": pts / t_s, "sequential_ms_per_step": t_s * 1e3,
+        "iters": [float(np.mean(r.iters)) for r in res],
+        "relres_max": max(max(r.relres) for r in res + res_s),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -238,6 +301,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "layers_uneven_batch":
+        batch_main(args)
         return
     import numpy as np
     import torch

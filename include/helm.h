@@ -75,6 +75,11 @@ typedef struct {
     int max_iter;       /* GMRES iteration cap; <= 0 selects 200                          */
     int chunk;          /* rows per chunk of the y-partitioned strip solver; 0 = auto     */
     void* stream;       /* hipStream_t for all device work; NULL = default stream        */
+    int graph;          /* 1 (default): in REDUCED mode, capture one application of
+                           Algorithm 3 per right-hand-side count into a HIP graph and replay
+                           it in every GMRES iteration (its input is first copied into a
+                           fixed buffer); 0: launch kernel by kernel.  Graphs are not used
+                           while kernel timing is enabled                               */
 } helm_opts;
 
 /* Default options for a 2-D problem of n_x x n_y interior points. */
@@ -121,6 +126,20 @@ helm_status helm_factor(helm_t H);
  */
 helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
                        int* iters, double* relres);
+
+/*
+ * Several independent problems solved concurrently (uneven grids, e.g. a batch of
+ * different sizes): problem p solves nrhs[p] right-hand sides rhs[p] into u[p] exactly as
+ * helm_solve(H[p], ...) would, each driven by its own host thread on its handle's stream,
+ * so that the kernels of different problems share the GPU.  Give every handle its own
+ * stream (handles that share a stream are still correct, only serialised).
+ *   H, nrhs, rhs, u   host arrays of nprob entries; rhs[p], u[p] device fields of H[p]
+ *   iters, relres     host, sum(nrhs) entries each (may be NULL), problem by problem
+ * Returns HELM_OK when every problem succeeded, else the status of the first failing
+ * problem (its message in helm_last_error(H[p])).  The handles must be distinct.
+ */
+helm_status helm_solve_batch(int nprob, const helm_t* H, const int* nrhs, const void* const* rhs,
+                             void* const* u, double tol, int* iters, double* relres);
 
 /*
  * Misfit and its gradient with respect to the squared slowness m = 1/c^2 on the interior

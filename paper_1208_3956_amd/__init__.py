@@ -5,11 +5,11 @@ binding with the same names and `solver.Helmholtz` a torch-facing wrapper.  Impo
 this package does not load the library; the first call does, and fails loudly if it
 has not been built (`python -m paper_1208_3956_amd.build`).
 """
-__all__ = ["Helmholtz", "SolveResult", "HelmMisfit", "misfit", "build"]
+__all__ = ["Helmholtz", "SolveResult", "solve_batch", "HelmMisfit", "misfit", "build"]
 
 
 def __getattr__(name):
-    if name in ("Helmholtz", "SolveResult"):
+    if name in ("Helmholtz", "SolveResult", "solve_batch"):
         from . import solver
         return getattr(solver, name)
     if name in ("HelmMisfit", "misfit"):

@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP"
 EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm_apply_P",
            "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
-           "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad"]
+           "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
+           "helm_solve_batch"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -42,6 +43,7 @@ class HelmOpts(ctypes.Structure):
         ("max_iter", ctypes.c_int),
         ("chunk", ctypes.c_int),
         ("stream", ctypes.c_void_p),
+        ("graph", ctypes.c_int),
     ]
 
 
@@ -73,6 +75,8 @@ def lib() -> ctypes.CDLL:
     L.helm_apply_P.argtypes = [vp, ci, vp, vp]
     L.helm_apply_AP_reduced.argtypes = [vp, ci, vp, vp]
     L.helm_apply_A.argtypes = [vp, ci, vp, vp, vp]
+    L.helm_solve_batch.argtypes = [ci, ctypes.POINTER(vp), pint, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   cd, pint, pdbl]
     L.helm_grad.argtypes = [vp, ci, vp, ci, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                             vp, pint]
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
@@ -137,6 +141,23 @@ def helm_apply_P(hdl, nrhs: int, f_ptr: int, out_ptr: int) -> None:
 def helm_apply_AP_reduced(hdl, nrhs: int, psi_ptr: int, out_ptr: int) -> None:
     check(lib().helm_apply_AP_reduced(hdl, int(nrhs), ctypes.c_void_p(psi_ptr),
                                       ctypes.c_void_p(out_ptr)), hdl)
+
+
+def helm_solve_batch(hdls, nrhs, rhs_ptrs, u_ptrs, tol: float):
+    """Returns (status, iterations, relres) over all right-hand sides, problem by problem."""
+    n = len(hdls)
+    tot = int(sum(nrhs))
+    H = (ctypes.c_void_p * n)(*hdls)
+    NR = (ctypes.c_int * n)(*[int(k) for k in nrhs])
+    R = (ctypes.c_void_p * n)(*rhs_ptrs)
+    U = (ctypes.c_void_p * n)(*u_ptrs)
+    its = (ctypes.c_int * tot)()
+    rel = (ctypes.c_double * tot)()
+    st = lib().helm_solve_batch(n, H, NR, R, U, float(tol), its, rel)
+    if st not in (HELM_OK, HELM_ENOCONV):
+        bad = next((h for h in hdls if helm_last_error(h)), hdls[0])
+        check(st, bad)
+    return st, list(its), list(rel)
 
 
 def helm_grad(hdl, nsrc: int, src_ptr: int, nrec: int, rec_ptr: int, d_ptr: int, tol: float,

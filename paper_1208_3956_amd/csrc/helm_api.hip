@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "helm_internal.hpp"
@@ -37,6 +38,7 @@ struct Work {
     double* npartial = nullptr;
     double2* y = nullptr;
     double2* red = nullptr;
+    double2* apin = nullptr;    // fixed input of the captured reduced operator
 };
 
 // Event-pair timing of kernel launches (helm_set_kernel_timing).
@@ -99,6 +101,14 @@ struct helm_problem {
     int* d_err = nullptr;
     Work wk;
     int stat_ap = 0, stat_restarts = 0;
+    int dev = 0;                // HIP device of the handle
+    int use_graph = 1;          // replay Algorithm 3 from a captured HIP graph (REDUCED)
+    hipGraphExec_t ap_exec = nullptr;
+    hipStream_t cap_st = nullptr;  // private stream the graph is captured on (capture is not
+                                   // allowed on the legacy default stream); replays go to st
+    int ap_nrhs = 0;
+    const void* ap_out = nullptr;
+    long ws_epoch = 0, ap_epoch = -1;  // workspace generation the graph was captured with
     double stat_ms = 0.0;
     std::vector<void*> owned;   // table allocations
     EventTimer* timer = nullptr; // non-null while kernel timing is enabled
@@ -190,7 +200,7 @@ helm_status upload(helm_t H, void** dptr, const void* src, size_t bytes) {
 // ---------------------------------------------------------------- workspaces
 void free_work(Work& w) {
     void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
-                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red};
+                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin};
     for (void* p : ps) dfree(p);
     w = Work();
 }
@@ -201,6 +211,7 @@ helm_status ensure_sweep_ws(helm_t H, int nrhs) {
     Work& w = H->wk;
     if (w.nrhs >= nrhs && w.V) return HELM_OK;
     free_work(w);
+    H->ws_epoch += 1;
     const auto& g = H->g;
     const size_t fb = field_bytes(H, nrhs);
     CHK(dmalloc(H, &w.Yw, (size_t)nrhs * g.Ny * WP * sizeof(double2)));
@@ -437,7 +448,10 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     Work& w = H->wk;
     if (w.basis && w.n == n && w.mcap >= mwant) return HELM_OK;
     dfree(w.basis); dfree(w.w); dfree(w.h1); dfree(w.h2); dfree(w.nrm); dfree(w.partial);
-    dfree(w.npartial); dfree(w.y); dfree(w.red);
+    dfree(w.npartial); dfree(w.y); dfree(w.red); dfree(w.apin);
+    w.basis = w.w = w.h1 = w.h2 = w.y = w.red = w.apin = w.partial = nullptr;
+    w.nrm = w.npartial = nullptr;
+    H->ws_epoch += 1;
     size_t freeb = 0, totb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totb));
     const size_t vb = (size_t)nrhs * n * sizeof(double2);
@@ -447,6 +461,7 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     CHK(dmalloc(H, &w.basis, vb * (m + 1)));
     CHK(dmalloc(H, &w.w, vb));
     CHK(dmalloc(H, &w.red, vb));
+    CHK(dmalloc(H, &w.apin, vb));
     CHK(dmalloc(H, &w.h1, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.h2, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.y, (size_t)nrhs * (m + 1) * sizeof(double2)));
@@ -467,7 +482,33 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
         HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, H->g, nrhs, H->wk.PF, nullptr, out, H->st)));
         return HELM_OK;
     }
-    return apply_AP_reduced(H, nrhs, x, out);
+    if (!H->use_graph || H->timer) return apply_AP_reduced(H, nrhs, x, out);
+    // graph replay: the captured launches read the fixed buffer apin and write `out`
+    Work& w = H->wk;
+    CHK(ensure_sweep_ws(H, nrhs));
+    const size_t bytes = (size_t)nrhs * H->g.Ny * 2 * (H->g.J - 1) * sizeof(double2);
+    HIPCHK(hipMemcpyAsync(w.apin, x, bytes, hipMemcpyDeviceToDevice, H->st));
+    if (!H->ap_exec || H->ap_nrhs != nrhs || H->ap_out != out || H->ap_epoch != H->ws_epoch) {
+        if (H->ap_exec) { HIPCHK(hipGraphExecDestroy(H->ap_exec)); H->ap_exec = nullptr; }
+        if (!H->cap_st) HIPCHK(hipStreamCreateWithFlags(&H->cap_st, hipStreamNonBlocking));
+        // the captured work only reads buffers written before the replay on st; nothing is
+        // executed during the capture itself
+        hipGraph_t graph = nullptr;
+        const hipStream_t user_st = H->st;
+        HIPCHK(hipStreamBeginCapture(H->cap_st, hipStreamCaptureModeRelaxed));
+        H->st = H->cap_st;
+        helm_status cs = apply_AP_reduced(H, nrhs, w.apin, out);
+        H->st = user_st;
+        hipError_t ce = hipStreamEndCapture(H->cap_st, &graph);
+        if (cs != HELM_OK) { if (graph) (void)hipGraphDestroy(graph); return cs; }
+        HIPCHK(ce);
+        hipError_t ie = hipGraphInstantiate(&H->ap_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(ie);
+        H->ap_nrhs = nrhs; H->ap_out = out; H->ap_epoch = H->ws_epoch;
+    }
+    HIPCHK(hipGraphLaunch(H->ap_exec, H->st));
+    return HELM_OK;
 }
 
 helm_status norms(helm_t H, const double2* v, int nrhs, long n, std::vector<double>& out) {
@@ -668,6 +709,7 @@ void helm_default_opts(helm_opts* o, int n_x, int n_y) {
     o->beta = nullptr; o->beta_rule = 0;
     o->prec = HELM_C128; o->mode = HELM_FULL; o->max_iter = 200; o->chunk = 0;
     o->stream = nullptr;
+    o->graph = 1;
 }
 
 helm_status helm_setup(const double* c, double omega, double h, const helm_opts* opts, int J,
@@ -740,6 +782,8 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     H->mode = opts->mode == HELM_REDUCED ? HELM_REDUCED : HELM_FULL;
     H->max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
     H->st = static_cast<hipStream_t>(opts->stream);
+    H->use_graph = opts->graph ? 1 : 0;
+    if (hipGetDevice(&H->dev) != hipSuccess) H->dev = 0;
 
     // ---- tables (FP64 complex), Sec. 2.1-2.2
     const int Nx = g.Nx, Ny = g.Ny;
@@ -820,6 +864,13 @@ helm_status helm_factor(helm_t H) {
     if (!H) return HELM_EINVAL;
     if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
     const auto& g = H->g;
+    // the captured reduced operator holds the factor addresses in its kernel arguments:
+    // drop it before the factors are freed (it is captured again on the next solve)
+    if (H->ap_exec) {
+        HIPCHK(hipGraphExecDestroy(H->ap_exec));
+        H->ap_exec = nullptr;
+    }
+    HIPCHK(hipStreamSynchronize(H->st));    // no queued work may still read the old factors
     dfree(H->F);
     H->F = nullptr;
     H->factored = false;
@@ -873,6 +924,36 @@ helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
     const auto t1 = std::chrono::steady_clock::now();
     H->stat_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     return s;
+}
+
+helm_status helm_solve_batch(int nprob, const helm_t* H, const int* nrhs, const void* const* rhs,
+                             void* const* u, double tol, int* iters, double* relres) {
+    if (nprob < 1 || !H || !nrhs || !rhs || !u) return HELM_EINVAL;
+    std::vector<long> off(nprob + 1, 0);
+    for (int p = 0; p < nprob; ++p) {
+        if (!H[p]) return HELM_EINVAL;
+        for (int q = 0; q < p; ++q)
+            if (H[q] == H[p]) return fail(H[p], HELM_EINVAL, "helm_solve_batch: a handle is listed twice");
+        if (nrhs[p] < 1) return fail(H[p], HELM_EINVAL, "helm_solve_batch: nrhs must be >= 1");
+        off[p + 1] = off[p] + nrhs[p];
+    }
+    std::vector<helm_status> st(nprob, HELM_OK);
+    std::vector<std::thread> th;
+    th.reserve(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        th.emplace_back([&, p]() {
+            if (hipSetDevice(H[p]->dev) != hipSuccess) {
+                st[p] = fail(H[p], HELM_EHIP, "hipSetDevice failed");
+                return;
+            }
+            st[p] = helm_solve(H[p], nrhs[p], rhs[p], u[p], tol, iters ? iters + off[p] : nullptr,
+                               relres ? relres + off[p] : nullptr);
+        });
+    }
+    for (auto& t : th) t.join();
+    for (int p = 0; p < nprob; ++p)
+        if (st[p] != HELM_OK) return st[p];
+    return HELM_OK;
 }
 
 helm_status helm_grad(helm_t H, int nsrc, const void* src, int nrec, const int64_t* rec,
@@ -1065,6 +1146,8 @@ void helm_destroy(helm_t H) {
     if (!H) return;
     if (H->st) (void)hipStreamSynchronize(H->st);
     else (void)hipDeviceSynchronize();
+    if (H->ap_exec) (void)hipGraphExecDestroy(H->ap_exec);
+    if (H->cap_st) (void)hipStreamDestroy(H->cap_st);
     free_work(H->wk);
     delete H->timer;
     dfree(H->F);

@@ -36,13 +36,15 @@ class Helmholtz:
     prec       "c128" or "mixed" (complex64 strip factors and sweeps, FP64 GMRES)
     mode       "full" or "reduced" (GMRES on the interface columns, Algorithms 2-5)
     chunk      rows per chunk of the y-partitioned strip solver (0 = library default)
+    stream     torch.cuda.Stream for all of the handle's work (default: the current stream)
+    graph      replay the reduced-form operator from a captured HIP graph (reduced mode)
     """
 
     def __init__(self, c, omega: float, h: float, J: int, pml_outer: int = 16,
                  pml_iface: int = 8, pml_power: float = 2.0, pml_s0: float = 10.0,
                  pml_cref: float = 0.0, prec: str = "c128", mode: str = "full",
                  max_iter: int = 200, chunk: int = 0, beta: Optional[Sequence[int]] = None,
-                 device="cuda:0"):
+                 device="cuda:0", stream=None, graph: bool = True):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the solver runs on a HIP device (cuda:N in torch)")
@@ -58,12 +60,14 @@ class Helmholtz:
         o.mode = {"full": L.HELM_FULL, "reduced": L.HELM_REDUCED}[mode]
         o.max_iter = int(max_iter)
         o.chunk = int(chunk)
+        o.graph = 1 if graph else 0
         self._beta = None
         if beta is not None:
             self._beta = (ctypes.c_int * len(beta))(*[int(b) for b in beta])
             o.beta = ctypes.cast(self._beta, ctypes.POINTER(ctypes.c_int))
         with torch.cuda.device(self.device):
-            o.stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            o.stream = ctypes.c_void_p(self.stream.cuda_stream)
             self._opts = o
             self.h = L.helm_setup(self._c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   omega, h, o, J)
@@ -90,21 +94,37 @@ class Helmholtz:
         return x.contiguous()
 
     def _sync(self):
-        torch.cuda.current_stream(self.device).synchronize()
+        self.stream.synchronize()
+
+    def _begin(self):
+        """Order the handle's stream after the caller's current stream (inputs ready)."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _end(self):
+        """Order the caller's current stream after the handle's work (outputs ready)."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
 
     # ------------------------------------------------------------------ API
     def factor(self) -> "Helmholtz":
+        self._begin()
         with torch.cuda.device(self.device):
             L.helm_factor(self.h)
+        self._end()
         self.factored = True
         return self
 
     def solve(self, rhs: torch.Tensor, tol: float = 1e-6) -> SolveResult:
         f = self._field(rhs, "rhs")
         u = torch.empty_like(f)
+        self._begin()
         with torch.cuda.device(self.device):
             st, it, rel = L.helm_solve(self.h, f.shape[0], f.data_ptr(), u.data_ptr(), tol)
             ap, rs, ms = L.helm_get_stats(self.h)
+        self._end()
         return SolveResult(u, it, rel, st, ap, rs, ms)
 
     def grad(self, src: torch.Tensor, rec, d: torch.Tensor, tol: float = 1e-6):
@@ -123,23 +143,29 @@ class Helmholtz:
         d = d.contiguous()
         n_y, n_x = self._c.shape
         g = torch.empty((n_y, n_x), dtype=torch.float64, device=self.device)
+        self._begin()
         with torch.cuda.device(self.device):
             st, mis, its = L.helm_grad(self.h, nsrc, f.data_ptr(), nrec, rec_t.data_ptr(), d.data_ptr(),
                                        tol, g.data_ptr())
+        self._end()
         return mis, g, its
 
     def apply_P(self, f: torch.Tensor) -> torch.Tensor:
         f = self._field(f, "f")
         out = torch.empty_like(f)
+        self._begin()
         with torch.cuda.device(self.device):
             L.helm_apply_P(self.h, f.shape[0], f.data_ptr(), out.data_ptr())
+        self._end()
         return out
 
     def apply_AP_reduced(self, psi: torch.Tensor) -> torch.Tensor:
         psi = self._field(psi, "psi", cols=2 * (self.J - 1))
         out = torch.empty_like(psi)
+        self._begin()
         with torch.cuda.device(self.device):
             L.helm_apply_AP_reduced(self.h, psi.shape[0], psi.data_ptr(), out.data_ptr())
+        self._end()
         return out
 
     def apply_A(self, u: torch.Tensor, f: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -149,9 +175,11 @@ class Helmholtz:
             if f.shape != u.shape:
                 raise ValueError("u and f must have the same shape")
         out = torch.empty_like(u)
+        self._begin()
         with torch.cuda.device(self.device):
             L.helm_apply_A(self.h, u.shape[0], u.data_ptr(), f.data_ptr() if f is not None else 0,
                            out.data_ptr())
+        self._end()
         return out
 
     def strip_solve(self, strip: int, r: torch.Tensor) -> torch.Tensor:
@@ -159,8 +187,10 @@ class Helmholtz:
             raise ValueError("strip out of range")
         r = self._field(r, "r", cols=self.strip_width[strip])
         x = torch.empty_like(r)
+        self._begin()
         with torch.cuda.device(self.device):
             L.helm_strip_solve(self.h, strip, r.shape[0], r.data_ptr(), x.data_ptr())
+        self._end()
         return x
 
     def set_kernel_timing(self, enable: bool = True):
@@ -187,3 +217,24 @@ class Helmholtz:
 
     def __exit__(self, *a):
         self.close()
+
+
+def solve_batch(problems: Sequence[Helmholtz], rhs: Sequence[torch.Tensor], tol: float = 1e-6):
+    """Solve several independent problems concurrently (helm_solve_batch): one host thread
+    per problem, each on its handle's stream.  Returns one SolveResult per problem."""
+    if len(problems) != len(rhs) or not problems:
+        raise ValueError("one right-hand-side tensor per problem is required")
+    fs = [H._field(f, "rhs") for H, f in zip(problems, rhs)]
+    us = [torch.empty_like(f) for f in fs]
+    for H in problems:
+        torch.cuda.current_stream(H.device).synchronize()   # inputs ready before other streams read them
+    nr = [f.shape[0] for f in fs]
+    st, its, rel = L.helm_solve_batch([H.h for H in problems], nr, [f.data_ptr() for f in fs],
+                                      [u.data_ptr() for u in us], tol)
+    out, k = [], 0
+    for H, u, n in zip(problems, us, nr):
+        H.stream.synchronize()
+        ap, rs, ms = L.helm_get_stats(H.h)
+        out.append(SolveResult(u, its[k:k + n], rel[k:k + n], st, ap, rs, ms))
+        k += n
+    return out

@@ -1,0 +1,101 @@
+"""Graph replay of the reduced operator and concurrent solves of uneven problems.
+
+Graph: a solve replays the captured Algorithm 3 once per GMRES iteration (with the
+program's own eager work and host synchronisations between replays); its iterations and
+field must equal the kernel-by-kernel solve bit for bit, on two consecutive solves and
+after a change of the right-hand-side count (a new capture).
+Batch: problems of different sizes solved concurrently on their own streams must equal
+their individual solves bit for bit and the oracle's direct solution to the field bar."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle.assemble import assemble_global  # noqa: E402
+from oracle.grid import geometry_from_workload  # noqa: E402
+from oracle.solve import solve_direct  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _wl(n, J, seed):
+    c = 1.0 + 0.3 * np.random.default_rng(seed).random((n, n))
+    return W.small(n=n, J=J, w_out=7, w=5, c=c, nsrc=3, seed=seed + 1)
+
+
+def _H(wl, prec, graph, stream=None, chunk=9):
+    from paper_1208_3956_amd import Helmholtz
+    return Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                     prec=prec, mode="reduced", chunk=chunk, device=DEV, stream=stream,
+                     graph=graph).factor()
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_graph_replay_equals_eager(prec):
+    wl = _wl(48, 4, 21)
+    f = torch.from_numpy(wl.rhs()).to(DEV)
+    He = _H(wl, prec, graph=False)
+    Hg = _H(wl, prec, graph=True)
+    ref = He.solve(f, 1e-8)
+    for rep in range(2):
+        got = Hg.solve(f, 1e-8)
+        assert got.iters == ref.iters, (rep, got.iters, ref.iters)
+        assert torch.equal(got.u, ref.u), rep
+    # a different right-hand-side count forces a new capture
+    ref1 = He.solve(f[1:2], 1e-8)
+    got1 = Hg.solve(f[1:2], 1e-8)
+    assert got1.iters == ref1.iters and torch.equal(got1.u, ref1.u)
+    got = Hg.solve(f, 1e-8)
+    assert got.iters == ref.iters and torch.equal(got.u, ref.u)
+    He.close()
+    Hg.close()
+
+
+def test_graph_after_refactor():
+    """Re-factoring frees and reallocates the factors; the next solve must capture the
+    operator again instead of replaying launches that point at the old factors."""
+    wl = _wl(40, 3, 25)
+    f = torch.from_numpy(wl.rhs()).to(DEV)
+    He = _H(wl, "mixed", graph=False)
+    Hg = _H(wl, "mixed", graph=True)
+    ref = He.solve(f, 1e-8)
+    for rep in range(3):
+        got = Hg.solve(f, 1e-8)
+        assert got.iters == ref.iters and torch.equal(got.u, ref.u), rep
+        Hg.factor()
+    He.close()
+    Hg.close()
+
+
+def test_solve_batch_uneven_problems():
+    from paper_1208_3956_amd import solve_batch
+    wls = [_wl(40, 3, 31), _wl(64, 5, 33), _wl(32, 2, 35)]
+    streams = [torch.cuda.Stream(DEV) for _ in wls]
+    Hs = [_H(wl, "mixed", True, stream=s) for wl, s in zip(wls, streams)]
+    fs = [torch.from_numpy(wl.rhs()).to(DEV) for wl in wls]
+    res = solve_batch(Hs, fs, 1e-6)
+    for wl, H, f, r in zip(wls, Hs, fs, res):
+        one = H.solve(f, 1e-6)
+        assert r.iters == one.iters and torch.equal(r.u, one.u)
+        assert max(r.relres) <= 1e-6
+        g = geometry_from_workload(wl)
+        ud = solve_direct(g, wl.rhs(), assemble_global(g))
+        err = max(np.linalg.norm(r.u.cpu().numpy()[k] - ud[k]) / np.linalg.norm(ud[k])
+                  for k in range(ud.shape[0]))
+        assert err < 1e-5, err
+    for H in Hs:
+        H.close()
+
+
+def test_solve_batch_rejects_repeated_handle():
+    from paper_1208_3956_amd import solve_batch
+    from paper_1208_3956_amd._lib import HelmError
+    wl = _wl(32, 2, 41)
+    H = _H(wl, "c128", True)
+    f = torch.from_numpy(wl.rhs()).to(DEV)
+    with pytest.raises(HelmError):
+        solve_batch([H, H], [f, f], 1e-6)
+    H.close()
