@@ -60,8 +60,42 @@ def assemble_5pt(ax: np.ndarray, axh: np.ndarray, ay: np.ndarray, ayh: np.ndarra
     return A.tocsr()
 
 
+def assemble_7pt(ax: np.ndarray, axh: np.ndarray, ay: np.ndarray, ayh: np.ndarray,
+                 az: np.ndarray, azh: np.ndarray, k2: np.ndarray, h: float) -> sp.csr_matrix:
+    """The 3-D paper-form operator (Sec. 2.2: the same second-difference form along each
+    of x, y, z) on an Nz x Ny x Nx grid; unknown (z, l, i) has flat index
+    (z * Ny + l) * Nx + i.  Tables as in assemble_5pt, az/azh along z; k2 (Nz, Ny, Nx)."""
+    Nz, Ny, Nx = k2.shape
+    assert ax.shape == (Nx,) and axh.shape == (Nx + 1,)
+    assert ay.shape == (Ny,) and ayh.shape == (Ny + 1,)
+    assert az.shape == (Nz,) and azh.shape == (Nz + 1,)
+    inv_h2 = 1.0 / (h * h)
+    Z, L, I = np.meshgrid(np.arange(Nz), np.arange(Ny), np.arange(Nx), indexing="ij")
+    Z, L, I = Z.ravel(), L.ravel(), I.ravel()
+    p = (Z * Ny + L) * Nx + I
+    rows, cols, vals = [p], [p], []
+    diag = -k2.ravel().astype(np.complex128)
+    # one axis at a time: alpha(point) [alpha(+half)(u+ - u) - alpha(-half)(u - u-)] / h^2
+    for idx, n, a, ah, stride in ((I, Nx, ax, axh, 1), (L, Ny, ay, ayh, Nx), (Z, Nz, az, azh, Nx * Ny)):
+        ap, plus, minus = a[idx], ah[idx + 1], ah[idx]
+        diag = diag + ap * (plus + minus) * inv_h2
+        m = idx + 1 < n
+        rows.append(p[m]); cols.append(p[m] + stride); vals.append(-ap[m] * plus[m] * inv_h2)
+        m = idx - 1 >= 0
+        rows.append(p[m]); cols.append(p[m] - stride); vals.append(-ap[m] * minus[m] * inv_h2)
+    vals.insert(0, diag)
+    A = sp.coo_matrix((np.concatenate(vals).astype(np.complex128),
+                       (np.concatenate(rows), np.concatenate(cols))), shape=(p.size, p.size))
+    return A.tocsr()
+
+
 def assemble_global(g: Geometry) -> sp.csr_matrix:
     """The global operator A on the padded grid."""
+    if g.dim == 3:
+        return assemble_7pt(g.alpha_outer(g.N_x, False), g.alpha_outer(g.N_x, True),
+                            g.alpha_outer(g.N_y, False), g.alpha_outer(g.N_y, True),
+                            g.alpha_outer(g.N_z, False), g.alpha_outer(g.N_z, True),
+                            g.k2(), g.h)
     return assemble_5pt(g.alpha_outer(g.N_x, False), g.alpha_outer(g.N_x, True),
                         g.alpha_outer(g.N_y, False), g.alpha_outer(g.N_y, True),
                         g.k2(), g.h)
@@ -69,7 +103,13 @@ def assemble_global(g: Geometry) -> sp.csr_matrix:
 
 def assemble_strip(g: Geometry, st: StripGeom, k2=None) -> sp.csr_matrix:
     """The padded strip operator A^(j) (Sec. 2.1-2.2, grid of eq. grid_A_j): its own
-    x-PML pads on internal sides, the global y-PML, the medium continued into the pads."""
+    x-PML pads on internal sides, the global y-PML (and z-PML in 3-D), the medium continued
+    into the pads."""
+    if g.dim == 3:
+        return assemble_7pt(g.alpha_strip_x(st, False), g.alpha_strip_x(st, True),
+                            g.alpha_outer(g.N_y, False), g.alpha_outer(g.N_y, True),
+                            g.alpha_outer(g.N_z, False), g.alpha_outer(g.N_z, True),
+                            g.strip_k2(st, k2), g.h)
     return assemble_5pt(g.alpha_strip_x(st, False), g.alpha_strip_x(st, True),
                         g.alpha_outer(g.N_y, False), g.alpha_outer(g.N_y, True),
                         g.strip_k2(st, k2), g.h)
@@ -81,7 +121,11 @@ def apply_A(A: sp.csr_matrix, u: np.ndarray) -> np.ndarray:
 
 
 def pml_scaling(g: Geometry) -> np.ndarray:
-    """D = alpha_x(x_i) alpha_y(y_l) on the padded grid: A = D S with S complex symmetric."""
+    """D = alpha_x(x_i) alpha_y(y_l) (alpha_z(z) in 3-D) on the padded grid: A = D S with S
+    complex symmetric."""
     ax = g.alpha_outer(g.N_x, False)
     ay = g.alpha_outer(g.N_y, False)
+    if g.dim == 3:
+        az = g.alpha_outer(g.N_z, False)
+        return az[:, None, None] * ay[None, :, None] * ax[None, None, :]
     return ay[:, None] * ax[None, :]

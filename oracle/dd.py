@@ -37,18 +37,18 @@ class StripSolvers:
 
     def solve(self, s: int, rhs: np.ndarray) -> np.ndarray:
         st = self.g.strips[s]
-        assert rhs.shape == (self.g.N_y, st.W)
+        assert rhs.shape == self.g.strip_shape(st)
         return self.lu[s].solve(rhs.ravel().astype(np.complex128)).reshape(rhs.shape)
 
 
 def sweep(g: Geometry, S: StripSolvers, A, f: np.ndarray, up_from: int = 0, dn_from: int = None):
-    """Both sweeps for input f (N_y, N_x).  Returns (v, w, residual g).
+    """Both sweeps for input f (N_y, N_x), or (N_z, N_y, N_x) in 3-D (slabs along x, the
+    transmission sources on two x-planes).  Returns (v, w, residual g).
 
     up_from / dn_from: first strip of each sweep (0-based).  The full preconditioner
     starts at strip 0 and at strip J-1; Algorithms 3 and 4 start at strip 1 and J-2
     because their inputs vanish on the skipped subdomains."""
     J, h = g.J, g.h
-    Ny, Nx = f.shape
     if dn_from is None:
         dn_from = J - 1
 
@@ -57,18 +57,18 @@ def sweep(g: Geometry, S: StripSolvers, A, f: np.ndarray, up_from: int = 0, dn_f
     prev = None
     for s in range(up_from, J):
         st = g.strips[s]
-        rhs = np.zeros((Ny, st.W), dtype=np.complex128)
+        rhs = np.zeros(g.strip_shape(st), dtype=np.complex128)
         lo, hi = st.core
-        rhs[:, lo - st.a:hi - st.a] = f[:, lo:hi]               # f^(j): f restricted to D^(j)
+        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]               # f^(j): f restricted to D^(j)
         if prev is not None:
             b = g.beta[s]                                          # b_{j-1} between columns b-1 and b
             pst, px = prev
-            dxv = (px[:, b - pst.a] - px[:, b - 1 - pst.a]) / h   # d_x v^(j-1)(b_{j-1})
+            dxv = (px[..., b - pst.a] - px[..., b - 1 - pst.a]) / h   # d_x v^(j-1)(b_{j-1})
             delta = 1.0 / (2.0 * h)                                # discrete delta on columns b-1, b
-            rhs[:, b - 1 - st.a] += -2.0 * delta * dxv
-            rhs[:, b - st.a] += -2.0 * delta * dxv
+            rhs[..., b - 1 - st.a] += -2.0 * delta * dxv
+            rhs[..., b - st.a] += -2.0 * delta * dxv
         x = S.solve(s, rhs)
-        v[:, lo:hi] = x[:, lo - st.a:hi - st.a]                   # v = v^(j) on D^(j)
+        v[..., lo:hi] = x[..., lo - st.a:hi - st.a]                   # v = v^(j) on D^(j)
         prev = (st, x)
 
     # ---- residual on the whole grid
@@ -79,18 +79,18 @@ def sweep(g: Geometry, S: StripSolvers, A, f: np.ndarray, up_from: int = 0, dn_f
     nxt = None
     for s in range(dn_from, -1, -1):
         st = g.strips[s]
-        rhs = np.zeros((Ny, st.W), dtype=np.complex128)
+        rhs = np.zeros(g.strip_shape(st), dtype=np.complex128)
         lo, hi = st.keep_dn
-        rhs[:, lo - st.a:hi - st.a] = res[:, lo:hi]             # g^(j): g restricted to D~^(j)
+        rhs[..., lo - st.a:hi - st.a] = res[..., lo:hi]             # g^(j): g restricted to D~^(j)
         if nxt is not None:
             b = g.beta[s + 1]                                      # b~_j between columns b and b+1
             nst, nx_ = nxt
-            dxw = (nx_[:, b + 1 - nst.a] - nx_[:, b - nst.a]) / h  # d_x w^(j+1)(b~_j)
+            dxw = (nx_[..., b + 1 - nst.a] - nx_[..., b - nst.a]) / h  # d_x w^(j+1)(b~_j)
             delta = 1.0 / (2.0 * h)
-            rhs[:, b - st.a] += 2.0 * delta * dxw
-            rhs[:, b + 1 - st.a] += 2.0 * delta * dxw
+            rhs[..., b - st.a] += 2.0 * delta * dxw
+            rhs[..., b + 1 - st.a] += 2.0 * delta * dxw
         x = S.solve(s, rhs)
-        w[:, lo:hi] = x[:, lo - st.a:hi - st.a]                   # w = w^(j) on D~^(j)
+        w[..., lo:hi] = x[..., lo - st.a:hi - st.a]                   # w = w^(j) on D~^(j)
         nxt = (st, x)
     return v, w, res
 
@@ -111,26 +111,26 @@ def apply_AP_full(g: Geometry, S: StripSolvers, A, f: np.ndarray) -> np.ndarray:
 def reduced_setup(g: Geometry, S: StripSolvers, A, f: np.ndarray):
     """Algorithm 2: u~^(j) = A^(j)^{-1} f~^(j) with f~^(j) = f on D~^(j); u~ = u~^(j) on
     D~^(j); returns (u~, phi = f - A u~)."""
-    Ny, Nx = f.shape
     ut = np.zeros_like(f)
     for s, st in enumerate(g.strips):
-        rhs = np.zeros((Ny, st.W), dtype=np.complex128)
+        rhs = np.zeros(g.strip_shape(st), dtype=np.complex128)
         lo, hi = st.keep_dn
-        rhs[:, lo - st.a:hi - st.a] = f[:, lo:hi]
+        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]
         x = S.solve(s, rhs)
-        ut[:, lo:hi] = x[:, lo - st.a:hi - st.a]
+        ut[..., lo:hi] = x[..., lo - st.a:hi - st.a]
     phi = f - (A @ ut.ravel()).reshape(f.shape)
     return ut, phi
 
 
 def to_reduced(g: Geometry, field: np.ndarray) -> np.ndarray:
-    """Restriction of a field to the reduced columns, shape (N_y, 2(J-1))."""
-    return field[:, g.reduced_columns()].copy()
+    """Restriction of a field to the reduced columns, shape (N_y, 2(J-1)) (3-D: the reduced
+    planes, (N_z, N_y, 2(J-1)))."""
+    return field[..., g.reduced_columns()].copy()
 
 
 def from_reduced(g: Geometry, red: np.ndarray) -> np.ndarray:
-    out = np.zeros((g.N_y, g.N_x), dtype=np.complex128)
-    out[:, g.reduced_columns()] = red
+    out = np.zeros(g.field_shape, dtype=np.complex128)
+    out[..., g.reduced_columns()] = red
     return out
 
 

@@ -73,6 +73,24 @@ class Geometry:
     beta: np.ndarray = None        # length J+1
     strips: List[StripGeom] = field(default_factory=list)
     cref: Optional[float] = None   # PML reference speed; None -> max(c)
+    n_z: int = 0                   # 3-D (Sec. 2.2, 7-point stencil): interior points along z;
+                                   # 0 for the 2-D problem.  c is then (n_z, n_y, n_x)
+
+    @property
+    def dim(self) -> int:
+        return 3 if self.n_z else 2
+
+    @property
+    def N_z(self) -> int:
+        return self.n_z + 2 * self.w_out if self.n_z else 1
+
+    @property
+    def field_shape(self) -> tuple:
+        """Shape of a field on the padded grid: (N_y, N_x), or (N_z, N_y, N_x) in 3-D."""
+        return (self.N_z, self.N_y, self.N_x) if self.n_z else (self.N_y, self.N_x)
+
+    def strip_shape(self, st: "StripGeom") -> tuple:
+        return self.field_shape[:-1] + (st.W,)
 
     @property
     def N_x(self) -> int:
@@ -98,6 +116,9 @@ class Geometry:
         Ny, Nx = self.N_y, self.N_x
         li = np.clip(np.arange(Ny) - self.w_out, 0, self.n_y - 1)
         ii = np.clip(np.arange(Nx) - self.w_out, 0, self.n_x - 1)
+        if self.n_z:
+            zi = np.clip(np.arange(self.N_z) - self.w_out, 0, self.n_z - 1)
+            return ((zi[:, None, None] * self.n_y + li[None, :, None]) * self.n_x + ii[None, None, :])
         return (li[:, None] * self.n_x + ii[None, :])
 
     # ---------------------------------------------------------------- PML tables
@@ -139,13 +160,14 @@ class Geometry:
         return _alpha(sig, self.omega)
 
     def strip_k2(self, st: StripGeom, k2: Optional[np.ndarray] = None) -> np.ndarray:
-        """Medium of A^(j) on the strip (N_y, W): the true k^2 on the non-pad columns and,
-        in each pad, k^2 of the adjacent non-pad column (x-independent extension, Sec. 2.1)."""
+        """Medium of A^(j) on the strip (N_y, W) (3-D: (N_z, N_y, W)): the true k^2 on the
+        non-pad columns and, in each pad, k^2 of the adjacent non-pad column (x-independent
+        extension, Sec. 2.1)."""
         if k2 is None:
             k2 = self.k2()
         cols = st.a + np.arange(st.W)
         cols = np.clip(cols, st.dom[0], st.dom[1] - 1)
-        return k2[:, cols]
+        return k2[..., cols]
 
     # ---------------------------------------------------------------- index sets
     def reduced_columns(self) -> np.ndarray:
@@ -182,7 +204,11 @@ def make_geometry(c: np.ndarray, omega: float, h: float, w_out: int, w: int, J: 
                   power: float = 2.0, s0: float = 10.0, beta: Optional[Sequence[int]] = None,
                   rule: str = "interior", cref: Optional[float] = None) -> Geometry:
     c = np.asarray(c, dtype=float)
-    n_y, n_x = c.shape
+    n_z = 0
+    if c.ndim == 3:
+        n_z, n_y, n_x = c.shape       # 3-D: slabs along x (Sec. 2.2, 3-D case)
+    else:
+        n_y, n_x = c.shape
     if J < 1:
         raise ValueError("J must be >= 1")
     if beta is None:
@@ -198,7 +224,7 @@ def make_geometry(c: np.ndarray, omega: float, h: float, w_out: int, w: int, J: 
     for s in range(1, J):
         if b[s] - 1 < w_out or b[s] + 1 > w_out + n_x - 1:
             raise ValueError("interfaces must lie inside the interior (outside the outer PML)")
-    g = Geometry(n_x, n_y, w_out, w, J, h, omega, c, power, s0, b, cref=cref)
+    g = Geometry(n_x, n_y, w_out, w, J, h, omega, c, power, s0, b, cref=cref, n_z=n_z)
     for s in range(J):
         lp = s > 0
         rp = s < J - 1

@@ -37,7 +37,7 @@ def relres(A, u: np.ndarray, f: np.ndarray) -> float:
 def solve_direct(g: Geometry, f: np.ndarray, A=None) -> np.ndarray:
     A = assemble_global(g) if A is None else A
     lu = spla.splu(A.tocsc(), permc_spec="COLAMD")
-    if f.ndim == 2:
+    if f.ndim == g.dim:
         return lu.solve(f.ravel().astype(np.complex128)).reshape(f.shape)
     return np.stack([lu.solve(fk.ravel().astype(np.complex128)).reshape(fk.shape) for fk in f])
 

@@ -228,10 +228,10 @@ def _mutated_sweep(old, new):
 
 @pytest.mark.parametrize("old,new", [
     ("+= -2.0 * delta * dxv", "+= 2.0 * delta * dxv"),                       # wrong sign
-    ("rhs[:, b - 1 - st.a] += -2.0", "rhs[:, b - 2 - st.a] += -2.0"),         # wrong column
+    ("rhs[..., b - 1 - st.a] += -2.0", "rhs[..., b - 2 - st.a] += -2.0"),         # wrong column
     ("delta = 1.0 / (2.0 * h)                                # discrete", "delta = 1.0 / h  # discrete"),
-    ("px[:, b - 1 - pst.a]) / h", "px[:, b - 2 - pst.a]) / h"),                # wrong derivative
-    ("rhs[:, b + 1 - st.a] += 2.0", "rhs[:, b - 1 - st.a] += 2.0"),           # wrong downward column
+    ("px[..., b - 1 - pst.a]) / h", "px[..., b - 2 - pst.a]) / h"),                # wrong derivative
+    ("rhs[..., b + 1 - st.a] += 2.0", "rhs[..., b - 1 - st.a] += 2.0"),           # wrong downward column
 ])
 def test_planted_transmission_mistakes_are_caught(old, new):
     """The Theorem-1 pin has teeth: each plausible mistake in the transmission terms

@@ -22,7 +22,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "homogeneous_100", "lens_1000", "layers", "layers_uneven_batch", "smooth_500", "small",
-    "smoothed_noise", "point_sources", "padded_rhs", "WORKLOADS",
+    "smoothed_noise", "point_sources", "padded_rhs", "WORKLOADS", "small3", "smooth_3d",
 ]
 
 
@@ -56,12 +56,30 @@ class Workload:
     extra: dict = field(default_factory=dict)
 
     @property
+    def dim(self) -> int:
+        return int(self.c.ndim)
+
+    @property
     def n_x(self) -> int:
-        return int(self.c.shape[1])
+        return int(self.c.shape[-1])
 
     @property
     def n_y(self) -> int:
-        return int(self.c.shape[0])
+        return int(self.c.shape[-2])
+
+    @property
+    def n_z(self) -> int:
+        """Interior points along z in 3-D (c of shape (n_z, n_y, n_x)); 0 in 2-D."""
+        return int(self.c.shape[0]) if self.c.ndim == 3 else 0
+
+    @property
+    def N_z(self) -> int:
+        return self.n_z + 2 * self.w_out if self.c.ndim == 3 else 1
+
+    @property
+    def n_points(self) -> int:
+        """Interior grid points."""
+        return int(self.c.size)
 
     @property
     def N_x(self) -> int:
@@ -76,7 +94,8 @@ class Workload:
         return len(self.src)
 
     def rhs(self, which=None) -> np.ndarray:
-        """Right-hand sides on the padded grid, shape (nrhs, N_y, N_x) complex128."""
+        """Right-hand sides on the padded grid, shape (nrhs, N_y, N_x) complex128
+        ((nrhs, N_z, N_y, N_x) in 3-D)."""
         return padded_rhs(self, which)
 
     def with_(self, **kw) -> "Workload":
@@ -84,7 +103,13 @@ class Workload:
 
 
 def padded_rhs(wl: Workload, which=None) -> np.ndarray:
+    """Point sources of strength 1/h^2 (2-D) or 1/h^3 (3-D) on the padded grid."""
     srcs = wl.src if which is None else [wl.src[k] for k in which]
+    if wl.dim == 3:
+        f = np.zeros((len(srcs), wl.N_z, wl.N_y, wl.N_x), dtype=np.complex128)
+        for k, (i, l, z) in enumerate(srcs):
+            f[k, z + wl.w_out, l + wl.w_out, i + wl.w_out] = 1.0 / wl.h ** 3
+        return f
     f = np.zeros((len(srcs), wl.N_y, wl.N_x), dtype=np.complex128)
     for k, (i, l) in enumerate(srcs):
         f[k, l + wl.w_out, i + wl.w_out] = 1.0 / wl.h ** 2
@@ -140,6 +165,39 @@ def small(n=24, J=3, w_out=6, w=5, c=None, nsrc=1, seed=11, ppw=10.0, **kw) -> W
     omega = 2 * math.pi / (ppw * h) * float(np.min(c))
     srcs = point_sources(c.shape[1], c.shape[0], nsrc, seed, margin=min(2, n // 4))
     return Workload(f"small{n}", np.asarray(c, float), omega, h, w_out, w, J, srcs, **kw)
+
+
+def small3(n=10, J=2, w_out=4, w=3, c=None, nsrc=1, seed=13, ppw=8.0, **kw) -> Workload:
+    """Small 3-D cube (n^3 interior) for oracle-sized parity tests; c (n, n, n) or 1."""
+    h = 1.0 / n
+    if c is None:
+        c = np.ones((n, n, n))
+    c = np.asarray(c, float)
+    omega = 2 * math.pi / (ppw * h) * float(np.min(c))
+    rng = np.random.default_rng(seed)
+    m = min(2, n // 4)
+    srcs = []
+    while len(srcs) < nsrc:
+        p = tuple(int(v) for v in rng.integers(m, n - m, 3))
+        if p not in srcs:
+            srcs.append(p)
+    return Workload(f"small3d_{n}", c, omega, h, w_out, w, J, srcs, **kw)
+
+
+def smooth_3d(n: int = 80, nsrc: int = 32, J: int = 16) -> Workload:
+    """n^3 smooth random medium c in [1, 2] (Gaussian-filtered white noise, 4-point width,
+    min-max mapped, seed 5001), omega = 2 pi 8 at n = 80 (10 points per wavelength at
+    c = 1), outer PML 8, interface PML 6, J slabs, `nsrc` sources on one z-plane at
+    seeded random (x, y) (seed 5002)."""
+    h = 1.0 / n
+    s = smoothed_noise((n, n, n), 4.0 * n / 80.0, 5001)
+    c = 1.0 + (s - s.min()) / (s.max() - s.min())
+    rng = np.random.default_rng(5002)
+    z0 = int(rng.integers(n // 4, 3 * n // 4))
+    pts = point_sources(n, n, nsrc, 5002 + 1)
+    srcs = [(i, l, z0) for (i, l) in pts]
+    omega = 2 * math.pi * 8.0 * n / 80.0
+    return Workload(f"smooth3d_{n}x{n}x{n}_J{J}", c, omega, h, 8, 6, J, srcs, precision="mixed")
 
 
 def homogeneous_100() -> Workload:
@@ -209,4 +267,5 @@ def smooth_500() -> Workload:
     return wl
 
 
-WORKLOADS = {"homogeneous_100": homogeneous_100, "lens_1000": lens_1000, "layers": layers, "smooth_500": smooth_500}
+WORKLOADS = {"homogeneous_100": homogeneous_100, "lens_1000": lens_1000, "layers": layers, "smooth_500": smooth_500,
+             "smooth_3d": smooth_3d}
