@@ -1,21 +1,23 @@
 /*
- * helm.h -- C ABI of an MI355X (gfx950) solver for the 2-D heterogeneous Helmholtz
- * equation  -u_xx - u_yy - k(x,y)^2 u = f,  k = omega / c  (paper Sec. 1, eq. helm1),
- * discretised with the 5-point stencil and truncated by a PML (Sec. 2.1-2.2), solved by
+ * helm.h -- C ABI of an MI355X (gfx950) solver for the heterogeneous Helmholtz equation
+ * -Laplace u - k^2 u = f,  k = omega / c  (paper Sec. 1, eq. helm1), in 2-D (5-point
+ * stencil) or 3-D (7-point stencil), truncated by a PML (Sec. 2.1-2.2), solved by
  * right-preconditioned GMRES (Sec. 2.3) with Stolk's double-sweep domain-decomposition
  * preconditioner P: J strips along x, each padded with PML at its internal sides and
  * coupled by single-layer-potential transmission sources (eqs. solve_upward and
  * solve_downward), forward sweep j = 1..J, residual, backward sweep J..1.
  *
  * Grids and layouts
- *   interior grid  n_x x n_y points, spacing h;  padded grid  N_x x N_y,
- *   N = n + 2*pml_outer.  The unknowns of the discrete system are all padded-grid points;
+ *   interior grid  n_x x n_y (x n_z) points, spacing h;  padded grid  N_x x N_y (x N_z),
+ *   N = n + 2*pml_outer.  In 3-D the subdomains are slabs along x (padded planes at
+ *   their internal faces) and every field row below is a (z, y) pair, row = z * N_y + y.  The unknowns of the discrete system are all padded-grid points;
  *   an outer PML of pml_outer cells surrounds the interior on all four faces, with
  *   homogeneous Dirichlet values beyond it.
  *   Fields (rhs, u, P-apply input and output) are complex128, interleaved re/im doubles
- *   (the layout of torch.complex128), indexed [rhs][y][x] on the PADDED grid, x fastest.
- *   The medium c is real float64 on the INTERIOR grid, [y][x], x fastest; the padded
- *   medium takes the value of the nearest interior point.
+ *   (the layout of torch.complex128), indexed [rhs][y][x] ([rhs][z][y][x] in 3-D) on the
+ *   PADDED grid, x fastest.  The medium c is real float64 on the INTERIOR grid, [y][x]
+ *   ([z][y][x]), x fastest; the padded medium takes the value of the nearest interior
+ *   point.
  *
  * Memory ownership
  *   The caller owns every array it passes.  Arrays documented "device" live on the
@@ -57,8 +59,8 @@ typedef enum { HELM_C128 = 0, HELM_MIXED_C64 = 1 } helm_precision;
 typedef enum { HELM_FULL = 0, HELM_REDUCED = 1 } helm_mode;
 
 typedef struct {
-    int dim;            /* 2 (the 3-D slab variant is not provided by this library)      */
-    int n[3];           /* interior points n_x, n_y (, n_z unused)                        */
+    int dim;            /* 2, or 3 (7-point stencil, slabs along x)                       */
+    int n[3];           /* interior points n_x, n_y, n_z (n_z used when dim = 3)          */
     int pml_outer;      /* outer PML width in cells, all faces (>= 1)                     */
     int pml_iface;      /* interface PML width w: pads on internal strip sides (>= 1)     */
     double pml_power;   /* profile sigma(xi) = sigma_max (xi / (w h))^power; default 2    */
@@ -73,7 +75,8 @@ typedef struct {
     int mode;           /* helm_mode: HELM_FULL (GMRES on the whole grid) or HELM_REDUCED
                            (Sec. 2.3 / Algorithms 2-5: GMRES on the interface columns)    */
     int max_iter;       /* GMRES iteration cap; <= 0 selects 200                          */
-    int chunk;          /* rows per chunk of the y-partitioned strip solver; 0 = auto     */
+    int chunk;          /* rows per chunk of the y-partitioned strip solver; 0 = auto
+                           (2-D only: a 3-D slab is one chunk)                           */
     void* stream;       /* hipStream_t for all device work; NULL = default stream        */
     int graph;          /* 1 (default): in REDUCED mode, capture one application of
                            Algorithm 3 per right-hand-side count into a HIP graph and replay
@@ -92,9 +95,10 @@ void helm_default_opts(helm_opts* o, int n_x, int n_y);
  *   c      host, n_y*n_x float64 wave speed (> 0, finite), [y][x]
  *   omega  angular frequency (> 0);  h  grid spacing (> 0);  J >= 1 strips
  *   out    receives the new handle (NULL on failure)
+ *   c      (3-D: n_z*n_y*n_x, [z][y][x])
  * HELM_EINVAL: J < 1, a strip core narrower than 2 columns, an interface column with a
- * neighbour inside the outer PML, a padded strip wider than 64 columns, c <= 0 or not
- * finite, omega or h <= 0.
+ * neighbour inside the outer PML, a padded strip wider than 64 columns, a 3-D slab block
+ * (padded width x N_z) above 8192, c <= 0 or not finite, omega or h <= 0, dim not 2 or 3.
  */
 helm_status helm_setup(const double* c, double omega, double h, const helm_opts* opts,
                        int J, helm_t* out);
@@ -104,7 +108,10 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
  * eq. grid_A_j).  Each strip is block-tridiagonal along y with W x W blocks; it is cut
  * into chunks of opts.chunk rows whose last row is a separator; every chunk is factored
  * by block LU with explicit inverses and its two spikes, and the separators by block LU
- * of their Schur complement.  Computed in FP64; stored in FP64 (HELM_C128) or FP32.
+ * of their Schur complement.  In 3-D a slab is block tridiagonal along y with dense
+ * (W N_z) x (W N_z) blocks (the (x, z) planes); each is inverted by blocked Gauss-Jordan
+ * elimination with partial pivoting, plane after plane (the blocks of all slabs of one
+ * plane together).  Computed in FP64; stored in FP64 (HELM_C128) or FP32.
  * HELM_ESINGULAR if a pivot is zero or not finite.
  */
 helm_status helm_factor(helm_t H);
@@ -161,8 +168,8 @@ helm_status helm_solve_batch(int nprob, const helm_t* H, const int* nrhs, const 
  *   misfit  host, one double (output)
  *   grad    device, n_y * n_x doubles, [y][x] interior grid (output, overwritten)
  *   iters   host, 2 * nsrc ints (may be NULL): forward then adjoint GMRES iterations
- * The call allocates and frees its own work arrays (3 * nsrc fields).  HELM_EINVAL for a
- * receiver index outside [0, N_x N_y) or nsrc, nrec < 1; HELM_ESTATE before helm_factor;
+ * The call allocates and frees its own work arrays (3 * nsrc fields).  2-D problems only.
+ * HELM_EINVAL for a 3-D handle, a receiver index outside [0, N_x N_y) or nsrc, nrec < 1; HELM_ESTATE before helm_factor;
  * HELM_ENOCONV if a solve misses tol (misfit and grad are still written).
  */
 helm_status helm_grad(helm_t H, int nsrc, const void* src, int nrec, const int64_t* rec,
@@ -193,6 +200,9 @@ helm_status helm_apply_A(helm_t H, int nrhs, const void* u, const void* f, void*
  * r, x: device, nrhs * N_y * W_j complex128, [rhs][y][strip-local column].
  */
 helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void* x);
+
+/* N_x, N_y, N_z (1 in 2-D) and J. */
+helm_status helm_get_dims3(helm_t H, int* N_x, int* N_y, int* N_z, int* J);
 
 /* Geometry queries: N_x, N_y; the J+1 interface columns beta (host, beta[0] = 0,
  * beta[J] = N_x); the first global column and width of each padded strip (host, J each). */

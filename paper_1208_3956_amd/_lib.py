@@ -22,7 +22,7 @@ EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm
            "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
            "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
-           "helm_solve_batch"]
+           "helm_solve_batch", "helm_get_dims3"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
                             vp, pint]
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
+    L.helm_get_dims3.argtypes = [vp, pint, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
     L.helm_get_chunks.argtypes = [vp, pint, pint]
     L.helm_get_stats.argtypes = [vp, pint, pint, pdbl]
@@ -219,6 +220,12 @@ def helm_get_kernel_times(hdl) -> dict:
     ms = (ctypes.c_double * n)()
     check(lib().helm_get_kernel_times(hdl, n, cnt, ms), hdl)
     return {k: (cnt[i], ms[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+
+def helm_get_dims3(hdl):
+    nx, ny, nz, J = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(lib().helm_get_dims3(hdl, ctypes.byref(nx), ctypes.byref(ny), ctypes.byref(nz), ctypes.byref(J)), hdl)
+    return nx.value, ny.value, nz.value, J.value
 
 
 def helm_last_error(hdl) -> str:

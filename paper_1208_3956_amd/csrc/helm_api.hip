@@ -205,7 +205,9 @@ void free_work(Work& w) {
     w = Work();
 }
 
-size_t field_bytes(helm_t H, int nrhs) { return (size_t)nrhs * H->g.Ny * H->g.Nx * sizeof(double2); }
+size_t field_bytes(helm_t H, int nrhs) { return (size_t)nrhs * H->g.Nrow() * H->g.Nx * sizeof(double2); }
+
+int rhs_pad16(int nrhs) { return (nrhs + 15) / 16 * 16; }
 
 helm_status ensure_sweep_ws(helm_t H, int nrhs) {
     Work& w = H->wk;
@@ -214,13 +216,15 @@ helm_status ensure_sweep_ws(helm_t H, int nrhs) {
     H->ws_epoch += 1;
     const auto& g = H->g;
     const size_t fb = field_bytes(H, nrhs);
-    CHK(dmalloc(H, &w.Yw, (size_t)nrhs * g.Ny * WP * sizeof(double2)));
+    const size_t yw = g.dim == 3 ? (size_t)g.Ny * g.Bp * rhs_pad16(nrhs) * sizeof(double2)
+                                 : (size_t)nrhs * g.Ny * WP * sizeof(double2);
+    CHK(dmalloc(H, &w.Yw, yw));
     double2** fields[] = {&w.V, &w.G, &w.PF, &w.Psi, &w.Wf, &w.Hf};
     for (double2** f : fields) {
         CHK(dmalloc(H, f, fb));
         HIPCHK(hipMemsetAsync(*f, 0, fb, H->st));
     }
-    const size_t tb = (size_t)std::max(1, g.J) * 2 * nrhs * g.Ny * sizeof(double2);
+    const size_t tb = (size_t)std::max(1, g.J) * 2 * nrhs * g.Nrow() * sizeof(double2);
     CHK(dmalloc(H, &w.Tup, tb));
     CHK(dmalloc(H, &w.Tdn, tb));
     HIPCHK(hipMemsetAsync(w.Tup, 0, tb, H->st));
@@ -239,7 +243,28 @@ struct TimedScope {
 
 // ---------------------------------------------------------------- sweeps
 template <typename T>
+helm_status strip_solve3(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
+    const auto& g = H->g;
+    helm::Solve3Args<T> a;
+    a.F = static_cast<const helm::cplx<T>*>(H->F) + (size_t)s * g.Ny * g.Bp * g.Bp;
+    a.Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
+    a.cy = H->t.cy;
+    a.by = H->t.by;
+    a.io = io;
+    if (!a.io.trA || !a.io.trB || a.io.q_t < 0) {
+        a.io.trA = a.io.trB = a.io.src;
+        a.io.q_t = -1;
+        a.io.coef = 0.0;
+    }
+    a.Ny = g.Ny; a.Nz = g.Nz; a.W = g.strips[s].W; a.B = a.W * g.Nz; a.Bp = g.Bp;
+    a.nrhs = nrhs; a.RP = rhs_pad16(nrhs); a.Nrow = g.Nrow();
+    HIPCHK(helm::launch_strip_solve3<T>(a, H->st, H->kt()));
+    return HELM_OK;
+}
+
+template <typename T>
 helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
+    if (H->g.dim == 3) return strip_solve3<T>(H, s, nrhs, io);
     const auto* F = static_cast<const helm::cplx<T>*>(H->F);
     const auto* Fc = static_cast<const helm::cplx<T>*>(H->Fc);
     auto* Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
@@ -252,15 +277,15 @@ helm_status strip_solve_any(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
                                 : strip_solve<float>(H, s, nrhs, io);
 }
 
-double2* trace(double2* base, int s, int k, int nrhs, int Ny) {
-    return base + ((size_t)s * 2 + k) * nrhs * Ny;
+double2* trace(double2* base, int s, int k, int nrhs, long Nrow) {
+    return base + ((size_t)s * 2 + k) * nrhs * Nrow;
 }
 
 helm::IOSpec field_io(helm_t H, int s) {
     helm::IOSpec io;
     const auto& g = H->g;
-    io.src_rs = (long)g.Ny * g.Nx; io.src_ls = g.Nx; io.src_off = g.strips[s].a;
-    io.dst_rs = (long)g.Ny * g.Nx; io.dst_ls = g.Nx; io.dst_off = g.strips[s].a;
+    io.src_rs = g.Nrow() * g.Nx; io.src_ls = g.Nx; io.src_off = g.strips[s].a;
+    io.dst_rs = g.Nrow() * g.Nx; io.dst_ls = g.Nx; io.dst_off = g.strips[s].a;
     return io;
 }
 
@@ -277,7 +302,7 @@ helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
         if (red_src) {
             // reduced input: columns beta_s, beta_s+1 of interface s (s >= 1)
             const int nred = 2 * (g.J - 1);
-            io.src = red_src; io.src_rs = (long)g.Ny * nred; io.src_ls = nred;
+            io.src = red_src; io.src_rs = g.Nrow() * nred; io.src_ls = nred;
             io.src_lo = g.beta[s] - S.a; io.src_hi = io.src_lo + 2;
             io.src_off = 2 * (s - 1) - io.src_lo;
         } else {
@@ -285,8 +310,8 @@ helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
             io.src_lo = S.core_lo - S.a; io.src_hi = S.core_hi - S.a;
         }
         if (s > s0) {
-            io.trA = trace(w.Tup, s - 1, 0, nrhs, g.Ny);
-            io.trB = trace(w.Tup, s - 1, 1, nrhs, g.Ny);
+            io.trA = trace(w.Tup, s - 1, 0, nrhs, g.Nrow());
+            io.trB = trace(w.Tup, s - 1, 1, nrhs, g.Nrow());
             io.q_t = g.beta[s] - 1 - S.a;
             io.coef = -ih2;                                   // -2 delta d_x v, delta = 1/(2h)
         }
@@ -299,8 +324,8 @@ helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
             if (s < g.J - 1) { io.o_lo[1] = S.core_hi - 2 - S.a; io.o_hi[1] = S.core_hi - S.a; }
         }
         if (s < g.J - 1) {
-            io.tro0 = trace(w.Tup, s, 0, nrhs, g.Ny);
-            io.tro1 = trace(w.Tup, s, 1, nrhs, g.Ny);
+            io.tro0 = trace(w.Tup, s, 0, nrhs, g.Nrow());
+            io.tro1 = trace(w.Tup, s, 1, nrhs, g.Nrow());
             io.qo0 = g.beta[s + 1] - 1 - S.a;
             io.qo1 = g.beta[s + 1] - S.a;
         }
@@ -322,8 +347,8 @@ helm_status sweep_down(helm_t H, int nrhs, double2* dst, bool full) {
         io.src = w.G;
         io.src_lo = g.beta[s + 1] - 1 - S.a; io.src_hi = io.src_lo + 2;
         if (s < g.J - 2) {
-            io.trA = trace(w.Tdn, s + 1, 0, nrhs, g.Ny);
-            io.trB = trace(w.Tdn, s + 1, 1, nrhs, g.Ny);
+            io.trA = trace(w.Tdn, s + 1, 0, nrhs, g.Nrow());
+            io.trB = trace(w.Tdn, s + 1, 1, nrhs, g.Nrow());
             io.q_t = g.beta[s + 1] - S.a;
             io.coef = ih2;                                     // +2 delta d_x w
         }
@@ -337,8 +362,8 @@ helm_status sweep_down(helm_t H, int nrhs, double2* dst, bool full) {
             if (s > 0) { io.o_lo[1] = g.beta[s] + 1 - S.a; io.o_hi[1] = io.o_lo[1] + 2; }
         }
         if (s > 0) {
-            io.tro0 = trace(w.Tdn, s, 0, nrhs, g.Ny);
-            io.tro1 = trace(w.Tdn, s, 1, nrhs, g.Ny);
+            io.tro0 = trace(w.Tdn, s, 0, nrhs, g.Nrow());
+            io.tro1 = trace(w.Tdn, s, 1, nrhs, g.Nrow());
             io.qo0 = g.beta[s] - S.a;
             io.qo1 = g.beta[s] + 1 - S.a;
         }
@@ -366,16 +391,16 @@ helm_status apply_AP_reduced(helm_t H, int nrhs, const double2* psi, double2* ou
     Work& w = H->wk;
     const int nred = 2 * (g.J - 1);
     if (nred == 0) return HELM_OK;
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(psi, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(psi, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.Psi, H->st)));
     // v^(1) = 0 (Algorithm 3 starts at j = 2): clear the columns of V it would own
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, -1, H->st)));
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Ny, g.Nx, w.V, 0, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Nrow(), g.Nx, w.V, -1, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Nrow(), g.Nx, w.V, 0, H->st)));
     CHK(sweep_up(H, nrhs, nullptr, 1, false, psi));
     HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, nred, w.V, w.Psi, w.G, H->st)));
     CHK(sweep_down(H, nrhs, w.Wf, false));
     // h = g - A w on the reduced columns; output psi - h
     HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.redcols, nred, w.Wf, w.G, w.Hf, H->st)));
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols_sub(w.Psi, w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, out, H->st)));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols_sub(w.Psi, w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, out, H->st)));
     return HELM_OK;
 }
 
@@ -466,7 +491,7 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     CHK(dmalloc(H, &w.h2, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.y, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.nrm, (size_t)nrhs * sizeof(double)));
-    const int nb = helm::dots_blocks(std::max(n, (long)H->g.Ny * H->g.Nx));
+    const int nb = helm::dots_blocks(std::max(n, H->g.Nrow() * H->g.Nx));
     CHK(dmalloc(H, &w.partial, (size_t)nb * nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.npartial, (size_t)nb * nrhs * sizeof(double)));
     w.mcap = m;
@@ -486,7 +511,7 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
     // graph replay: the captured launches read the fixed buffer apin and write `out`
     Work& w = H->wk;
     CHK(ensure_sweep_ws(H, nrhs));
-    const size_t bytes = (size_t)nrhs * H->g.Ny * 2 * (H->g.J - 1) * sizeof(double2);
+    const size_t bytes = (size_t)nrhs * H->g.Nrow() * 2 * (H->g.J - 1) * sizeof(double2);
     HIPCHK(hipMemcpyAsync(w.apin, x, bytes, hipMemcpyDeviceToDevice, H->st));
     if (!H->ap_exec || H->ap_nrhs != nrhs || H->ap_out != out || H->ap_epoch != H->ws_epoch) {
         if (H->ap_exec) { HIPCHK(hipGraphExecDestroy(H->ap_exec)); H->ap_exec = nullptr; }
@@ -605,10 +630,10 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     const auto& g = H->g;
     CHK(ensure_sweep_ws(H, nrhs));
     Work& w = H->wk;
-    const long nfull = (long)g.Ny * g.Nx;
+    const long nfull = g.Nrow() * g.Nx;
     const int nred = 2 * (g.J - 1);
     const bool reduced = H->mode == HELM_REDUCED && nred > 0;
-    const long n = reduced ? (long)g.Ny * nred : nfull;
+    const long n = reduced ? g.Nrow() * nred : nfull;
     CHK(ensure_gmres_ws(H, nrhs, n, std::min(H->max_iter, reduced ? 60 : 30)));
     if (!w.R) {
         CHK(dmalloc(H, &w.R, field_bytes(H, nrhs)));
@@ -646,7 +671,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
             HIPCHK(hipMemsetAsync(w.Ut, 0, field_bytes(H, nrhs), H->st));
             CHK(reduced_setup(H, nrhs, w.R, w.Ut));
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
-            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.red, H->st)));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
             b = w.red;
         }
         CHK(norms(H, b, nrhs, n, bn));
@@ -669,7 +694,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
         if (reduced) {
             // Algorithm 4: u += P psi + u~   (psi scattered onto the grid)
             HIPCHK(hipMemsetAsync(w.Psi, 0, field_bytes(H, nrhs), H->st));
-            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, H->t.redcols, nred, nrhs, g.Ny, g.Nx, w.Psi, H->st)));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.Psi, H->st)));
             CHK(apply_P_full(H, nrhs, w.Psi, w.Hf));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_axpby(w.Hf, w.Ut, w.Hf, 1.0, 1.0, nrhs * nfull, H->st)));
         } else {
@@ -724,22 +749,27 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         delete H;
         return HELM_EINVAL;
     };
-    if (opts->dim != 2) return bad("only dim = 2 is supported");
-    const int nx = opts->n[0], ny = opts->n[1];
-    if (nx < 2 || ny < 2) return bad("interior grid must be at least 2 x 2");
+    if (opts->dim != 2 && opts->dim != 3) return bad("dim must be 2 or 3");
+    const int dim = opts->dim;
+    const int nx = opts->n[0], ny = opts->n[1], nz = dim == 3 ? opts->n[2] : 1;
+    if (nx < 2 || ny < 2 || nz < 1 || (dim == 3 && nz < 2))
+        return bad("interior grid must be at least 2 points along every axis");
     if (!(omega > 0) || !std::isfinite(omega)) return bad("omega must be positive and finite");
     if (!(h > 0) || !std::isfinite(h)) return bad("h must be positive and finite");
     if (J < 1) return bad("J must be >= 1");
     if (opts->pml_outer < 1) return bad("pml_outer must be >= 1");
     if (J > 1 && opts->pml_iface < 1) return bad("pml_iface must be >= 1");
     double cmax = 0.0;
-    for (size_t i = 0; i < (size_t)nx * ny; ++i) {
+    for (size_t i = 0; i < (size_t)nx * ny * nz; ++i) {
         if (!(c[i] > 0.0) || !std::isfinite(c[i])) return bad("c must be positive and finite");
         cmax = std::max(cmax, c[i]);
     }
     helm::Geom& g = H->g;
     g.nx = nx; g.ny = ny; g.wout = opts->pml_outer; g.w = opts->pml_iface; g.J = J;
     g.Nx = nx + 2 * g.wout; g.Ny = ny + 2 * g.wout;
+    g.dim = dim;
+    g.nz = dim == 3 ? nz : 0;
+    g.Nz = dim == 3 ? nz + 2 * g.wout : 1;
     g.h = h; g.omega = omega;
     g.power = opts->pml_power > 0 ? opts->pml_power : 2.0;
     g.s0 = opts->pml_s0 >= 0 ? opts->pml_s0 : 10.0;
@@ -772,9 +802,18 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         if (S.W > WP) return bad("padded strip " + std::to_string(s) + " is " + std::to_string(S.W) +
                                  " columns wide; at most 64 are supported (use more strips)");
     }
+    if (dim == 3) {
+        int Bmax = 0;
+        for (const auto& S : g.strips) Bmax = std::max(Bmax, S.W * g.Nz);
+        g.Bp = (Bmax + 63) / 64 * 64;
+        if (g.Bp > helm::BP3_MAX)
+            return bad("3-D slab blocks of " + std::to_string(Bmax) + " unknowns exceed " +
+                       std::to_string(helm::BP3_MAX) + " (use thinner slabs or fewer z points)");
+    }
     // ---- chunks along y
     int m = opts->chunk > 0 ? opts->chunk : 32;
     if (m < 2) m = 2;
+    if (dim == 3) m = g.Ny;        // 3-D slabs: one chunk (each plane step is a large product)
     H->ch.m = m;
     H->ch.P = (g.Ny + m - 1) / m;
     if (H->ch.P > 1 && (H->ch.P - 1) * m >= g.Ny) H->ch.P -= 1;
@@ -786,15 +825,24 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if (hipGetDevice(&H->dev) != hipSuccess) H->dev = 0;
 
     // ---- tables (FP64 complex), Sec. 2.1-2.2
-    const int Nx = g.Nx, Ny = g.Ny;
-    std::vector<double> k2((size_t)Nx * Ny);
-    for (int l = 0; l < Ny; ++l) {
-        const int li = std::min(std::max(l - g.wout, 0), ny - 1);
-        for (int i = 0; i < Nx; ++i) {
-            const int ii = std::min(std::max(i - g.wout, 0), nx - 1);
-            const double cc = c[(size_t)li * nx + ii];
-            k2[(size_t)l * Nx + i] = (omega / cc) * (omega / cc);
+    const int Nx = g.Nx, Ny = g.Ny, Nz = g.Nz;
+    std::vector<double> k2((size_t)Nx * Ny * Nz);
+    for (int z = 0; z < Nz; ++z) {
+        const int zi = dim == 3 ? std::min(std::max(z - g.wout, 0), nz - 1) : 0;
+        for (int l = 0; l < Ny; ++l) {
+            const int li = std::min(std::max(l - g.wout, 0), ny - 1);
+            for (int i = 0; i < Nx; ++i) {
+                const int ii = std::min(std::max(i - g.wout, 0), nx - 1);
+                const double cc = c[((size_t)zi * ny + li) * nx + ii];
+                k2[((size_t)z * Ny + l) * Nx + i] = (omega / cc) * (omega / cc);
+            }
         }
+    }
+    std::vector<double2> az, azh;
+    if (dim == 3) {
+        az.resize(Nz); azh.resize(Nz + 1);
+        for (int z = 0; z < Nz; ++z) az[z] = d2(alpha_outer(g, z, Nz));
+        for (int z = 0; z <= Nz; ++z) azh[z] = d2(alpha_outer(g, z - 0.5, Nz));
     }
     std::vector<double2> ax(Nx), axh(Nx + 1), ay(Ny), ayh(Ny + 1), cy(Ny), by(Ny);
     for (int i = 0; i < Nx; ++i) ax[i] = d2(alpha_outer(g, i, Nx));
@@ -854,9 +902,66 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if ((st = upload(H, (void**)&t.rcols, rcols.data(), rcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.redcols, redcols.data(), redcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.tcol, tcol.data(), tcol.size() * sizeof(int))) != HELM_OK) return st;
+    if (dim == 3) {
+        if ((st = upload(H, (void**)&t.az, az.data(), az.size() * sizeof(double2))) != HELM_OK) return st;
+        if ((st = upload(H, (void**)&t.azh, azh.data(), azh.size() * sizeof(double2))) != HELM_OK) return st;
+    }
     if ((st = dmalloc(H, &H->d_err, sizeof(int))) != HELM_OK) return st;
     H->err.clear();
     *out = H;
+    return HELM_OK;
+}
+
+// 3-D: the inverses G_l of every slab, plane by plane (all slabs of a plane together)
+helm_status factor3(helm_t H) {
+    const auto& g = H->g;
+    const size_t BB = (size_t)g.Bp * g.Bp;
+    const bool single = H->prec != HELM_C128;
+    const size_t esz = single ? sizeof(float2) : sizeof(double2);
+    void* F = nullptr;
+    CHK(dmalloc(H, &F, (size_t)g.J * g.Ny * BB * esz));
+    struct Bufs {
+        std::vector<void*> p;
+        ~Bufs() { for (void* q : p) dfree(q); }
+    } bufs;
+    auto alloc = [&](void** q, size_t bytes) -> helm_status {
+        CHK(dmalloc(H, q, bytes));
+        bufs.p.push_back(*q);
+        return HELM_OK;
+    };
+    const size_t nb = helm::factor3_panel_width();
+    double2 *S, *G64, *Tm, *Cm;
+    int *perm, *pi;
+    helm_status st;
+    if ((st = alloc((void**)&S, g.J * BB * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&G64, g.J * BB * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&Tm, (size_t)g.J * g.Bp * nb * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&Cm, (size_t)g.J * g.Bp * nb * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&perm, (size_t)g.J * g.Bp * sizeof(int))) != HELM_OK ||
+        (st = alloc((void**)&pi, (size_t)g.J * g.Bp * sizeof(int))) != HELM_OK) {
+        dfree(F);
+        return st;
+    }
+    HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
+    helm::Fac3Args a;
+    a.J = g.J; a.Ny = g.Ny; a.Nz = g.Nz; a.Nx = g.Nx; a.Bp = g.Bp;
+    a.sW = H->t.sW; a.sax = H->t.sax; a.saxh = H->t.saxh; a.scol = H->t.scol;
+    a.ay = H->t.ay; a.ayh = H->t.ayh; a.az = H->t.az; a.azh = H->t.azh;
+    a.cy = H->t.cy; a.by = H->t.by; a.k2 = H->t.k2;
+    a.ih2 = 1.0 / (g.h * g.h);
+    for (int l = 0; l < g.Ny; ++l) {
+        void* out = static_cast<char*>(F) + (size_t)l * BB * esz;
+        hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS,
+                             helm::launch_factor3_plane(a, l, l > 0 ? G64 : nullptr, S, Tm, Cm, perm, pi,
+                                                        H->d_err, G64, out, single, (size_t)g.Ny * BB, H->st));
+        if (e != hipSuccess) { dfree(F); HIPCHK(e); }
+    }
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    H->F = F;
+    if (herr) return fail(H, HELM_ESINGULAR, "zero or non-finite pivot in a slab factorisation");
+    H->factored = true;
     return HELM_OK;
 }
 
@@ -874,6 +979,9 @@ helm_status helm_factor(helm_t H) {
     dfree(H->F);
     H->F = nullptr;
     H->factored = false;
+    dfree(H->Fc);
+    H->Fc = nullptr;
+    if (g.dim == 3) return factor3(H);
     const size_t nel = (size_t)g.J * g.Ny * NSLOT * BLK;
     double2* F64 = nullptr;
     CHK(dmalloc(H, &F64, nel * sizeof(double2)));
@@ -964,6 +1072,7 @@ helm_status helm_grad(helm_t H, int nsrc, const void* src, int nrec, const int64
         return fail(H, HELM_EINVAL, "nsrc, nrec >= 1 and non-null src, rec, d, misfit, grad required");
     if (!(tol > 0)) return fail(H, HELM_EINVAL, "tol must be positive");
     const auto& g = H->g;
+    if (g.dim != 2) return fail(H, HELM_EINVAL, "helm_grad supports the 2-D problem only");
     const long field = (long)g.Nx * g.Ny;
     // receivers: validated on the host, grouped by point (repeated receivers add up)
     std::vector<int64_t> hrec(nrec);
@@ -1072,12 +1181,21 @@ helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void*
     const int W = g.strips[strip].W;
     helm::IOSpec io;
     io.src = static_cast<const double2*>(r);
-    io.src_rs = (long)g.Ny * W; io.src_ls = W; io.src_off = 0;
+    io.src_rs = g.Nrow() * W; io.src_ls = W; io.src_off = 0;
     io.src_lo = 0; io.src_hi = W;
     io.dst = static_cast<double2*>(x);
-    io.dst_rs = (long)g.Ny * W; io.dst_ls = W; io.dst_off = 0;
+    io.dst_rs = g.Nrow() * W; io.dst_ls = W; io.dst_off = 0;
     io.o_lo[0] = 0; io.o_hi[0] = W;
     return strip_solve_any(H, strip, nrhs, io);
+}
+
+helm_status helm_get_dims3(helm_t H, int* N_x, int* N_y, int* N_z, int* J) {
+    if (!H) return HELM_EINVAL;
+    if (N_x) *N_x = H->g.Nx;
+    if (N_y) *N_y = H->g.Ny;
+    if (N_z) *N_z = H->g.Nz;
+    if (J) *J = H->g.J;
+    return HELM_OK;
 }
 
 helm_status helm_get_dims(helm_t H, int* N_x, int* N_y, int* J) {

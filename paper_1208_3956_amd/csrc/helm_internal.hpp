@@ -58,6 +58,10 @@ struct Strip {
 
 struct Geom {
     int nx = 0, ny = 0, Nx = 0, Ny = 0, wout = 0, w = 0, J = 0;
+    int dim = 2, nz = 0, Nz = 1;  // 3-D: nz interior points along z, Nz = nz + 2 wout
+    int Bp = 0;                   // 3-D: slab block size W * Nz padded to a multiple of 64
+    // rows of a field: fields are [rhs][row][x] with row = z * Ny + y
+    long Nrow() const { return (long)Nz * Ny; }
     double h = 0, omega = 0, power = 2, s0 = 10, cref = 0;
     std::vector<int> beta;       // J+1 entries
     std::vector<Strip> strips;
@@ -105,6 +109,32 @@ struct DevTables {
     int* rcols = nullptr;       // 2(J-1)   residual columns beta_j - 1, beta_j
     int* redcols = nullptr;     // 2(J-1)   reduced columns beta_j, beta_j + 1
     int* tcol = nullptr;        // J*8      strip-local columns whose spike rows are kept compact
+    double2* az = nullptr;      // Nz       (3-D) alpha_z at points
+    double2* azh = nullptr;     // Nz+1     (3-D) alpha_z at half-points
+};
+
+// ---- 3-D slabs (kernels_3d.hip)
+constexpr int BP3_MAX = 8192;   // largest padded slab block
+
+struct Fac3Args {
+    int J, Ny, Nz, Nx, Bp;
+    const int* sW;
+    const double2* sax; const double2* saxh; const int* scol;
+    const double2* ay; const double2* ayh; const double2* az; const double2* azh;
+    const double2* cy; const double2* by;
+    const double* k2;
+    double ih2;
+};
+
+template <typename T>
+struct Solve3Args {
+    const cplx<T>* F;     // factors of the slab: [Ny][Bp*Bp], column-major inverses G_l
+    cplx<T>* Yw;          // workspace [Ny][Bp][RP]
+    const double2* cy;
+    const double2* by;
+    IOSpec io;            // rows of src / dst are z * Ny + y; traces are [rhs][Nrow]
+    int Ny, Nz, W, B, Bp, nrhs, RP;
+    long Nrow;
 };
 
 // Optional per-launch event timing: launchers call begin/end around each kernel.
@@ -163,6 +193,17 @@ hipError_t launch_axpby(const double2* x, const double2* y, double2* out, double
                         long n, hipStream_t st);
 
 int dots_blocks(long n);
+
+// one plane l of the 3-D slab factorisation for every slab: S = T_l - c_l b_{l-1} Gprev,
+// inverted in place by blocked Gauss-Jordan; the inverse goes to G64 (FP64, may be null)
+// and to out + s * out_stride (complex64 if out_single, else complex128)
+hipError_t launch_factor3_plane(const Fac3Args& a, int l, const double2* Gprev, double2* S,
+                                double2* Tm, double2* Cm, int* perm, int* pi, int* err,
+                                double2* G64, void* out, bool out_single, size_t out_stride,
+                                hipStream_t st);
+size_t factor3_panel_width();
+template <typename T>
+hipError_t launch_strip_solve3(const Solve3Args<T>& a, hipStream_t st, KTimer* kt);
 
 // ---- misfit and adjoint gradient (kernels_grad.hip)
 hipError_t launch_rec_residual(const double2* u, long field, const long* rec, int nrec,

@@ -1,7 +1,7 @@
 // FP64 kernels on whole fields: the PML stencil (Sec. 2.2) and the batched vector
 // operations of right-preconditioned GMRES (Sec. 2.3).
 //
-// Fields are [nrhs][Ny][Nx] complex128, x fastest.  Reductions are deterministic: every
+// Fields are [nrhs][Ny][Nx] complex128 ([nrhs][Nz][Ny][Nx] in 3-D), x fastest.  Reductions are deterministic: every
 // block reduces in a fixed tree and the per-block partial sums are added in block order.
 #include "helm_internal.hpp"
 
@@ -15,16 +15,20 @@ struct StencilArgs {
     const double2* axh;
     const double2* ay;
     const double2* ayh;
-    int Nx, Ny;
+    const double2* az;     // 3-D only (null in 2-D)
+    const double2* azh;
+    int Nx, Ny, Nz;
     double inv_h2;
 };
 
 // (A u) at (l, i) in the paper form:
 //   -alpha_x(i)/h^2 [alpha_x(i+1/2)(u_{i+1}-u_i) - alpha_x(i-1/2)(u_i-u_{i-1})]
 //   -alpha_y(l)/h^2 [alpha_y(l+1/2)(u_{l+1}-u_l) - alpha_y(l-1/2)(u_l-u_{l-1})] - k^2 u
-// with zero Dirichlet ghosts.
-__device__ inline double2 stencil_at(const StencilArgs& s, const double2* __restrict__ u, int l, int i) {
-    const size_t p = (size_t)l * s.Nx + i;
+// with zero Dirichlet ghosts; in 3-D the same z-term is added (7-point stencil).  `row`
+// is z * Ny + l.
+__device__ inline double2 stencil_at(const StencilArgs& s, const double2* __restrict__ u, int row, int i) {
+    const int l = row % s.Ny, z = row / s.Ny;
+    const size_t p = (size_t)row * s.Nx + i;
     const double2 uc = u[p];
     const double2 ue = (i + 1 < s.Nx) ? u[p + 1] : cmk<double2>(0, 0);
     const double2 uw = (i > 0) ? u[p - 1] : cmk<double2>(0, 0);
@@ -38,6 +42,13 @@ __device__ inline double2 stencil_at(const StencilArgs& s, const double2* __rest
     double2 yp = cadd(cmul(an, csub(uc, un)), cmul(as, csub(uc, us)));
     yp = cmul(s.ay[l], yp);
     double2 r = cadd(xp, yp);
+    if (s.Nz > 1) {
+        const size_t pl = (size_t)s.Ny * s.Nx;
+        const double2 uu = (z + 1 < s.Nz) ? u[p + pl] : cmk<double2>(0, 0);
+        const double2 ud = (z > 0) ? u[p - pl] : cmk<double2>(0, 0);
+        double2 zp = cadd(cmul(s.azh[z + 1], csub(uc, uu)), cmul(s.azh[z], csub(uc, ud)));
+        r = cadd(r, cmul(s.az[z], zp));
+    }
     r.x *= s.inv_h2; r.y *= s.inv_h2;
     const double kk = s.k2[p];
     r.x -= kk * uc.x;
@@ -49,9 +60,9 @@ __global__ void __launch_bounds__(256) k_apply_A(StencilArgs s, const double2* _
                                                  const double2* __restrict__ f,
                                                  double2* __restrict__ out) {
     const int i = blockIdx.x * 64 + threadIdx.x;
-    const int l = blockIdx.y * 4 + threadIdx.y;
-    const size_t off = (size_t)blockIdx.z * s.Nx * s.Ny;
-    if (i >= s.Nx || l >= s.Ny) return;
+    const int l = blockIdx.y * 4 + threadIdx.y;           // row z * Ny + y
+    const size_t off = (size_t)blockIdx.z * s.Nx * s.Ny * s.Nz;
+    if (i >= s.Nx || l >= s.Ny * s.Nz) return;
     double2 a = stencil_at(s, u + off, l, i);
     const size_t p = off + (size_t)l * s.Nx + i;
     out[p] = f ? csub(f[p], a) : a;
@@ -61,10 +72,10 @@ __global__ void __launch_bounds__(256) k_apply_A_cols(StencilArgs s, const int* 
                                                       int ncols, const double2* __restrict__ u,
                                                       const double2* __restrict__ f,
                                                       double2* __restrict__ out) {
-    const int l = blockIdx.x * 256 + threadIdx.x;
+    const int l = blockIdx.x * 256 + threadIdx.x;       // row z * Ny + y
     const int i = cols[blockIdx.y];
-    const size_t off = (size_t)blockIdx.z * s.Nx * s.Ny;
-    if (l >= s.Ny) return;
+    const size_t off = (size_t)blockIdx.z * s.Nx * s.Ny * s.Nz;
+    if (l >= s.Ny * s.Nz) return;
     double2 a = stencil_at(s, u + off, l, i);
     const size_t p = off + (size_t)l * s.Nx + i;
     out[p] = f ? csub(f[p], a) : a;
@@ -73,7 +84,8 @@ __global__ void __launch_bounds__(256) k_apply_A_cols(StencilArgs s, const int* 
 StencilArgs stencil_args(const DevTables& t, const Geom& g) {
     StencilArgs s;
     s.k2 = t.k2; s.ax = t.ax; s.axh = t.axh; s.ay = t.ay; s.ayh = t.ayh;
-    s.Nx = g.Nx; s.Ny = g.Ny; s.inv_h2 = 1.0 / (g.h * g.h);
+    s.az = t.az; s.azh = t.azh;
+    s.Nx = g.Nx; s.Ny = g.Ny; s.Nz = g.Nz; s.inv_h2 = 1.0 / (g.h * g.h);
     return s;
 }
 
@@ -269,7 +281,7 @@ int dots_blocks(long n) {
 hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
                           const double2* f, double2* out, hipStream_t st) {
     StencilArgs s = stencil_args(t, g);
-    dim3 grid((g.Nx + 63) / 64, (g.Ny + 3) / 4, nrhs);
+    dim3 grid((g.Nx + 63) / 64, (unsigned)((g.Nrow() + 3) / 4), nrhs);
     hipLaunchKernelGGL(k_apply_A, grid, dim3(64, 4), 0, st, s, u, f, out);
     return hipGetLastError();
 }
@@ -279,7 +291,7 @@ hipError_t launch_apply_A_cols(const DevTables& t, const Geom& g, int nrhs, cons
                                hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     StencilArgs s = stencil_args(t, g);
-    dim3 grid((g.Ny + 255) / 256, ncols, nrhs);
+    dim3 grid((unsigned)((g.Nrow() + 255) / 256), ncols, nrhs);
     hipLaunchKernelGGL(k_apply_A_cols, grid, dim3(256), 0, st, s, cols, ncols, u, f, out);
     return hipGetLastError();
 }

@@ -27,9 +27,10 @@ class SolveResult:
 
 
 class Helmholtz:
-    """One discretised 2-D Helmholtz problem with its strip factors.
+    """One discretised 2-D or 3-D Helmholtz problem with its strip (slab) factors.
 
-    c          interior wave speed, (n_y, n_x) float64 (numpy or torch; copied to the host)
+    c          interior wave speed, (n_y, n_x) or (n_z, n_y, n_x) float64 (numpy or torch;
+               copied to the host); 3-D uses the 7-point stencil and slabs along x
     omega, h   angular frequency and grid spacing
     J          number of strips along x
     pml_outer  outer PML width (cells); pml_iface: interface PML width w
@@ -50,10 +51,13 @@ class Helmholtz:
             raise ValueError("the solver runs on a HIP device (cuda:N in torch)")
         c = c.detach().cpu().numpy() if isinstance(c, torch.Tensor) else np.asarray(c)
         self._c = np.ascontiguousarray(c, dtype=np.float64)
-        if self._c.ndim != 2:
-            raise ValueError("c must be a 2-D (n_y, n_x) array")
-        n_y, n_x = self._c.shape
+        if self._c.ndim not in (2, 3):
+            raise ValueError("c must be a (n_y, n_x) or (n_z, n_y, n_x) array")
+        n_y, n_x = self._c.shape[-2:]
         o = L.helm_default_opts(n_x, n_y)
+        if self._c.ndim == 3:
+            o.dim = 3
+            o.n[2] = int(self._c.shape[0])
         o.pml_outer, o.pml_iface = int(pml_outer), int(pml_iface)
         o.pml_power, o.pml_s0, o.pml_cref = float(pml_power), float(pml_s0), float(pml_cref)
         o.prec = {"c128": L.HELM_C128, "mixed": L.HELM_MIXED_C64, "c64": L.HELM_MIXED_C64}[prec]
@@ -71,7 +75,9 @@ class Helmholtz:
             self._opts = o
             self.h = L.helm_setup(self._c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   omega, h, o, J)
-        self.N_x, self.N_y, self.J = L.helm_get_dims(self.h)
+        self.N_x, self.N_y, self.N_z, self.J = L.helm_get_dims3(self.h)
+        self.dim = self._c.ndim
+        self.row_shape = (self.N_z, self.N_y) if self.dim == 3 else (self.N_y,)
         self.beta, self.strip_first, self.strip_width = L.helm_get_partition(self.h, self.J)
         self.chunk_rows, self.n_chunks = L.helm_get_chunks(self.h)
         self.prec, self.mode = prec, mode
@@ -87,10 +93,11 @@ class Helmholtz:
             raise TypeError(f"{name} must be complex128")
         if x.device != self.device:
             raise ValueError(f"{name} must live on {self.device}")
-        if x.dim() == 2:
+        want = self.row_shape + (cols,)
+        if x.dim() == len(want):
             x = x.unsqueeze(0)
-        if x.dim() != 3 or x.shape[1] != self.N_y or x.shape[2] != cols:
-            raise ValueError(f"{name} must have shape (nrhs, {self.N_y}, {cols}), got {tuple(x.shape)}")
+        if tuple(x.shape[1:]) != want:
+            raise ValueError(f"{name} must have shape (nrhs, {', '.join(map(str, want))}), got {tuple(x.shape)}")
         return x.contiguous()
 
     def _sync(self):
@@ -141,6 +148,8 @@ class Helmholtz:
         if tuple(d.shape) != (nsrc, nrec):
             raise ValueError(f"d must have shape ({nsrc}, {nrec}), got {tuple(d.shape)}")
         d = d.contiguous()
+        if self.dim != 2:
+            raise ValueError("the gradient is provided for 2-D problems")
         n_y, n_x = self._c.shape
         g = torch.empty((n_y, n_x), dtype=torch.float64, device=self.device)
         self._begin()

@@ -42,7 +42,8 @@ def _setup(c, omega=2 * np.pi * 5, h=0.05, J=2, **kw):
     (dict(J=0), "J must be"),
     (dict(omega=0.0), "omega"),
     (dict(h=-1.0), "h must"),
-    (dict(dim=3), "dim"),
+    (dict(dim=4), "dim"),
+    (dict(dim=3), "every axis"),
     (dict(J=12), "at least two columns"),
     (dict(J=1, pml_outer=25), "64"),
     (dict(J=2, pml_iface=60), "64"),
@@ -79,3 +80,14 @@ def test_destroy_null_is_noop():
 
 def test_grad_null_handle_is_einval():
     assert L.lib().helm_grad(None, 1, None, 1, None, None, 1e-6, None, None, None) == L.HELM_EINVAL
+
+
+def test_setup_rejects_oversized_3d_slabs():
+    """A 28-column slab with N_z = 308 has blocks of 8624 unknowns (> 8192)."""
+    o = L.helm_default_opts(20, 20)
+    o.dim, o.pml_outer, o.pml_iface = 3, 4, 3
+    o.n[2] = 300
+    c = np.ascontiguousarray(np.ones((300, 20, 20)))
+    with pytest.raises(L.HelmError) as e:
+        L.helm_setup(c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2 * np.pi * 5, 0.05, o, 1)
+    assert e.value.status == L.HELM_EINVAL and "8192" in str(e.value)
