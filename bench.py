@@ -32,7 +32,7 @@ def parse():
     p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="layers",
-                   choices=["homogeneous_100", "lens_1000", "layers", "layers_uneven_batch"])
+                   choices=["homogeneous_100", "lens_1000", "layers", "layers_uneven_batch", "smooth_3d"])
     p.add_argument("--n", type=int, default=None, help="grid size for the layers family")
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--prec", default="mixed", choices=["mixed", "c128"])
@@ -54,6 +54,8 @@ def workload(args):
         wl = W.homogeneous_100()
     elif args.workload == "lens_1000":
         wl = W.lens_1000(nsrc=args.nrhs or 16)
+    elif args.workload == "smooth_3d":
+        wl = W.smooth_3d(n=args.n or 80, nsrc=args.nrhs or 32)
     else:
         wl = W.layers(n=args.n or 2000, nsrc=args.nrhs or 64)
     return wl
@@ -61,8 +63,16 @@ def workload(args):
 
 def phase_flops(H, wl, nrhs):
     """Algorithmic real flops of one launch of each strip-solve phase and of the factor,
-    averaged over strips (8 real flops per complex multiply-add)."""
+    averaged over strips (8 real flops per complex multiply-add).  In 3-D one timed
+    phase-A launch is a whole slab solve (2 N_y - 1 plane products with the B x B inverses,
+    B = W N_z) and one factor launch is one plane of every slab (B^3 multiply-adds of
+    Gauss-Jordan per slab)."""
     Ny = H.N_y
+    if H.dim == 3:
+        B = [w * H.N_z for w in H.strip_width]
+        B2 = sum(b * b for b in B) / len(B)
+        return {"phase_a": 8.0 * B2 * nrhs * (2 * Ny - 1), "phase_b": 0.0, "phase_c": 0.0,
+                "factor_chunks": 8.0 * sum(b ** 3 for b in B), "factor_separators": 0.0}
     m = H.chunk_rows
     P = -(-Ny // m)
     n_int = Ny - (P - 1)                    # interior rows over all chunks
@@ -109,13 +119,13 @@ def cpu_baseline(wl, iters_mean, budget_s=10.0):
         lu = spla.splu(assemble_strip(g, st, k2).tocsc(), permc_spec="COLAMD")
         t_fac.append(time.time() - ta)
         for _ in range(2):
-            r = rng.standard_normal(g.N_y * st.W) + 0j
+            r = rng.standard_normal(int(np.prod(g.strip_shape(st)))) + 0j
             ta = time.time()
             lu.solve(r)
             t_ss.append(time.time() - ta)
         if len(t_fac) >= 2 and time.time() - t0 > budget_s:
             break
-    u = rng.standard_normal(g.N_y * g.N_x) + 0j
+    u = rng.standard_normal(int(np.prod(g.field_shape))) + 0j
     ta = time.time()
     for _ in range(2):
         _ = u - A @ u
@@ -125,7 +135,7 @@ def cpu_baseline(wl, iters_mean, budget_s=10.0):
     t_ap = 2 * (g.J - 1) * t_ss_s + 2 * t_res
     est = t_fac_s * g.J + wl.nrhs * (iters_mean + 2.0) * t_ap
     return {
-        "value": wl.nrhs * wl.n_x * wl.n_y / est, "unit": "RHS*gridpts/s", "cores": 1,
+        "value": wl.nrhs * wl.n_points / est, "unit": "RHS*gridpts/s", "cores": 1,
         "kind": "oracle",
         "sample": (f"oracle (scipy SuperLU, single thread) pieces on {wl.name}: {len(t_fac)} of {g.J} strip "
                    f"factorisations ({t_fac_s:.2f} s each), {len(t_ss)} strip solves ({t_ss_s * 1e3:.1f} ms each), "
@@ -207,7 +217,7 @@ def c128_legs(wl, f, tol, plain_rhs=2):
                   prec="c128", mode="reduced", device="cuda:0")
     H.factor()
     torch.cuda.synchronize()
-    pts_rhs = wl.n_x * wl.n_y
+    pts_rhs = wl.n_points
     ta = time.perf_counter()
     res = H.solve(f, tol)
     torch.cuda.synchronize()
@@ -341,7 +351,7 @@ def main():
     kt = H.kernel_times()
     H.set_kernel_timing(False)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    pts = nrhs * wl.n_x * wl.n_y
+    pts = nrhs * wl.n_points
     value = pts / (ms_step / 1e3)
     solve_ms = ms_step - t_fac * 1e3 / args.steps
     dtype = "c64" if args.prec == "mixed" else "c128"
@@ -358,12 +368,13 @@ def main():
             "launches": cnt, "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl[dom]}
     if dom == "phase_a":
         roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(H, nrhs, args.prec)
+    metric = METRIC if wl.dim == 2 else "RHS*gridpts/s to 1e-6 residual, 80^3 3-D, c64-mixed, 1 GPU"
     out = {
-        "metric": METRIC, "value": value, "unit": "RHS*gridpts/s", "n_gpus": 1,
+        "metric": metric, "value": value, "unit": "RHS*gridpts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": wl.name, "n": wl.n_x, "nrhs": nrhs, "J": wl.J,
+        "config": {"workload": wl.name, "n": wl.n_x, "dim": wl.dim, "nrhs": nrhs, "J": wl.J,
                    "pml_outer": wl.w_out, "pml_iface": wl.w, "prec": args.prec,
                    "mode": args.mode, "chunk_rows": H.chunk_rows, "tol": args.tol,
                    "step": "helm_factor + helm_solve"},

@@ -216,7 +216,7 @@ helm_status ensure_sweep_ws(helm_t H, int nrhs) {
     H->ws_epoch += 1;
     const auto& g = H->g;
     const size_t fb = field_bytes(H, nrhs);
-    const size_t yw = g.dim == 3 ? (size_t)g.Ny * g.Bp * rhs_pad16(nrhs) * sizeof(double2)
+    const size_t yw = g.dim == 3 ? (size_t)(g.Ny + 2) * g.Bp * rhs_pad16(nrhs) * sizeof(double2)
                                  : (size_t)nrhs * g.Ny * WP * sizeof(double2);
     CHK(dmalloc(H, &w.Yw, yw));
     double2** fields[] = {&w.V, &w.G, &w.PF, &w.Psi, &w.Wf, &w.Hf};
@@ -258,6 +258,7 @@ helm_status strip_solve3(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
     }
     a.Ny = g.Ny; a.Nz = g.Nz; a.W = g.strips[s].W; a.B = a.W * g.Nz; a.Bp = g.Bp;
     a.nrhs = nrhs; a.RP = rhs_pad16(nrhs); a.Nrow = g.Nrow();
+    a.Tw = a.Yw + (size_t)g.Ny * g.Bp * a.RP;     // two planes after the Ny planes of Yw
     HIPCHK(helm::launch_strip_solve3<T>(a, H->st, H->kt()));
     return HELM_OK;
 }

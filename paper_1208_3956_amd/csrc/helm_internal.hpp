@@ -130,6 +130,7 @@ template <typename T>
 struct Solve3Args {
     const cplx<T>* F;     // factors of the slab: [Ny][Bp*Bp], column-major inverses G_l
     cplx<T>* Yw;          // workspace [Ny][Bp][RP]
+    cplx<T>* Tw;          // workspace 2 x [Bp][RP]: right-hand sides of the forward planes
     const double2* cy;
     const double2* by;
     IOSpec io;            // rows of src / dst are z * Ny + y; traces are [rhs][Nrow]

@@ -20,9 +20,11 @@
 // the identity.
 //
 // A solve step is one dense product per plane: G_l (Bp x Bp, column-major) times a panel
-// of right-hand sides, each workgroup a 16-row x 16-column tile, with the right-hand side
-// of the step (input field, transmission planes, previous plane) formed while it is
-// staged.
+// of right-hand sides ([k][RP], right-hand sides fastest), each workgroup a 16-row x
+// 16-column tile with its four waves splitting the k range.  Operands are read straight
+// from global memory in the MFMA lane layout.  The right-hand side of the next forward
+// plane (input field, transmission planes, minus c_{l+1} y_l) is formed by the tile that
+// computes y_l, so every element is gathered once.
 #include "helm_internal.hpp"
 
 namespace helm {
@@ -302,63 +304,145 @@ __device__ inline void scatter3(const Solve3Args<T>& a, int r, int l, int k, cpl
     if (q == io.qo1 && io.tro1) io.tro1[(size_t)r * a.Nrow + rho] = xv;
 }
 
-// One plane of the forward (FWD) or backward substitution for 16 rows x 16 right-hand
-// sides per workgroup:  FWD  y_l = G_l (r_l - c_l y_{l-1});  BWD  x_l = y_l - G_l (b_l x_{l+1}).
-// Yw holds y (then x) as [l][k][RP].
-template <typename T, bool FWD>
-__global__ void __launch_bounds__(256) k3_step(Solve3Args<T> a, int l) {
-    using V = cplx<T>;
-    constexpr int KC = 64;
-    __shared__ V Gs[KC][16];
-    __shared__ V Ts[KC][16];
-    const int t = threadIdx.x, ti = t % 16, tj = t / 16;
-    const int i0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
-    const V* G = a.F + (size_t)l * a.Bp * a.Bp;
-    const size_t plane = (size_t)a.Bp * a.RP;
-    V coupling;
-    const V* vin;
-    if (FWD) {
-        const double2 c = a.cy[l];
-        coupling = cmk<V>((decltype(V{}.x))c.x, (decltype(V{}.x))c.y);
-        vin = l > 0 ? a.Yw + (size_t)(l - 1) * plane : nullptr;
-    } else {
-        const double2 b = a.by[l];
-        coupling = cmk<V>((decltype(V{}.x))b.x, (decltype(V{}.x))b.y);
-        vin = a.Yw + (size_t)(l + 1) * plane;
-    }
-    V acc = cmk<V>(0, 0);
-    for (int k0 = 0; k0 < a.B; k0 += KC) {
-        for (int e = t; e < KC * 16; e += 256) {
-            const int kk = e / 16, ii = e % 16, k = k0 + kk;
-            Gs[kk][ii] = k < a.B ? G[(size_t)k * a.Bp + i0 + ii] : cmk<V>(0, 0);
-            const int r = r0 + ii;   // e % 16 indexes the right-hand side here
-            V tv = cmk<V>(0, 0);
-            if (k < a.B && r < a.nrhs) {
-                if (FWD) {
-                    tv = gather3<T>(a, r, l, k);
-                    if (vin) tv = csub(tv, cmul(coupling, vin[(size_t)k * a.RP + r]));
-                } else {
-                    tv = cmul(coupling, vin[(size_t)k * a.RP + r]);
-                }
-            }
-            Ts[kk][ii] = tv;
+typedef float mf4 __attribute__((ext_vector_type(4)));
+
+// Right-hand side of plane 0: Tw[i][r] = r_0(i, r), zero on the padding rows and on the
+// right-hand-side columns beyond nrhs.
+template <typename T>
+__global__ void __launch_bounds__(256) k3_rhs0(Solve3Args<T> a, cplx<T>* __restrict__ Tw) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)a.Bp * a.RP) return;
+    const int i = (int)(e / a.RP), r = (int)(e % a.RP);
+    Tw[e] = (i < a.B && r < a.nrhs) ? gather3<T>(a, r, 0, i) : cmk<cplx<T>>(0, 0);
+}
+
+// Z = G X for a 16-row x 16-column tile: G column-major Bp x Bp, X [k][RP].  The k range
+// is cut into blocks of 16; wave w of NW3 takes blocks w, w + NW3, ... (several waves per
+// SIMD hide the load latency; each wave also loads its next block before it multiplies
+// the current one).  The NW3 partial tiles are added through LDS.  Returns, for thread
+// t < 256, the entry (row t / 16, column t % 16) of the tile.
+// complex64: v_mfma_f32_16x16x4f32, four real products per complex one (lane layout
+// A[l % 16][l / 16], B[l / 16][l % 16], C[4 (l / 16) + j][l % 16] in component j).
+constexpr int NW3 = 16;
+constexpr int NT3 = 64 * NW3;
+
+__device__ inline float2 tile_product(const float2* __restrict__ G, const float2* __restrict__ X, int Bp,
+                                      int RP, int i0, int r0, float2 (*red)[16][16]) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
+    const int nblk = Bp / 16;
+    mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+    const float2* gp = G + (size_t)q4 * Bp + i0 + n;
+    const float2* xp = X + (size_t)q4 * RP + r0 + n;
+    float2 g[4], x[4], gn[4], xn[4];
+    auto load = [&](int b, float2 (&gg)[4], float2 (&xx)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            gg[u] = gp[(size_t)(16 * b + 4 * u) * Bp];
+            xx[u] = xp[(size_t)(16 * b + 4 * u) * RP];
         }
-        __syncthreads();
-#pragma unroll 8
-        for (int kk = 0; kk < KC; ++kk) cfma(acc, Gs[kk][ti], Ts[kk][tj]);
-        __syncthreads();
+    };
+    if (w < nblk) load(w, g, x);
+    for (int b = w; b < nblk; b += NW3) {
+        const int bn = b + NW3 < nblk ? b + NW3 : b;     // clamped: the last prefetch is a re-read
+        load(bn, gn, xn);
+#pragma unroll
+        for (int u = 0; u < 4; u += 2) {
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].x, x[u].x, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].x, x[u].y, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].x, x[u + 1].x, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].x, x[u + 1].y, aI1, 0, 0, 0);
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g[u].y, x[u].y, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].y, x[u].x, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g[u + 1].y, x[u + 1].y, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].y, x[u + 1].x, aI1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { g[u] = gn[u]; x[u] = xn[u]; }
     }
-    const int i = i0 + ti, r = r0 + tj;
-    if (i >= a.B || r >= a.nrhs) return;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[w][4 * q4 + j][n] = make_float2(aR0[j] + aR1[j], aI0[j] + aI1[j]);
+    __syncthreads();
+    float2 z = make_float2(0.f, 0.f);
+    if (t < 256) {
+        const int i = t >> 4, c = t & 15;
+#pragma unroll
+        for (int v = 0; v < NW3; ++v) { z.x += red[v][i][c].x; z.y += red[v][i][c].y; }
+    }
+    return z;
+}
+
+// complex128: FMA, each lane four rows (4 (l / 16) + j) of one column (l % 16)
+__device__ inline double2 tile_product(const double2* __restrict__ G, const double2* __restrict__ X, int Bp,
+                                       int RP, int i0, int r0, double2 (*red)[16][16]) {
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
+    const int nblk = Bp / 16;
+    double2 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = make_double2(0.0, 0.0);
+    const double2* gp = G + i0 + 4 * q4;
+    const double2* xp = X + r0 + n;
+    for (int b = w; b < nblk; b += NW3) {
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = 16 * b + kk;
+            const double2 xv = xp[(size_t)k * RP];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cfma(acc[j], gp[(size_t)k * Bp + j], xv);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[w][4 * q4 + j][n] = acc[j];
+    __syncthreads();
+    double2 z = make_double2(0.0, 0.0);
+    if (t < 256) {
+        const int i = t >> 4, c = t & 15;
+#pragma unroll
+        for (int v = 0; v < NW3; ++v) { z.x += red[v][i][c].x; z.y += red[v][i][c].y; }
+    }
+    return z;
+}
+
+// Forward plane l: y_l = G_l Tw_l, kept in Yw[l]; the tile's rows of the next right-hand
+// side Tn = r_{l+1} - c_{l+1} y_l are formed here (the last plane scatters x = y instead).
+template <typename T>
+__global__ void __launch_bounds__(NT3) k3_fwd(Solve3Args<T> a, int l, const cplx<T>* __restrict__ Tw,
+                                             cplx<T>* __restrict__ Tn) {
+    using V = cplx<T>;
+    __shared__ V red[NW3][16][16];
+    const int i0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
+    const V y = tile_product(a.F + (size_t)l * a.Bp * a.Bp, Tw, a.Bp, a.RP, i0, r0, red);
+    if (threadIdx.x >= 256) return;
+    const int i = i0 + (threadIdx.x >> 4), r = r0 + (threadIdx.x & 15);
+    const size_t at = (size_t)i * a.RP + r;
+    a.Yw[(size_t)l * a.Bp * a.RP + at] = y;
+    const bool live = i < a.B && r < a.nrhs;
+    if (l + 1 < a.Ny) {
+        V tn = cmk<V>(0, 0);
+        if (live) {
+            const double2 c = a.cy[l + 1];
+            tn = csub(gather3<T>(a, r, l + 1, i), cmul(ccast<V>(c), y));
+        }
+        Tn[at] = tn;
+    } else if (live) {
+        scatter3<T>(a, r, l, i, y);
+    }
+}
+
+// Backward plane l: x_l = y_l - b_l G_l x_{l+1}, kept in Yw[l] and scattered.
+template <typename T>
+__global__ void __launch_bounds__(NT3) k3_bwd(Solve3Args<T> a, int l) {
+    using V = cplx<T>;
+    __shared__ V red[NW3][16][16];
+    const int i0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
+    const size_t plane = (size_t)a.Bp * a.RP;
+    const V z = tile_product(a.F + (size_t)l * a.Bp * a.Bp, a.Yw + (size_t)(l + 1) * plane, a.Bp, a.RP,
+                             i0, r0, red);
+    if (threadIdx.x >= 256) return;
+    const int i = i0 + (threadIdx.x >> 4), r = r0 + (threadIdx.x & 15);
     V* yl = a.Yw + (size_t)l * plane + (size_t)i * a.RP + r;
-    if (FWD) {
-        *yl = acc;
-        if (l == a.Ny - 1) scatter3<T>(a, r, l, i, acc);
-    } else {
-        const V x = csub(*yl, acc);
-        *yl = x;
-        scatter3<T>(a, r, l, i, x);
-    }
+    const V x = csub(*yl, cmul(ccast<V>(a.by[l]), z));
+    *yl = x;
+    if (i < a.B && r < a.nrhs) scatter3<T>(a, r, l, i, x);
 }
 
 }  // namespace
@@ -388,9 +472,12 @@ hipError_t launch_factor3_plane(const Fac3Args& a, int l, const double2* Gprev, 
 template <typename T>
 hipError_t launch_strip_solve3(const Solve3Args<T>& a, hipStream_t st, KTimer* kt) {
     dim3 grid(a.Bp / 16, a.RP / 16);
+    cplx<T>* Tw[2] = {a.Tw, a.Tw + (size_t)a.Bp * a.RP};
     if (kt) kt->begin(K_PHASE_A, st);
-    for (int l = 0; l < a.Ny; ++l) hipLaunchKernelGGL((k3_step<T, true>), grid, dim3(256), 0, st, a, l);
-    for (int l = a.Ny - 2; l >= 0; --l) hipLaunchKernelGGL((k3_step<T, false>), grid, dim3(256), 0, st, a, l);
+    hipLaunchKernelGGL(k3_rhs0<T>, dim3((unsigned)(((size_t)a.Bp * a.RP + 255) / 256)), dim3(256), 0, st, a, Tw[0]);
+    for (int l = 0; l < a.Ny; ++l)
+        hipLaunchKernelGGL(k3_fwd<T>, grid, dim3(NT3), 0, st, a, l, Tw[l & 1], Tw[(l + 1) & 1]);
+    for (int l = a.Ny - 2; l >= 0; --l) hipLaunchKernelGGL(k3_bwd<T>, grid, dim3(NT3), 0, st, a, l);
     if (kt) kt->end(K_PHASE_A, st);
     return hipGetLastError();
 }
