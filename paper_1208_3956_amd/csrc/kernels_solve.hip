@@ -19,6 +19,8 @@
 // Arithmetic is in T (float or double complex); gathered and scattered fields are FP64.
 #include "helm_internal.hpp"
 
+#include <type_traits>
+
 namespace helm {
 
 namespace {
@@ -393,18 +395,27 @@ __global__ void __launch_bounds__(NT) k_phase_b0(SolveArgs<T> a) {
 // and combined through LDS.  Forward z'_0 = a_0, z'_c = a_c - K_c z'_{c-1}; backward
 // x_{P-2} = z'_{P-2}, x_c = z'_c - U'_c x_{c+1}.  The blocks of the next D steps are in
 // flight in registers while a step runs (ring of D+1 LDS buffers).
-template <typename T, int D>
+constexpr int ZMAX = 64;   // separators whose z' the chain keeps in LDS
+
+// Thread (i, w) owns row i of the matvec and the 16 columns 16w..16w+15 of every block:
+// the blocks of the next D steps are loaded straight into registers in that layout (no
+// LDS staging), so a step is 16 multiply-adds from registers, one partial-sum exchange
+// and two barriers.  ZB: the forward results z'_c stay in LDS (zb) for the backward pass
+// and the forward inputs a_c are loaded D steps ahead into a register ring (requires
+// P - 1 <= ZMAX); otherwise the next input is loaded one step ahead from global memory.
+template <typename T, int D, bool ZB>
 __global__ void __launch_bounds__(NT) k_phase_b(SolveArgs<T> a) {
     using V = cplx<T>;
-    __shared__ V Gs[D + 1][BLK];
     __shared__ V vec[WP];
     __shared__ V part[4][WP];
+    __shared__ V zb[ZB ? ZMAX + 1 : 1][WP];     // row ZMAX: discard row for backward steps
     const int t = threadIdx.x, i = t & (WP - 1), w = t >> 6;
     const int r = blockIdx.x;
     const int ns = a.P - 1;                  // separators
     const int nf = ns - 1;                   // forward steps (c = 1..ns-1)
     const int steps = nf + (ns - 1);         // + backward steps (c = ns-2..0)
     if (steps <= 0) return;
+    const int k0 = w * 16;
     auto sep = [&](int c) { return c * a.m + a.m - 1; };
     // separator row and factor block of step k (clamped to the last step: loads past the
     // end re-read the last block and are never used)
@@ -416,43 +427,67 @@ __global__ void __launch_bounds__(NT) k_phase_b(SolveArgs<T> a) {
         k = k < steps ? k : steps - 1;
         return k < nf ? fslot(a, sep(k + 1), 1) : fslot(a, sep(ns - 2 - (k - nf)), 2);
     };
+    auto load_blk = [&](int k, V (&b)[16]) {
+        const V* g = blk(k) + (size_t)k0 * WP + i;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) b[kk] = g[kk * WP];
+    };
+    // forward input of step k: a_{k+1} (clamped to the last forward step)
+    auto fwd_in = [&](int k) { return sep((k < nf ? k : nf - 1) + 1); };
     V* Yr = a.Yw + (size_t)r * a.Ny * WP;
     // every thread keeps the value of its row i; the four waves hold identical copies
-    vec[i] = Yr[(size_t)sep(0) * WP + i];    // z'_0 = a_0
-    V nextv = Yr[(size_t)sep_of(0) * WP + i];
-    BlockPipe<T> pipe[D];
+    const V a0 = Yr[(size_t)sep(0) * WP + i];    // z'_0 = a_0
+    vec[i] = a0;
+    V nextv = cmk<V>(0, 0);
+    V av[D];
+    if (ZB) {
+        zb[0][i] = a0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) pipe[d].load(blk(d));
-    pipe[0].store(Gs[0]);
-    pipe[0].load(blk(D));
+        for (int d = 0; d < D; ++d) av[d] = Yr[(size_t)fwd_in(d) * WP + i];
+    } else {
+        nextv = Yr[(size_t)sep_of(0) * WP + i];
+    }
+    V breg[D][16];
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_blk(d, breg[d]);
     __syncthreads();
-    const int k0 = w * 16;
-    auto step = [&](int k, BlockPipe<T>& nxt) {
+    auto step = [&](int k, int j) {
         const int s = sep_of(k);
-        const V curv = nextv;                           // a_c (forward) or z'_c (backward)
-        nextv = Yr[(size_t)sep_of(k + 1) * WP + i];
-        V acc = cmk<V>(0, 0);
-        const V* M = Gs[k % (D + 1)] + k0 * WP + i;
+        const bool fwd = k < nf;
+        V curv;                                  // a_c (forward) or z'_c (backward)
+        if (ZB) {
+            const int cb = fwd ? ZMAX : ns - 2 - (k - nf);
+            const V zr = zb[cb][i];
+            curv = fwd ? av[j] : zr;
+            av[j] = Yr[(size_t)fwd_in(k + D) * WP + i];
+        } else {
+            curv = nextv;
+            nextv = Yr[(size_t)sep_of(k + 1) * WP + i];
+        }
+        V acc0 = cmk<V>(0, 0), acc1 = acc0;
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) cfma(acc, M[kk * WP], vec[k0 + kk]);
-        part[w][i] = acc;
+        for (int kk = 0; kk < 16; kk += 2) {
+            cfma(acc0, breg[j][kk], vec[k0 + kk]);
+            cfma(acc1, breg[j][kk + 1], vec[k0 + kk + 1]);
+        }
+        part[w][i] = cadd(acc0, acc1);
+        load_blk(k + D, breg[j]);               // block of step k + D into the freed slot
         __syncthreads();
         const V sum = cadd(cadd(part[0][i], part[1][i]), cadd(part[2][i], part[3][i]));
         const V v = csub(curv, sum);            // a_c - K_c z'  or  z'_c - U'_c x
         Yr[(size_t)s * WP + i] = v;
         vec[i] = v;
-        nxt.store(Gs[(k + 1) % (D + 1)]);       // block k+1, in flight since step k+1-D
-        nxt.load(blk(k + 1 + D));
+        if (ZB) zb[fwd ? k + 1 : ZMAX][i] = v;
         __syncthreads();
     };
     int k = 0;
     for (; k + D <= steps; k += D) {
 #pragma unroll
-        for (int j = 0; j < D; ++j) step(k + j, pipe[(j + 1) % D]);
+        for (int j = 0; j < D; ++j) step(k + j, j);
     }
 #pragma unroll
     for (int j = 0; j < D; ++j)
-        if (k + j < steps) step(k + j, pipe[(j + 1) % D]);
+        if (k + j < steps) step(k + j, j);
 }
 
 // ---------------------------------------------------------------- phase C (all columns)
@@ -556,8 +591,8 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets(SolveArgs<T> a) {
     }
 }
 
-template <typename T> struct Depth { static constexpr int D = 1; };
-template <> struct Depth<float> { static constexpr int D = 3; };
+template <typename T> struct Depth { static constexpr int D = 2; };
+template <> struct Depth<float> { static constexpr int D = 4; };
 
 template <typename T, int R>
 void launch_phase_a(const SolveArgs<T>& a, int RG, hipStream_t st) {
@@ -577,8 +612,12 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
     if (a.P > 1) {
         if (kt) kt->begin(K_PHASE_B, st);
         hipLaunchKernelGGL((k_phase_b0<T, R>), dim3(a.P - 1, RG), dim3(NT), 0, st, a);
-        if (a.P > 2)
-            hipLaunchKernelGGL((k_phase_b<T, Depth<T>::D>), dim3(a.nrhs), dim3(NT), 0, st, a);
+        if (a.P > 2) {
+            if (a.P - 1 <= ZMAX)
+                hipLaunchKernelGGL((k_phase_b<T, Depth<T>::D, true>), dim3(a.nrhs), dim3(NT), 0, st, a);
+            else
+                hipLaunchKernelGGL((k_phase_b<T, Depth<T>::D, false>), dim3(a.nrhs), dim3(NT), 0, st, a);
+        }
         if (kt) kt->end(K_PHASE_B, st);
     }
     if (kt) kt->begin(K_PHASE_C, st);
