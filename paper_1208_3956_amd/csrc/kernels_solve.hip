@@ -215,52 +215,67 @@ __global__ void __launch_bounds__(NT) k_phase_a(SolveArgs<T> a) {
 // C[4 (l / 16) + j][l % 16] in component j.
 typedef float mf4 __attribute__((ext_vector_type(4)));
 
+// The blocks G_l are not staged through LDS: each lane loads exactly its MFMA A operands
+// (16 values per block, A[16w + n][4s + q4] for k-step s) straight from global memory into
+// a ring of D register blocks, D steps ahead.  Only the right-hand-side panel of a step
+// (64 x 16) goes through LDS, double-buffered, so a step has a single barrier.  Each lane
+// gathers the right-hand-side values of its own four output positions.
+template <int D>
 __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
     using V = float2;
     constexpr int R = 16;
-    __shared__ V Gs[2][BLK];
-    __shared__ V Vs[WP][R];
-    __shared__ V Rs[WP][R];
-    __shared__ unsigned char tmask[WP];
+    __shared__ V Vs[2][WP][R];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int n = lane & 15, q4 = lane >> 4;            // MFMA column (rhs), row quad
-    const int gi = t & (WP - 1), gr = t >> 6;            // gather: row gi, rhs gr + 4u
     const int c = blockIdx.x, rbase = blockIdx.y * R;
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
     const int nr = r1 - r0;
+    const int nsteps = 2 * nr - 1;                       // forward nr rows, backward nr - 1
     const V zero = make_float2(0.f, 0.f);
     const int rn = rbase + n;                            // rhs of this lane's MFMA column
     const bool rn_ok = rn < a.nrhs;
-    const size_t ybase = (size_t)(rn_ok ? rn : 0) * a.Ny * WP + 16 * w + 4 * q4;
+    const int qrow = 16 * w + 4 * q4;                    // first of this lane's 4 output rows
+    const size_t ybase = (size_t)(rn_ok ? rn : 0) * a.Ny * WP + qrow;
     // targets-only solves read y at the compact target columns (phase C) and on the first
     // and last interior row (the separators' right-hand sides); full solves read it all
-    if (t < WP) {
+    bool tm[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
         bool on = false;
-        for (int k = 0; k < 8; ++k) on = on || (a.tcol[k] == t);
-        tmask[t] = on ? 1 : 0;
+        for (int k = 0; k < 8; ++k) on = on || (a.tcol[k] == qrow + j);
+        tm[j] = on;
     }
-    V z[4];
+    auto row_of = [&](int k) {
+        k = k < nsteps ? k : nsteps - 1;
+        return k < nr ? r0 + k : r1 - 2 - (k - nr);
+    };
+    auto load_g = [&](int k, V (&g)[16]) {
+        const V* G = fslot(a, row_of(k), 0) + 16 * w + n;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) z[j] = zero;
+        for (int s4 = 0; s4 < 16; ++s4) g[s4] = G[(4 * s4 + q4) * WP];
+    };
     RawRhs raw[4];
-    auto load_rows = [&](int l) {
+    auto load_rhs = [&](int l) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) raw[u] = load_raw(a.io, rbase + gr + 4 * u, l, gi, a.Ny, a.nrhs, a.W);
+        for (int j = 0; j < 4; ++j) raw[j] = load_raw(a.io, rn, l, qrow + j, a.Ny, a.nrhs, a.W);
     };
-    auto store_rows = [&]() {
+    V greg[D][16];
+    V z[4], zn[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) Rs[gi][gr + 4 * u] = combine<float>(a.io, raw[u]);
-    };
-    BlockPipe<float> pipe;
-    auto mfma_block = [&](const V* Gb, V (&out)[4]) {
+    for (int j = 0; j < 4; ++j) { z[j] = zero; zn[j] = zero; }
+    double2 cnext = a.cy[r0], bnext = a.by[r0];
+    load_rhs(r0);
+#pragma unroll
+    for (int d = 0; d < D; ++d) load_g(d, greg[d]);
+
+    auto mfma_block = [&](const V (&g)[16], const V (*Vb)[R], V (&out)[4]) {
         mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
 #pragma unroll
-        for (int k0 = 0; k0 < WP; k0 += 8) {
-            const V g0 = Gb[(k0 + q4) * WP + 16 * w + n];
-            const V v0 = Vs[k0 + q4][n];
-            const V g1 = Gb[(k0 + 4 + q4) * WP + 16 * w + n];
-            const V v1 = Vs[k0 + 4 + q4][n];
+        for (int s4 = 0; s4 < 16; s4 += 2) {
+            const V g0 = g[s4], g1 = g[s4 + 1];
+            const V v0 = Vb[4 * s4 + q4][n];
+            const V v1 = Vb[4 * s4 + 4 + q4][n];
             aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
             aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
             aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
@@ -274,85 +289,91 @@ __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
         for (int j = 0; j < 4; ++j) out[j] = make_float2(aR0[j] + aR1[j], aI0[j] + aI1[j]);
     };
 
-    // prologue: block and right-hand side of row r0
-    load_rows(r0);
-    pipe.load(fslot(a, r0, 0));
-    store_rows();
-    pipe.store(Gs[0]);
-    __syncthreads();
-    int cur = 0;
-
-    // ---- forward:  z_l = G_l (r_l - c_l z_{l-1})
-    // (vmcnt retires loads in issue order: every value used inside a step is loaded one
-    // step earlier and issued before the large prefetches)
-    double2 cnext = a.cy[r0];
-    for (int l = r0; l < r1; ++l) {
-        const V cl = ccast<V>(cnext);
-        // next step's loads, all issued here: coupling, right-hand side of row l+1, then
-        // its block (the last forward step prefetches the block of the first backward row)
-        const int ln = l + 1 < r1 ? l + 1 : l;
-        const int lb = l + 1 < r1 ? l + 1 : (r1 - 2 >= r0 ? r1 - 2 : l);
-        cnext = a.cy[ln];
-        load_rows(ln);
-        pipe.load(fslot(a, lb, 0));
-        const bool first = l == r0;
+    // component-wise select (a select of whole float2 values goes through scratch memory)
+    auto keep = [](bool on, V x) { return make_float2(on ? x.x : 0.f, on ? x.y : 0.f); };
+    // ---- forward row l = r0 + k:  z_l = G_l (r_l - c_l z_{l-1})
+    auto fwd_step = [&](int k, int j) {
+        const int buf = k & 1;
+        const int l = r0 + k;
+        // the first row of a chunk has no coupling inside phase A (scalar selects: no
+        // aggregate select that would go through memory)
+        const float clx = k > 0 ? (float)cnext.x : 0.f, cly = k > 0 ? (float)cnext.y : 0.f;
+        const V cl = make_float2(clx, cly);
+        V v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int i = 16 * w + 4 * q4 + j;
-            V v = Rs[i][n];
-            if (!first) v = csub(v, cmul(cl, z[j]));
-            Vs[i][n] = v;
-        }
+        for (int u = 0; u < 4; ++u) v[u] = csub(combine<float>(a.io, raw[u]), cmul(cl, z[u]));
+        // next step's small loads first (vmcnt retires in issue order); clamped, branch-free
+        const int ln = l + 1 < r1 ? l + 1 : l;
+        cnext = a.cy[ln];
+        load_rhs(ln);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Vs[buf][qrow + u][n] = v[u];
         __syncthreads();
         V acc[4];
-        mfma_block(Gs[cur], acc);
+        mfma_block(greg[j], Vs[buf], acc);
+        load_g(k + D, greg[j]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            z[j] = rn_ok ? acc[j] : zero;
-            if (rn_ok) a.Yw[ybase + (size_t)l * WP + j] = acc[j];
+        for (int u = 0; u < 4; ++u) {
+            z[u] = keep(rn_ok, acc[u]);
+            if (rn_ok) a.Yw[ybase + (size_t)l * WP + u] = acc[u];
         }
-        __syncthreads();            // everyone is done with Rs and Gs[cur ^ 1]
-        store_rows();
-        pipe.store(Gs[cur ^ 1]);
-        __syncthreads();
-        cur ^= 1;
-    }
-    // ---- backward:  y_l = z_l - b_l G_l y_{l+1},  l = r1-2 .. r0
-    V zn[4];
-    double2 bnext = a.by[r1 - 2 >= r0 ? r1 - 2 : r0];
-    if (r1 - 2 >= r0) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) zn[j] = rn_ok ? a.Yw[ybase + (size_t)(r1 - 2) * WP + j] : zero;
-    }
-    for (int l = r1 - 2; l >= r0; --l) {
+    };
+    // ---- backward row l = r1 - 2 - (k - nr):  y_l = z_l - b_l G_l y_{l+1}
+    auto bwd_step = [&](int k, int j) {
+        const int buf = k & 1;
+        const int l = r1 - 2 - (k - nr);
         V zl[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) zl[j] = zn[j];
+        for (int u = 0; u < 4; ++u) zl[u] = zn[u];
         const V bl = ccast<V>(bnext);
         const int lb = l - 1 >= r0 ? l - 1 : l;
-        // next step's loads: coupling and z of row l-1 (stored by the forward pass), then
-        // its block
         bnext = a.by[lb];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) zn[j] = rn_ok ? a.Yw[ybase + (size_t)lb * WP + j] : zero;
-        pipe.load(fslot(a, lb, 0));
+        for (int u = 0; u < 4; ++u) zn[u] = a.Yw[ybase + (size_t)lb * WP + u];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) Vs[16 * w + 4 * q4 + j][n] = z[j];
+        for (int u = 0; u < 4; ++u) Vs[buf][qrow + u][n] = z[u];
         __syncthreads();
         V acc[4];
-        mfma_block(Gs[cur], acc);
-        const bool store_y = !a.io.targets_only || l == r0 || l == r1 - 1;
+        mfma_block(greg[j], Vs[buf], acc);
+        load_g(k + D, greg[j]);
+        const bool store_y = !a.io.targets_only || l == r0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const V y = csub(zl[j], cmul(bl, acc[j]));
-            z[j] = rn_ok ? y : zero;
-            if (rn_ok && (store_y || tmask[16 * w + 4 * q4 + j])) a.Yw[ybase + (size_t)l * WP + j] = y;
+        for (int u = 0; u < 4; ++u) {
+            const V y = csub(zl[u], cmul(bl, acc[u]));
+            z[u] = keep(rn_ok, y);
+            if (rn_ok && (store_y || tm[u])) a.Yw[ybase + (size_t)l * WP + u] = y;
         }
-        __syncthreads();
-        pipe.store(Gs[cur ^ 1]);
-        __syncthreads();
-        cur ^= 1;
+    };
+    int k = 0;
+    for (; k + D <= nr; k += D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) fwd_step(k + j, j);
     }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (k + j < nr) fwd_step(k + j, j);
+    if (nr < 2) return;
+    // z_{r1-2} and b_{r1-2} of the first backward row (ybase is valid for every lane: lanes
+    // beyond nrhs read rows of right-hand side 0 and discard them)
+    bnext = a.by[r1 - 2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) zn[u] = a.Yw[ybase + (size_t)(r1 - 2) * WP + u];
+    // backward steps k = nr .. 2 nr - 2 use ring slot k % D: the loop is unrolled for the
+    // slot of its first step
+    auto bwd_loop = [&](auto off_tag) {
+        constexpr int OFF = decltype(off_tag)::value;
+        int kb = nr;
+        for (; kb + D <= nsteps; kb += D) {
+#pragma unroll
+            for (int j = 0; j < D; ++j) bwd_step(kb + j, (j + OFF) % D);
+        }
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if (kb + j < nsteps) bwd_step(kb + j, (j + OFF) % D);
+    };
+    static_assert(D == 2, "the backward ring alignment below is written for D = 2");
+    if (nr % 2 == 0) bwd_loop(std::integral_constant<int, 0>{});
+    else bwd_loop(std::integral_constant<int, 1>{});
 }
 
 // ---------------------------------------------------------------- phase B0
@@ -600,7 +621,7 @@ void launch_phase_a(const SolveArgs<T>& a, int RG, hipStream_t st) {
 }
 template <>
 void launch_phase_a<float, 16>(const SolveArgs<float>& a, int RG, hipStream_t st) {
-    hipLaunchKernelGGL(k_phase_a_mfma, dim3(a.P, RG), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_phase_a_mfma<2>, dim3(a.P, RG), dim3(NT), 0, st, a);
 }
 
 template <typename T, int R>
