@@ -97,6 +97,7 @@ struct helm_problem {
     std::string err;
     void* F = nullptr;          // factors: double2 (C128) or float2 (MIXED)
     void* Fc = nullptr;         // compact spike rows at the target columns, same precision
+    void* Fs = nullptr;         // separator propagators of the two-level separator solve
     bool factored = false;
     int* d_err = nullptr;
     Work wk;
@@ -272,8 +273,9 @@ helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
     if (H->g.dim == 3) return strip_solve3<T>(H, s, nrhs, io);
     const auto* F = static_cast<const helm::cplx<T>*>(H->F);
     const auto* Fc = static_cast<const helm::cplx<T>*>(H->Fc);
+    const auto* Fs = static_cast<const helm::cplx<T>*>(H->Fs);
     auto* Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
-    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Fc, Yw, nrhs, io, H->st, H->kt()));
+    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Fc, Fs, Yw, nrhs, io, H->st, H->kt()));
     return HELM_OK;
 }
 
@@ -839,6 +841,12 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     H->ch.m = m;
     H->ch.P = (g.Ny + m - 1) / m;
     if (H->ch.P > 1 && (H->ch.P - 1) * m >= g.Ny) H->ch.P -= 1;
+    {
+        // separator groups for the two-level separator solve: q ~ sqrt(#separators)
+        const int ns = H->ch.P - 1;
+        H->ch.q = std::max(2, (int)std::ceil(std::sqrt((double)std::max(ns, 1))));
+        H->ch.G = ns >= 4 ? (ns + H->ch.q - 1) / H->ch.q : 1;
+    }
     H->prec = opts->prec == HELM_MIXED_C64 ? HELM_MIXED_C64 : HELM_C128;
     H->mode = opts->mode == HELM_REDUCED ? HELM_REDUCED : HELM_FULL;
     H->max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
@@ -1003,6 +1011,8 @@ helm_status helm_factor(helm_t H) {
     H->factored = false;
     dfree(H->Fc);
     H->Fc = nullptr;
+    dfree(H->Fs);
+    H->Fs = nullptr;
     if (g.dim == 3) return factor3(H);
     const size_t nel = (size_t)g.J * g.Ny * NSLOT * BLK;
     double2* F64 = nullptr;
@@ -1011,11 +1021,20 @@ helm_status helm_factor(helm_t H) {
     HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
     HIPCHK(TIMED(H, helm::K_FACTOR_CHUNKS, helm::launch_factor_chunks(H->t, g, H->ch, F64, H->d_err, H->st)));
     HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_separators(H->t, g, H->ch, F64, H->d_err, H->st)));
+    // propagators of the two-level separator solve (FP64, converted with the factor)
+    double2* Fs64 = nullptr;
+    const size_t nsel = H->ch.G >= 2 ? (size_t)g.J * (H->ch.P - 1) * 2 * BLK : 0;
+    if (nsel) {
+        helm_status s2 = dmalloc(H, &Fs64, nsel * sizeof(double2));
+        if (s2 != HELM_OK) { dfree(F64); return s2; }
+        HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_propagators(H->t, g, H->ch, F64, Fs64, H->st)));
+    }
     dfree(H->Fc);
     H->Fc = nullptr;
     const size_t ncomp = (size_t)g.J * g.Ny * 2 * 8 * WP;
     if (H->prec == HELM_C128) {
         H->F = F64;
+        H->Fs = Fs64;
         double2* Fc = nullptr;
         CHK(dmalloc(H, &Fc, ncomp * sizeof(double2)));
         H->Fc = Fc;
@@ -1025,8 +1044,16 @@ helm_status helm_factor(helm_t H) {
         helm_status s = dmalloc(H, &F32, nel * sizeof(float2));
         if (s != HELM_OK) { dfree(F64); return s; }
         HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_convert_factor(F64, F32, nel, H->st)));
+        if (nsel) {
+            float2* Fs32 = nullptr;
+            helm_status s3 = dmalloc(H, &Fs32, nsel * sizeof(float2));
+            if (s3 != HELM_OK) { dfree(F64); dfree(Fs64); dfree(F32); return s3; }
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_convert_factor(Fs64, Fs32, nsel, H->st)));
+            H->Fs = Fs32;
+        }
         HIPCHK(hipStreamSynchronize(H->st));
         dfree(F64);
+        dfree(Fs64);
         H->F = F32;
         float2* Fc = nullptr;
         CHK(dmalloc(H, &Fc, ncomp * sizeof(float2)));
@@ -1292,6 +1319,7 @@ void helm_destroy(helm_t H) {
     delete H->timer;
     dfree(H->F);
     dfree(H->Fc);
+    dfree(H->Fs);
     dfree(H->d_err);
     for (void* p : H->owned) dfree(p);
     delete H;

@@ -70,6 +70,11 @@ struct Geom {
 // y-partition of every strip into chunks of m rows whose last row is a separator
 struct Chunks {
     int m = 0, P = 0;            // rows per chunk, number of chunks
+    // the P-1 separators form groups of q consecutive ones (G groups, the last ragged) for
+    // the two-level separator solve; G < 2 means one chain
+    int q = 0, G = 0;
+    int gfirst(int g) const { return g * q; }
+    int glast(int g) const { return (g * q + q < P - 1 ? g * q + q : P - 1) - 1; }
     int first(int c) const { return c * m; }
     int end(int c, int Ny) const { return c < P - 1 ? c * m + m - 1 : Ny; }   // interior end
     int sep(int c) const { return c * m + m - 1; }                              // c < P-1
@@ -153,6 +158,11 @@ hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks&
 hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chunks& ch,
                                     double2* F64, int* err, hipStream_t st);
 hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipStream_t st);
+// propagators of the two-level separator solve, Fs[s][c][2][BLK] (FP64): forward
+// Phi_c = -K_c Phi_{c-1} from the first separator of each group on (groups 1..G-1), backward
+// Psi_c = -U'_c Psi_{c+1} from the last one down (groups 0..G-2)
+hipError_t launch_factor_propagators(const DevTables& t, const Geom& g, const Chunks& ch,
+                                     const double2* F64, double2* Fs, hipStream_t st);
 // copies of the spike rows at the 8 target columns tcol[s*8 + t] (-1 = unused) of each strip
 template <typename V>
 hipError_t launch_extract_targets(const V* F, V* Fc, const int* tcol, const Geom& g,
@@ -160,8 +170,8 @@ hipError_t launch_extract_targets(const V* F, V* Fc, const int* tcol, const Geom
 
 template <typename T>
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
-                              const cplx<T>* F, const cplx<T>* Fc, cplx<T>* Yw, int nrhs,
-                              const IOSpec& io, hipStream_t st, KTimer* kt = nullptr);
+                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
+                              int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt = nullptr);
 
 hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
                           const double2* f, double2* out, hipStream_t st);

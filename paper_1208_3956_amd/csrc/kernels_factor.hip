@@ -322,6 +322,40 @@ __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
     }
 }
 
+// Propagators of the two-level separator solve (grid: strips x groups x direction).
+// Forward (group g >= 1, separators c0..c1): Phi_{c0} = -K_{c0}, Phi_c = -K_c Phi_{c-1}, so
+// that z'_c = zeta_c + Phi_c z'_{c0-1} with zeta the group's own recurrence started from 0.
+// Backward (group g <= G-2): Psi_{c1} = -U'_{c1}, Psi_c = -U'_c Psi_{c+1}, so that
+// x_c = xi_c + Psi_c x_{c1+1}.
+__global__ void __launch_bounds__(NT) k_factor_propagators(FactorArgs a, int q, int G, double2* __restrict__ Fs) {
+    __shared__ double2 Am[WP * LDM];
+    __shared__ double2 Bm[WP * LDM];
+    const int s = blockIdx.x, g = blockIdx.y, dir = blockIdx.z;
+    const int ns = a.P - 1;
+    const int c0 = g * q, c1 = min(c0 + q, ns) - 1;
+    if (dir == 0 && g == 0) return;
+    if (dir == 1 && g == G - 1) return;
+    const double2 one = cmk<double2>(1.0, 0.0), mone = cmk<double2>(-1.0, 0.0);
+    auto sep = [&](int c) { return c * a.m + a.m - 1; };
+    auto out = [&](int c) { return Fs + (((size_t)s * ns + c) * 2 + dir) * BLK; };
+    const int first = dir == 0 ? c0 : c1;
+    const int step = dir == 0 ? 1 : -1;
+    const int sl = dir == 0 ? 1 : 2;                 // K_c in slot 1, U'_c in slot 2
+    load_blk(Am, slot(a, s, sep(first), sl));
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < WP * LDM; idx += NT) Am[idx] = cmul(Am[idx], mone);
+    __syncthreads();
+    store_blk(out(first), Am, one);
+    double2* cur = Am;
+    double2* nxt = Bm;
+    for (int c = first + step; c >= c0 && c <= c1; c += step) {
+        gemm64(nxt, LDM, slot(a, s, sep(c), sl), WP, cur, LDM, mone, nullptr, 0);
+        store_blk(out(c), nxt, one);
+        __syncthreads();
+        double2* tmp = cur; cur = nxt; nxt = tmp;
+    }
+}
+
 // Fc[((s*Ny + l)*2 + side)*8*WP + t*WP + k] = (side ? Y~ : X~)_l(tcol[s*8+t], k), interior rows
 template <typename V>
 __global__ void k_extract_targets(const V* __restrict__ F, V* __restrict__ Fc,
@@ -367,6 +401,14 @@ hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chu
     if (ch.P < 2) return hipSuccess;
     FactorArgs a = make_args(t, g, ch, F64, err);
     hipLaunchKernelGGL(k_factor_separators, dim3(g.J), dim3(NT), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_propagators(const DevTables& t, const Geom& g, const Chunks& ch,
+                                     const double2* F64, double2* Fs, hipStream_t st) {
+    if (ch.G < 2) return hipSuccess;
+    FactorArgs a = make_args(t, g, ch, const_cast<double2*>(F64), nullptr);
+    hipLaunchKernelGGL(k_factor_propagators, dim3(g.J, ch.G, 2), dim3(NT), 0, st, a, ch.q, ch.G, Fs);
     return hipGetLastError();
 }
 

@@ -32,11 +32,13 @@ struct SolveArgs {
     const cplx<T>* F;     // factors of the strip: [Ny][NSLOT][WP*WP]
     const cplx<T>* Fc;    // compact spike rows of the strip: [Ny][2][8][WP] (reduced phase C)
     const int* tcol;      // 8 strip-local columns of the compact rows (-1 = unused)
+    const cplx<T>* Fs;    // separator propagators of the strip: [P-1][2][WP*WP] (two-level solve)
     cplx<T>* Yw;          // workspace [nrhs][Ny][WP]
     const double2* cy;
     const double2* by;
     IOSpec io;
     int Ny, W, m, P, nrhs;
+    int q, G;             // separator groups (two-level separator solve when G >= 2)
 };
 
 template <typename T>
@@ -511,6 +513,141 @@ __global__ void __launch_bounds__(NT) k_phase_b(SolveArgs<T> a) {
         if (k + j < steps) step(k + j, j);
 }
 
+// ---------------------------------------------------------------- phase B, two levels
+// The separator recurrences are cut into G groups of q separators.  With zeta / xi the
+// recurrences of a group started from zero and the propagators Phi / Psi of the factor,
+//   forward   z'_c = zeta_c + Phi_c z'_{first-1},   backward  x_c = xi_c + Psi_c x_{last+1},
+// so the solve is: local forward chains (all groups in parallel), a chain over the groups'
+// last separators, fix-up + local backward chains (parallel), a chain over the groups'
+// first separators, fix-up (parallel): about 2q + 2G dependent steps instead of 2(P-1).
+//
+// sep_chain: thread (i, w) owns row i and the 16 columns 16w..16w+15 of every block; wave
+// w keeps its own copy of the vector (its 16 entries are produced by its own lanes), so a
+// step needs one barrier (for the 4-wave partial sums).  Step k:
+//   v_k = in_k + sgn (M_k vec),  out_k = v_k,  vec = v_k if chain (else vec stays v0).
+// Blocks and inputs of the next D steps are in flight in registers.
+template <typename T, int D, typename BF, typename RF>
+__device__ void sep_chain(int n, bool chain, cplx<T> v0, T sgn, BF blk, RF row,
+                          cplx<T> (*vecw)[WP], cplx<T> (*part)[4][WP]) {
+    using V = cplx<T>;
+    if (n <= 0) return;
+    const int t = threadIdx.x, i = t & (WP - 1), w = t >> 6, k0 = 16 * w;
+    vecw[w][i] = v0;
+    __builtin_amdgcn_wave_barrier();   // the wave's own lanes produced the entries it reads
+    V breg[D][16], ireg[D];
+    auto load = [&](int k, V (&b)[16], V& x) {
+        const int kc = k < n ? k : n - 1;
+        const V* M = blk(kc) + (size_t)k0 * WP + i;
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) b[kk] = M[kk * WP];
+        x = row(kc)[i];
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) load(d, breg[d], ireg[d]);
+    auto step = [&](int k, int j) {
+        V acc0 = cmk<V>(0, 0), acc1 = acc0;
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 2) {
+            cfma(acc0, breg[j][kk], vecw[w][k0 + kk]);
+            cfma(acc1, breg[j][kk + 1], vecw[w][k0 + kk + 1]);
+        }
+        const V xin = ireg[j];
+        V* dst = row(k);
+        load(k + D, breg[j], ireg[j]);
+        part[k & 1][w][i] = cadd(acc0, acc1);
+        __syncthreads();
+        const V sum = cadd(cadd(part[k & 1][0][i], part[k & 1][1][i]), cadd(part[k & 1][2][i], part[k & 1][3][i]));
+        const V v = cmk<V>(xin.x + sgn * sum.x, xin.y + sgn * sum.y);
+        dst[i] = v;
+        if (chain) vecw[w][i] = v;
+        __builtin_amdgcn_wave_barrier();
+    };
+    int k = 0;
+    for (; k + D <= n; k += D) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) step(k + j, j);
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (k + j < n) step(k + j, j);
+    __syncthreads();
+}
+
+template <typename T>
+struct SepCtx {
+    const SolveArgs<T>& a;
+    int ns;
+    __device__ int sep(int c) const { return c * a.m + a.m - 1; }
+    __device__ int first(int g) const { return g * a.q; }
+    __device__ int last(int g) const { return min(g * a.q + a.q, ns) - 1; }
+    __device__ const cplx<T>* prop(int c, int dir) const { return a.Fs + ((size_t)c * 2 + dir) * BLK; }
+    __device__ cplx<T>* yrow(cplx<T>* Yr, int c) const { return Yr + (size_t)sep(c) * WP; }
+};
+
+#define SEPK_PROLOGUE                                                     \
+    using V = cplx<T>;                                                    \
+    __shared__ V vecw[4][WP];                                             \
+    __shared__ V part[2][4][WP];                                          \
+    const int i = threadIdx.x & (WP - 1);                                 \
+    const int r = blockIdx.x;                                             \
+    SepCtx<T> X{a, a.P - 1};                                              \
+    V* Yr = a.Yw + (size_t)r * a.Ny * WP;                                 \
+    (void)i;
+
+// local forward chains: zeta_c = a_c - K_c zeta_{c-1} inside group g = blockIdx.y
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) {
+    SEPK_PROLOGUE
+    const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
+    sep_chain<T, D>(c1 - c0, true, X.yrow(Yr, c0)[i], T(-1),
+                    [&](int k) { return fslot(a, X.sep(c0 + 1 + k), 1); },
+                    [&](int k) { return X.yrow(Yr, c0 + 1 + k); }, vecw, part);
+}
+
+// chain over the groups' last separators: z'_{last g} = zeta_{last g} + Phi_{last g} z'_{last g-1}
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fwd_top(SolveArgs<T> a) {
+    SEPK_PROLOGUE
+    sep_chain<T, D>(a.G - 1, true, X.yrow(Yr, X.last(0))[i], T(1),
+                    [&](int k) { return X.prop(X.last(k + 1), 0); },
+                    [&](int k) { return X.yrow(Yr, X.last(k + 1)); }, vecw, part);
+}
+
+// fix-up of the group's other separators, then its local backward chain
+// xi_c = z'_c - U'_c xi_{c+1} (the group's last separator starts it)
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) {
+    SEPK_PROLOGUE
+    const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
+    if (g >= 1)
+        sep_chain<T, D>(c1 - c0, false, X.yrow(Yr, X.last(g - 1))[i], T(1),
+                        [&](int k) { return X.prop(c0 + k, 0); },
+                        [&](int k) { return X.yrow(Yr, c0 + k); }, vecw, part);
+    sep_chain<T, D>(c1 - c0, true, X.yrow(Yr, c1)[i], T(-1),
+                    [&](int k) { return fslot(a, X.sep(c1 - 1 - k), 2); },
+                    [&](int k) { return X.yrow(Yr, c1 - 1 - k); }, vecw, part);
+}
+
+// chain over the groups' first separators: x_{first g} = xi_{first g} + Psi_{first g} x_{first g+1}
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_bwd_top(SolveArgs<T> a) {
+    SEPK_PROLOGUE
+    sep_chain<T, D>(a.G - 1, true, X.yrow(Yr, X.first(a.G - 1))[i], T(1),
+                    [&](int k) { return X.prop(X.first(a.G - 2 - k), 1); },
+                    [&](int k) { return X.yrow(Yr, X.first(a.G - 2 - k)); }, vecw, part);
+}
+
+// fix-up of the group's other separators: x_c = xi_c + Psi_c x_{first g+1}
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_bwd_fix(SolveArgs<T> a) {
+    SEPK_PROLOGUE
+    const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
+    sep_chain<T, D>(c1 - c0, false, X.yrow(Yr, X.first(g + 1))[i], T(1),
+                    [&](int k) { return X.prop(c0 + 1 + k, 1); },
+                    [&](int k) { return X.yrow(Yr, c0 + 1 + k); }, vecw, part);
+}
+#undef SEPK_PROLOGUE
+
 // ---------------------------------------------------------------- phase C (all columns)
 template <typename T, int R>
 __global__ void __launch_bounds__(NT) k_phase_c(SolveArgs<T> a) {
@@ -612,6 +749,95 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets(SolveArgs<T> a) {
     }
 }
 
+// complex64 target columns per chunk as one small product on v_mfma_f32_16x16x4f32:
+// rows (l, t) of the chunk's interior rows l and the 8 target columns t, columns 16
+// right-hand sides, k over [x_above; x_below] (128): out = Fc(l, t, :) [xa; xb], x = y - out.
+// Grid (chunks, right-hand-side groups of 16); wave w takes row tiles w, w + 4, ...  The
+// separator row that closes the chunk is copied (its x is final after phase B).
+__global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a) {
+    using V = float2;
+    __shared__ V X[2 * WP][16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
+    const int c = blockIdx.x, rbase = blockIdx.y * 16;
+    const int r0 = c * a.m;
+    const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
+    const int nr = r1 - r0;
+    const bool has_a = c > 0, has_b = c < a.P - 1;
+    // branch-free staging: every lane loads (a clamped address) and keeps or drops the value
+    {
+        V xv[8];
+        bool keepv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = t + NT * u;
+            const int k = e >> 4, j = e & 15, r = rbase + j, kk = k & (WP - 1);
+            const bool above = k < WP;
+            keepv[u] = r < a.nrhs && kk < a.W && (above ? has_a : has_b);
+            const int row = above ? (has_a ? r0 - 1 : r0) : (has_b ? r1 : r0);
+            xv[u] = a.Yw[((size_t)(r < a.nrhs ? r : 0) * a.Ny + row) * WP + kk];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = t + NT * u;
+            X[e >> 4][e & 15] = make_float2(keepv[u] ? xv[u].x : 0.f, keepv[u] ? xv[u].y : 0.f);
+        }
+    }
+    __syncthreads();
+    const int rn = rbase + n;
+    const int nrows = nr * 8, ntile = (nrows + 15) / 16;
+    for (int tile = w; tile < ntile; tile += 4) {
+        // A operands: row rho = 16 tile + n (clamped), k = 4 s + q4
+        const int rho = min(16 * tile + n, nrows - 1);
+        const int l = r0 + (rho >> 3), tt = rho & 7;
+        const V* fa = a.Fc + ((size_t)(l * 2 + 0) * 8 + tt) * WP + q4;
+        const V* fb = a.Fc + ((size_t)(l * 2 + 1) * 8 + tt) * WP + q4;
+        V g[32];
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) { g[s4] = fa[4 * s4]; g[16 + s4] = fb[4 * s4]; }
+        // the y values of this lane's four outputs, loaded before the products (the
+        // stores of the outputs below could alias them, so they cannot move up by themselves)
+        V y[4];
+        int qo[4], lo4[4];
+        bool ok[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ro = 16 * tile + 4 * q4 + j;
+            const int roc = ro < nrows ? ro : nrows - 1;
+            lo4[j] = r0 + (roc >> 3);
+            qo[j] = a.tcol[roc & 7];
+            ok[j] = ro < nrows && qo[j] >= 0 && rn < a.nrhs;
+            const size_t yi = ((size_t)(rn < a.nrhs ? rn : 0) * a.Ny + lo4[j]) * WP + (qo[j] >= 0 ? qo[j] : 0);
+            y[j] = a.Yw[yi];
+        }
+        mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+#pragma unroll
+        for (int s4 = 0; s4 < 32; s4 += 2) {
+            const V g0 = g[s4], g1 = g[s4 + 1];
+            const V v0 = X[4 * s4 + q4][n], v1 = X[4 * s4 + 4 + q4][n];
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.y, aI1, 0, 0, 0);
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g0.y, v0.y, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.x, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g1.y, v1.y, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.x, aI1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (ok[j]) {
+                const V x = make_float2(y[j].x - (aR0[j] + aR1[j]), y[j].y - (aI0[j] + aI1[j]));
+                scatter<float>(a, rn, lo4[j], qo[j], x);
+            }
+        }
+    }
+    // the separator row closing this chunk
+    if (has_b && t < 8 * 16) {
+        const int tt = t >> 4, r = rbase + (t & 15), q = a.tcol[tt];
+        if (q >= 0 && r < a.nrhs) scatter<float>(a, r, r1, q, a.Yw[((size_t)r * a.Ny + r1) * WP + q]);
+    }
+}
+
 template <typename T> struct Depth { static constexpr int D = 2; };
 template <> struct Depth<float> { static constexpr int D = 4; };
 
@@ -633,7 +859,15 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
     if (a.P > 1) {
         if (kt) kt->begin(K_PHASE_B, st);
         hipLaunchKernelGGL((k_phase_b0<T, R>), dim3(a.P - 1, RG), dim3(NT), 0, st, a);
-        if (a.P > 2) {
+        if (a.P > 2 && a.G >= 2 && a.Fs) {
+            constexpr int DS = Depth<T>::D;
+            const unsigned nr = (unsigned)a.nrhs;
+            hipLaunchKernelGGL((k_sep_fwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_sep_fwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_sep_bwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
+            hipLaunchKernelGGL((k_sep_bwd_fix<T, DS>), dim3(nr, a.G - 1), dim3(NT), 0, st, a);
+        } else if (a.P > 2) {
             if (a.P - 1 <= ZMAX)
                 hipLaunchKernelGGL((k_phase_b<T, Depth<T>::D, true>), dim3(a.nrhs), dim3(NT), 0, st, a);
             else
@@ -642,9 +876,13 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
         if (kt) kt->end(K_PHASE_B, st);
     }
     if (kt) kt->begin(K_PHASE_C, st);
-    if (targets)
-        hipLaunchKernelGGL((k_phase_c_targets<T>), dim3((a.Ny + CT_ROWS - 1) / CT_ROWS, (a.nrhs + 31) / 32),
-                           dim3(NT), 0, st, a);
+    if (targets) {
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL(k_phase_c_targets_mfma, dim3(a.P, (a.nrhs + 15) / 16), dim3(NT), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_phase_c_targets<T>), dim3((a.Ny + CT_ROWS - 1) / CT_ROWS, (a.nrhs + 31) / 32),
+                               dim3(NT), 0, st, a);
+    }
     else
         hipLaunchKernelGGL((k_phase_c<T, R>), dim3(a.Ny, RG), dim3(NT), 0, st, a);
     if (kt) kt->end(K_PHASE_C, st);
@@ -655,10 +893,13 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
 
 template <typename T>
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
-                              const cplx<T>* F, const cplx<T>* Fc, cplx<T>* Yw, int nrhs,
-                              const IOSpec& io, hipStream_t st, KTimer* kt) {
+                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
+                              int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt) {
     SolveArgs<T> a;
     a.F = F + (size_t)s * g.Ny * NSLOT * BLK;
+    a.Fs = Fs ? Fs + (size_t)s * (ch.P - 1) * 2 * BLK : nullptr;
+    a.q = ch.q;
+    a.G = ch.G;
     a.Fc = Fc ? Fc + (size_t)s * g.Ny * 2 * 8 * WP : nullptr;
     a.tcol = t.tcol + s * 8;
     a.Yw = Yw;
@@ -682,10 +923,10 @@ hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& c
 }
 
 template hipError_t launch_strip_solve<float>(const DevTables&, const Geom&, const Chunks&, int,
-                                              const float2*, const float2*, float2*, int,
+                                              const float2*, const float2*, const float2*, float2*, int,
                                               const IOSpec&, hipStream_t, KTimer*);
 template hipError_t launch_strip_solve<double>(const DevTables&, const Geom&, const Chunks&, int,
-                                               const double2*, const double2*, double2*, int,
-                                               const IOSpec&, hipStream_t, KTimer*);
+                                               const double2*, const double2*, const double2*, double2*,
+                                               int, const IOSpec&, hipStream_t, KTimer*);
 
 }  // namespace helm
