@@ -73,7 +73,9 @@ __device__ void build_T(double2* M, const FactorArgs& a, int s, int l, int W) {
 }
 
 // C = alpha * A * B (+ D), full WP x WP, column-major with leading dimensions.  Operands
-// may live in LDS or global memory; C may alias A, B or D.
+// may live in LDS or global memory; C may alias A, B or D.  Thread (ti, tj) computes rows
+// 4 ti.., columns 4 tj..; the k loop is unrolled so that the loads of A (usually a factor
+// block in global memory) of several k are in flight together.
 __device__ void gemm64(double2* C, int ldc, const double2* A, int lda, const double2* B, int ldb,
                        double2 alpha, const double2* D, int ldd) {
     const int t = threadIdx.x;
@@ -83,6 +85,7 @@ __device__ void gemm64(double2* C, int ldc, const double2* A, int lda, const dou
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = cmk<double2>(0.0, 0.0);
+#pragma unroll 8
     for (int k = 0; k < WP; ++k) {
         double2 av[4], bv[4];
 #pragma unroll
@@ -157,14 +160,18 @@ __device__ void invert_inplace(double2* M, int n, InvScratch& sc, int* err) {
             sc.fcol[t] = (t == k) ? cmk<double2>(0.0, 0.0) : M[t + k * LDM];
         }
         __syncthreads();
-        for (int idx = t; idx < n * n; idx += NT) {
-            const int i = idx % n, j = idx / n;
-            double2 r = sc.rowk[j];
-            if (i == k) {
-                M[i + j * LDM] = r;
-            } else {
-                double2 cur = (j == k) ? cmk<double2>(0.0, 0.0) : M[i + j * LDM];
-                M[i + j * LDM] = csub(cur, cmul(sc.fcol[i], r));
+        {
+            const int j = t & (WP - 1);
+            if (j < n) {
+                const double2 r = sc.rowk[j];
+                for (int i = t >> 6; i < n; i += NT / WP) {
+                    if (i == k) {
+                        M[i + j * LDM] = r;
+                    } else {
+                        const double2 cur = (j == k) ? cmk<double2>(0.0, 0.0) : M[i + j * LDM];
+                        M[i + j * LDM] = csub(cur, cmul(sc.fcol[i], r));
+                    }
+                }
             }
         }
         __syncthreads();
@@ -226,12 +233,22 @@ __global__ void __launch_bounds__(NT) k_factor_chunks(FactorArgs a) {
         double2* tmp = Pm; Pm = Cm; Cm = tmp;
         __syncthreads();
     }
-    __threadfence();
-    __syncthreads();
+}
+
+// The two spikes of a chunk (blockIdx.z = 0: top, 1: bottom), after the inversions.
+__global__ void __launch_bounds__(NT) k_factor_spikes(FactorArgs a) {
+    __shared__ double2 bufA[WP * LDM];
+    __shared__ double2 bufB[WP * LDM];
+    const int c = blockIdx.x, s = blockIdx.y, side = blockIdx.z;
+    const int r0 = c * a.m;
+    const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
+    const double2 one = cmk<double2>(1.0, 0.0);
+    double2* Pm = bufA;
+    double2* Cm = bufB;
 
     // ---- top spike: forward Z_r0 = G_r0, Z_l = -c_l G_l Z_{l-1}; backward
     //      X_l = Z_l - b_l G_l X_{l+1};  stored scaled by c_r0
-    if (c > 0) {
+    if (side == 0 && c > 0) {
         load_blk(Pm, slot(a, s, r0, 0));
         __syncthreads();
         store_blk(slot(a, s, r0, 1), Pm, one);
@@ -256,7 +273,7 @@ __global__ void __launch_bounds__(NT) k_factor_chunks(FactorArgs a) {
     }
 
     // ---- bottom spike: Y_{r1-1} = G_{r1-1}, Y_l = -b_l G_l Y_{l+1}; stored scaled by b_{r1-1}
-    if (c < a.P - 1) {
+    if (side == 1 && c < a.P - 1) {
         const double2 bbot = a.by[r1 - 1];
         load_blk(Pm, slot(a, s, r1 - 1, 0));
         __syncthreads();
@@ -393,6 +410,7 @@ hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks&
     FactorArgs a = make_args(t, g, ch, F64, err);
     dim3 grid(ch.P, g.J);
     hipLaunchKernelGGL(k_factor_chunks, grid, dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_factor_spikes, dim3(ch.P, g.J, 2), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 

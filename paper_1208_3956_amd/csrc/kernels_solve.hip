@@ -373,9 +373,12 @@ __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
         for (int j = 0; j < D; ++j)
             if (kb + j < nsteps) bwd_step(kb + j, (j + OFF) % D);
     };
-    static_assert(D == 2, "the backward ring alignment below is written for D = 2");
-    if (nr % 2 == 0) bwd_loop(std::integral_constant<int, 0>{});
-    else bwd_loop(std::integral_constant<int, 1>{});
+    static_assert(D >= 1 && D <= 4, "ring alignment dispatch below covers D <= 4");
+    const int off = nr % D;
+    if (off == 0) bwd_loop(std::integral_constant<int, 0>{});
+    if constexpr (D > 1) { if (off == 1) bwd_loop(std::integral_constant<int, 1 % D>{}); }
+    if constexpr (D > 2) { if (off == 2) bwd_loop(std::integral_constant<int, 2 % D>{}); }
+    if constexpr (D > 3) { if (off == 3) bwd_loop(std::integral_constant<int, 3 % D>{}); }
 }
 
 // ---------------------------------------------------------------- phase B0
