@@ -158,6 +158,119 @@ __global__ void __launch_bounds__(NTP) k3_gj_panel(double2* __restrict__ S, int 
     }
 }
 
+// The same reduction of the panel [k0, k0 + NB) with the panel itself blocked: inner panels
+// of NI columns are reduced in LDS (pivot search, exchange, scaling, elimination of all other
+// rows), written back, and applied to the other columns of the panel as one rank-NI update
+// (after their row exchanges).  The panel's global traffic drops from NB passes over NB
+// columns to about NB / NI passes.  Requires Bp <= BPI_MAX (the inner panel lives in LDS).
+constexpr int NI = 4;
+constexpr int BPI_MAX = 2048;
+constexpr int NTI = 1024;
+
+__global__ void __launch_bounds__(NTI) k3_gj_panel_lds(double2* __restrict__ S, int Bp, int k0,
+                                                      int* __restrict__ perm, int* __restrict__ err) {
+    const int s = blockIdx.x, t = threadIdx.x;
+    double2* A = S + (size_t)s * Bp * Bp;
+    __shared__ double2 Ps[NI][BPI_MAX];
+    __shared__ double2 rowk[NI];
+    __shared__ double2 tv[NB][NI];
+    __shared__ double bv[NTI / 64];
+    __shared__ int bi[NTI / 64];
+    __shared__ int pv[NI];
+    for (int ki = k0; ki < k0 + NB; ki += NI) {
+        for (int e = t; e < NI * Bp; e += NTI) Ps[e / Bp][e % Bp] = A[(size_t)(ki + e / Bp) * Bp + e % Bp];
+        __syncthreads();
+        for (int kk = 0; kk < NI; ++kk) {
+            const int k = ki + kk;
+            // pivot: largest |P(i, kk)|, i >= k, first of equal values
+            double best = -1.0;
+            int arg = k;
+            for (int i = k + t; i < Bp; i += NTI) {
+                const double2 v = Ps[kk][i];
+                const double m = v.x * v.x + v.y * v.y;
+                if (m > best) { best = m; arg = i; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int oa = __shfl_xor(arg, off);
+                if (ob > best || (ob == best && oa < arg)) { best = ob; arg = oa; }
+            }
+            if ((t & 63) == 0) { bv[t >> 6] = best; bi[t >> 6] = arg; }
+            __syncthreads();
+            if (t == 0) {
+                double b = bv[0];
+                int a = bi[0];
+                for (int w = 1; w < NTI / 64; ++w)
+                    if (bv[w] > b || (bv[w] == b && bi[w] < a)) { b = bv[w]; a = bi[w]; }
+                const bool bad = !(b > 0.0) || !isfinite(b);
+                if (bad) { a = k; err[0] = 1; }
+                pv[kk] = a;
+                perm[(size_t)s * Bp + k] = a;
+            }
+            __syncthreads();
+            const int p = pv[kk];
+            if (p != k && t < NI) {
+                const double2 x = Ps[t][k];
+                Ps[t][k] = Ps[t][p];
+                Ps[t][p] = x;
+            }
+            __syncthreads();
+            if (t < NI) {
+                double2 piv = Ps[kk][k];
+                if (!(piv.x * piv.x + piv.y * piv.y > 0.0)) piv = make_double2(1.0, 0.0);
+                const double2 v = t == kk ? make_double2(1.0, 0.0) : Ps[t][k];
+                rowk[t] = cdiv(v, piv);
+            }
+            __syncthreads();
+            for (int i = t; i < Bp; i += NTI) {
+                if (i == k) {
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) Ps[c][i] = rowk[c];
+                } else {
+                    const double2 m = Ps[kk][i];
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) {
+                        const double2 old = c == kk ? make_double2(0.0, 0.0) : Ps[c][i];
+                        Ps[c][i] = csub(old, cmul(m, rowk[c]));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // the reduced inner columns back to global memory
+        for (int e = t; e < NI * Bp; e += NTI) A[(size_t)(ki + e / Bp) * Bp + e % Bp] = Ps[e / Bp][e % Bp];
+        // the other columns of the panel: the inner exchanges, then the rank-NI update
+        // A(:, j) += (C - E) A(K_in, j)
+        if (t < NB) {
+            const int j = k0 + t;
+            if (j < ki || j >= ki + NI) {
+                double2* col = A + (size_t)j * Bp;
+                for (int kk = 0; kk < NI; ++kk) {
+                    const int k = ki + kk, p = pv[kk];
+                    if (p != k) { const double2 x = col[k]; col[k] = col[p]; col[p] = x; }
+                }
+#pragma unroll
+                for (int kk = 0; kk < NI; ++kk) tv[t][kk] = col[ki + kk];
+            }
+        }
+        __syncthreads();
+        for (int e = t; e < NB * Bp; e += NTI) {
+            const int jj = e / Bp, i = e % Bp, j = k0 + jj;
+            if (j >= ki && j < ki + NI) continue;
+            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int kk = 0; kk < NI; ++kk) {
+                double2 c = Ps[kk][i];
+                if (i == ki + kk) c.x -= 1.0;
+                acc = cadd(acc, cmul(c, tv[jj][kk]));
+            }
+            double2* q = A + (size_t)j * Bp + i;
+            *q = cadd(*q, acc);
+        }
+        __syncthreads();
+    }
+}
+
 // Outside the panel: the panel's row exchanges (in order) and the operands of the update,
 // Tm(kk, j) = A(k0 + kk, j) for j outside the panel (0 inside),  Cm(i, kk) = C(i, kk) - [i = k0 + kk].
 __global__ void __launch_bounds__(256) k3_gj_prep(double2* __restrict__ S, int Bp, int k0,
@@ -455,7 +568,10 @@ hipError_t launch_factor3_plane(const Fac3Args& a, int l, const double2* Gprev, 
     unsigned nb = (unsigned)std::min<size_t>((BB + 255) / 256, 4096);
     hipLaunchKernelGGL(k3_build_S, dim3(nb, a.J), dim3(256), 0, st, a, l, Gprev, S);
     for (int k0 = 0; k0 < a.Bp; k0 += NB) {
-        hipLaunchKernelGGL(k3_gj_panel, dim3(a.J), dim3(NTP), 0, st, S, a.Bp, k0, perm, err);
+        if (a.Bp <= BPI_MAX)
+            hipLaunchKernelGGL(k3_gj_panel_lds, dim3(a.J), dim3(NTI), 0, st, S, a.Bp, k0, perm, err);
+        else
+            hipLaunchKernelGGL(k3_gj_panel, dim3(a.J), dim3(NTP), 0, st, S, a.Bp, k0, perm, err);
         hipLaunchKernelGGL(k3_gj_prep, dim3((a.Bp + 255) / 256, a.J), dim3(256), 0, st, S, a.Bp, k0, perm, Tm, Cm);
         hipLaunchKernelGGL(k3_gemm_update, dim3(a.Bp / 64, a.Bp / 64, a.J), dim3(256), 0, st, S, a.Bp, Tm, Cm);
     }
