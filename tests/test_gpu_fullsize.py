@@ -1,0 +1,80 @@
+"""Parity at the benchmark's full size (2000² layered medium, J = 64, 64 right-hand sides,
+mixed precision, reduced GMRES, default chunking — the configuration bench.py times), on
+outputs the oracle can check one by one:
+
+* the residual f - A u of sampled right-hand sides, with A assembled by the oracle;
+* sampled strip solves against the oracle's SuperLU factorisations of the same strips;
+* the preconditioner P applied to one right-hand side against the oracle's sweeps.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle.assemble import assemble_global, assemble_strip  # noqa: E402
+from oracle.dd import StripSolvers, apply_P  # noqa: E402
+from oracle.grid import geometry_from_workload  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def big():
+    wl = W.layers(n=2000, nsrc=64)
+    g = geometry_from_workload(wl)
+    return wl, g, assemble_global(g)
+
+
+def _H(wl, prec, mode="reduced"):
+    from paper_1208_3956_amd import Helmholtz
+    return Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                     prec=prec, mode=mode, device=DEV).factor()
+
+
+def test_full_size_solve_residual_by_oracle_operator(big):
+    wl, g, A = big
+    H = _H(wl, "mixed")
+    f = wl.rhs()
+    res = H.solve(torch.from_numpy(f).to(DEV), tol=1e-6)
+    assert res.status == 0 and max(res.relres) <= 1e-6
+    for k in (0, 31, 63):
+        u = res.u[k].cpu().numpy()
+        r = f[k].ravel() - A @ u.ravel()
+        rel = np.linalg.norm(r) / np.linalg.norm(f[k])
+        assert rel <= 1e-6 * (1 + 1e-9), (k, rel)
+        assert abs(rel - res.relres[k]) <= 1e-9 * max(rel, 1e-12) + 1e-15, (k, rel, res.relres[k])
+    H.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 2e-4), ("c128", 1e-10)])
+def test_full_size_strip_solves(big, prec, tol):
+    import scipy.sparse.linalg as spla
+    wl, g, A = big
+    H = _H(wl, prec)
+    k2 = g.k2()
+    rng = np.random.default_rng(7)
+    for s in (0, 31, 63):
+        st = g.strips[s]
+        lu = spla.splu(assemble_strip(g, st, k2).tocsc(), permc_spec="COLAMD")
+        r = rng.standard_normal((2, g.N_y, st.W)) + 1j * rng.standard_normal((2, g.N_y, st.W))
+        x = H.strip_solve(s, torch.from_numpy(r).to(DEV)).cpu().numpy()
+        ref = np.stack([lu.solve(rk.ravel()).reshape(rk.shape) for rk in r])
+        err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+        assert err < tol, (s, err)
+    H.close()
+
+
+def test_full_size_preconditioner_one_rhs(big):
+    wl, g, A = big
+    S = StripSolvers(g)
+    f = wl.rhs([5])
+    ref = apply_P(g, S, A, f[0])
+    for prec, tol in (("c128", 1e-10), ("mixed", 2e-4)):
+        H = _H(wl, prec, mode="full")
+        pf = H.apply_P(torch.from_numpy(f).to(DEV)).cpu().numpy()[0]
+        err = np.linalg.norm(pf - ref) / np.linalg.norm(ref)
+        assert err < tol, (prec, err)
+        H.close()
