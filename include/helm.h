@@ -228,6 +228,9 @@ helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* sol
  *   6 GMRES vector kernels                        7 other
  * launches, total_ms: host arrays of nclass entries.  At most 65536 launches are
  * recorded per enable; later ones are counted but not timed (ms stays a lower bound).
+ * enable is a bit mask of the classes to time (bit c = class c, 0xFF = all); launches of
+ * the other classes are still counted.  0 disables timing.  Every timed launch costs two
+ * event records on the stream, so timing only the classes of interest disturbs less.
  */
 helm_status helm_set_kernel_timing(helm_t H, int enable);
 helm_status helm_get_kernel_times(helm_t H, int nclass, int* launches, double* total_ms);

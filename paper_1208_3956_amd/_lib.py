@@ -210,8 +210,9 @@ def helm_get_stats(hdl):
     return a.value, r.value, ms.value
 
 
-def helm_set_kernel_timing(hdl, enable: bool) -> None:
-    check(lib().helm_set_kernel_timing(hdl, 1 if enable else 0), hdl)
+def helm_set_kernel_timing(hdl, mask: int) -> None:
+    """mask: bit c times kernel class KERNEL_CLASSES[c]; 0 disables timing."""
+    check(lib().helm_set_kernel_timing(hdl, int(mask) & 0xFF), hdl)
 
 
 def helm_get_kernel_times(hdl) -> dict:

@@ -50,6 +50,7 @@ struct EventTimer : helm::KTimer {
     long counts[helm::K_NCLASS] = {0};
     double ms[helm::K_NCLASS] = {0};
     int pending_cls = -1;
+    unsigned mask = 0xFFu;       // classes whose launches are timed (all are counted)
     hipEvent_t get(int idx) {
         while ((int)pool.size() <= idx) {
             hipEvent_t e;
@@ -60,7 +61,7 @@ struct EventTimer : helm::KTimer {
     }
     void begin(int c, hipStream_t st) override {
         counts[c] += 1;
-        if (used >= kMax) { pending_cls = -1; return; }
+        if (used >= kMax || !(mask & (1u << c))) { pending_cls = -1; return; }
         hipEvent_t e = get(2 * used);
         if (!e || !get(2 * used + 1)) { pending_cls = -1; return; }
         (void)hipEventRecord(e, st);
@@ -1286,6 +1287,7 @@ helm_status helm_set_kernel_timing(helm_t H, int enable) {
         if (!H->timer) H->timer = new EventTimer();
         HIPCHK(H->st ? hipStreamSynchronize(H->st) : hipDeviceSynchronize());
         H->timer->reset();
+        H->timer->mask = (unsigned)enable & 0xFFu;
     } else if (H->timer) {
         HIPCHK(H->st ? hipStreamSynchronize(H->st) : hipDeviceSynchronize());
         delete H->timer;

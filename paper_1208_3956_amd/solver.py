@@ -202,9 +202,13 @@ class Helmholtz:
         self._end()
         return x
 
-    def set_kernel_timing(self, enable: bool = True):
-        """Bracket every hot-kernel launch with HIP events (see helm_set_kernel_timing)."""
-        L.helm_set_kernel_timing(self.h, enable)
+    def set_kernel_timing(self, enable=True, classes=None):
+        """Bracket hot-kernel launches with HIP events (see helm_set_kernel_timing): all
+        classes, or only those named in `classes` (names as in kernel_times())."""
+        mask = 0
+        if enable:
+            mask = 0xFF if classes is None else sum(1 << L.KERNEL_CLASSES.index(c) for c in classes)
+        L.helm_set_kernel_timing(self.h, mask)
 
     def kernel_times(self) -> dict:
         """{class: (launches, total ms)} since timing was enabled."""

@@ -104,3 +104,23 @@ def test_solve_batch_rejects_repeated_handle():
     with pytest.raises(HelmError):
         solve_batch([H, H], [f, f], 1e-6)
     H.close()
+
+
+def test_kernel_timing_class_mask():
+    """Timing only some kernel classes: every launch is still counted, only the masked
+    classes accumulate time, and the field is the untimed one bit for bit."""
+    wl = _wl(48, 4, 31)
+    f = torch.from_numpy(wl.rhs()).to(DEV)
+    H = _H(wl, "mixed", graph=False)
+    ref = H.solve(f, 1e-6)
+    H2 = _H(wl, "mixed", graph=False)
+    H2.set_kernel_timing(True, classes=["phase_a"])
+    res = H2.solve(f, 1e-6)
+    kt = H2.kernel_times()
+    H2.set_kernel_timing(False)
+    assert res.iters == ref.iters and torch.equal(res.u, ref.u)
+    assert kt["phase_a"][0] > 0 and kt["phase_a"][1] > 0
+    assert kt["stencil"][0] > 0 and kt["stencil"][1] == 0
+    assert kt["phase_c"][0] > 0 and kt["phase_c"][1] == 0
+    H.close()
+    H2.close()
