@@ -15,7 +15,8 @@
 // LU (G'_c, K_c = G'_c L_c, U'_c = G'_c S^_{c,c+1}).  Storage per row l: three WP x WP blocks
 // (slot 0: G or G', slot 1: X~ or K, slot 2: Y~ or U').
 //
-// Inverses are formed by Gauss-Jordan elimination with partial (row) pivoting in LDS.
+// Inverses are formed by Gauss-Jordan elimination with partial (row) pivoting, the matrix
+// held in registers (one row per lane, the 64 columns split over the four waves).
 #include "helm_internal.hpp"
 
 namespace helm {
@@ -113,78 +114,108 @@ __device__ void gemm64(double2* C, int ldc, const double2* A, int lda, const dou
     __syncthreads();
 }
 
-struct InvScratch {
-    double2 fcol[WP];
-    double2 rowk[WP];
+// ---------------------------------------------------------------- register Gauss-Jordan
+// Layout: lane i holds row i; wave g holds columns j = g + 4 r, r = 0..15, in M[r].  A step k
+// pivots on column k (wave k % 4) at the unused row p of largest modulus and eliminates
+// column k from every other row.  No rows are swapped and the pivot row is not scaled at
+// its step: row p keeps its values (its column-k entry becomes 1) and is multiplied by its
+// reciprocal pivot after the last step, which leaves every elimination unchanged because the
+// updates are linear in the pivot row.  The finished array holds the inverse with row i at
+// position step(i) (the step that pivoted on row i) and column j at position perm(j) (the row
+// pivoted at step j).  The columns cycle through the registers: after every four steps the
+// array is rotated by one register, so the column of the current step is always M[0].
+struct GJShared {
+    double2 fcol[2][WP];     // pivot column of the step (double-buffered: one barrier per step)
+    int piv[2];
     int perm[WP];
-    int piv;
 };
 
-// In-place inverse of the leading n x n block of M (leading dimension LDM) by
-// Gauss-Jordan elimination with partial pivoting; columns are unscrambled at the end.
-__device__ void invert_inplace(double2* M, int n, InvScratch& sc, int* err) {
-    const int t = threadIdx.x;
-    for (int k = 0; k < n; ++k) {
-        if (t < 64) {
-            double v = -1.0;
-            int idx = t;
-            if (t >= k && t < n) {
-                double2 q = M[t + k * LDM];
-                v = q.x * q.x + q.y * q.y;
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                double ov = __shfl_xor(v, off);
-                int oi = __shfl_xor(idx, off);
-                if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-            }
-            if (t == 0) {
-                sc.piv = idx;
-                sc.perm[k] = idx;
-                if (!(v > 0.0) || !isfinite(v)) atomicOr(err, 1);
-            }
-        }
-        __syncthreads();
-        const int p = sc.piv;
-        if (p != k && t < n) {
-            double2 x = M[k + t * LDM];
-            M[k + t * LDM] = M[p + t * LDM];
-            M[p + t * LDM] = x;
-        }
-        __syncthreads();
-        if (t < n) {
-            double2 q = M[k + k * LDM];
-            double den = q.x * q.x + q.y * q.y;
-            double2 inv = den > 0.0 ? cmk<double2>(q.x / den, -q.y / den) : cmk<double2>(0.0, 0.0);
-            double2 val = (t == k) ? cmk<double2>(1.0, 0.0) : M[k + t * LDM];
-            sc.rowk[t] = cmul(val, inv);
-            sc.fcol[t] = (t == k) ? cmk<double2>(0.0, 0.0) : M[t + k * LDM];
-        }
-        __syncthreads();
-        {
-            const int j = t & (WP - 1);
-            if (j < n) {
-                const double2 r = sc.rowk[j];
-                for (int i = t >> 6; i < n; i += NT / WP) {
-                    if (i == k) {
-                        M[i + j * LDM] = r;
-                    } else {
-                        const double2 cur = (j == k) ? cmk<double2>(0.0, 0.0) : M[i + j * LDM];
-                        M[i + j * LDM] = csub(cur, cmul(sc.fcol[i], r));
+// wavefront maximum (device library; declared by the HIP headers only on request)
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
+
+// component-wise select (a select of whole double2 values goes through scratch memory)
+__device__ inline double2 sel(bool c, double2 a, double2 b) {
+    return cmk<double2>(c ? a.x : b.x, c ? a.y : b.y);
+}
+
+__device__ inline double readlane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Inverse of the leading W x W block of the matrix in M (zero elsewhere), written column-major
+// with leading dimension WP to dst (zero outside the leading block); ends with a barrier so
+// that dst can be read back by the workgroup.  Sets err when a pivot is zero or not finite.
+__device__ void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, double2* __restrict__ dst,
+                                int* err) {
+    const int i = threadIdx.x & (WP - 1), g = threadIdx.x >> 6;
+    bool used = i >= W;
+    int my_step = i;                               // rows beyond W keep their position
+    double2 my_inv = cmk<double2>(1.0, 0.0);
+    int rot = 0;                                   // rotations done: M[r] holds column g + 4 (r + rot)
+    for (int kk = 0; 4 * kk < W; ++kk) {
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) {
+            const int k = 4 * kk + gg;
+            if (k < W) {
+                const int buf = k & 1;
+                if (g == gg) {
+                    // pivot search over the unused rows: the key orders by |m|^2 (its low 6
+                    // mantissa bits replaced by 63 - row, so ties go to the lower row)
+                    const double2 v = M[0];
+                    const double mag = v.x * v.x + v.y * v.y;
+                    const unsigned long long key =
+                        used ? 0ull : (((unsigned long long)__double_as_longlong(mag) & ~63ull) |
+                                       (unsigned long long)(63 - i));
+                    const unsigned long long best = __ockl_wfred_max_u64(key);
+                    sh.fcol[buf][i] = v;
+                    if (i == 0) {
+                        const int p = 63 - (int)(best & 63ull);
+                        sh.piv[buf] = p;
+                        sh.perm[k] = p;
                     }
+                }
+                __syncthreads();
+                const int p = sh.piv[buf];
+                const double2 pv = sh.fcol[buf][p];
+                const double2 fk = sh.fcol[buf][i];
+                const double den = pv.x * pv.x + pv.y * pv.y;
+                if (threadIdx.x == 0 && !(den > 0.0 && isfinite(den))) atomicOr(err, 1);
+                const double2 inv = sel(den > 0.0, cmk<double2>(pv.x / den, -pv.y / den),
+                                        cmk<double2>(0.0, 0.0));
+                const double2 f = sel(i == p, cmk<double2>(0.0, 0.0), cmul(fk, inv));
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const double Rx = readlane_f64(M[r].x, p), Ry = readlane_f64(M[r].y, p);
+                    M[r].x = fma(-f.x, Rx, fma(f.y, Ry, M[r].x));
+                    M[r].y = fma(-f.x, Ry, fma(-f.y, Rx, M[r].y));
+                }
+                if (g == gg) {
+                    M[0] = sel(i == p, cmk<double2>(1.0, 0.0), cmk<double2>(-f.x, -f.y));
+                }
+                if (i == p) {
+                    used = true;
+                    my_step = k;
+                    my_inv = inv;
                 }
             }
         }
-        __syncthreads();
+        // rotate: the next four columns come to M[0]
+        const double2 m0 = M[0];
+#pragma unroll
+        for (int r = 0; r < 15; ++r) M[r] = M[r + 1];
+        M[15] = m0;
+        ++rot;
     }
-    for (int k = n - 1; k >= 0; --k) {
-        const int p = sc.perm[k];
-        if (p != k && t < n) {
-            double2 x = M[t + k * LDM];
-            M[t + k * LDM] = M[t + p * LDM];
-            M[t + p * LDM] = x;
-        }
-        __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int j = g + 4 * ((r + rot) & 15);
+        const int pj = j < W ? sh.perm[j] : j;
+        dst[(size_t)pj * WP + my_step] = cmul(M[r], my_inv);
     }
+    __syncthreads();
 }
 
 __device__ inline double2* slot(const FactorArgs& a, int s, int l, int sl) {
@@ -205,33 +236,46 @@ __device__ void load_blk(double2* M, const double2* src) {
     }
 }
 
+// Block LU of the chunk interior, G_l = (T_l - c_l b_{l-1} G_{l-1})^{-1}, one chunk per
+// workgroup, the matrices in registers (layout of gj_invert_store).  G_{l-1} is read back
+// from its slot in natural order.
 __global__ void __launch_bounds__(NT) k_factor_chunks(FactorArgs a) {
-    __shared__ double2 bufA[WP * LDM];
-    __shared__ double2 bufB[WP * LDM];
-    __shared__ InvScratch sc;
+    __shared__ GJShared sh;
     const int c = blockIdx.x, s = blockIdx.y;
     const int W = a.sW[s];
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
-    const double2 one = cmk<double2>(1.0, 0.0);
-    double2* Pm = bufA;
-    double2* Cm = bufB;
-
-    // ---- block LU of the chunk interior: G_l = (T_l - c_l b_{l-1} G_{l-1})^{-1}
+    const int i = threadIdx.x & (WP - 1), g = threadIdx.x >> 6;
+    // the x part of row i of T_l (the same on every row l of the strip)
+    double2 xd = cmk<double2>(0.0, 0.0), xup = xd, xlo = xd;
+    int col = 0;
+    if (i < W) {
+        const double2 axq = a.sax[(size_t)s * WP + i];
+        const double2 e = a.saxh[(size_t)s * (WP + 1) + i + 1], wv = a.saxh[(size_t)s * (WP + 1) + i];
+        xd = cmul(axq, cadd(e, wv));
+        const double2 o = cmul(axq, e), q = cmul(axq, wv);
+        xup = cmk<double2>(-o.x * a.inv_h2, -o.y * a.inv_h2);
+        xlo = cmk<double2>(-q.x * a.inv_h2, -q.y * a.inv_h2);
+        col = a.scol[(size_t)s * WP + i];
+    }
+    double2 M[16];
     for (int l = r0; l < r1; ++l) {
-        build_T(Cm, a, s, l, W);
-        if (l > r0) {
-            const double2 cb = cmul(a.cy[l], a.by[l - 1]);
-            for (int idx = threadIdx.x; idx < W * W; idx += NT) {
-                const int i = idx % W, k = idx / W;
-                Cm[i + k * LDM] = csub(Cm[i + k * LDM], cmul(cb, Pm[i + k * LDM]));
+        double2 d = cadd(xd, cmul(a.ay[l], cadd(a.ayh[l + 1], a.ayh[l])));
+        d.x *= a.inv_h2; d.y *= a.inv_h2;
+        d.x -= a.k2[(size_t)l * a.Nx + col];
+        const double2 cb = l > r0 ? cmul(a.cy[l], a.by[l - 1]) : cmk<double2>(0.0, 0.0);
+        const double2* Gp = slot(a, s, l > r0 ? l - 1 : l, 0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int j = g + 4 * r;
+            double2 v = cmk<double2>(0.0, 0.0);
+            if (i < W && j < W) {
+                v = sel(j == i, d, sel(j == i + 1, xup, sel(j == i - 1, xlo, v)));
+                if (l > r0) v = csub(v, cmul(cb, Gp[(size_t)j * WP + i]));
             }
-            __syncthreads();
+            M[r] = v;
         }
-        invert_inplace(Cm, W, sc, a.err);
-        store_blk(slot(a, s, l, 0), Cm, one);
-        double2* tmp = Pm; Pm = Cm; Cm = tmp;
-        __syncthreads();
+        gj_invert_store(M, W, sh, slot(a, s, l, 0), a.err);
     }
 }
 
@@ -297,7 +341,7 @@ __global__ void __launch_bounds__(NT) k_factor_spikes(FactorArgs a) {
 __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
     __shared__ double2 Am[WP * LDM];
     __shared__ double2 Bm[WP * LDM];
-    __shared__ InvScratch sc;
+    __shared__ GJShared sh;
     const int s = blockIdx.x;
     const int W = a.sW[s];
     const double2 one = cmk<double2>(1.0, 0.0);
@@ -321,18 +365,23 @@ __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
             // Bm = Bm - L_c U'_{c-1},  L_c = S^_{c,c-1} = -c_s X~^(c)_{s-1}
             gemm64(Bm, LDM, slot(a, s, r - 1, 1), WP, Am, LDM, cs, Bm, LDM);
         }
-        invert_inplace(Bm, W, sc, a.err);
-        store_blk(slot(a, s, r, 0), Bm, one);
-        __syncthreads();
+        {
+            double2 M[16];
+            const int i = threadIdx.x & (WP - 1), g = threadIdx.x >> 6;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) M[q] = Bm[i + (g + 4 * q) * LDM];
+            gj_invert_store(M, W, sh, slot(a, s, r, 0), a.err);
+        }
+        const double2* Gp = slot(a, s, r, 0);
         if (c >= 1) {
             // K_c = G'_c L_c = -c_s G'_c X~^(c)_{s-1} replaces L_c in slot 1, so that the
             // forward separator recurrence is z'_c = G'_c r^_c - K_c z'_{c-1}
-            gemm64(Am, LDM, Bm, LDM, slot(a, s, r - 1, 1), WP, cmk<double2>(-cs.x, -cs.y), nullptr, 0);
+            gemm64(Am, LDM, Gp, WP, slot(a, s, r - 1, 1), WP, cmk<double2>(-cs.x, -cs.y), nullptr, 0);
             store_blk(slot(a, s, r, 1), Am, one);
             __syncthreads();
         }
         if (c + 2 < a.P) {
-            gemm64(Am, LDM, Bm, LDM, slot(a, s, r + 1, 2), WP, cmk<double2>(-bs.x, -bs.y), nullptr, 0);
+            gemm64(Am, LDM, Gp, WP, slot(a, s, r + 1, 2), WP, cmk<double2>(-bs.x, -bs.y), nullptr, 0);
             store_blk(slot(a, s, r, 2), Am, one);
             __syncthreads();
         }
