@@ -26,6 +26,8 @@ struct Work {
     void* Yw = nullptr;
     double2 *V = nullptr, *G = nullptr, *PF = nullptr, *Psi = nullptr, *Wf = nullptr,
             *Hf = nullptr, *Ut = nullptr, *R = nullptr, *Tup = nullptr, *Tdn = nullptr;
+    // interface-window fields of the reduced operator (v, g = psi - A v, w)
+    double2 *Vw = nullptr, *Gw = nullptr, *Ww = nullptr;
     // GMRES
     int mcap = 0;
     long n = 0;
@@ -205,7 +207,7 @@ helm_status upload(helm_t H, void** dptr, const void* src, size_t bytes) {
 
 // ---------------------------------------------------------------- workspaces
 void free_work(Work& w) {
-    void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
+    void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Vw, w.Gw, w.Ww, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
                   w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin};
     for (void* p : ps) dfree(p);
     w = Work();
@@ -229,6 +231,14 @@ helm_status ensure_sweep_ws(helm_t H, int nrhs) {
     for (double2** f : fields) {
         CHK(dmalloc(H, f, fb));
         HIPCHK(hipMemsetAsync(*f, 0, fb, H->st));
+    }
+    // window fields: entries no sweep writes (the windows' outer columns, the columns of
+    // strips a reduced sweep skips) must stay zero
+    const size_t wb = (size_t)nrhs * g.Nrow() * std::max(1, g.J - 1) * helm::IWIN * sizeof(double2);
+    double2** wfields[] = {&w.Vw, &w.Gw, &w.Ww};
+    for (double2** f : wfields) {
+        CHK(dmalloc(H, f, wb));
+        HIPCHK(hipMemsetAsync(*f, 0, wb, H->st));
     }
     const size_t tb = (size_t)std::max(1, g.J) * 2 * nrhs * g.Nrow() * sizeof(double2);
     CHK(dmalloc(H, &w.Tup, tb));
@@ -293,8 +303,16 @@ helm::IOSpec field_io(helm_t H, int s) {
     helm::IOSpec io;
     const auto& g = H->g;
     io.src_rs = g.Nrow() * g.Nx; io.src_ls = g.Nx; io.src_off = g.strips[s].a;
-    io.dst_rs = g.Nrow() * g.Nx; io.dst_ls = g.Nx; io.dst_off = g.strips[s].a;
+    io.dst_rs = g.Nrow() * g.Nx; io.dst_ls = g.Nx; io.dst_off[0] = io.dst_off[1] = g.strips[s].a;
     return io;
+}
+
+// Offset that maps strip-local column q of strip s to its place in the window of interface j
+// (window column x - (beta_j - 2) for x = a_s + q); false if [x0, x0 + n) leaves the window.
+bool win_off(const helm::Geom& g, int s, int j, int x0, int n, int* off) {
+    const int w0 = g.beta[j] - 2;
+    *off = (j - 1) * helm::IWIN - w0 + g.strips[s].a;
+    return x0 >= w0 && x0 + n <= w0 + helm::IWIN;
 }
 
 // Upward sweep (eq. solve_upward) for strips s0..J-1.  full: keep v^(j) on its whole core;
@@ -323,13 +341,22 @@ helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
             io.q_t = g.beta[s] - 1 - S.a;
             io.coef = -ih2;                                   // -2 delta d_x v, delta = 1/(2h)
         }
-        io.dst = w.V;
+        io.dst = full ? w.V : w.Vw;
         io.targets_only = full ? 0 : 1;
         if (full) {
             io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = S.core_hi - S.a;
         } else {
+            // window fields: the first two core columns in the window of interface s, the
+            // last two in that of interface s + 1
+            const long wrow = (long)(g.J - 1) * helm::IWIN;
+            io.dst_rs = g.Nrow() * wrow; io.dst_ls = (int)wrow;
             io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = io.o_lo[0] + 2;
-            if (s < g.J - 1) { io.o_lo[1] = S.core_hi - 2 - S.a; io.o_hi[1] = S.core_hi - S.a; }
+            bool in = win_off(g, s, s, S.core_lo, 2, &io.dst_off[0]);
+            if (s < g.J - 1) {
+                io.o_lo[1] = S.core_hi - 2 - S.a; io.o_hi[1] = S.core_hi - S.a;
+                in = in && win_off(g, s, s + 1, S.core_hi - 2, 2, &io.dst_off[1]);
+            }
+            if (!in) return fail(H, HELM_EINVAL, "core columns outside the interface window");
         }
         if (s < g.J - 1) {
             io.tro0 = trace(w.Tup, s, 0, nrhs, g.Nrow());
@@ -352,8 +379,15 @@ helm_status sweep_down(helm_t H, int nrhs, double2* dst, bool full) {
     for (int s = g.J - 2; s >= 0; --s) {
         const auto& S = g.strips[s];
         helm::IOSpec io = field_io(H, s);
-        io.src = w.G;
+        const long wrow = (long)(g.J - 1) * helm::IWIN;
+        io.src = full ? w.G : w.Gw;
         io.src_lo = g.beta[s + 1] - 1 - S.a; io.src_hi = io.src_lo + 2;
+        if (!full) {
+            io.src_rs = g.Nrow() * wrow; io.src_ls = (int)wrow;
+            if (!win_off(g, s, s + 1, g.beta[s + 1] - 1, 2, &io.src_off))
+                return fail(H, HELM_EINVAL, "columns outside the interface window");
+            io.dst_rs = g.Nrow() * wrow; io.dst_ls = (int)wrow;
+        }
         if (s < g.J - 2) {
             io.trA = trace(w.Tdn, s + 1, 0, nrhs, g.Nrow());
             io.trB = trace(w.Tdn, s + 1, 1, nrhs, g.Nrow());
@@ -367,7 +401,12 @@ helm_status sweep_down(helm_t H, int nrhs, double2* dst, bool full) {
             io.accumulate = 1;
         } else {
             io.o_lo[0] = g.beta[s + 1] - 1 - S.a; io.o_hi[0] = io.o_lo[0] + 2;
-            if (s > 0) { io.o_lo[1] = g.beta[s] + 1 - S.a; io.o_hi[1] = io.o_lo[1] + 2; }
+            io.dst_off[0] = io.src_off;
+            if (s > 0) {
+                io.o_lo[1] = g.beta[s] + 1 - S.a; io.o_hi[1] = io.o_lo[1] + 2;
+                if (!win_off(g, s, s, g.beta[s] + 1, 2, &io.dst_off[1]))
+                    return fail(H, HELM_EINVAL, "columns outside the interface window");
+            }
         }
         if (s > 0) {
             io.tro0 = trace(w.Tdn, s, 0, nrhs, g.Nrow());
@@ -386,29 +425,26 @@ helm_status apply_P_full(helm_t H, int nrhs, const double2* f, double2* out) {
     const auto& g = H->g;
     Work& w = H->wk;
     CHK(sweep_up(H, nrhs, f, 0, true, nullptr));
-    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, 2 * (g.J - 1), w.V, f, w.G, H->st)));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_pairs(H->t, g, nrhs, H->t.rcols, g.J - 1, w.V, f, w.G, H->st)));
     HIPCHK(hipMemcpyAsync(out, w.V, field_bytes(H, nrhs), hipMemcpyDeviceToDevice, H->st));
     CHK(sweep_down(H, nrhs, out, true));
     return HELM_OK;
 }
 
-// Algorithm 3: out = (A P psi) on the reduced columns for reduced psi.
+// Algorithm 3: out = (A P psi) on the reduced columns for reduced psi.  v, g and w live on
+// interface windows only: the reduced sweeps write just the window columns, the residual
+// stencils read just them.
 helm_status apply_AP_reduced(helm_t H, int nrhs, const double2* psi, double2* out) {
     CHK(ensure_sweep_ws(H, nrhs));
     const auto& g = H->g;
     Work& w = H->wk;
-    const int nred = 2 * (g.J - 1);
-    if (nred == 0) return HELM_OK;
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(psi, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.Psi, H->st)));
-    // v^(1) = 0 (Algorithm 3 starts at j = 2): clear the columns of V it would own
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Nrow(), g.Nx, w.V, -1, H->st)));
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_zero_cols(H->t.rcols, 1, nrhs, g.Nrow(), g.Nx, w.V, 0, H->st)));
+    if (g.J < 2) return HELM_OK;
+    // v^(1) = 0 (Algorithm 3 starts at j = 2): strip 1 never writes its window columns
     CHK(sweep_up(H, nrhs, nullptr, 1, false, psi));
-    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.rcols, nred, w.V, w.Psi, w.G, H->st)));
-    CHK(sweep_down(H, nrhs, w.Wf, false));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_stencil_win(0, H->t, g, nrhs, w.Vw, psi, w.Gw, nullptr, H->st)));
+    CHK(sweep_down(H, nrhs, w.Ww, false));
     // h = g - A w on the reduced columns; output psi - h
-    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A_cols(H->t, g, nrhs, H->t.redcols, nred, w.Wf, w.G, w.Hf, H->st)));
-    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols_sub(w.Psi, w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, out, H->st)));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_stencil_win(1, H->t, g, nrhs, w.Ww, psi, w.Gw, out, H->st)));
     return HELM_OK;
 }
 
@@ -897,12 +933,22 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         }
         for (int q = 0; q <= S.W; ++q) saxh[(size_t)s * (WP + 1) + q] = d2(alpha_strip(g, S, S.a + q - 0.5));
     }
+    // pairs of adjacent columns per interface (the pair stencil kernel relies on it)
     std::vector<int> rcols, redcols;
     for (int s = 1; s < J; ++s) {
         rcols.push_back(g.beta[s] - 1); rcols.push_back(g.beta[s]);
         redcols.push_back(g.beta[s]); redcols.push_back(g.beta[s] + 1);
     }
     rcols.push_back(0); redcols.push_back(0);   // never empty
+    // interface windows: first column and k^2 on the window columns
+    const int NI = std::max(1, J - 1);
+    std::vector<int> bw(NI, 0);
+    for (int s = 1; s < J; ++s) bw[s - 1] = g.beta[s] - 2;
+    std::vector<double> k2w((size_t)Nz * Ny * NI * helm::IWIN, 0.0);
+    for (size_t row = 0; row < (size_t)Nz * Ny; ++row)
+        for (int s = 1; s < J; ++s)
+            for (int c = 0; c < helm::IWIN; ++c)
+                k2w[(row * NI + (s - 1)) * helm::IWIN + c] = k2[row * Nx + (bw[s - 1] + c)];
     // per strip, the strip-local columns the reduced sweeps read: beta_s .. beta_s+2 on the
     // left interface, beta_{s+1}-2 .. beta_{s+1} on the right one
     std::vector<int> tcol((size_t)J * 8, -1);
@@ -933,6 +979,8 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if ((st = upload(H, (void**)&t.rcols, rcols.data(), rcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.redcols, redcols.data(), redcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.tcol, tcol.data(), tcol.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.bw, bw.data(), bw.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&t.k2w, k2w.data(), k2w.size() * sizeof(double))) != HELM_OK) return st;
     if (dim == 3) {
         if ((st = upload(H, (void**)&t.az, az.data(), az.size() * sizeof(double2))) != HELM_OK) return st;
         if ((st = upload(H, (void**)&t.azh, azh.data(), azh.size() * sizeof(double2))) != HELM_OK) return st;
@@ -1234,7 +1282,7 @@ helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void*
     io.src_rs = g.Nrow() * W; io.src_ls = W; io.src_off = 0;
     io.src_lo = 0; io.src_hi = W;
     io.dst = static_cast<double2*>(x);
-    io.dst_rs = g.Nrow() * W; io.dst_ls = W; io.dst_off = 0;
+    io.dst_rs = g.Nrow() * W; io.dst_ls = W; io.dst_off[0] = io.dst_off[1] = 0;
     io.o_lo[0] = 0; io.o_hi[0] = W;
     return strip_solve_any(H, strip, nrhs, io);
 }

@@ -87,8 +87,9 @@ struct IOSpec {
     int src_lo = 0, src_hi = 0;    // strip-local columns taken from src
     // transmission source coef * (trB - trA) added at columns q_t and q_t + 1
     const double2* trA = nullptr; const double2* trB = nullptr; int q_t = -1; double coef = 0;
-    // outputs: up to two strip-local column ranges written (or accumulated) into dst
-    double2* dst = nullptr;  long dst_rs = 0; int dst_ls = 0; int dst_off = 0;
+    // outputs: up to two strip-local column ranges written (or accumulated) into dst; column
+    // q of range k goes to dst[r * dst_rs + row * dst_ls + q + dst_off[k]]
+    double2* dst = nullptr;  long dst_rs = 0; int dst_ls = 0; int dst_off[2] = {0, 0};
     int o_lo[2] = {0, 0}, o_hi[2] = {0, 0};
     int accumulate = 0;
     // outgoing traces: x[qo[0]] -> tro[0][r*Ny + l], x[qo[1]] -> tro[1][r*Ny + l]
@@ -114,9 +115,16 @@ struct DevTables {
     int* rcols = nullptr;       // 2(J-1)   residual columns beta_j - 1, beta_j
     int* redcols = nullptr;     // 2(J-1)   reduced columns beta_j, beta_j + 1
     int* tcol = nullptr;        // J*8      strip-local columns whose spike rows are kept compact
+    int* bw = nullptr;          // J-1      first column beta_j - 2 of each interface window
+    double* k2w = nullptr;      // Nrow*(J-1)*IWIN  k^2 on the interface windows
     double2* az = nullptr;      // Nz       (3-D) alpha_z at points
     double2* azh = nullptr;     // Nz+1     (3-D) alpha_z at half-points
 };
+
+// Interface windows: the reduced form only ever touches the columns beta_j - 2 .. beta_j + 2
+// around each interface j = 1..J-1.  Window fields hold just those, [nrhs][Nrow][J-1][IWIN]
+// (the IWIN columns of consecutive interfaces side by side in a row).
+constexpr int IWIN = 5;
 
 // ---- 3-D slabs (kernels_3d.hip)
 constexpr int BP3_MAX = 8192;   // largest padded slab block
@@ -175,9 +183,16 @@ hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& c
 
 hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
                           const double2* f, double2* out, hipStream_t st);
-hipError_t launch_apply_A_cols(const DevTables& t, const Geom& g, int nrhs, const int* cols,
-                               int ncols, const double2* u, const double2* f, double2* out,
+// f - A u (or A u when f is null) on npairs pairs of adjacent columns: cols[2q + 1] == cols[2q] + 1
+hipError_t launch_apply_A_pairs(const DevTables& t, const Geom& g, int nrhs, const int* cols,
+                               int npairs, const double2* u, const double2* f, double2* out,
                                hipStream_t st);
+// Reduced-form stencils on interface windows (u, g window fields; psi, out reduced vectors
+// [nrhs][Nrow][2(J-1)] holding columns beta_j, beta_j + 1):
+//   mode 0: g = psi - A u on the window columns beta_j - 1, beta_j (psi is 0 on beta_j - 1)
+//   mode 1: out = psi - (g - A u) on beta_j, beta_j + 1
+hipError_t launch_stencil_win(int mode, const DevTables& t, const Geom& g, int nrhs, const double2* u,
+                              const double2* psi, double2* gw, double2* out, hipStream_t st);
 
 // Batched FP64 vector kernels for GMRES; vectors are [nrhs][n] complex, a basis is
 // kmax contiguous vectors of nrhs*n each.
@@ -193,13 +208,9 @@ hipError_t launch_lincomb(const double2* V, int nvec, const double2* y, double2*
                           int nrhs, long n, int accumulate, hipStream_t st);
 hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, int nrhs,
                               int Ny, int Nx, double2* red, hipStream_t st);
-hipError_t launch_gather_cols_sub(const double2* fa, const double2* fb, const int* cols, int ncols,
-                                  int nrhs, int Ny, int Nx, double2* red, hipStream_t st);
 hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
                                int Ny, int Nx, double2* field, hipStream_t st);
 // zero column cols[k] + shift of every row, k < ncols
-hipError_t launch_zero_cols(const int* cols, int ncols, int nrhs, int Ny, int Nx, double2* field,
-                            int shift, hipStream_t st);
 hipError_t launch_axpby(const double2* x, const double2* y, double2* out, double a, double b,
                         long n, hipStream_t st);
 

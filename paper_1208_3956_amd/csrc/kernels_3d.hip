@@ -408,9 +408,10 @@ __device__ inline void scatter3(const Solve3Args<T>& a, int r, int l, int k, cpl
     const int q = k % a.W, z = k / a.W;
     const size_t rho = (size_t)z * a.Ny + l;
     const double2 xv = ccast<double2>(x);
-    const bool o = (q >= io.o_lo[0] && q < io.o_hi[0]) || (q >= io.o_lo[1] && q < io.o_hi[1]);
+    const bool o0 = q >= io.o_lo[0] && q < io.o_hi[0];
+    const bool o = o0 || (q >= io.o_lo[1] && q < io.o_hi[1]);
     if (o && io.dst) {
-        double2* p = io.dst + (size_t)r * io.dst_rs + rho * io.dst_ls + (q + io.dst_off);
+        double2* p = io.dst + (size_t)r * io.dst_rs + rho * io.dst_ls + (q + io.dst_off[o0 ? 0 : 1]);
         *p = io.accumulate ? cadd(*p, xv) : xv;
     }
     if (q == io.qo0 && io.tro0) io.tro0[(size_t)r * a.Nrow + rho] = xv;

@@ -93,9 +93,10 @@ template <typename T>
 __device__ inline void scatter(const SolveArgs<T>& a, int r, int l, int i, cplx<T> x) {
     const IOSpec& io = a.io;
     const double2 xv = ccast<double2>(x);
-    const bool o = (i >= io.o_lo[0] && i < io.o_hi[0]) || (i >= io.o_lo[1] && i < io.o_hi[1]);
+    const bool o0 = i >= io.o_lo[0] && i < io.o_hi[0];
+    const bool o = o0 || (i >= io.o_lo[1] && i < io.o_hi[1]);
     if (o && io.dst) {
-        double2* p = io.dst + (size_t)r * io.dst_rs + (size_t)l * io.dst_ls + (i + io.dst_off);
+        double2* p = io.dst + (size_t)r * io.dst_rs + (size_t)l * io.dst_ls + (i + io.dst_off[o0 ? 0 : 1]);
         *p = io.accumulate ? cadd(*p, xv) : xv;
     }
     if (i == io.qo0 && io.tro0) io.tro0[(size_t)r * a.Ny + l] = xv;
@@ -755,8 +756,10 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets(SolveArgs<T> a) {
 // complex64 target columns per chunk as one small product on v_mfma_f32_16x16x4f32:
 // rows (l, t) of the chunk's interior rows l and the 8 target columns t, columns 16
 // right-hand sides, k over [x_above; x_below] (128): out = Fc(l, t, :) [xa; xb], x = y - out.
-// Grid (chunks, right-hand-side groups of 16); wave w takes row tiles w, w + 4, ...  The
-// separator row that closes the chunk is copied (its x is final after phase B).
+// Grid (chunks, right-hand-side groups of 16, tile groups); wave w of tile group z takes row
+// tiles w + 4 z, w + 4 z + 4 gridDim.z, ...  Every workgroup stages the chunk's two separator
+// vectors; the separator row that closes the chunk is copied (its x is final after phase B)
+// by tile group 0.
 __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a) {
     using V = float2;
     __shared__ V X[2 * WP][16];
@@ -788,7 +791,7 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
     __syncthreads();
     const int rn = rbase + n;
     const int nrows = nr * 8, ntile = (nrows + 15) / 16;
-    for (int tile = w; tile < ntile; tile += 4) {
+    for (int tile = w + 4 * (int)blockIdx.z; tile < ntile; tile += 4 * (int)gridDim.z) {
         // A operands: row rho = 16 tile + n (clamped), k = 4 s + q4
         const int rho = min(16 * tile + n, nrows - 1);
         const int l = r0 + (rho >> 3), tt = rho & 7;
@@ -835,7 +838,7 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
         }
     }
     // the separator row closing this chunk
-    if (has_b && t < 8 * 16) {
+    if (has_b && blockIdx.z == 0 && t < 8 * 16) {
         const int tt = t >> 4, r = rbase + (t & 15), q = a.tcol[tt];
         if (q >= 0 && r < a.nrhs) scatter<float>(a, r, r1, q, a.Yw[((size_t)r * a.Ny + r1) * WP + q]);
     }
@@ -880,8 +883,13 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
     }
     if (kt) kt->begin(K_PHASE_C, st);
     if (targets) {
-        if constexpr (std::is_same<T, float>::value)
-            hipLaunchKernelGGL(k_phase_c_targets_mfma, dim3(a.P, (a.nrhs + 15) / 16), dim3(NT), 0, st, a);
+        if constexpr (std::is_same<T, float>::value) {
+            // the 16-row tiles of a chunk are spread over TS workgroups (two tiles per wave
+            // at m = 32: measured faster than one or four)
+            const int tiles = ((a.m - 1) * 8 + 15) / 16;
+            const int TS = std::min(8, std::max(1, (tiles + 7) / 8));
+            hipLaunchKernelGGL(k_phase_c_targets_mfma, dim3(a.P, (a.nrhs + 15) / 16, TS), dim3(NT), 0, st, a);
+        }
         else
             hipLaunchKernelGGL((k_phase_c_targets<T>), dim3((a.Ny + CT_ROWS - 1) / CT_ROWS, (a.nrhs + 31) / 32),
                                dim3(NT), 0, st, a);

@@ -68,17 +68,110 @@ __global__ void __launch_bounds__(256) k_apply_A(StencilArgs s, const double2* _
     out[p] = f ? csub(f[p], a) : a;
 }
 
-__global__ void __launch_bounds__(256) k_apply_A_cols(StencilArgs s, const int* __restrict__ cols,
-                                                      int ncols, const double2* __restrict__ u,
-                                                      const double2* __restrict__ f,
-                                                      double2* __restrict__ out) {
-    const int l = blockIdx.x * 256 + threadIdx.x;       // row z * Ny + y
-    const int i = cols[blockIdx.y];
-    const size_t off = (size_t)blockIdx.z * s.Nx * s.Ny * s.Nz;
-    if (l >= s.Ny * s.Nz) return;
-    double2 a = stencil_at(s, u + off, l, i);
-    const size_t p = off + (size_t)l * s.Nx + i;
-    out[p] = f ? csub(f[p], a) : a;
+// The same on pairs of adjacent columns (cols[2q + 1] = cols[2q] + 1): a workgroup takes 64
+// rows of one pair and one right-hand side; the 4-column window i0 - 1 .. i0 + 2 of its rows
+// and the two rows around them go through LDS with 64-byte contiguous loads per row (a
+// thread per row and column would touch a separate cache line for every value).
+__global__ void __launch_bounds__(256) k_apply_A_pairs(StencilArgs s, const int* __restrict__ cols,
+                                                       const double2* __restrict__ u,
+                                                       const double2* __restrict__ f,
+                                                       double2* __restrict__ out) {
+    __shared__ double2 T[66][4];
+    const int t = threadIdx.x, c = t & 3, rr = t >> 2;
+    const int i0 = cols[2 * blockIdx.y];
+    const int nrow = s.Ny * s.Nz;
+    const int row0 = blockIdx.x * 64;
+    const size_t off = (size_t)blockIdx.z * s.Nx * nrow;
+    const int x = i0 - 1 + c;
+    const bool xin = x >= 0 && x < s.Nx;
+    auto ld = [&](int row) {
+        return (xin && row >= 0 && row < nrow) ? u[off + (size_t)row * s.Nx + x] : cmk<double2>(0, 0);
+    };
+    T[rr + 1][c] = ld(row0 + rr);
+    if (t < 8) T[t < 4 ? 0 : 65][c] = ld(t < 4 ? row0 - 1 : row0 + 64);
+    __syncthreads();
+    const int row = row0 + rr;
+    if (c == 0 || c == 3 || row >= nrow || !xin) return;
+    const int i = x, l = row % s.Ny, z = row / s.Ny;
+    const double2 uc = T[rr + 1][c];
+    const double2 ue = T[rr + 1][c + 1], uw = T[rr + 1][c - 1];
+    const double2 un = (l + 1 < s.Ny) ? T[rr + 2][c] : cmk<double2>(0, 0);
+    const double2 us = (l > 0) ? T[rr][c] : cmk<double2>(0, 0);
+    const double2 ae = s.axh[i + 1], aw = s.axh[i];
+    const double2 an = s.ayh[l + 1], as = s.ayh[l];
+    double2 xp = cadd(cmul(ae, csub(uc, ue)), cmul(aw, csub(uc, uw)));
+    xp = cmul(s.ax[i], xp);
+    double2 yp = cadd(cmul(an, csub(uc, un)), cmul(as, csub(uc, us)));
+    yp = cmul(s.ay[l], yp);
+    double2 r = cadd(xp, yp);
+    const size_t p = off + (size_t)row * s.Nx + i;
+    if (s.Nz > 1) {
+        const size_t pl = (size_t)s.Ny * s.Nx;
+        const double2 uu = (z + 1 < s.Nz) ? u[p + pl] : cmk<double2>(0, 0);
+        const double2 ud = (z > 0) ? u[p - pl] : cmk<double2>(0, 0);
+        double2 zp = cadd(cmul(s.azh[z + 1], csub(uc, uu)), cmul(s.azh[z], csub(uc, ud)));
+        r = cadd(r, cmul(s.az[z], zp));
+    }
+    r.x *= s.inv_h2; r.y *= s.inv_h2;
+    const double kk = s.k2[(size_t)row * s.Nx + i];
+    r.x -= kk * uc.x;
+    r.y -= kk * uc.y;
+    out[p] = f ? csub(f[p], r) : r;
+}
+
+// Reduced-form stencils on interface windows (layout [nrhs][Nrow][NI][IWIN], window j holding
+// the columns bw[j] .. bw[j] + IWIN - 1).  One thread per row, interface and output column;
+// consecutive threads take the two columns of one window, then the next window of the row.
+//   MODE 0: g[c] = psi(c) - (A u)[c], c = 1, 2, with psi(c) = psi[.., 2 j + c - 2] for c = 2, 0 for c = 1
+//   MODE 1: out[.., 2 j + k] = psi[.., 2 j + k] - (g[2 + k] - (A u)[2 + k]), k = 0, 1
+template <int MODE>
+__global__ void __launch_bounds__(256) k_stencil_win(StencilArgs s, const int* __restrict__ bw,
+                                                     const double* __restrict__ k2w, int NI, int nrhs,
+                                                     const double2* __restrict__ u,
+                                                     const double2* __restrict__ psi,
+                                                     double2* __restrict__ gw, double2* __restrict__ out) {
+    const int nrow = s.Ny * s.Nz;
+    const size_t wrow = (size_t)NI * IWIN;
+    const size_t tot = (size_t)nrhs * nrow * NI * 2;
+    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
+         q += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(q & 1);
+        const int j = (int)((q >> 1) % NI);
+        const size_t rr = (q >> 1) / NI;            // r * nrow + row
+        const int row = (int)(rr % nrow);
+        const int c = (MODE == 0 ? 1 : 2) + k;
+        const int i = bw[j] + c;
+        const int l = row % s.Ny, z = row / s.Ny;
+        const size_t b = rr * wrow + (size_t)j * IWIN + c;
+        const double2 uc = u[b], ue = u[b + 1], uw = u[b - 1];
+        const double2 un = (l + 1 < s.Ny) ? u[b + wrow] : cmk<double2>(0, 0);
+        const double2 us = (l > 0) ? u[b - wrow] : cmk<double2>(0, 0);
+        const double2 ae = s.axh[i + 1], aw = s.axh[i];
+        const double2 an = s.ayh[l + 1], as = s.ayh[l];
+        double2 xp = cadd(cmul(ae, csub(uc, ue)), cmul(aw, csub(uc, uw)));
+        xp = cmul(s.ax[i], xp);
+        double2 yp = cadd(cmul(an, csub(uc, un)), cmul(as, csub(uc, us)));
+        yp = cmul(s.ay[l], yp);
+        double2 a = cadd(xp, yp);
+        if (s.Nz > 1) {
+            const size_t pl = (size_t)s.Ny * wrow;
+            const double2 uu = (z + 1 < s.Nz) ? u[b + pl] : cmk<double2>(0, 0);
+            const double2 ud = (z > 0) ? u[b - pl] : cmk<double2>(0, 0);
+            double2 zp = cadd(cmul(s.azh[z + 1], csub(uc, uu)), cmul(s.azh[z], csub(uc, ud)));
+            a = cadd(a, cmul(s.az[z], zp));
+        }
+        a.x *= s.inv_h2; a.y *= s.inv_h2;
+        const double kk = k2w[(size_t)row * wrow + (size_t)j * IWIN + c];
+        a.x -= kk * uc.x;
+        a.y -= kk * uc.y;
+        const size_t pr = rr * (2 * (size_t)NI) + 2 * (size_t)j + (c - 2);
+        if (MODE == 0) {
+            const double2 f = c >= 2 ? psi[pr] : cmk<double2>(0, 0);
+            gw[b] = csub(f, a);
+        } else {
+            out[pr] = csub(psi[pr], csub(gw[b], a));
+        }
+    }
 }
 
 StencilArgs stencil_args(const DevTables& t, const Geom& g) {
@@ -220,19 +313,6 @@ __global__ void k_gather_cols(const double2* __restrict__ field, const int* __re
     }
 }
 
-// red[r][l][k] = a[r][l][cols[k]] - b[r][l][cols[k]]
-__global__ void k_gather_cols_sub(const double2* __restrict__ fa, const double2* __restrict__ fb,
-                                  const int* __restrict__ cols, int ncols, int nrhs, int Ny, int Nx,
-                                  double2* __restrict__ red) {
-    const size_t tot = (size_t)nrhs * Ny * ncols;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
-         q += (size_t)gridDim.x * blockDim.x) {
-        const int k = (int)(q % ncols);
-        const size_t p = (q / ncols) * Nx + cols[k];
-        red[q] = csub(fa[p], fb[p]);
-    }
-}
-
 __global__ void k_scatter_cols(const double2* __restrict__ red, const int* __restrict__ cols,
                                int ncols, int nrhs, int Ny, int Nx, double2* __restrict__ field) {
     const size_t tot = (size_t)nrhs * Ny * ncols;
@@ -241,17 +321,6 @@ __global__ void k_scatter_cols(const double2* __restrict__ red, const int* __res
         const int k = (int)(q % ncols);
         const size_t rl = q / ncols;
         field[rl * Nx + cols[k]] = red[q];
-    }
-}
-
-__global__ void k_zero_cols(const int* __restrict__ cols, int ncols, int nrhs, int Ny, int Nx,
-                            double2* __restrict__ field, int shift) {
-    const size_t tot = (size_t)nrhs * Ny * ncols;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
-         q += (size_t)gridDim.x * blockDim.x) {
-        const int k = (int)(q % ncols);
-        const size_t rl = q / ncols;
-        field[rl * Nx + cols[k] + shift] = cmk<double2>(0, 0);
     }
 }
 
@@ -286,13 +355,27 @@ hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_apply_A_cols(const DevTables& t, const Geom& g, int nrhs, const int* cols,
-                               int ncols, const double2* u, const double2* f, double2* out,
+hipError_t launch_apply_A_pairs(const DevTables& t, const Geom& g, int nrhs, const int* cols,
+                               int npairs, const double2* u, const double2* f, double2* out,
                                hipStream_t st) {
-    if (ncols <= 0) return hipSuccess;
+    if (npairs <= 0) return hipSuccess;
     StencilArgs s = stencil_args(t, g);
-    dim3 grid((unsigned)((g.Nrow() + 255) / 256), ncols, nrhs);
-    hipLaunchKernelGGL(k_apply_A_cols, grid, dim3(256), 0, st, s, cols, ncols, u, f, out);
+    dim3 grid((unsigned)((g.Nrow() + 63) / 64), npairs, nrhs);
+    hipLaunchKernelGGL(k_apply_A_pairs, grid, dim3(256), 0, st, s, cols, u, f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_stencil_win(int mode, const DevTables& t, const Geom& g, int nrhs, const double2* u,
+                              const double2* psi, double2* gw, double2* out, hipStream_t st) {
+    const int NI = g.J - 1;
+    if (NI <= 0) return hipSuccess;
+    StencilArgs s = stencil_args(t, g);
+    const size_t tot = (size_t)nrhs * g.Nrow() * NI * 2;
+    const dim3 grid(grid_for(tot));
+    if (mode == 0)
+        hipLaunchKernelGGL(k_stencil_win<0>, grid, dim3(256), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
+    else
+        hipLaunchKernelGGL(k_stencil_win<1>, grid, dim3(256), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
     return hipGetLastError();
 }
 
@@ -342,27 +425,11 @@ hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, 
     return hipGetLastError();
 }
 
-hipError_t launch_gather_cols_sub(const double2* fa, const double2* fb, const int* cols, int ncols,
-                                  int nrhs, int Ny, int Nx, double2* red, hipStream_t st) {
-    if (ncols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_cols_sub, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
-                       fa, fb, cols, ncols, nrhs, Ny, Nx, red);
-    return hipGetLastError();
-}
-
 hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
                                int Ny, int Nx, double2* field, hipStream_t st) {
     if (ncols <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_cols, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
                        red, cols, ncols, nrhs, Ny, Nx, field);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero_cols(const int* cols, int ncols, int nrhs, int Ny, int Nx, double2* field,
-                            int shift, hipStream_t st) {
-    if (ncols <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_cols, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
-                       cols, ncols, nrhs, Ny, Nx, field, shift);
     return hipGetLastError();
 }
 
