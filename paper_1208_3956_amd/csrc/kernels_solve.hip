@@ -577,6 +577,29 @@ __device__ void sep_chain(int n, bool chain, cplx<T> v0, T sgn, BF blk, RF row,
     __syncthreads();
 }
 
+// Independent updates v_k = in_k + M_k v (k < n, the same vector v for every k): wave w
+// takes k = w, w + 4, ..., each lane one row of the full 64-column product, so the waves need
+// no barrier between updates.  v0 is this lane's entry of v.
+template <typename T, typename BF, typename RF>
+__device__ void sep_fix(int n, cplx<T> v0, BF blk, RF row, cplx<T> (*vecw)[WP]) {
+    using V = cplx<T>;
+    const int i = threadIdx.x & (WP - 1), w = threadIdx.x >> 6;
+    vecw[w][i] = v0;
+    __builtin_amdgcn_wave_barrier();
+    for (int k = w; k < n; k += 4) {
+        const V* M = blk(k) + i;
+        V acc0 = cmk<V>(0, 0), acc1 = acc0;
+#pragma unroll 16
+        for (int kk = 0; kk < WP; kk += 2) {
+            cfma(acc0, M[(size_t)kk * WP], vecw[w][kk]);
+            cfma(acc1, M[(size_t)(kk + 1) * WP], vecw[w][kk + 1]);
+        }
+        V* dst = row(k) + i;
+        *dst = cadd(*dst, cadd(acc0, acc1));
+    }
+    __syncthreads();
+}
+
 template <typename T>
 struct SepCtx {
     const SolveArgs<T>& a;
@@ -598,11 +621,37 @@ struct SepCtx {
     V* Yr = a.Yw + (size_t)r * a.Ny * WP;                                 \
     (void)i;
 
-// local forward chains: zeta_c = a_c - K_c zeta_{c-1} inside group g = blockIdx.y
+// local forward chains: zeta_c = a_c - K_c zeta_{c-1} inside group g = blockIdx.y.  First
+// the group's right-hand sides a_c = G'_c r^_c, r^_c = r_s - c_s y_{s-1} - b_s y_{s+1}
+// (s = sep(c)), independent per separator: wave w takes c0 + w, c0 + w + 4, ...
 template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) {
     SEPK_PROLOGUE
     const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
+    {
+        const int w = threadIdx.x >> 6;
+        for (int c = c0 + w; c <= c1; c += 4) {
+            const int sr = X.sep(c);
+            V v = cmk<V>(0, 0);
+            if (i < a.W) {
+                v = gather<T>(a.io, r, sr, i, a.Ny);
+                v = csub(v, cmul(ccast<V>(a.cy[sr]), Yr[(size_t)(sr - 1) * WP + i]));
+                v = csub(v, cmul(ccast<V>(a.by[sr]), Yr[(size_t)(sr + 1) * WP + i]));
+            }
+            vecw[w][i] = v;
+            __builtin_amdgcn_wave_barrier();
+            const V* M = fslot(a, sr, 0) + i;
+            V acc0 = cmk<V>(0, 0), acc1 = acc0;
+#pragma unroll 16
+            for (int kk = 0; kk < WP; kk += 2) {
+                cfma(acc0, M[(size_t)kk * WP], vecw[w][kk]);
+                cfma(acc1, M[(size_t)(kk + 1) * WP], vecw[w][kk + 1]);
+            }
+            Yr[(size_t)sr * WP + i] = cadd(acc0, acc1);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+    }
     sep_chain<T, D>(c1 - c0, true, X.yrow(Yr, c0)[i], T(-1),
                     [&](int k) { return fslot(a, X.sep(c0 + 1 + k), 1); },
                     [&](int k) { return X.yrow(Yr, c0 + 1 + k); }, vecw, part);
@@ -624,9 +673,9 @@ __global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) {
     SEPK_PROLOGUE
     const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
     if (g >= 1)
-        sep_chain<T, D>(c1 - c0, false, X.yrow(Yr, X.last(g - 1))[i], T(1),
-                        [&](int k) { return X.prop(c0 + k, 0); },
-                        [&](int k) { return X.yrow(Yr, c0 + k); }, vecw, part);
+        sep_fix<T>(c1 - c0, X.yrow(Yr, X.last(g - 1))[i],
+                   [&](int k) { return X.prop(c0 + k, 0); },
+                   [&](int k) { return X.yrow(Yr, c0 + k); }, vecw);
     sep_chain<T, D>(c1 - c0, true, X.yrow(Yr, c1)[i], T(-1),
                     [&](int k) { return fslot(a, X.sep(c1 - 1 - k), 2); },
                     [&](int k) { return X.yrow(Yr, c1 - 1 - k); }, vecw, part);
@@ -646,9 +695,9 @@ template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_bwd_fix(SolveArgs<T> a) {
     SEPK_PROLOGUE
     const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
-    sep_chain<T, D>(c1 - c0, false, X.yrow(Yr, X.first(g + 1))[i], T(1),
-                    [&](int k) { return X.prop(c0 + 1 + k, 1); },
-                    [&](int k) { return X.yrow(Yr, c0 + 1 + k); }, vecw, part);
+    sep_fix<T>(c1 - c0, X.yrow(Yr, X.first(g + 1))[i],
+               [&](int k) { return X.prop(c0 + 1 + k, 1); },
+               [&](int k) { return X.yrow(Yr, c0 + 1 + k); }, vecw);
 }
 #undef SEPK_PROLOGUE
 
@@ -864,8 +913,8 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
     if (kt) kt->end(K_PHASE_A, st);
     if (a.P > 1) {
         if (kt) kt->begin(K_PHASE_B, st);
-        hipLaunchKernelGGL((k_phase_b0<T, R>), dim3(a.P - 1, RG), dim3(NT), 0, st, a);
         if (a.P > 2 && a.G >= 2 && a.Fs) {
+            // the local forward chains form their own right-hand sides a_c
             constexpr int DS = Depth<T>::D;
             const unsigned nr = (unsigned)a.nrhs;
             hipLaunchKernelGGL((k_sep_fwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
@@ -873,7 +922,10 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
             hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
             hipLaunchKernelGGL((k_sep_bwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
             hipLaunchKernelGGL((k_sep_bwd_fix<T, DS>), dim3(nr, a.G - 1), dim3(NT), 0, st, a);
-        } else if (a.P > 2) {
+        } else {
+            hipLaunchKernelGGL((k_phase_b0<T, R>), dim3(a.P - 1, RG), dim3(NT), 0, st, a);
+        }
+        if (a.P > 2 && !(a.G >= 2 && a.Fs)) {
             if (a.P - 1 <= ZMAX)
                 hipLaunchKernelGGL((k_phase_b<T, Depth<T>::D, true>), dim3(a.nrhs), dim3(NT), 0, st, a);
             else
