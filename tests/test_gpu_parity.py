@@ -100,12 +100,16 @@ def test_strip_solve_c128(case, chunk, nrhs):
     H.close()
 
 
-def test_strip_solve_mixed(case):
+@pytest.mark.parametrize("chunk", [2, 9, 16, 24])
+@pytest.mark.parametrize("nrhs", [5, 19])
+def test_strip_solve_mixed(case, chunk, nrhs):
+    """complex64 strip solves: one-wave chains (chunks of up to 16 rows, including the
+    single-row chunks of chunk = 2) and four-wave chains (24), ragged right-hand-side groups."""
     wl, g, A, S = case
-    H = _gpu(wl, prec="mixed", chunk=9)
-    rng = np.random.default_rng(3)
+    H = _gpu(wl, prec="mixed", chunk=chunk)
+    rng = np.random.default_rng(3 + chunk + nrhs)
     for s, st in enumerate(g.strips):
-        r = _rand(rng, (5, g.N_y, st.W))
+        r = _rand(rng, (nrhs, g.N_y, st.W))
         x = H.strip_solve(s, _t(r)).cpu().numpy()
         ref = np.stack([S.solve(s, rk) for rk in r])
         assert _rel(x, ref) < TOL_P_C64, (s, _rel(x, ref))
