@@ -39,7 +39,6 @@ struct SolveArgs {
     IOSpec io;
     int Ny, W, m, P, nrhs;
     int q, G;             // separator groups (two-level separator solve when G >= 2)
-    int qlo, qhi;         // strip-local columns that carry a source (k_rhs_prep)
 };
 
 template <typename T>
@@ -383,207 +382,6 @@ __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
     if constexpr (D > 3) { if (off == 3) bwd_loop(std::integral_constant<int, 3 % D>{}); }
 }
 
-// ---------------------------------------------------------------- right-hand side preparation
-// The strip right-hand side (source field plus transmission term) in the working precision on
-// the columns [qlo, qhi) that carry a source, written into the phase-A workspace for every row.
-template <typename T>
-__global__ void __launch_bounds__(256) k_rhs_prep(SolveArgs<T> a) {
-    const int nq = a.qhi - a.qlo;
-    const size_t tot = (size_t)a.nrhs * a.Ny * nq;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < tot;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int q = a.qlo + (int)(e % nq);
-        const size_t rl = e / nq;                 // r * Ny + l
-        const int l = (int)(rl % a.Ny), r = (int)(rl / a.Ny);
-        a.Yw[rl * WP + q] = gather<T>(a.io, r, l, q, a.Ny);
-    }
-}
-
-// ---------------------------------------------------------------- phase A, one wave per chain
-// complex64, 16 right-hand sides per wave and the whole 64-row block product in one wave
-// (four 16-row tiles, 256 MFMAs per step).  A chain then needs no barrier: the step's
-// right-hand-side panel goes through the wave's own LDS slice (written and read by the same
-// wave, in order).  The factor blocks come from global memory straight into registers, in
-// two half blocks (k-steps 0-7 and 8-15): once the products of a half are issued, the same
-// half of the next step's block is loaded into its registers, so every load has the other
-// half's products (128 MFMAs) to arrive.  Lane (n, q4) owns output rows 16 t + 4 q4 + j of
-// right-hand side n.
-// Suited to short chunks (several chains per SIMD's worth of chunks).
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-k_phase_a_w1(SolveArgs<float> a) {
-    using V = float2;
-    __shared__ V Vs[WP][16];
-    const int lane = threadIdx.x, n = lane & 15, q4 = lane >> 4;
-    const int c = blockIdx.x, rbase = blockIdx.y * 16;
-    const int r0 = c * a.m;
-    const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
-    const int nr = r1 - r0;
-    const int nsteps = 2 * nr - 1;
-    const V zero = make_float2(0.f, 0.f);
-    const int rn = rbase + n;
-    const bool rn_ok = rn < a.nrhs;
-    const size_t ybase = (size_t)(rn_ok ? rn : 0) * a.Ny * WP + 4 * q4;
-    // targets-only solves keep y at the compact target columns: a 64-bit column mask
-    unsigned long long tmask = 0;
-    for (int k = 0; k < 8; ++k)
-        if (a.tcol[k] >= 0) tmask |= 1ull << a.tcol[k];
-    auto row_of = [&](int k) __attribute__((always_inline)) {
-        k = k < nsteps ? k : nsteps - 1;
-        return k < nr ? r0 + k : r1 - 2 - (k - nr);
-    };
-    // half h of the block of step k: k-steps 8 h .. 8 h + 7
-    auto load_half = [&](int k, int h, V (&g)[4][8]) __attribute__((always_inline)) {
-        const V* G = fslot(a, row_of(k), 0) + n;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int ss = 0; ss < 8; ++ss) g[t][ss] = G[(size_t)(4 * (8 * h + ss) + q4) * WP + 16 * t];
-    };
-    V H0[4][8], H1[4][8];
-    load_half(0, 0, H0);
-    load_half(0, 1, H1);
-    // right-hand side of the lane's 16 outputs (forward rows): k_rhs_prep left it in Yw on
-    // the columns [qlo, qhi); the other columns of Yw hold stale values and are masked
-    float4 rr[4][2];
-    auto load_rhs = [&](int l) __attribute__((always_inline)) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float4* p = reinterpret_cast<const float4*>(a.Yw + ybase + (size_t)l * WP + 16 * t);
-            rr[t][0] = p[0];
-            rr[t][1] = p[1];
-        }
-    };
-    V zc[4][4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) zc[t][j] = zero;
-    auto keep = [](bool on, V x) __attribute__((always_inline)) { return make_float2(on ? x.x : 0.f, on ? x.y : 0.f); };
-
-    // product of the block of step k with the panel in Vs; then the next step's halves
-    auto product = [&](int k, V (&out)[4][4]) __attribute__((always_inline)) {
-        V (&ga)[4][8] = H0;
-        V (&gb)[4][8] = H1;
-        V vb[16];
-#pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) vb[s4] = Vs[4 * s4 + q4][n];
-        mf4 aR[4], aI[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) { aR[t] = mf4{0.f, 0.f, 0.f, 0.f}; aI[t] = aR[t]; }
-#pragma unroll
-        for (int ss = 0; ss < 8; ++ss)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const V g = ga[t][ss], v = vb[ss];
-                aR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x, v.x, aR[t], 0, 0, 0);
-                aI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x, v.y, aI[t], 0, 0, 0);
-                aR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-g.y, v.y, aR[t], 0, 0, 0);
-                aI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.y, v.x, aI[t], 0, 0, 0);
-            }
-        load_half(k + 1, 0, ga);
-#pragma unroll
-        for (int ss = 0; ss < 8; ++ss)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const V g = gb[t][ss], v = vb[8 + ss];
-                aR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x, v.x, aR[t], 0, 0, 0);
-                aI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x, v.y, aI[t], 0, 0, 0);
-                aR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-g.y, v.y, aR[t], 0, 0, 0);
-                aI[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g.y, v.x, aI[t], 0, 0, 0);
-            }
-        load_half(k + 1, 1, gb);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) out[t][j] = make_float2(aR[t][j], aI[t][j]);
-    };
-    auto put_panel = [&](const V (&v)[4][4]) __attribute__((always_inline)) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) Vs[16 * t + 4 * q4 + j][n] = v[t][j];
-        __builtin_amdgcn_wave_barrier();
-    };
-
-    // ---- forward row l = r0 + k:  z_l = G_l (r_l - c_l z_{l-1})
-    double2 cnext = a.cy[r0];
-    load_rhs(r0);
-    auto fwd_step = [&](int k) __attribute__((always_inline)) {
-        const int l = r0 + k;
-        const float clx = k > 0 ? (float)cnext.x : 0.f, cly = k > 0 ? (float)cnext.y : 0.f;
-        const V cl = make_float2(clx, cly);
-        V v[4][4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float4 u = rr[t][j >> 1];
-                const V rv = (j & 1) ? make_float2(u.z, u.w) : make_float2(u.x, u.y);
-                const int q = 16 * t + 4 * q4 + j;
-                v[t][j] = csub(keep(q >= a.qlo && q < a.qhi, rv), cmul(cl, zc[t][j]));
-            }
-        const int ln = l + 1 < r1 ? l + 1 : l;
-        cnext = a.cy[ln];
-        load_rhs(ln);
-        put_panel(v);
-        V acc[4][4];
-        product(k, acc);
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) zc[t][j] = keep(rn_ok, acc[t][j]);
-            if (rn_ok) {
-                float4* p = reinterpret_cast<float4*>(a.Yw + ybase + (size_t)l * WP + 16 * t);
-                p[0] = make_float4(acc[t][0].x, acc[t][0].y, acc[t][1].x, acc[t][1].y);
-                p[1] = make_float4(acc[t][2].x, acc[t][2].y, acc[t][3].x, acc[t][3].y);
-            }
-        }
-    };
-    for (int k = 0; k < nr; ++k) fwd_step(k);
-    if (nr < 2) return;
-    // ---- backward row l = r1 - 2 - (k - nr):  y_l = z_l - b_l G_l y_{l+1}
-    double2 bnext = a.by[r1 - 2];
-    V zn[4][4];
-    auto load_z = [&](int l) __attribute__((always_inline)) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const float4* p = reinterpret_cast<const float4*>(a.Yw + ybase + (size_t)l * WP + 16 * t);
-            const float4 u0 = p[0], u1 = p[1];
-            zn[t][0] = make_float2(u0.x, u0.y); zn[t][1] = make_float2(u0.z, u0.w);
-            zn[t][2] = make_float2(u1.x, u1.y); zn[t][3] = make_float2(u1.z, u1.w);
-        }
-    };
-    load_z(r1 - 2);
-    auto bwd_step = [&](int kk) __attribute__((always_inline)) {
-        const int l = r1 - 2 - (kk - nr);
-        V zl[4][4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) zl[t][j] = zn[t][j];
-        const V bl = ccast<V>(bnext);
-        const int lb = l - 1 >= r0 ? l - 1 : l;
-        bnext = a.by[lb];
-        load_z(lb);
-        put_panel(zc);
-        V acc[4][4];
-        product(kk, acc);
-        __builtin_amdgcn_wave_barrier();
-        const bool store_y = !a.io.targets_only || l == r0;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const V y = csub(zl[t][j], cmul(bl, acc[t][j]));
-                zc[t][j] = keep(rn_ok, y);
-                const bool tq = (tmask >> (16 * t + 4 * q4 + j)) & 1ull;
-                if (rn_ok && (store_y || tq)) a.Yw[ybase + (size_t)l * WP + 16 * t + j] = y;
-            }
-    };
-    for (int kk = nr; kk < nsteps; ++kk) bwd_step(kk);
-}
-
 // ---------------------------------------------------------------- phase B0
 // a_c = G'_c r^_c for every separator (grid: separators x rhs groups), stored at row s_c.
 template <typename T, int R>
@@ -791,7 +589,7 @@ __device__ void sep_fix(int n, cplx<T> v0, BF blk, RF row, cplx<T> (*vecw)[WP]) 
     for (int k = w; k < n; k += 4) {
         const V* M = blk(k) + i;
         V acc0 = cmk<V>(0, 0), acc1 = acc0;
-#pragma unroll
+#pragma unroll 16
         for (int kk = 0; kk < WP; kk += 2) {
             cfma(acc0, M[(size_t)kk * WP], vecw[w][kk]);
             cfma(acc1, M[(size_t)(kk + 1) * WP], vecw[w][kk + 1]);
@@ -844,7 +642,7 @@ __global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) {
             __builtin_amdgcn_wave_barrier();
             const V* M = fslot(a, sr, 0) + i;
             V acc0 = cmk<V>(0, 0), acc1 = acc0;
-#pragma unroll
+#pragma unroll 16
             for (int kk = 0; kk < WP; kk += 2) {
                 cfma(acc0, M[(size_t)kk * WP], vecw[w][kk]);
                 cfma(acc1, M[(size_t)(kk + 1) * WP], vecw[w][kk + 1]);
@@ -1095,9 +893,6 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
     }
 }
 
-// chunks of at most this many rows use the one-wave-per-chain phase A (complex64)
-constexpr int W1_MAX_M = 16;
-
 template <typename T> struct Depth { static constexpr int D = 2; };
 template <> struct Depth<float> { static constexpr int D = 4; };
 
@@ -1107,16 +902,6 @@ void launch_phase_a(const SolveArgs<T>& a, int RG, hipStream_t st) {
 }
 template <>
 void launch_phase_a<float, 16>(const SolveArgs<float>& a, int RG, hipStream_t st) {
-    if (a.m <= W1_MAX_M) {
-        // short chunks: one wave per chain, right-hand side prepared in the workspace first
-        if (a.qhi > a.qlo) {
-            const size_t tot = (size_t)a.nrhs * a.Ny * (a.qhi - a.qlo);
-            const unsigned nb = (unsigned)std::min<size_t>(4096, (tot + 255) / 256);
-            hipLaunchKernelGGL(k_rhs_prep<float>, dim3(nb), dim3(256), 0, st, a);
-        }
-        hipLaunchKernelGGL(k_phase_a_w1, dim3(a.P, RG), dim3(64), 0, st, a);
-        return;
-    }
     hipLaunchKernelGGL(k_phase_a_mfma<2>, dim3(a.P, RG), dim3(NT), 0, st, a);
 }
 
@@ -1192,14 +977,6 @@ hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& c
     }
     a.Ny = g.Ny;
     a.W = g.strips[s].W;
-    {
-        // columns that carry a source: the source range and the two transmission columns
-        int lo = a.io.src_lo < a.io.src_hi ? a.io.src_lo : a.W, hi = a.io.src_lo < a.io.src_hi ? a.io.src_hi : 0;
-        if (a.io.q_t >= 0) { lo = std::min(lo, a.io.q_t); hi = std::max(hi, a.io.q_t + 2); }
-        a.qlo = std::max(lo, 0);
-        a.qhi = std::min(hi, a.W);
-        if (a.qhi < a.qlo) a.qhi = a.qlo;
-    }
     a.m = ch.m;
     a.P = ch.P;
     a.nrhs = nrhs;

@@ -103,8 +103,8 @@ def test_strip_solve_c128(case, chunk, nrhs):
 @pytest.mark.parametrize("chunk", [2, 9, 16, 24])
 @pytest.mark.parametrize("nrhs", [5, 19])
 def test_strip_solve_mixed(case, chunk, nrhs):
-    """complex64 strip solves: one-wave chains (chunks of up to 16 rows, including the
-    single-row chunks of chunk = 2) and four-wave chains (24), ragged right-hand-side groups."""
+    """complex64 strip solves over chunk sizes (single-row chunks at chunk = 2, a ragged last
+    chunk) and ragged right-hand-side groups."""
     wl, g, A, S = case
     H = _gpu(wl, prec="mixed", chunk=chunk)
     rng = np.random.default_rng(3 + chunk + nrhs)
