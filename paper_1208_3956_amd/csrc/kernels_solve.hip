@@ -76,6 +76,37 @@ __device__ inline RawRhs load_raw(const IOSpec& io, int r, int l, int q, int Ny,
     if (!in_tr) { x.ta = cmk<double2>(0.0, 0.0); x.tb = x.ta; }
     return x;
 }
+// The same for the four consecutive columns q0 .. q0 + 3 of one row: the transmission term
+// is the same for both of its columns, so the two trace values are loaded once.
+struct RawRhs4 {
+    double2 v[4];
+    double2 ta, tb;
+};
+__device__ inline void load_raw4(RawRhs4& x, const IOSpec& io, int r, int l, int q0, int Ny, int nrhs, int W) {
+    const bool rok = r < nrhs;
+    const bool tr = rok && io.q_t >= 0 && io.q_t + 1 >= q0 && io.q_t <= q0 + 3;
+    const size_t pt = tr ? (size_t)r * Ny + l : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int q = q0 + j;
+        const bool in_src = rok && q < W && q >= io.src_lo && q < io.src_hi;
+        const size_t ps = in_src ? (size_t)r * io.src_rs + (size_t)l * io.src_ls + (q + io.src_off) : 0;
+        x.v[j] = io.src[ps];
+        if (!in_src) x.v[j] = cmk<double2>(0.0, 0.0);
+    }
+    x.ta = io.trA[pt];
+    x.tb = io.trB[pt];
+    if (!tr) { x.ta = cmk<double2>(0.0, 0.0); x.tb = x.ta; }
+}
+__device__ inline float2 combine4(const IOSpec& io, const RawRhs4& x, int j, int q) {
+    double2 v = x.v[j];
+    if (q == io.q_t || q == io.q_t + 1) {
+        v.x += io.coef * (x.tb.x - x.ta.x);
+        v.y += io.coef * (x.tb.y - x.ta.y);
+    }
+    return make_float2((float)v.x, (float)v.y);
+}
+
 template <typename T>
 __device__ inline cplx<T> combine(const IOSpec& io, const RawRhs& x) {
     double2 v = x.v;
@@ -258,10 +289,9 @@ __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
 #pragma unroll
         for (int s4 = 0; s4 < 16; ++s4) g[s4] = G[(4 * s4 + q4) * WP];
     };
-    RawRhs raw[4];
+    RawRhs4 raw;
     auto load_rhs = [&](int l) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) raw[j] = load_raw(a.io, rn, l, qrow + j, a.Ny, a.nrhs, a.W);
+        load_raw4(raw, a.io, rn, l, qrow, a.Ny, a.nrhs, a.W);
     };
     V greg[D][16];
     V z[4], zn[4];
@@ -274,11 +304,16 @@ __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
 
     auto mfma_block = [&](const V (&g)[16], const V (*Vb)[R], V (&out)[4]) {
         mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+        // the whole B panel of the lane first: one LDS round trip per step
+        V vb[16];
+#pragma unroll
+        for (int s4 = 0; s4 < 16; ++s4) vb[s4] = Vb[4 * s4 + q4][n];
+        __builtin_amdgcn_sched_barrier(0);     // keep the scheduler from sinking the reads
 #pragma unroll
         for (int s4 = 0; s4 < 16; s4 += 2) {
             const V g0 = g[s4], g1 = g[s4 + 1];
-            const V v0 = Vb[4 * s4 + q4][n];
-            const V v1 = Vb[4 * s4 + 4 + q4][n];
+            const V v0 = vb[s4];
+            const V v1 = vb[s4 + 1];
             aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
             aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
             aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
@@ -304,7 +339,7 @@ __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
         const V cl = make_float2(clx, cly);
         V v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = csub(combine<float>(a.io, raw[u]), cmul(cl, z[u]));
+        for (int u = 0; u < 4; ++u) v[u] = csub(combine4(a.io, raw, u, qrow + u), cmul(cl, z[u]));
         // next step's small loads first (vmcnt retires in issue order); clamped, branch-free
         const int ln = l + 1 < r1 ? l + 1 : l;
         cnext = a.cy[ln];
