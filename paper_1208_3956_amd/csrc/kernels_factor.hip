@@ -73,44 +73,52 @@ __device__ void build_T(double2* M, const FactorArgs& a, int s, int l, int W) {
     __syncthreads();
 }
 
-// C = alpha * A * B (+ D), full WP x WP, column-major with leading dimensions.  Operands
-// may live in LDS or global memory; C may alias A, B or D.  Thread (ti, tj) computes rows
-// 4 ti.., columns 4 tj..; the k loop is unrolled so that the loads of A (usually a factor
-// block in global memory) of several k are in flight together.
-__device__ void gemm64(double2* C, int ldc, const double2* A, int lda, const double2* B, int ldb,
-                       double2 alpha, const double2* D, int ldd) {
-    const int t = threadIdx.x;
-    const int ti = t & 15, tj = t >> 4;
-    double2 acc[4][4];
+// C = alpha * A * B (+ D) on v_mfma_f64_16x16x4f64: full WP x WP, column-major with leading
+// dimensions, operands in LDS or global memory, C may alias A, B or D.  Wave w computes rows
+// 16 w .. 16 w + 15 in four 16-column tiles; a complex product is four real ones.  Lane
+// layout (one 16x16x4 block of doubles): A[l % 16][l / 16], B[l / 16][l % 16] and
+// C[l / 16 + 4 j][l % 16] in component j (rows interleaved by 4, unlike the FP32 block).
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+__device__ __attribute__((always_inline)) void gemm64_mfma(double2* C, int ldc, const double2* A, int lda, const double2* B, int ldb,
+                            double2 alpha, const double2* D, int ldd) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 15, q4 = lane >> 4;
+    double2 av[16];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int s = 0; s < 16; ++s) av[s] = A[(16 * w + n) + (size_t)(4 * s + q4) * lda];
+    md4 cr[4], ci[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = cmk<double2>(0.0, 0.0);
-#pragma unroll 8
-    for (int k = 0; k < WP; ++k) {
-        double2 av[4], bv[4];
+    for (int tt = 0; tt < 4; ++tt) { cr[tt] = md4{0.0, 0.0, 0.0, 0.0}; ci[tt] = cr[tt]; }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) av[r] = A[(4 * ti + r) + (size_t)k * lda];
+    for (int s = 0; s < 16; ++s) {
+        double2 bv[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) bv[c] = B[k + (size_t)(4 * tj + c) * ldb];
+        for (int tt = 0; tt < 4; ++tt) bv[tt] = B[(4 * s + q4) + (size_t)(16 * tt + n) * ldb];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int tt = 0; tt < 4; ++tt) {
+            cr[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[tt].x, cr[tt], 0, 0, 0);
+            ci[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[tt].y, ci[tt], 0, 0, 0);
+        }
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cfma(acc[r][c], av[r], bv[c]);
+        for (int tt = 0; tt < 4; ++tt) {
+            cr[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[s].y, bv[tt].y, cr[tt], 0, 0, 0);
+            ci[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[tt].x, ci[tt], 0, 0, 0);
+        }
     }
+    double2 v[4][4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            double2 v = cmul(alpha, acc[r][c]);
-            if (D) v = cadd(v, D[(4 * ti + r) + (size_t)(4 * tj + c) * ldd]);
-            acc[r][c] = v;
+        for (int j = 0; j < 4; ++j) {
+            double2 x = cmul(alpha, cmk<double2>(cr[tt][j], ci[tt][j]));
+            if (D) x = cadd(x, D[(16 * w + q4 + 4 * j) + (size_t)(16 * tt + n) * ldd]);
+            v[tt][j] = x;
         }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) C[(4 * ti + r) + (size_t)(4 * tj + c) * ldc] = acc[r][c];
+        for (int j = 0; j < 4; ++j) C[(16 * w + q4 + 4 * j) + (size_t)(16 * tt + n) * ldc] = v[tt][j];
     __syncthreads();
 }
 
@@ -298,7 +306,7 @@ __global__ void __launch_bounds__(NT) k_factor_spikes(FactorArgs a) {
         store_blk(slot(a, s, r0, 1), Pm, one);
         for (int l = r0 + 1; l < r1; ++l) {
             const double2 cl = a.cy[l];
-            gemm64(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-cl.x, -cl.y), nullptr, 0);
+            gemm64_mfma(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-cl.x, -cl.y), nullptr, 0);
             store_blk(slot(a, s, l, 1), Cm, one);
             double2* tmp = Pm; Pm = Cm; Cm = tmp;
         }
@@ -308,7 +316,7 @@ __global__ void __launch_bounds__(NT) k_factor_spikes(FactorArgs a) {
         store_blk(slot(a, s, r1 - 1, 1), Pm, ctop);
         for (int l = r1 - 2; l >= r0; --l) {
             const double2 bl = a.by[l];
-            gemm64(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y),
+            gemm64_mfma(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y),
                    slot(a, s, l, 1), WP);
             store_blk(slot(a, s, l, 1), Cm, ctop);
             double2* tmp = Pm; Pm = Cm; Cm = tmp;
@@ -324,7 +332,7 @@ __global__ void __launch_bounds__(NT) k_factor_spikes(FactorArgs a) {
         store_blk(slot(a, s, r1 - 1, 2), Pm, bbot);
         for (int l = r1 - 2; l >= r0; --l) {
             const double2 bl = a.by[l];
-            gemm64(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y), nullptr, 0);
+            gemm64_mfma(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y), nullptr, 0);
             store_blk(slot(a, s, l, 2), Cm, bbot);
             double2* tmp = Pm; Pm = Cm; Cm = tmp;
         }
@@ -363,7 +371,7 @@ __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
         __syncthreads();
         if (c >= 1) {
             // Bm = Bm - L_c U'_{c-1},  L_c = S^_{c,c-1} = -c_s X~^(c)_{s-1}
-            gemm64(Bm, LDM, slot(a, s, r - 1, 1), WP, Am, LDM, cs, Bm, LDM);
+            gemm64_mfma(Bm, LDM, slot(a, s, r - 1, 1), WP, Am, LDM, cs, Bm, LDM);
         }
         {
             double2 M[16];
@@ -376,12 +384,12 @@ __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
         if (c >= 1) {
             // K_c = G'_c L_c = -c_s G'_c X~^(c)_{s-1} replaces L_c in slot 1, so that the
             // forward separator recurrence is z'_c = G'_c r^_c - K_c z'_{c-1}
-            gemm64(Am, LDM, Gp, WP, slot(a, s, r - 1, 1), WP, cmk<double2>(-cs.x, -cs.y), nullptr, 0);
+            gemm64_mfma(Am, LDM, Gp, WP, slot(a, s, r - 1, 1), WP, cmk<double2>(-cs.x, -cs.y), nullptr, 0);
             store_blk(slot(a, s, r, 1), Am, one);
             __syncthreads();
         }
         if (c + 2 < a.P) {
-            gemm64(Am, LDM, Gp, WP, slot(a, s, r + 1, 2), WP, cmk<double2>(-bs.x, -bs.y), nullptr, 0);
+            gemm64_mfma(Am, LDM, Gp, WP, slot(a, s, r + 1, 2), WP, cmk<double2>(-bs.x, -bs.y), nullptr, 0);
             store_blk(slot(a, s, r, 2), Am, one);
             __syncthreads();
         }
@@ -415,7 +423,7 @@ __global__ void __launch_bounds__(NT) k_factor_propagators(FactorArgs a, int q, 
     double2* cur = Am;
     double2* nxt = Bm;
     for (int c = first + step; c >= c0 && c <= c1; c += step) {
-        gemm64(nxt, LDM, slot(a, s, sep(c), sl), WP, cur, LDM, mone, nullptr, 0);
+        gemm64_mfma(nxt, LDM, slot(a, s, sep(c), sl), WP, cur, LDM, mone, nullptr, 0);
         store_blk(out(c), nxt, one);
         __syncthreads();
         double2* tmp = cur; cur = nxt; nxt = tmp;
