@@ -685,7 +685,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     }
     std::vector<double> fn, rn;
     CHK(norms(H, f, nrhs, nfull, fn));
-    HIPCHK(hipMemsetAsync(u, 0, field_bytes(H, nrhs), H->st));
+    // u is first written at the end of cycle 0 (u = correction), so it starts unset
     std::vector<int> total(nrhs, 0), its;
     std::vector<double> resid;
     int used = 0;
@@ -694,8 +694,11 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     std::vector<double> est0;      // GMRES residual estimates at the end of the first cycle
     bool floor_used = false;       // the first cycle ended at the recorded floor
     for (int cycle = 0; used < H->max_iter; ++cycle) {
-        // explicit FP64 residual of the current iterate
-        HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st)));
+        // explicit FP64 residual of the current iterate (u = 0 in cycle 0: r = f)
+        if (cycle == 0)
+            HIPCHK(hipMemcpyAsync(w.R, f, field_bytes(H, nrhs), hipMemcpyDeviceToDevice, H->st));
+        else
+            HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st)));
         CHK(norms(H, w.R, nrhs, nfull, rn));
         if (cycle == 1 && H->prec != HELM_C128) {
             // a first cycle that ran far below its true residual measures the floor; one
@@ -721,8 +724,8 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
                     HIPCHK(hipMemsetAsync(w.R + (size_t)r * nfull, 0, nfull * sizeof(double2), H->st));
         const double2* b = w.R;
         if (reduced) {
-            // Algorithm 2 on the current residual: u~ and phi = r - A u~ (reduced columns)
-            HIPCHK(hipMemsetAsync(w.Ut, 0, field_bytes(H, nrhs), H->st));
+            // Algorithm 2 on the current residual: u~ and phi = r - A u~ (reduced columns);
+            // the strips' D~ ranges partition the columns, so u~ is written everywhere
             CHK(reduced_setup(H, nrhs, w.R, w.Ut));
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
@@ -743,26 +746,22 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
                 floor_used = true;
             }
         }
-        double2* ycorr = reduced ? w.Psi : w.PF;
         // GMRES on op(y) = b; the solution increment is P y (+ u~)
-        double2* ydev = reduced ? w.Hf : w.G;  // reuse as scratch for y
-        (void)ydev;
         CHK(gmres_cycle(H, nrhs, n, b, bn, target, H->max_iter - used, w.w, its, resid));
         if (cycle == 0) est0 = resid;
         int kmax = 0;
         for (int r = 0; r < nrhs; ++r) { total[r] += its[r]; kmax = std::max(kmax, its[r]); }
         used += std::max(kmax, 1);
         if (reduced) {
-            // Algorithm 4: u += P psi + u~   (psi scattered onto the grid)
-            HIPCHK(hipMemsetAsync(w.Psi, 0, field_bytes(H, nrhs), H->st));
+            // Algorithm 4: u += P psi + u~   (psi scattered onto the reduced columns of Psi,
+            // which is zero everywhere else: nothing but this scatter writes it)
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.Psi, H->st)));
             CHK(apply_P_full(H, nrhs, w.Psi, w.Hf));
-            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_axpby(w.Hf, w.Ut, w.Hf, 1.0, 1.0, nrhs * nfull, H->st)));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_sum3(cycle == 0 ? nullptr : u, w.Hf, w.Ut, u, nrhs * nfull, H->st)));
         } else {
             CHK(apply_P_full(H, nrhs, w.w, w.Hf));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_sum3(cycle == 0 ? nullptr : u, w.Hf, nullptr, u, nrhs * nfull, H->st)));
         }
-        (void)ycorr;
-        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_axpby(u, w.Hf, u, 1.0, 1.0, nrhs * nfull, H->st)));
     }
     if (!ok) {
         HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st)));
@@ -775,7 +774,6 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
         if (iters) iters[r] = total[r];
         conv = conv && (rr <= tol);
     }
-    if (H->mode == HELM_REDUCED && nred > 0) HIPCHK(hipMemsetAsync(w.Psi, 0, field_bytes(H, nrhs), H->st));
     if (!conv) return fail(H, HELM_ENOCONV, "GMRES did not reach the tolerance within max_iter");
     return HELM_OK;
 }

@@ -211,9 +211,9 @@ hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, 
 hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
                                int Ny, int Nx, double2* field, hipStream_t st);
 // zero column cols[k] + shift of every row, k < ncols
-hipError_t launch_axpby(const double2* x, const double2* y, double2* out, double a, double b,
-                        long n, hipStream_t st);
-
+// out = x + y + z; x or z may be null
+hipError_t launch_sum3(const double2* x, const double2* y, const double2* z, double2* out, long n,
+                       hipStream_t st);
 int dots_blocks(long n);
 
 // one plane l of the 3-D slab factorisation for every slab: S = T_l - c_l b_{l-1} Gprev,

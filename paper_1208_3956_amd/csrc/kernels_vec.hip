@@ -324,12 +324,14 @@ __global__ void k_scatter_cols(const double2* __restrict__ red, const int* __res
     }
 }
 
-__global__ void k_axpby(const double2* __restrict__ x, const double2* __restrict__ y,
-                        double2* __restrict__ out, double a, double b, long n) {
+// out = x + y + z (x or z may be null: treated as zero)
+__global__ void k_sum3(const double2* __restrict__ x, const double2* __restrict__ y,
+                       const double2* __restrict__ z, double2* __restrict__ out, long n) {
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
-        const double2 xv = x[q];
-        const double2 yv = y ? y[q] : cmk<double2>(0, 0);
-        out[q] = cmk<double2>(a * xv.x + b * yv.x, a * xv.y + b * yv.y);
+        double2 v = y[q];
+        if (x) v = cadd(x[q], v);
+        if (z) v = cadd(v, z[q]);
+        out[q] = v;
     }
 }
 
@@ -433,9 +435,9 @@ hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, i
     return hipGetLastError();
 }
 
-hipError_t launch_axpby(const double2* x, const double2* y, double2* out, double a, double b,
-                        long n, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpby, dim3(grid_for((size_t)n)), dim3(256), 0, st, x, y, out, a, b, n);
+hipError_t launch_sum3(const double2* x, const double2* y, const double2* z, double2* out, long n,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_sum3, dim3(grid_for((size_t)n)), dim3(256), 0, st, x, y, z, out, n);
     return hipGetLastError();
 }
 
