@@ -559,46 +559,61 @@ __global__ void __launch_bounds__(NT) k_phase_b(SolveArgs<T> a) {
 // so the solve is: local forward chains (all groups in parallel), a chain over the groups'
 // last separators, fix-up + local backward chains (parallel), a chain over the groups'
 // first separators, fix-up (parallel): about 2q + 2G dependent steps instead of 2(P-1).
+// A workgroup takes RB right-hand sides (every block it loads serves all of them); entries
+// of right-hand sides beyond nrhs (a ragged last group) are computed from clamped loads and
+// never stored.  The chains are latency bound: at 64 right-hand sides one per workgroup was
+// the fastest (separator solve per strip 77 us; two per workgroup 84, four 105, eight 237).
 //
 // sep_chain: thread (i, w) owns row i and the 16 columns 16w..16w+15 of every block; wave
-// w keeps its own copy of the vector (its 16 entries are produced by its own lanes), so a
-// step needs one barrier (for the 4-wave partial sums).  Step k:
+// w keeps its own copy of the vectors (their 16 entries it reads are produced by its own
+// lanes), so a step needs one barrier (for the 4-wave partial sums).  Step k:
 //   v_k = in_k + sgn (M_k vec),  out_k = v_k,  vec = v_k if chain (else vec stays v0).
 // Blocks and inputs of the next D steps are in flight in registers.
-template <typename T, int D, typename BF, typename RF>
-__device__ void sep_chain(int n, bool chain, cplx<T> v0, T sgn, BF blk, RF row,
-                          cplx<T> (*vecw)[WP], cplx<T> (*part)[4][WP]) {
+template <typename T> struct SepRB { static constexpr int RB = 1; };
+
+template <typename T, int D, int RB, typename BF, typename RF>
+__device__ void sep_chain(int n, bool chain, const cplx<T> (&v0)[RB], T sgn, BF blk, RF row,
+                          const bool (&okb)[RB], cplx<T> (*vecw)[RB][WP], cplx<T> (*part)[4][RB][WP]) {
     using V = cplx<T>;
     if (n <= 0) return;
     const int t = threadIdx.x, i = t & (WP - 1), w = t >> 6, k0 = 16 * w;
-    vecw[w][i] = v0;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) vecw[w][b][i] = v0[b];
     __builtin_amdgcn_wave_barrier();   // the wave's own lanes produced the entries it reads
-    V breg[D][16], ireg[D];
-    auto load = [&](int k, V (&b)[16], V& x) {
+    V breg[D][16], ireg[D][RB];
+    auto load = [&](int k, V (&bl)[16], V (&x)[RB]) {
         const int kc = k < n ? k : n - 1;
         const V* M = blk(kc) + (size_t)k0 * WP + i;
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) b[kk] = M[kk * WP];
-        x = row(kc)[i];
+        for (int kk = 0; kk < 16; ++kk) bl[kk] = M[kk * WP];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) x[b] = row(kc, b)[i];
     };
 #pragma unroll
     for (int d = 0; d < D; ++d) load(d, breg[d], ireg[d]);
     auto step = [&](int k, int j) {
-        V acc0 = cmk<V>(0, 0), acc1 = acc0;
+        V acc[RB];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 2) {
-            cfma(acc0, breg[j][kk], vecw[w][k0 + kk]);
-            cfma(acc1, breg[j][kk + 1], vecw[w][k0 + kk + 1]);
-        }
-        const V xin = ireg[j];
-        V* dst = row(k);
+        for (int b = 0; b < RB; ++b) acc[b] = cmk<V>(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+            for (int b = 0; b < RB; ++b) cfma(acc[b], breg[j][kk], vecw[w][b][k0 + kk]);
+        V xin[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) xin[b] = ireg[j][b];
         load(k + D, breg[j], ireg[j]);
-        part[k & 1][w][i] = cadd(acc0, acc1);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) part[k & 1][w][b][i] = acc[b];
         __syncthreads();
-        const V sum = cadd(cadd(part[k & 1][0][i], part[k & 1][1][i]), cadd(part[k & 1][2][i], part[k & 1][3][i]));
-        const V v = cmk<V>(xin.x + sgn * sum.x, xin.y + sgn * sum.y);
-        dst[i] = v;
-        if (chain) vecw[w][i] = v;
+#pragma unroll
+        for (int b = 0; b < RB; ++b) {
+            const V sum = cadd(cadd(part[k & 1][0][b][i], part[k & 1][1][b][i]),
+                               cadd(part[k & 1][2][b][i], part[k & 1][3][b][i]));
+            const V v = cmk<V>(xin[b].x + sgn * sum.x, xin[b].y + sgn * sum.y);
+            if (okb[b]) row(k, b)[i] = v;
+            if (chain) vecw[w][b][i] = v;
+        }
         __builtin_amdgcn_wave_barrier();
     };
     int k = 0;
@@ -612,25 +627,34 @@ __device__ void sep_chain(int n, bool chain, cplx<T> v0, T sgn, BF blk, RF row,
     __syncthreads();
 }
 
-// Independent updates v_k = in_k + M_k v (k < n, the same vector v for every k): wave w
-// takes k = w, w + 4, ..., each lane one row of the full 64-column product, so the waves need
-// no barrier between updates.  v0 is this lane's entry of v.
-template <typename T, typename BF, typename RF>
-__device__ void sep_fix(int n, cplx<T> v0, BF blk, RF row, cplx<T> (*vecw)[WP]) {
+// Independent updates v_k = in_k + M_k v (k < n, the same vectors v for every k): wave w
+// takes k = w, w + 4, ..., each lane one row of the full 64-column products, so the waves
+// need no barrier between updates.  v0 holds this lane's entries of the vectors.
+template <typename T, int RB, typename BF, typename RF>
+__device__ void sep_fix(int n, const cplx<T> (&v0)[RB], BF blk, RF row, const bool (&okb)[RB],
+                        cplx<T> (*vecw)[RB][WP]) {
     using V = cplx<T>;
     const int i = threadIdx.x & (WP - 1), w = threadIdx.x >> 6;
-    vecw[w][i] = v0;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) vecw[w][b][i] = v0[b];
     __builtin_amdgcn_wave_barrier();
     for (int k = w; k < n; k += 4) {
         const V* M = blk(k) + i;
-        V acc0 = cmk<V>(0, 0), acc1 = acc0;
+        V acc[RB];
+#pragma unroll
+        for (int b = 0; b < RB; ++b) acc[b] = cmk<V>(0, 0);
 #pragma unroll 16
-        for (int kk = 0; kk < WP; kk += 2) {
-            cfma(acc0, M[(size_t)kk * WP], vecw[w][kk]);
-            cfma(acc1, M[(size_t)(kk + 1) * WP], vecw[w][kk + 1]);
+        for (int kk = 0; kk < WP; ++kk) {
+            const V m = M[(size_t)kk * WP];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) cfma(acc[b], m, vecw[w][b][kk]);
         }
-        V* dst = row(k) + i;
-        *dst = cadd(*dst, cadd(acc0, acc1));
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            if (okb[b]) {
+                V* dst = row(k, b) + i;
+                *dst = cadd(*dst, acc[b]);
+            }
     }
     __syncthreads();
 }
@@ -638,22 +662,28 @@ __device__ void sep_fix(int n, cplx<T> v0, BF blk, RF row, cplx<T> (*vecw)[WP]) 
 template <typename T>
 struct SepCtx {
     const SolveArgs<T>& a;
-    int ns;
+    int ns, rbase;
     __device__ int sep(int c) const { return c * a.m + a.m - 1; }
     __device__ int first(int g) const { return g * a.q; }
     __device__ int last(int g) const { return min(g * a.q + a.q, ns) - 1; }
     __device__ const cplx<T>* prop(int c, int dir) const { return a.Fs + ((size_t)c * 2 + dir) * BLK; }
-    __device__ cplx<T>* yrow(cplx<T>* Yr, int c) const { return Yr + (size_t)sep(c) * WP; }
+    __device__ bool ok(int b) const { return rbase + b < a.nrhs; }
+    __device__ int rhs(int b) const { return rbase + b < a.nrhs ? rbase + b : a.nrhs - 1; }   // clamped
+    __device__ cplx<T>* yrow(int b, int c) const { return a.Yw + ((size_t)rhs(b) * a.Ny + sep(c)) * WP; }
 };
 
 #define SEPK_PROLOGUE                                                     \
     using V = cplx<T>;                                                    \
-    __shared__ V vecw[4][WP];                                             \
-    __shared__ V part[2][4][WP];                                          \
+    constexpr int RB = SepRB<T>::RB;                                      \
+    __shared__ V vecw[4][RB][WP];                                         \
+    __shared__ V part[2][4][RB][WP];                                      \
     const int i = threadIdx.x & (WP - 1);                                 \
-    const int r = blockIdx.x;                                             \
-    SepCtx<T> X{a, a.P - 1};                                              \
-    V* Yr = a.Yw + (size_t)r * a.Ny * WP;                                 \
+    SepCtx<T> X{a, a.P - 1, (int)blockIdx.x * RB};                        \
+    bool okb[RB];                                                         \
+    for (int b = 0; b < RB; ++b) okb[b] = X.ok(b);                        \
+    auto vecs_at = [&](int c, V (&v)[RB]) {                               \
+        for (int b = 0; b < RB; ++b) v[b] = X.yrow(b, c)[i];              \
+    };                                                                    \
     (void)i;
 
 // local forward chains: zeta_c = a_c - K_c zeta_{c-1} inside group g = blockIdx.y.  First
@@ -667,38 +697,52 @@ __global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) {
         const int w = threadIdx.x >> 6;
         for (int c = c0 + w; c <= c1; c += 4) {
             const int sr = X.sep(c);
-            V v = cmk<V>(0, 0);
-            if (i < a.W) {
-                v = gather<T>(a.io, r, sr, i, a.Ny);
-                v = csub(v, cmul(ccast<V>(a.cy[sr]), Yr[(size_t)(sr - 1) * WP + i]));
-                v = csub(v, cmul(ccast<V>(a.by[sr]), Yr[(size_t)(sr + 1) * WP + i]));
+#pragma unroll
+            for (int b = 0; b < RB; ++b) {
+                const int r = X.rhs(b);
+                const V* Yr = a.Yw + (size_t)r * a.Ny * WP;
+                V v = cmk<V>(0, 0);
+                if (i < a.W) {
+                    v = gather<T>(a.io, r, sr, i, a.Ny);
+                    v = csub(v, cmul(ccast<V>(a.cy[sr]), Yr[(size_t)(sr - 1) * WP + i]));
+                    v = csub(v, cmul(ccast<V>(a.by[sr]), Yr[(size_t)(sr + 1) * WP + i]));
+                }
+                vecw[w][b][i] = v;
             }
-            vecw[w][i] = v;
             __builtin_amdgcn_wave_barrier();
             const V* M = fslot(a, sr, 0) + i;
-            V acc0 = cmk<V>(0, 0), acc1 = acc0;
+            V acc[RB];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) acc[b] = cmk<V>(0, 0);
 #pragma unroll 16
-            for (int kk = 0; kk < WP; kk += 2) {
-                cfma(acc0, M[(size_t)kk * WP], vecw[w][kk]);
-                cfma(acc1, M[(size_t)(kk + 1) * WP], vecw[w][kk + 1]);
+            for (int kk = 0; kk < WP; ++kk) {
+                const V m = M[(size_t)kk * WP];
+#pragma unroll
+                for (int b = 0; b < RB; ++b) cfma(acc[b], m, vecw[w][b][kk]);
             }
-            Yr[(size_t)sr * WP + i] = cadd(acc0, acc1);
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                if (okb[b]) a.Yw[((size_t)X.rhs(b) * a.Ny + sr) * WP + i] = acc[b];
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
     }
-    sep_chain<T, D>(c1 - c0, true, X.yrow(Yr, c0)[i], T(-1),
-                    [&](int k) { return fslot(a, X.sep(c0 + 1 + k), 1); },
-                    [&](int k) { return X.yrow(Yr, c0 + 1 + k); }, vecw, part);
+    V v0[RB];
+    vecs_at(c0, v0);
+    sep_chain<T, D, RB>(c1 - c0, true, v0, T(-1),
+                        [&](int k) { return fslot(a, X.sep(c0 + 1 + k), 1); },
+                        [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw, part);
 }
 
 // chain over the groups' last separators: z'_{last g} = zeta_{last g} + Phi_{last g} z'_{last g-1}
 template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_fwd_top(SolveArgs<T> a) {
     SEPK_PROLOGUE
-    sep_chain<T, D>(a.G - 1, true, X.yrow(Yr, X.last(0))[i], T(1),
-                    [&](int k) { return X.prop(X.last(k + 1), 0); },
-                    [&](int k) { return X.yrow(Yr, X.last(k + 1)); }, vecw, part);
+    V v0[RB];
+    vecs_at(X.last(0), v0);
+    sep_chain<T, D, RB>(a.G - 1, true, v0, T(1),
+                        [&](int k) { return X.prop(X.last(k + 1), 0); },
+                        [&](int k, int b) { return X.yrow(b, X.last(k + 1)); }, okb, vecw, part);
 }
 
 // fix-up of the group's other separators, then its local backward chain
@@ -707,22 +751,29 @@ template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) {
     SEPK_PROLOGUE
     const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
-    if (g >= 1)
-        sep_fix<T>(c1 - c0, X.yrow(Yr, X.last(g - 1))[i],
-                   [&](int k) { return X.prop(c0 + k, 0); },
-                   [&](int k) { return X.yrow(Yr, c0 + k); }, vecw);
-    sep_chain<T, D>(c1 - c0, true, X.yrow(Yr, c1)[i], T(-1),
-                    [&](int k) { return fslot(a, X.sep(c1 - 1 - k), 2); },
-                    [&](int k) { return X.yrow(Yr, c1 - 1 - k); }, vecw, part);
+    if (g >= 1) {
+        V vf[RB];
+        vecs_at(X.last(g - 1), vf);
+        sep_fix<T, RB>(c1 - c0, vf,
+                       [&](int k) { return X.prop(c0 + k, 0); },
+                       [&](int k, int b) { return X.yrow(b, c0 + k); }, okb, vecw);
+    }
+    V v0[RB];
+    vecs_at(c1, v0);
+    sep_chain<T, D, RB>(c1 - c0, true, v0, T(-1),
+                        [&](int k) { return fslot(a, X.sep(c1 - 1 - k), 2); },
+                        [&](int k, int b) { return X.yrow(b, c1 - 1 - k); }, okb, vecw, part);
 }
 
 // chain over the groups' first separators: x_{first g} = xi_{first g} + Psi_{first g} x_{first g+1}
 template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_bwd_top(SolveArgs<T> a) {
     SEPK_PROLOGUE
-    sep_chain<T, D>(a.G - 1, true, X.yrow(Yr, X.first(a.G - 1))[i], T(1),
-                    [&](int k) { return X.prop(X.first(a.G - 2 - k), 1); },
-                    [&](int k) { return X.yrow(Yr, X.first(a.G - 2 - k)); }, vecw, part);
+    V v0[RB];
+    vecs_at(X.first(a.G - 1), v0);
+    sep_chain<T, D, RB>(a.G - 1, true, v0, T(1),
+                        [&](int k) { return X.prop(X.first(a.G - 2 - k), 1); },
+                        [&](int k, int b) { return X.yrow(b, X.first(a.G - 2 - k)); }, okb, vecw, part);
 }
 
 // fix-up of the group's other separators: x_c = xi_c + Psi_c x_{first g+1}
@@ -730,9 +781,11 @@ template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_bwd_fix(SolveArgs<T> a) {
     SEPK_PROLOGUE
     const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
-    sep_fix<T>(c1 - c0, X.yrow(Yr, X.first(g + 1))[i],
-               [&](int k) { return X.prop(c0 + 1 + k, 1); },
-               [&](int k) { return X.yrow(Yr, c0 + 1 + k); }, vecw);
+    V vf[RB];
+    vecs_at(X.first(g + 1), vf);
+    sep_fix<T, RB>(c1 - c0, vf,
+                   [&](int k) { return X.prop(c0 + 1 + k, 1); },
+                   [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw);
 }
 #undef SEPK_PROLOGUE
 
@@ -951,7 +1004,7 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
         if (a.P > 2 && a.G >= 2 && a.Fs) {
             // the local forward chains form their own right-hand sides a_c
             constexpr int DS = Depth<T>::D;
-            const unsigned nr = (unsigned)a.nrhs;
+            const unsigned nr = (unsigned)((a.nrhs + SepRB<T>::RB - 1) / SepRB<T>::RB);
             hipLaunchKernelGGL((k_sep_fwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
             hipLaunchKernelGGL((k_sep_fwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
             hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
