@@ -207,6 +207,27 @@ def copy_calibration(mib):
                       "dispatches": 3}), flush=True)
 
 
+def stencil_roofline(H, wl, f, reps=5):
+    """HBM roofline of the full-field stencil r = f - A u (helm_apply_A) on the bench's
+    right-hand sides: algorithmic bytes = read u, read f, write r (16 B each per point and
+    right-hand side) + k^2 once (8 B per point), over its average launch (HIP events)."""
+    import torch
+    H.set_kernel_timing(True, classes=["stencil"])
+    for _ in range(reps):
+        out = H.apply_A(f, f)
+    torch.cuda.synchronize()
+    cnt, ms = H.kernel_times()["stencil"]
+    H.set_kernel_timing(False)
+    del out
+    avg_s = ms / 1e3 / max(cnt, 1)
+    pts = wl.N_x * wl.N_y * wl.N_z if wl.dim == 3 else wl.N_x * wl.N_y
+    nbytes = f.shape[0] * pts * 48 + pts * 8
+    ach = nbytes / avg_s / 1e9
+    return {"kernel": "k_apply_A", "bound": "hbm", "achieved": ach, "peak": 8000.0, "unit": "GB/s",
+            "frac": ach / 8000.0, "avg_launch_us": avg_s * 1e6, "bytes_per_launch": nbytes,
+            "launches": cnt}
+
+
 def c128_legs(wl, f, tol, plain_rhs=2):
     """Complex128 comparison on the same workload: the batched solve (all right-hand sides in
     one helm_solve) and the plain path (one right-hand side per helm_solve), each after a
@@ -394,6 +415,7 @@ def main():
         "kernel_ms_per_step": {k: v[1] for k, v in kt_all.items()},
         "kernel_ms_per_step_from": "one untimed step with every class timed",
         "roofline": roof,
+        "stencil_roofline": stencil_roofline(H, wl, f),
     }
     H.close()
     if args.prec == "mixed" and not args.no_c128_leg:

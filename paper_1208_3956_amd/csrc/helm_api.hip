@@ -101,6 +101,8 @@ struct helm_problem {
     void* F = nullptr;          // factors: double2 (C128) or float2 (MIXED)
     void* Fc = nullptr;         // compact spike rows at the target columns, same precision
     void* Fs = nullptr;         // separator propagators of the two-level separator solve
+    double2* F64 = nullptr;     // FP64 factor (the complex64 path's factorisation workspace)
+    double2* Fs64 = nullptr;    // FP64 propagators (idem)
     bool factored = false;
     int* d_err = nullptr;
     Work wk;
@@ -1053,60 +1055,50 @@ helm_status helm_factor(helm_t H) {
         H->ap_exec = nullptr;
     }
     HIPCHK(hipStreamSynchronize(H->st));    // no queued work may still read the old factors
-    dfree(H->F);
-    H->F = nullptr;
     H->factored = false;
-    dfree(H->Fc);
-    H->Fc = nullptr;
-    dfree(H->Fs);
-    H->Fs = nullptr;
-    if (g.dim == 3) return factor3(H);
+    if (g.dim == 3) {
+        dfree(H->F);
+        H->F = nullptr;
+        return factor3(H);
+    }
+    // The factor buffers keep their size for the handle's life: they are allocated (and
+    // cleared: slots no factorisation writes must read as zero) once, and every later
+    // factorisation overwrites the same slots.  The complex64 path keeps the FP64 factor as
+    // workspace and receives each block rounded as it is stored.
     const size_t nel = (size_t)g.J * g.Ny * NSLOT * BLK;
-    double2* F64 = nullptr;
-    CHK(dmalloc(H, &F64, nel * sizeof(double2)));
-    HIPCHK(hipMemsetAsync(F64, 0, nel * sizeof(double2), H->st));
-    HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
-    HIPCHK(TIMED(H, helm::K_FACTOR_CHUNKS, helm::launch_factor_chunks(H->t, g, H->ch, F64, H->d_err, H->st)));
-    HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_separators(H->t, g, H->ch, F64, H->d_err, H->st)));
-    // propagators of the two-level separator solve (FP64, converted with the factor)
-    double2* Fs64 = nullptr;
     const size_t nsel = H->ch.G >= 2 ? (size_t)g.J * (H->ch.P - 1) * 2 * BLK : 0;
-    if (nsel) {
-        helm_status s2 = dmalloc(H, &Fs64, nsel * sizeof(double2));
-        if (s2 != HELM_OK) { dfree(F64); return s2; }
-        HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_propagators(H->t, g, H->ch, F64, Fs64, H->st)));
-    }
-    dfree(H->Fc);
-    H->Fc = nullptr;
     const size_t ncomp = (size_t)g.J * g.Ny * 2 * 8 * WP;
-    if (H->prec == HELM_C128) {
-        H->F = F64;
-        H->Fs = Fs64;
-        double2* Fc = nullptr;
-        CHK(dmalloc(H, &Fc, ncomp * sizeof(double2)));
-        H->Fc = Fc;
-        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<double2>(F64, Fc, H->t.tcol, g, H->ch, H->st)));
-    } else {
-        float2* F32 = nullptr;
-        helm_status s = dmalloc(H, &F32, nel * sizeof(float2));
-        if (s != HELM_OK) { dfree(F64); return s; }
-        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_convert_factor(F64, F32, nel, H->st)));
-        if (nsel) {
-            float2* Fs32 = nullptr;
-            helm_status s3 = dmalloc(H, &Fs32, nsel * sizeof(float2));
-            if (s3 != HELM_OK) { dfree(F64); dfree(Fs64); dfree(F32); return s3; }
-            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_convert_factor(Fs64, Fs32, nsel, H->st)));
-            H->Fs = Fs32;
+    const bool single = H->prec != HELM_C128;
+    const size_t esz = single ? sizeof(float2) : sizeof(double2);
+    if (!H->F64) {
+        CHK(dmalloc(H, &H->F64, nel * sizeof(double2)));
+        HIPCHK(hipMemsetAsync(H->F64, 0, nel * sizeof(double2), H->st));
+        if (nsel) CHK(dmalloc(H, &H->Fs64, nsel * sizeof(double2)));
+        if (single) {
+            CHK(dmalloc(H, &H->F, nel * esz));
+            HIPCHK(hipMemsetAsync(H->F, 0, nel * esz, H->st));
+            if (nsel) CHK(dmalloc(H, &H->Fs, nsel * esz));
+        } else {
+            H->F = H->F64;
+            H->Fs = H->Fs64;
         }
-        HIPCHK(hipStreamSynchronize(H->st));
-        dfree(F64);
-        dfree(Fs64);
-        H->F = F32;
-        float2* Fc = nullptr;
-        CHK(dmalloc(H, &Fc, ncomp * sizeof(float2)));
-        H->Fc = Fc;
-        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<float2>(F32, Fc, H->t.tcol, g, H->ch, H->st)));
+        CHK(dmalloc(H, &H->Fc, ncomp * esz));
     }
+    double2* F64 = H->F64;
+    float2* F32 = single ? static_cast<float2*>(H->F) : nullptr;
+    HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
+    HIPCHK(TIMED(H, helm::K_FACTOR_CHUNKS, helm::launch_factor_chunks(H->t, g, H->ch, F64, F32, H->d_err, H->st)));
+    HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_separators(H->t, g, H->ch, F64, F32, H->d_err, H->st)));
+    if (nsel)
+        HIPCHK(TIMED(H, helm::K_FACTOR_SEPS,
+                     helm::launch_factor_propagators(H->t, g, H->ch, F64, H->Fs64,
+                                                     single ? static_cast<float2*>(H->Fs) : nullptr, H->st)));
+    if (single)
+        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<float2>(F32, static_cast<float2*>(H->Fc),
+                                                                           H->t.tcol, g, H->ch, H->st)));
+    else
+        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<double2>(F64, static_cast<double2*>(H->Fc),
+                                                                            H->t.tcol, g, H->ch, H->st)));
     int herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
@@ -1365,9 +1357,11 @@ void helm_destroy(helm_t H) {
     if (H->cap_st) (void)hipStreamDestroy(H->cap_st);
     free_work(H->wk);
     delete H->timer;
-    dfree(H->F);
+    if (H->F != H->F64) dfree(H->F);
+    if (H->Fs != H->Fs64) dfree(H->Fs);
+    dfree(H->F64);
+    dfree(H->Fs64);
     dfree(H->Fc);
-    dfree(H->Fs);
     dfree(H->d_err);
     for (void* p : H->owned) dfree(p);
     delete H;

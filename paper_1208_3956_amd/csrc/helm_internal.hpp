@@ -161,16 +161,17 @@ enum KClass { K_PHASE_A = 0, K_PHASE_B, K_PHASE_C, K_FACTOR_CHUNKS, K_FACTOR_SEP
               K_GMRES, K_OTHER, K_NCLASS };
 
 // ---------------------------------------------------------------- kernels (launchers)
+// F32 (complex64 path) receives every stored block rounded to complex64, null otherwise
 hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks& ch,
-                                double2* F64, int* err, hipStream_t st);
+                                double2* F64, float2* F32, int* err, hipStream_t st);
 hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chunks& ch,
-                                    double2* F64, int* err, hipStream_t st);
-hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipStream_t st);
-// propagators of the two-level separator solve, Fs[s][c][2][BLK] (FP64): forward
-// Phi_c = -K_c Phi_{c-1} from the first separator of each group on (groups 1..G-1), backward
-// Psi_c = -U'_c Psi_{c+1} from the last one down (groups 0..G-2)
+                                    double2* F64, float2* F32, int* err, hipStream_t st);
+// propagators of the two-level separator solve, Fs[s][c][2][BLK] (FP64, and rounded into
+// Fs32 when it is not null): forward Phi_c = -K_c Phi_{c-1} from the first separator of each
+// group on (groups 1..G-1), backward Psi_c = -U'_c Psi_{c+1} from the last one down
+// (groups 0..G-2)
 hipError_t launch_factor_propagators(const DevTables& t, const Geom& g, const Chunks& ch,
-                                     const double2* F64, double2* Fs, hipStream_t st);
+                                     const double2* F64, double2* Fs, float2* Fs32, hipStream_t st);
 // copies of the spike rows at the 8 target columns tcol[s*8 + t] (-1 = unused) of each strip
 template <typename V>
 hipError_t launch_extract_targets(const V* F, V* Fc, const int* tcol, const Geom& g,

@@ -28,6 +28,7 @@ constexpr int NT = 256;
 
 struct FactorArgs {
     double2* F;
+    float2* F32;            // complex64 copy of every stored block (null: none)
     const double* k2;
     const double2* ay;
     const double2* ayh;
@@ -157,7 +158,7 @@ __device__ inline double readlane_f64(double v, int lane) {
 // with leading dimension WP to dst (zero outside the leading block); ends with a barrier so
 // that dst can be read back by the workgroup.  Sets err when a pivot is zero or not finite.
 __device__ void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, double2* __restrict__ dst,
-                                int* err) {
+                                float2* __restrict__ dst32, int* err) {
     const int i = threadIdx.x & (WP - 1), g = threadIdx.x >> 6;
     bool used = i >= W;
     int my_step = i;                               // rows beyond W keep their position
@@ -221,7 +222,9 @@ __device__ void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, double2* 
     for (int r = 0; r < 16; ++r) {
         const int j = g + 4 * ((r + rot) & 15);
         const int pj = j < W ? sh.perm[j] : j;
-        dst[(size_t)pj * WP + my_step] = cmul(M[r], my_inv);
+        const double2 v = cmul(M[r], my_inv);
+        dst[(size_t)pj * WP + my_step] = v;
+        if (dst32) dst32[(size_t)pj * WP + my_step] = make_float2((float)v.x, (float)v.y);
     }
     __syncthreads();
 }
@@ -229,12 +232,18 @@ __device__ void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, double2* 
 __device__ inline double2* slot(const FactorArgs& a, int s, int l, int sl) {
     return a.F + (((size_t)s * a.Ny + l) * NSLOT + sl) * BLK;
 }
+__device__ inline float2* slot32(const FactorArgs& a, int s, int l, int sl) {
+    return a.F32 ? a.F32 + (((size_t)s * a.Ny + l) * NSLOT + sl) * BLK : nullptr;
+}
 
-// LDS (ld LDM) -> global (ld WP), optionally scaled.
-__device__ void store_blk(double2* dst, const double2* M, double2 scale) {
+// LDS (ld LDM) -> global (ld WP), optionally scaled; dst32 (if not null) gets the same
+// block rounded to complex64.
+__device__ void store_blk(double2* dst, float2* dst32, const double2* M, double2 scale) {
     for (int idx = threadIdx.x; idx < BLK; idx += NT) {
         const int i = idx & (WP - 1), k = idx / WP;
-        dst[idx] = cmul(M[i + k * LDM], scale);
+        const double2 v = cmul(M[i + k * LDM], scale);
+        dst[idx] = v;
+        if (dst32) dst32[idx] = make_float2((float)v.x, (float)v.y);
     }
 }
 __device__ void load_blk(double2* M, const double2* src) {
@@ -283,7 +292,7 @@ __global__ void __launch_bounds__(NT) k_factor_chunks(FactorArgs a) {
             }
             M[r] = v;
         }
-        gj_invert_store(M, W, sh, slot(a, s, l, 0), a.err);
+        gj_invert_store(M, W, sh, slot(a, s, l, 0), slot32(a, s, l, 0), a.err);
     }
 }
 
@@ -303,22 +312,22 @@ __global__ void __launch_bounds__(NT) k_factor_spikes(FactorArgs a) {
     if (side == 0 && c > 0) {
         load_blk(Pm, slot(a, s, r0, 0));
         __syncthreads();
-        store_blk(slot(a, s, r0, 1), Pm, one);
+        store_blk(slot(a, s, r0, 1), slot32(a, s, r0, 1), Pm, one);
         for (int l = r0 + 1; l < r1; ++l) {
             const double2 cl = a.cy[l];
             gemm64_mfma(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-cl.x, -cl.y), nullptr, 0);
-            store_blk(slot(a, s, l, 1), Cm, one);
+            store_blk(slot(a, s, l, 1), slot32(a, s, l, 1), Cm, one);
             double2* tmp = Pm; Pm = Cm; Cm = tmp;
         }
         __threadfence();
         __syncthreads();
         const double2 ctop = a.cy[r0];
-        store_blk(slot(a, s, r1 - 1, 1), Pm, ctop);
+        store_blk(slot(a, s, r1 - 1, 1), slot32(a, s, r1 - 1, 1), Pm, ctop);
         for (int l = r1 - 2; l >= r0; --l) {
             const double2 bl = a.by[l];
             gemm64_mfma(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y),
                    slot(a, s, l, 1), WP);
-            store_blk(slot(a, s, l, 1), Cm, ctop);
+            store_blk(slot(a, s, l, 1), slot32(a, s, l, 1), Cm, ctop);
             double2* tmp = Pm; Pm = Cm; Cm = tmp;
         }
         __syncthreads();
@@ -329,11 +338,11 @@ __global__ void __launch_bounds__(NT) k_factor_spikes(FactorArgs a) {
         const double2 bbot = a.by[r1 - 1];
         load_blk(Pm, slot(a, s, r1 - 1, 0));
         __syncthreads();
-        store_blk(slot(a, s, r1 - 1, 2), Pm, bbot);
+        store_blk(slot(a, s, r1 - 1, 2), slot32(a, s, r1 - 1, 2), Pm, bbot);
         for (int l = r1 - 2; l >= r0; --l) {
             const double2 bl = a.by[l];
             gemm64_mfma(Cm, LDM, slot(a, s, l, 0), WP, Pm, LDM, cmk<double2>(-bl.x, -bl.y), nullptr, 0);
-            store_blk(slot(a, s, l, 2), Cm, bbot);
+            store_blk(slot(a, s, l, 2), slot32(a, s, l, 2), Cm, bbot);
             double2* tmp = Pm; Pm = Cm; Cm = tmp;
         }
     }
@@ -378,19 +387,19 @@ __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
             const int i = threadIdx.x & (WP - 1), g = threadIdx.x >> 6;
 #pragma unroll
             for (int q = 0; q < 16; ++q) M[q] = Bm[i + (g + 4 * q) * LDM];
-            gj_invert_store(M, W, sh, slot(a, s, r, 0), a.err);
+            gj_invert_store(M, W, sh, slot(a, s, r, 0), slot32(a, s, r, 0), a.err);
         }
         const double2* Gp = slot(a, s, r, 0);
         if (c >= 1) {
             // K_c = G'_c L_c = -c_s G'_c X~^(c)_{s-1} replaces L_c in slot 1, so that the
             // forward separator recurrence is z'_c = G'_c r^_c - K_c z'_{c-1}
             gemm64_mfma(Am, LDM, Gp, WP, slot(a, s, r - 1, 1), WP, cmk<double2>(-cs.x, -cs.y), nullptr, 0);
-            store_blk(slot(a, s, r, 1), Am, one);
+            store_blk(slot(a, s, r, 1), slot32(a, s, r, 1), Am, one);
             __syncthreads();
         }
         if (c + 2 < a.P) {
             gemm64_mfma(Am, LDM, Gp, WP, slot(a, s, r + 1, 2), WP, cmk<double2>(-bs.x, -bs.y), nullptr, 0);
-            store_blk(slot(a, s, r, 2), Am, one);
+            store_blk(slot(a, s, r, 2), slot32(a, s, r, 2), Am, one);
             __syncthreads();
         }
     }
@@ -401,7 +410,8 @@ __global__ void __launch_bounds__(NT) k_factor_separators(FactorArgs a) {
 // that z'_c = zeta_c + Phi_c z'_{c0-1} with zeta the group's own recurrence started from 0.
 // Backward (group g <= G-2): Psi_{c1} = -U'_{c1}, Psi_c = -U'_c Psi_{c+1}, so that
 // x_c = xi_c + Psi_c x_{c1+1}.
-__global__ void __launch_bounds__(NT) k_factor_propagators(FactorArgs a, int q, int G, double2* __restrict__ Fs) {
+__global__ void __launch_bounds__(NT) k_factor_propagators(FactorArgs a, int q, int G, double2* __restrict__ Fs,
+                                                           float2* __restrict__ Fs32) {
     __shared__ double2 Am[WP * LDM];
     __shared__ double2 Bm[WP * LDM];
     const int s = blockIdx.x, g = blockIdx.y, dir = blockIdx.z;
@@ -412,6 +422,7 @@ __global__ void __launch_bounds__(NT) k_factor_propagators(FactorArgs a, int q, 
     const double2 one = cmk<double2>(1.0, 0.0), mone = cmk<double2>(-1.0, 0.0);
     auto sep = [&](int c) { return c * a.m + a.m - 1; };
     auto out = [&](int c) { return Fs + (((size_t)s * ns + c) * 2 + dir) * BLK; };
+    auto out32 = [&](int c) { return Fs32 ? Fs32 + (((size_t)s * ns + c) * 2 + dir) * BLK : nullptr; };
     const int first = dir == 0 ? c0 : c1;
     const int step = dir == 0 ? 1 : -1;
     const int sl = dir == 0 ? 1 : 2;                 // K_c in slot 1, U'_c in slot 2
@@ -419,12 +430,12 @@ __global__ void __launch_bounds__(NT) k_factor_propagators(FactorArgs a, int q, 
     __syncthreads();
     for (int idx = threadIdx.x; idx < WP * LDM; idx += NT) Am[idx] = cmul(Am[idx], mone);
     __syncthreads();
-    store_blk(out(first), Am, one);
+    store_blk(out(first), out32(first), Am, one);
     double2* cur = Am;
     double2* nxt = Bm;
     for (int c = first + step; c >= c0 && c <= c1; c += step) {
         gemm64_mfma(nxt, LDM, slot(a, s, sep(c), sl), WP, cur, LDM, mone, nullptr, 0);
-        store_blk(out(c), nxt, one);
+        store_blk(out(c), out32(c), nxt, one);
         __syncthreads();
         double2* tmp = cur; cur = nxt; nxt = tmp;
     }
@@ -446,15 +457,9 @@ __global__ void k_extract_targets(const V* __restrict__ F, V* __restrict__ Fc,
     }
 }
 
-__global__ void k_convert(const double2* __restrict__ in, float2* __restrict__ out, size_t n) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x)
-        out[i] = make_float2((float)in[i].x, (float)in[i].y);
-}
-
-FactorArgs make_args(const DevTables& t, const Geom& g, const Chunks& ch, double2* F, int* err) {
+FactorArgs make_args(const DevTables& t, const Geom& g, const Chunks& ch, double2* F, float2* F32, int* err) {
     FactorArgs a;
-    a.F = F; a.k2 = t.k2; a.ay = t.ay; a.ayh = t.ayh; a.cy = t.cy; a.by = t.by;
+    a.F = F; a.F32 = F32; a.k2 = t.k2; a.ay = t.ay; a.ayh = t.ayh; a.cy = t.cy; a.by = t.by;
     a.sax = t.sax; a.saxh = t.saxh; a.scol = t.scol; a.sW = t.sW; a.err = err;
     a.Nx = g.Nx; a.Ny = g.Ny; a.m = ch.m; a.P = ch.P; a.inv_h2 = 1.0 / (g.h * g.h);
     return a;
@@ -463,8 +468,8 @@ FactorArgs make_args(const DevTables& t, const Geom& g, const Chunks& ch, double
 }  // namespace
 
 hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks& ch,
-                                double2* F64, int* err, hipStream_t st) {
-    FactorArgs a = make_args(t, g, ch, F64, err);
+                                double2* F64, float2* F32, int* err, hipStream_t st) {
+    FactorArgs a = make_args(t, g, ch, F64, F32, err);
     dim3 grid(ch.P, g.J);
     hipLaunchKernelGGL(k_factor_chunks, grid, dim3(NT), 0, st, a);
     hipLaunchKernelGGL(k_factor_spikes, dim3(ch.P, g.J, 2), dim3(NT), 0, st, a);
@@ -472,18 +477,18 @@ hipError_t launch_factor_chunks(const DevTables& t, const Geom& g, const Chunks&
 }
 
 hipError_t launch_factor_separators(const DevTables& t, const Geom& g, const Chunks& ch,
-                                    double2* F64, int* err, hipStream_t st) {
+                                    double2* F64, float2* F32, int* err, hipStream_t st) {
     if (ch.P < 2) return hipSuccess;
-    FactorArgs a = make_args(t, g, ch, F64, err);
+    FactorArgs a = make_args(t, g, ch, F64, F32, err);
     hipLaunchKernelGGL(k_factor_separators, dim3(g.J), dim3(NT), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_factor_propagators(const DevTables& t, const Geom& g, const Chunks& ch,
-                                     const double2* F64, double2* Fs, hipStream_t st) {
+                                     const double2* F64, double2* Fs, float2* Fs32, hipStream_t st) {
     if (ch.G < 2) return hipSuccess;
-    FactorArgs a = make_args(t, g, ch, const_cast<double2*>(F64), nullptr);
-    hipLaunchKernelGGL(k_factor_propagators, dim3(g.J, ch.G, 2), dim3(NT), 0, st, a, ch.q, ch.G, Fs);
+    FactorArgs a = make_args(t, g, ch, const_cast<double2*>(F64), nullptr, nullptr);
+    hipLaunchKernelGGL(k_factor_propagators, dim3(g.J, ch.G, 2), dim3(NT), 0, st, a, ch.q, ch.G, Fs, Fs32);
     return hipGetLastError();
 }
 
@@ -498,10 +503,5 @@ template hipError_t launch_extract_targets<float2>(const float2*, float2*, const
                                                    const Chunks&, hipStream_t);
 template hipError_t launch_extract_targets<double2>(const double2*, double2*, const int*,
                                                     const Geom&, const Chunks&, hipStream_t);
-
-hipError_t launch_convert_factor(const double2* F64, float2* F32, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_convert, dim3(2048), dim3(256), 0, st, F64, F32, n);
-    return hipGetLastError();
-}
 
 }  // namespace helm
