@@ -900,16 +900,31 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets(SolveArgs<T> a) {
 __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a) {
     using V = float2;
     __shared__ V X[2 * WP][16];
+    __shared__ V XF[2][WP][16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
     const int c = blockIdx.x, rbase = blockIdx.y * 16;
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
     const int nr = r1 - r0;
     const bool has_a = c > 0, has_b = c < a.P - 1;
+    // The two-level separator solve leaves the fix-up x_s = xi_s + Psi_s x_{first(g+1)} of the
+    // separators that are not the first of their group g < G-1 to this kernel: each chunk
+    // applies it to its own two separators (side 0 above, side 1 below).
+    bool fix[2];
+    int sfirst[2], sidx[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int cs = side ? c : c - 1;
+        const int g = cs >= 0 && a.q > 0 ? cs / a.q : 0;
+        sidx[side] = cs;
+        fix[side] = a.io.targets_only && a.G >= 2 && a.Fs && a.P > 2 && (side ? has_b : has_a) &&
+                    g < a.G - 1 && cs != g * a.q;
+        sfirst[side] = (g + 1) * a.q;
+    }
     // branch-free staging: every lane loads (a clamped address) and keeps or drops the value
     {
-        V xv[8];
-        bool keepv[8];
+        V xv[8], fv[8];
+        bool keepv[8], keepf[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = t + NT * u;
@@ -917,17 +932,58 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
             const bool above = k < WP;
             keepv[u] = r < a.nrhs && kk < a.W && (above ? has_a : has_b);
             const int row = above ? (has_a ? r0 - 1 : r0) : (has_b ? r1 : r0);
-            xv[u] = a.Yw[((size_t)(r < a.nrhs ? r : 0) * a.Ny + row) * WP + kk];
+            const size_t rr = (size_t)(r < a.nrhs ? r : 0) * a.Ny;
+            xv[u] = a.Yw[(rr + row) * WP + kk];
+            const int side = above ? 0 : 1;
+            keepf[u] = keepv[u] && fix[side];
+            const int frow = fix[side] ? sfirst[side] * a.m + a.m - 1 : row;
+            fv[u] = a.Yw[(rr + frow) * WP + kk];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = t + NT * u;
             X[e >> 4][e & 15] = make_float2(keepv[u] ? xv[u].x : 0.f, keepv[u] ? xv[u].y : 0.f);
+            (&XF[0][0][0])[e] = make_float2(keepf[u] ? fv[u].x : 0.f, keepf[u] ? fv[u].y : 0.f);
         }
     }
     __syncthreads();
+    if (fix[0] || fix[1]) {
+        // X[side] += Psi_s XF[side] (64 x 64 by 64 x 16 on MFMA; wave w: rows 16 w ..)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            if (!fix[side]) continue;
+            const V* Ps = a.Fs + ((size_t)sidx[side] * 2 + 1) * BLK + 16 * w + n;
+            V g[16];
+#pragma unroll
+            for (int s4 = 0; s4 < 16; ++s4) g[s4] = Ps[(size_t)(4 * s4 + q4) * WP];
+            mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+#pragma unroll
+            for (int s4 = 0; s4 < 16; s4 += 2) {
+                const V g0 = g[s4], g1 = g[s4 + 1];
+                const V v0 = XF[side][4 * s4 + q4][n], v1 = XF[side][4 * s4 + 4 + q4][n];
+                aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
+                aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
+                aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
+                aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.y, aI1, 0, 0, 0);
+                aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g0.y, v0.y, aR0, 0, 0, 0);
+                aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.x, aI0, 0, 0, 0);
+                aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g1.y, v1.y, aR1, 0, 0, 0);
+                aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.x, aI1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                V& xr = X[WP * side + 16 * w + 4 * q4 + j][n];
+                xr = make_float2(xr.x + aR0[j] + aR1[j], xr.y + aI0[j] + aI1[j]);
+            }
+        }
+        __syncthreads();
+    }
     const int rn = rbase + n;
     const int nrows = nr * 8, ntile = (nrows + 15) / 16;
+    // the B panel of every tile: [x_above; x_below] in this lane's MFMA layout
+    V vb[32];
+#pragma unroll
+    for (int s4 = 0; s4 < 32; ++s4) vb[s4] = X[4 * s4 + q4][n];
     for (int tile = w + 4 * (int)blockIdx.z; tile < ntile; tile += 4 * (int)gridDim.z) {
         // A operands: row rho = 16 tile + n (clamped), k = 4 s + q4
         const int rho = min(16 * tile + n, nrows - 1);
@@ -956,7 +1012,7 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
 #pragma unroll
         for (int s4 = 0; s4 < 32; s4 += 2) {
             const V g0 = g[s4], g1 = g[s4 + 1];
-            const V v0 = X[4 * s4 + q4][n], v1 = X[4 * s4 + 4 + q4][n];
+            const V v0 = vb[s4], v1 = vb[s4 + 1];
             aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
             aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
             aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
@@ -974,10 +1030,10 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
             }
         }
     }
-    // the separator row closing this chunk
+    // the separator row closing this chunk (its x, fixed up above if needed, is in X)
     if (has_b && blockIdx.z == 0 && t < 8 * 16) {
         const int tt = t >> 4, r = rbase + (t & 15), q = a.tcol[tt];
-        if (q >= 0 && r < a.nrhs) scatter<float>(a, r, r1, q, a.Yw[((size_t)r * a.Ny + r1) * WP + q]);
+        if (q >= 0 && r < a.nrhs) scatter<float>(a, r, r1, q, X[WP + q][t & 15]);
     }
 }
 
@@ -1009,7 +1065,9 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
             hipLaunchKernelGGL((k_sep_fwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
             hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
             hipLaunchKernelGGL((k_sep_bwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
-            hipLaunchKernelGGL((k_sep_bwd_fix<T, DS>), dim3(nr, a.G - 1), dim3(NT), 0, st, a);
+            // complex64 targets-only solves fix the separators up inside phase C
+            if (!(std::is_same<T, float>::value && targets))
+                hipLaunchKernelGGL((k_sep_bwd_fix<T, DS>), dim3(nr, a.G - 1), dim3(NT), 0, st, a);
         } else {
             hipLaunchKernelGGL((k_phase_b0<T, R>), dim3(a.P - 1, RG), dim3(NT), 0, st, a);
         }
