@@ -120,28 +120,27 @@ __global__ void __launch_bounds__(256) k_apply_A_pairs(StencilArgs s, const int*
 }
 
 // Reduced-form stencils on interface windows (layout [nrhs][Nrow][NI][IWIN], window j holding
-// the columns bw[j] .. bw[j] + IWIN - 1).  One thread per row, interface and output column;
-// consecutive threads take the two columns of one window, then the next window of the row.
+// the columns bw[j] .. bw[j] + IWIN - 1).  Grid (rows, right-hand sides): a workgroup takes
+// one row of one right-hand side, a thread one output column (the two of a window side by
+// side, then the next window), so no index needs a division.
 //   MODE 0: g[c] = psi(c) - (A u)[c], c = 1, 2, with psi(c) = psi[.., 2 j + c - 2] for c = 2, 0 for c = 1
 //   MODE 1: out[.., 2 j + k] = psi[.., 2 j + k] - (g[2 + k] - (A u)[2 + k]), k = 0, 1
 template <int MODE>
-__global__ void __launch_bounds__(256) k_stencil_win(StencilArgs s, const int* __restrict__ bw,
+__global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* __restrict__ bw,
                                                      const double* __restrict__ k2w, int NI, int nrhs,
                                                      const double2* __restrict__ u,
                                                      const double2* __restrict__ psi,
                                                      double2* __restrict__ gw, double2* __restrict__ out) {
     const int nrow = s.Ny * s.Nz;
     const size_t wrow = (size_t)NI * IWIN;
-    const size_t tot = (size_t)nrhs * nrow * NI * 2;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
-         q += (size_t)gridDim.x * blockDim.x) {
-        const int k = (int)(q & 1);
-        const int j = (int)((q >> 1) % NI);
-        const size_t rr = (q >> 1) / NI;            // r * nrow + row
-        const int row = (int)(rr % nrow);
+    const int row = blockIdx.x;
+    const size_t rr = (size_t)blockIdx.y * nrow + row;   // r * nrow + row
+    const int l = row % s.Ny, z = row / s.Ny;
+    (void)nrhs;
+    for (int q = threadIdx.x; q < 2 * NI; q += blockDim.x) {
+        const int k = q & 1, j = q >> 1;
         const int c = (MODE == 0 ? 1 : 2) + k;
         const int i = bw[j] + c;
-        const int l = row % s.Ny, z = row / s.Ny;
         const size_t b = rr * wrow + (size_t)j * IWIN + c;
         const double2 uc = u[b], ue = u[b + 1], uw = u[b - 1];
         const double2 un = (l + 1 < s.Ny) ? u[b + wrow] : cmk<double2>(0, 0);
@@ -241,12 +240,13 @@ __global__ void k_reduce_partials(const double2* __restrict__ partial, int nb, i
 }
 
 // w[r] -= sum_i h[r][i] V_i[r]
+// grid (blocks, right-hand sides): blockIdx.y is the right-hand side (no division per element)
 __global__ void k_update(const double2* __restrict__ V, int nvec, const double2* __restrict__ h,
                          double2* __restrict__ w, int nrhs, long n) {
     const size_t tot = (size_t)nrhs * n;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
-         q += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(q / n);
+    const int r = blockIdx.y;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
+        const size_t q = (size_t)r * n + p;
         double2 acc = w[q];
         for (int i = 0; i < nvec; ++i) acc = csub(acc, cmul(h[r * nvec + i], V[(size_t)i * tot + q]));
         w[q] = acc;
@@ -293,9 +293,9 @@ __global__ void k_scale(const double2* __restrict__ w, const double* __restrict_
 __global__ void k_lincomb(const double2* __restrict__ V, int nvec, const double2* __restrict__ y,
                           double2* __restrict__ out, int nrhs, long n, int accumulate) {
     const size_t tot = (size_t)nrhs * n;
-    for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
-         q += (size_t)gridDim.x * blockDim.x) {
-        const int r = (int)(q / n);
+    const int r = blockIdx.y;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < n; p += (long)gridDim.x * blockDim.x) {
+        const size_t q = (size_t)r * n + p;
         double2 acc = accumulate ? out[q] : cmk<double2>(0, 0);
         for (int i = 0; i < nvec; ++i) acc = cadd(acc, cmul(y[r * nvec + i], V[(size_t)i * tot + q]));
         out[q] = acc;
@@ -372,12 +372,11 @@ hipError_t launch_stencil_win(int mode, const DevTables& t, const Geom& g, int n
     const int NI = g.J - 1;
     if (NI <= 0) return hipSuccess;
     StencilArgs s = stencil_args(t, g);
-    const size_t tot = (size_t)nrhs * g.Nrow() * NI * 2;
-    const dim3 grid(grid_for(tot));
+    const dim3 grid((unsigned)g.Nrow(), (unsigned)nrhs);
     if (mode == 0)
-        hipLaunchKernelGGL(k_stencil_win<0>, grid, dim3(256), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
+        hipLaunchKernelGGL(k_stencil_win<0>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
     else
-        hipLaunchKernelGGL(k_stencil_win<1>, grid, dim3(256), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
+        hipLaunchKernelGGL(k_stencil_win<1>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
     return hipGetLastError();
 }
 
@@ -392,8 +391,8 @@ hipError_t launch_dots(const double2* V, int nvec, const double2* w, int nrhs, l
 
 hipError_t launch_update(const double2* V, int nvec, const double2* h, double2* w, int nrhs,
                          long n, hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3(grid_for((size_t)nrhs * n)), dim3(256), 0, st, V, nvec, h,
-                       w, nrhs, n);
+    const unsigned bx = std::max(1u, grid_for((size_t)nrhs * n) / (unsigned)nrhs);
+    hipLaunchKernelGGL(k_update, dim3(bx, nrhs), dim3(256), 0, st, V, nvec, h, w, nrhs, n);
     return hipGetLastError();
 }
 
@@ -414,8 +413,8 @@ hipError_t launch_scale(const double2* w, const double* nrm, double2* out, int n
 
 hipError_t launch_lincomb(const double2* V, int nvec, const double2* y, double2* out,
                           int nrhs, long n, int accumulate, hipStream_t st) {
-    hipLaunchKernelGGL(k_lincomb, dim3(grid_for((size_t)nrhs * n)), dim3(256), 0, st, V, nvec, y,
-                       out, nrhs, n, accumulate);
+    const unsigned bx = std::max(1u, grid_for((size_t)nrhs * n) / (unsigned)nrhs);
+    hipLaunchKernelGGL(k_lincomb, dim3(bx, nrhs), dim3(256), 0, st, V, nvec, y, out, nrhs, n, accumulate);
     return hipGetLastError();
 }
 
