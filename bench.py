@@ -39,7 +39,10 @@ def parse():
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--prec", default="mixed", choices=["mixed", "c128"])
     p.add_argument("--mode", default="reduced", choices=["reduced", "full"])
-    p.add_argument("--chunk", type=int, default=0)
+    p.add_argument("--chunk", type=int, default=0,
+                   help="rows per chunk of the strip solver; 0 = autotuned before the timed steps")
+    p.add_argument("--tune-candidates", default="16,24,32,40,48",
+                   help="chunk sizes the autotuner times (2-D)")
     p.add_argument("--tol", type=float, default=1e-6)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-c128-leg", action="store_true",
@@ -238,7 +241,10 @@ def c128_legs(wl, f, tol, plain_rhs=2):
     from paper_1208_3956_amd import Helmholtz
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
                   prec="c128", mode="reduced", device="cuda:0")
-    H.factor()
+    if wl.dim == 2:
+        H.autotune(f, reps=1, cache=None)     # factors with its own best chunk size
+    else:
+        H.factor()
     torch.cuda.synchronize()
     pts_rhs = wl.n_points
     ta = time.perf_counter()
@@ -351,6 +357,14 @@ def main():
           file=sys.stderr, flush=True)
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
                   prec=args.prec, mode=args.mode, chunk=args.chunk, device=dev)
+    tuned = None
+    if args.chunk == 0 and wl.dim == 2:
+        # outside the timed region: one GMRES iteration's operator timed per candidate
+        cand = [int(x) for x in args.tune_candidates.split(",") if x.strip()]
+        tuned = H.autotune(f, candidates=cand, reps=2, cache=None)
+        print(f"# autotune: chunk {tuned['chunk_rows']} "
+              f"({', '.join(f'{c}: {t:.1f} ms' for c, t in tuned['ms_per_apply'].items())})",
+              file=sys.stderr, flush=True)
     res = None
     for k in range(args.warmup):
         H.factor()
@@ -406,6 +420,7 @@ def main():
         "config": {"workload": wl.name, "n": wl.n_x, "dim": wl.dim, "nrhs": nrhs, "J": wl.J,
                    "pml_outer": wl.w_out, "pml_iface": wl.w, "prec": args.prec,
                    "mode": args.mode, "chunk_rows": H.chunk_rows, "tol": args.tol,
+                   "autotune": tuned,
                    "step": "helm_factor + helm_solve"},
         "solve_only_value": pts / (solve_ms / 1e3), "solve_ms": solve_ms,
         "factor_ms": t_fac * 1e3 / args.steps,

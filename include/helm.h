@@ -117,16 +117,39 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
 helm_status helm_factor(helm_t H);
 
 /*
+ * Autotuner of the strip solver's y-partition (2-D): for each candidate number of rows
+ * per chunk, refactor and time `reps` applications of the operator one GMRES iteration
+ * applies (Algorithm 3 on the reduced columns of `rhs` in REDUCED mode, A P on `rhs` in
+ * FULL mode) with HIP events on the handle's stream; the handle is left factored with
+ * the fastest candidate.  The chunk size changes only the order of the substitutions
+ * (the strip inverse is the same in exact arithmetic), so any candidate is correct.
+ *   rhs     device, nrhs * N_y * N_x complex128 (padded grid): the panel to time on
+ *   cand    host, ncand ints >= 2: candidate rows per chunk
+ *   best    host, one int (may be NULL): the chosen rows per chunk
+ *   ms      host, ncand doubles (may be NULL): milliseconds per application
+ * 3-D handles have one chunk per slab: nothing is timed, best = N_y, ms = 0 (factored if
+ * it was not).  HELM_EINVAL for nrhs, ncand or reps < 1, a candidate below 2 or a null
+ * rhs / cand; errors of helm_factor are passed on.
+ */
+helm_status helm_autotune(helm_t H, int nrhs, const void* rhs, const int* cand, int ncand,
+                          int reps, int* best, double* ms);
+
+/*
  * Algorithm 5: solve A u = f for nrhs right-hand sides by right-preconditioned GMRES
  * with the double-sweep preconditioner, starting from u = 0 (FULL) or u = u~ (REDUCED,
  * Algorithm 2), stopping when the GMRES residual has dropped by `tol` relative to its
  * start (Sec. 4: reduction by 1e-6, capped at tol ||f||), then checking the true
  * residual ||f - A u|| / ||f|| in FP64 and, while it exceeds tol, running another GMRES
- * cycle on that residual (iterative refinement; right-hand sides that already meet tol
- * take no part), up to max_iter applications of A P in total.
+ * cycle on that residual r (iterative refinement; right-hand sides that already meet tol
+ * take no part), up to max_iter applications of A P in total.  In REDUCED mode such a
+ * cycle starts from u~ = P r instead of the strip solves of Algorithm 2: r - A P r lives
+ * on the same interface columns (Sec. 2.1), and the sweep also removes what the
+ * complex64 strip solves leave off those columns; this application of P counts as one
+ * iteration.
  *   rhs     device, nrhs * N_y * N_x complex128 (padded grid)
  *   u       device, same shape, output
- *   iters   host, nrhs ints (may be NULL): GMRES iterations (applications of A P)
+ *   iters   host, nrhs ints (may be NULL): GMRES iterations (applications of A P, plus
+ *           one per REDUCED restart)
  *   relres  host, nrhs doubles (may be NULL): explicit ||f - A u|| / ||f||
  * HELM_ESTATE before helm_factor; HELM_ENOCONV if some right-hand side missed tol after
  * max_iter (u and relres still hold the best iterate).

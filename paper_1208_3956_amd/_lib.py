@@ -22,7 +22,7 @@ EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm
            "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
            "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
-           "helm_solve_batch", "helm_get_dims3"]
+           "helm_solve_batch", "helm_get_dims3", "helm_autotune"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
     L.helm_grad.argtypes = [vp, ci, vp, ci, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                             vp, pint]
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
+    L.helm_autotune.argtypes = [vp, ci, vp, pint, ci, ci, pint, pdbl]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
     L.helm_get_dims3.argtypes = [vp, pint, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
@@ -133,6 +134,17 @@ def helm_solve(hdl, nrhs: int, rhs_ptr: int, u_ptr: int, tol: float):
     if st not in (HELM_OK, HELM_ENOCONV):
         check(st, hdl)
     return st, list(iters), list(rel)
+
+
+def helm_autotune(hdl, nrhs: int, rhs_ptr: int, cand, reps: int):
+    """Returns (chosen rows per chunk, milliseconds per application for each candidate)."""
+    n = len(cand)
+    C = (ctypes.c_int * n)(*[int(c) for c in cand])
+    ms = (ctypes.c_double * n)()
+    best = ctypes.c_int(0)
+    check(lib().helm_autotune(hdl, int(nrhs), ctypes.c_void_p(rhs_ptr), C, n, int(reps),
+                              ctypes.byref(best), ms), hdl)
+    return best.value, list(ms)
 
 
 def helm_apply_P(hdl, nrhs: int, f_ptr: int, out_ptr: int) -> None:

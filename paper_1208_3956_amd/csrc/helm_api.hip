@@ -103,6 +103,7 @@ struct helm_problem {
     void* Fs = nullptr;         // separator propagators of the two-level separator solve
     double2* F64 = nullptr;     // FP64 factor (the complex64 path's factorisation workspace)
     double2* Fs64 = nullptr;    // FP64 propagators (idem)
+    int fac_m = 0;              // rows per chunk the factor buffers were laid out for
     bool factored = false;
     int* d_err = nullptr;
     Work wk;
@@ -128,6 +129,19 @@ struct helm_problem {
 namespace {
 
 thread_local std::string g_setup_err;   // message of the last failed helm_setup
+
+// y-partition of the strip solver: m rows per chunk, the last row of every chunk but the
+// last a separator; separator groups of q ~ sqrt(#separators) for the two-level solve
+void set_chunks(helm_t H, int m) {
+    const int Ny = H->g.Ny;
+    m = std::max(2, m);
+    H->ch.m = m;
+    H->ch.P = (Ny + m - 1) / m;
+    if (H->ch.P > 1 && (H->ch.P - 1) * m >= Ny) H->ch.P -= 1;
+    const int ns = H->ch.P - 1;
+    H->ch.q = std::max(2, (int)std::ceil(std::sqrt((double)std::max(ns, 1))));
+    H->ch.G = ns >= 4 ? (ns + H->ch.q - 1) / H->ch.q : 1;
+}
 
 // HELM_TRACE=1 in the environment prints the residual history of every GMRES cycle to stderr
 bool trace_on() {
@@ -726,9 +740,23 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
                     HIPCHK(hipMemsetAsync(w.R + (size_t)r * nfull, 0, nfull * sizeof(double2), H->st));
         const double2* b = w.R;
         if (reduced) {
-            // Algorithm 2 on the current residual: u~ and phi = r - A u~ (reduced columns);
-            // the strips' D~ ranges partition the columns, so u~ is written everywhere
-            CHK(reduced_setup(H, nrhs, w.R, w.Ut));
+            // first cycle, Algorithm 2: u~ from independent strip solves of f on D~^(j)
+            // (the strips' D~ ranges partition the columns, so u~ is written everywhere).
+            // A restart starts from u~ = P r instead: r - A P r is again supported on the
+            // reduced columns (Sec. 2.1, exact arithmetic), and the sweep removes the
+            // complex64 rounding residual left off those columns (which the reduced GMRES
+            // cannot see) together with its transmission across the interfaces, where
+            // strip solves alone would leave it on the interface columns.  This
+            // application of P is counted as an iteration.
+            if (cycle == 0) {
+                CHK(reduced_setup(H, nrhs, w.R, w.Ut));
+            } else {
+                H->stat_ap += 1;
+                CHK(apply_P_full(H, nrhs, w.R, w.Ut));
+                for (int r = 0; r < nrhs; ++r)
+                    if (rn[r] > tol * fn[r]) total[r] += 1;
+                used += 1;
+            }
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
             b = w.red;
@@ -871,19 +899,8 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
             return bad("3-D slab blocks of " + std::to_string(Bmax) + " unknowns exceed " +
                        std::to_string(helm::BP3_MAX) + " (use thinner slabs or fewer z points)");
     }
-    // ---- chunks along y
-    int m = opts->chunk > 0 ? opts->chunk : 32;
-    if (m < 2) m = 2;
-    if (dim == 3) m = g.Ny;        // 3-D slabs: one chunk (each plane step is a large product)
-    H->ch.m = m;
-    H->ch.P = (g.Ny + m - 1) / m;
-    if (H->ch.P > 1 && (H->ch.P - 1) * m >= g.Ny) H->ch.P -= 1;
-    {
-        // separator groups for the two-level separator solve: q ~ sqrt(#separators)
-        const int ns = H->ch.P - 1;
-        H->ch.q = std::max(2, (int)std::ceil(std::sqrt((double)std::max(ns, 1))));
-        H->ch.G = ns >= 4 ? (ns + H->ch.q - 1) / H->ch.q : 1;
-    }
+    // ---- chunks along y (3-D slabs: one chunk, each plane step is a large product)
+    set_chunks(H, dim == 3 ? g.Ny : (opts->chunk > 0 ? opts->chunk : 32));
     H->prec = opts->prec == HELM_MIXED_C64 ? HELM_MIXED_C64 : HELM_C128;
     H->mode = opts->mode == HELM_REDUCED ? HELM_REDUCED : HELM_FULL;
     H->max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
@@ -1072,17 +1089,25 @@ helm_status helm_factor(helm_t H) {
     const size_t esz = single ? sizeof(float2) : sizeof(double2);
     if (!H->F64) {
         CHK(dmalloc(H, &H->F64, nel * sizeof(double2)));
-        HIPCHK(hipMemsetAsync(H->F64, 0, nel * sizeof(double2), H->st));
-        if (nsel) CHK(dmalloc(H, &H->Fs64, nsel * sizeof(double2)));
-        if (single) {
-            CHK(dmalloc(H, &H->F, nel * esz));
-            HIPCHK(hipMemsetAsync(H->F, 0, nel * esz, H->st));
-            if (nsel) CHK(dmalloc(H, &H->Fs, nsel * esz));
-        } else {
-            H->F = H->F64;
-            H->Fs = H->Fs64;
-        }
+        if (single) CHK(dmalloc(H, &H->F, nel * esz));
+        else H->F = H->F64;
         CHK(dmalloc(H, &H->Fc, ncomp * esz));
+        H->fac_m = 0;
+    }
+    if (H->fac_m != H->ch.m) {
+        // first factorisation, or a new y-partition (autotuning): the slots a partition
+        // leaves unwritten read as zero, and the propagators take its separator count
+        HIPCHK(hipMemsetAsync(H->F64, 0, nel * sizeof(double2), H->st));
+        if (single) HIPCHK(hipMemsetAsync(H->F, 0, nel * esz, H->st));
+        if (H->Fs != H->Fs64) dfree(H->Fs);
+        dfree(H->Fs64);
+        H->Fs = H->Fs64 = nullptr;
+        if (nsel) {
+            CHK(dmalloc(H, &H->Fs64, nsel * sizeof(double2)));
+            if (single) CHK(dmalloc(H, &H->Fs, nsel * esz));
+            else H->Fs = H->Fs64;
+        }
+        H->fac_m = H->ch.m;
     }
     double2* F64 = H->F64;
     float2* F32 = single ? static_cast<float2*>(H->F) : nullptr;
@@ -1120,6 +1145,72 @@ helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
     const auto t1 = std::chrono::steady_clock::now();
     H->stat_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     return s;
+}
+
+helm_status helm_autotune(helm_t H, int nrhs, const void* rhs, const int* cand, int ncand, int reps,
+                          int* best, double* ms) {
+    if (!H) return HELM_EINVAL;
+    if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
+    if (nrhs < 1 || !rhs || !cand || ncand < 1 || reps < 1)
+        return fail(H, HELM_EINVAL, "helm_autotune: nrhs, reps, ncand >= 1 and non-null rhs, cand required");
+    for (int c = 0; c < ncand; ++c)
+        if (cand[c] < 2) return fail(H, HELM_EINVAL, "helm_autotune: candidate chunk sizes must be >= 2");
+    const auto& g = H->g;
+    if (g.dim == 3) {
+        // a slab is one chunk: nothing to choose
+        if (best) *best = H->ch.m;
+        if (ms) for (int c = 0; c < ncand; ++c) ms[c] = 0.0;
+        if (!H->factored) return helm_factor(H);
+        return HELM_OK;
+    }
+    const bool reduced = H->mode == HELM_REDUCED && g.J >= 2;
+    const int nred = 2 * (g.J - 1);
+    CHK(ensure_sweep_ws(H, nrhs));
+    // the operator one GMRES iteration applies: Algorithm 3 on the right-hand sides'
+    // reduced columns (REDUCED), or P followed by A (FULL)
+    const size_t in_bytes = reduced ? (size_t)nrhs * g.Nrow() * nred * sizeof(double2) : field_bytes(H, nrhs);
+    double2 *xin = nullptr, *xout = nullptr;
+    struct Bufs { double2** a; double2** b; ~Bufs() { dfree(*a); dfree(*b); } } bufs{&xin, &xout};
+    CHK(dmalloc(H, &xin, in_bytes));
+    CHK(dmalloc(H, &xout, in_bytes));
+    if (reduced)
+        HIPCHK(helm::launch_gather_cols(static_cast<const double2*>(rhs), H->t.redcols, nred, nrhs, g.Nrow(),
+                                        g.Nx, xin, H->st));
+    else
+        HIPCHK(hipMemcpyAsync(xin, rhs, in_bytes, hipMemcpyDeviceToDevice, H->st));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } ev{e0, e1};
+    auto apply = [&]() -> helm_status {
+        if (reduced) return apply_AP_reduced(H, nrhs, xin, xout);
+        CHK(apply_P_full(H, nrhs, xin, H->wk.PF));
+        HIPCHK(helm::launch_apply_A(H->t, g, nrhs, H->wk.PF, nullptr, xout, H->st));
+        return HELM_OK;
+    };
+    int bi = -1;
+    double bms = 0.0;
+    for (int c = 0; c < ncand; ++c) {
+        set_chunks(H, cand[c]);
+        CHK(helm_factor(H));
+        CHK(apply());                      // warm-up (first touch of the layout)
+        HIPCHK(hipEventRecord(e0, H->st));
+        for (int r = 0; r < reps; ++r) CHK(apply());
+        HIPCHK(hipEventRecord(e1, H->st));
+        HIPCHK(hipEventSynchronize(e1));
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, e0, e1));
+        const double per = (double)t / reps;
+        if (ms) ms[c] = per;
+        if (bi < 0 || per < bms) { bi = c; bms = per; }
+    }
+    if (best) *best = cand[bi];
+    if (cand[bi] != H->ch.m) {
+        set_chunks(H, cand[bi]);
+        CHK(helm_factor(H));
+    }
+    HIPCHK(hipStreamSynchronize(H->st));
+    return HELM_OK;
 }
 
 helm_status helm_solve_batch(int nprob, const helm_t* H, const int* nrhs, const void* const* rhs,

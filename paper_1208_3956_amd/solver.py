@@ -124,6 +124,35 @@ class Helmholtz:
         self.factored = True
         return self
 
+    def autotune(self, rhs: torch.Tensor, candidates: Sequence[int] = (16, 24, 32, 40, 48),
+                 reps: int = 2, cache: Optional[str] = "default") -> dict:
+        """Pick the strip solver's rows per chunk by timing one GMRES iteration's operator
+        on `rhs` for each candidate (helm_autotune); leaves the handle factored with the
+        fastest.  Results are kept in a JSON cache keyed by the problem's shape (device
+        name, precision, mode, padded grid, strip widths, right-hand sides): a hit skips the
+        timing and only refactors with the cached choice.  cache=None disables it;
+        "default" is $HELM_TUNE_CACHE or ~/.cache/paper_1208_3956_amd/tune.json."""
+        from . import tune
+        f = self._field(rhs, "rhs")
+        key = tune.key(torch.cuda.get_device_name(self.device), self.prec, self.mode,
+                       (self.N_x, self.N_y, self.N_z), self.strip_width, f.shape[0])
+        path = tune.cache_path(cache)
+        hit = tune.lookup(path, key) if path else None
+        self._begin()
+        with torch.cuda.device(self.device):
+            if hit is not None:
+                best, ms = L.helm_autotune(self.h, f.shape[0], f.data_ptr(), [int(hit)], 1)
+                times = {}
+            else:
+                best, ms = L.helm_autotune(self.h, f.shape[0], f.data_ptr(), list(candidates), reps)
+                times = {int(c): t for c, t in zip(candidates, ms)}
+        self._end()
+        if hit is None and path and self.dim == 2:
+            tune.store(path, key, best, times)
+        self.chunk_rows, self.n_chunks = L.helm_get_chunks(self.h)
+        self.factored = True
+        return {"chunk_rows": best, "ms_per_apply": times, "cached": hit is not None}
+
     def solve(self, rhs: torch.Tensor, tol: float = 1e-6) -> SolveResult:
         f = self._field(rhs, "rhs")
         u = torch.empty_like(f)
