@@ -110,8 +110,13 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
  * by block LU with explicit inverses and its two spikes, and the separators by block LU
  * of their Schur complement.  In 3-D a slab is block tridiagonal along y with dense
  * (W N_z) x (W N_z) blocks (the (x, z) planes); each is inverted by blocked Gauss-Jordan
- * elimination with partial pivoting, plane after plane (the blocks of all slabs of one
- * plane together).  Computed in FP64; stored in FP64 (HELM_C128) or FP32.
+ * elimination, plane after plane (the blocks of all slabs of one plane together).  2-D:
+ * computed in FP64, stored in FP64 (HELM_C128) or rounded to complex64.  3-D HELM_C128:
+ * FP64 with partial pivoting over the whole column.  3-D HELM_MIXED_C64: complex64 with
+ * FP32 accumulation, pivoting inside the 64 x 64 diagonal blocks only (their inverses in
+ * FP64); if a diagonal block is singular or its 1-norm condition exceeds 1e6 the
+ * factorisation is redone by the FP64 route and rounded (helm_get_factor_path tells
+ * which ran).
  * HELM_ESINGULAR if a pivot is zero or not finite.
  */
 helm_status helm_factor(helm_t H);
@@ -231,6 +236,14 @@ helm_status helm_get_dims3(helm_t H, int* N_x, int* N_y, int* N_z, int* J);
  * beta[J] = N_x); the first global column and width of each padded strip (host, J each). */
 helm_status helm_get_dims(helm_t H, int* N_x, int* N_y, int* J);
 helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip_width);
+
+/* Which factorisation produced the stored 3-D slab inverses (host int):
+ *   1  complex64 blocked Gauss-Jordan with pivoting inside the 64 x 64 diagonal blocks
+ *      (HELM_MIXED_C64, every diagonal block inverted with a 1-norm condition <= 1e6),
+ *   0  FP64 Gauss-Jordan with partial pivoting over the whole column (HELM_C128, a
+ *      complex64 attempt that met a singular or ill-conditioned diagonal block, and 2-D).
+ * HELM_ESTATE before helm_factor. */
+helm_status helm_get_factor_path(helm_t H, int* path);
 
 /* y-partition of the strip solver: rows per chunk (the last row of every chunk but the
  * last is a separator) and the number of chunks (host ints). */

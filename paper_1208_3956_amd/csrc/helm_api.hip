@@ -104,6 +104,7 @@ struct helm_problem {
     double2* F64 = nullptr;     // FP64 factor (the complex64 path's factorisation workspace)
     double2* Fs64 = nullptr;    // FP64 propagators (idem)
     int fac_m = 0;              // rows per chunk the factor buffers were laid out for
+    int factor_path = 0;        // 3-D: 1 = complex64 blocked Gauss-Jordan, 0 = FP64 inverses
     bool factored = false;
     int* d_err = nullptr;
     Work wk;
@@ -1028,7 +1029,40 @@ helm_status factor3(helm_t H) {
     const size_t nb = helm::factor3_panel_width();
     double2 *S, *G64, *Tm, *Cm;
     int *perm, *pi;
+    void* work32 = nullptr;
     helm_status st;
+    helm::Fac3Args a;
+    a.J = g.J; a.Ny = g.Ny; a.Nz = g.Nz; a.Nx = g.Nx; a.Bp = g.Bp;
+    a.sW = H->t.sW; a.sax = H->t.sax; a.saxh = H->t.saxh; a.scol = H->t.scol;
+    a.ay = H->t.ay; a.ayh = H->t.ayh; a.az = H->t.az; a.azh = H->t.azh;
+    a.cy = H->t.cy; a.by = H->t.by; a.k2 = H->t.k2;
+    a.ih2 = 1.0 / (g.h * g.h);
+    int herr = 0;
+    if (single) {
+        // complex64 blocked Gauss-Jordan in place in the stored factor; a diagonal block
+        // that is singular or ill-conditioned sends the whole factorisation to the FP64
+        // Gauss-Jordan with partial pivoting over the whole column below
+        if ((st = alloc(&work32, helm::factor3_f32_work_bytes(g.J, g.Bp))) != HELM_OK) { dfree(F); return st; }
+        HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
+        for (int l = 0; l < g.Ny; ++l) {
+            hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS,
+                                 helm::launch_factor3_plane_f32(a, l, static_cast<float2*>(F), (size_t)g.Ny * BB,
+                                                                work32, H->d_err, H->st));
+            if (e != hipSuccess) { dfree(F); HIPCHK(e); }
+        }
+        HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
+        HIPCHK(hipStreamSynchronize(H->st));
+        H->factor_path = herr ? 0 : 1;
+        if (trace_on())
+            std::fprintf(stderr, "[helm] 3-D complex64 blocked Gauss-Jordan: %s\n",
+                         herr ? "ill-conditioned diagonal block, redone in FP64" : "accepted");
+        if (!herr) {
+            H->F = F;
+            H->factored = true;
+            return HELM_OK;
+        }
+    }
+    H->factor_path = 0;
     if ((st = alloc((void**)&S, g.J * BB * sizeof(double2))) != HELM_OK ||
         (st = alloc((void**)&G64, g.J * BB * sizeof(double2))) != HELM_OK ||
         (st = alloc((void**)&Tm, (size_t)g.J * g.Bp * nb * sizeof(double2))) != HELM_OK ||
@@ -1039,12 +1073,6 @@ helm_status factor3(helm_t H) {
         return st;
     }
     HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
-    helm::Fac3Args a;
-    a.J = g.J; a.Ny = g.Ny; a.Nz = g.Nz; a.Nx = g.Nx; a.Bp = g.Bp;
-    a.sW = H->t.sW; a.sax = H->t.sax; a.saxh = H->t.saxh; a.scol = H->t.scol;
-    a.ay = H->t.ay; a.ayh = H->t.ayh; a.az = H->t.az; a.azh = H->t.azh;
-    a.cy = H->t.cy; a.by = H->t.by; a.k2 = H->t.k2;
-    a.ih2 = 1.0 / (g.h * g.h);
     for (int l = 0; l < g.Ny; ++l) {
         void* out = static_cast<char*>(F) + (size_t)l * BB * esz;
         hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS,
@@ -1052,7 +1080,7 @@ helm_status factor3(helm_t H) {
                                                         H->d_err, G64, out, single, (size_t)g.Ny * BB, H->st));
         if (e != hipSuccess) { dfree(F); HIPCHK(e); }
     }
-    int herr = 0;
+    herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
     H->F = F;
@@ -1407,6 +1435,13 @@ helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* sol
     if (ap_applies) *ap_applies = H->stat_ap;
     if (restarts) *restarts = H->stat_restarts;
     if (solve_ms) *solve_ms = H->stat_ms;
+    return HELM_OK;
+}
+
+helm_status helm_get_factor_path(helm_t H, int* path) {
+    if (!H || !path) return HELM_EINVAL;
+    if (!H->factored) return fail(H, HELM_ESTATE, "helm_get_factor_path before helm_factor");
+    *path = H->g.dim == 3 ? H->factor_path : 0;
     return HELM_OK;
 }
 

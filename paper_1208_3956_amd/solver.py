@@ -153,6 +153,12 @@ class Helmholtz:
         self.factored = True
         return {"chunk_rows": best, "ms_per_apply": times, "cached": hit is not None}
 
+    @property
+    def factor_path(self) -> int:
+        """3-D: 1 when the slab inverses came from the complex64 blocked Gauss-Jordan, 0
+        when from the FP64 one (always 0 in 2-D)."""
+        return L.helm_get_factor_path(self.h)
+
     def solve(self, rhs: torch.Tensor, tol: float = 1e-6) -> SolveResult:
         f = self._field(rhs, "rhs")
         u = torch.empty_like(f)

@@ -133,3 +133,42 @@ def test_3d_one_slab_is_one_iteration():
     res = H.solve(_t(wl.rhs()), tol=1e-10)
     assert res.iters == [1] and max(res.relres) < 1e-10
     H.close()
+
+
+def test_factor_path_by_precision(case):
+    """complex64 slabs are inverted by the complex64 blocked Gauss-Jordan (its diagonal
+    blocks are well conditioned here); complex128 by the FP64 one."""
+    wl, g, A, S = case
+    H = _gpu(wl, prec="mixed")
+    assert H.factor_path == 1
+    H.close()
+    H = _gpu(wl, prec="c128")
+    assert H.factor_path == 0
+    H.close()
+
+
+@pytest.fixture(scope="module")
+def smooth40():
+    wl = W.smooth_3d(n=40, nsrc=4)
+    g = geometry_from_workload(wl)
+    return wl, g
+
+
+@pytest.mark.parametrize("s", [7, 15])
+def test_complex64_slab_factor_multiblock(smooth40, s):
+    """40^3 smooth medium (blocks of 14 x 64 unknowns after padding): slab solves of the
+    complex64 blocked Gauss-Jordan factor against the oracle's SuperLU slab solves."""
+    from oracle.assemble import assemble_strip
+    import scipy.sparse.linalg as spla
+    wl, g = smooth40
+    H = _gpu(wl, prec="mixed")
+    assert H.factor_path == 1
+    st = g.strips[s]
+    print(f"slab {s}: {g.strip_shape(st)}", flush=True)
+    lu = spla.splu(assemble_strip(g, st).tocsc(), permc_spec="COLAMD")
+    rng = np.random.default_rng(40 + s)
+    r = _rand(rng, (3,) + g.strip_shape(st))
+    x = H.strip_solve(s, _t(r)).cpu().numpy()
+    ref = np.stack([lu.solve(rk.ravel()).reshape(rk.shape) for rk in r])
+    assert _rel(x, ref) < TOL_C64, _rel(x, ref)
+    H.close()
