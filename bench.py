@@ -70,14 +70,14 @@ def phase_flops(H, wl, nrhs):
     """Algorithmic real flops of one launch of each strip-solve phase and of the factor,
     averaged over strips (8 real flops per complex multiply-add).  In 3-D one timed
     phase-A launch is a whole slab solve (2 N_y - 1 plane products with the B x B inverses,
-    B = W N_z) and one factor launch is one plane of every slab (B^3 multiply-adds of
-    Gauss-Jordan per slab)."""
+    B = W N_z) and one timed factor unit is the whole factorisation (B^3 multiply-adds of
+    Gauss-Jordan per slab and plane)."""
     Ny = H.N_y
     if H.dim == 3:
         B = [w * H.N_z for w in H.strip_width]
         B2 = sum(b * b for b in B) / len(B)
         return {"phase_a": 8.0 * B2 * nrhs * (2 * Ny - 1), "phase_b": 0.0, "phase_c": 0.0,
-                "factor_chunks": 8.0 * sum(b ** 3 for b in B), "factor_separators": 0.0}
+                "factor_chunks": 8.0 * sum(b ** 3 for b in B) * Ny, "factor_separators": 0.0}
     m = H.chunk_rows
     P = -(-Ny // m)
     n_int = Ny - (P - 1)                    # interior rows over all chunks

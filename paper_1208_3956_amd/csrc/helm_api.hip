@@ -116,6 +116,7 @@ struct helm_problem {
     int dev = 0;                // HIP device of the handle
     int use_graph = 1;          // replay Algorithm 3 from a captured HIP graph (REDUCED)
     hipGraphExec_t ap_exec = nullptr;
+    hipStream_t st2 = nullptr;     // second stream of the 3-D complex64 factorisation
     hipStream_t cap_st = nullptr;  // private stream the graph is captured on (capture is not
                                    // allowed on the legacy default stream); replays go to st
     int ap_nrhs = 0;
@@ -1044,12 +1045,31 @@ helm_status factor3(helm_t H) {
         // Gauss-Jordan with partial pivoting over the whole column below
         if ((st = alloc(&work32, helm::factor3_f32_work_bytes(g.J, g.Bp))) != HELM_OK) { dfree(F); return st; }
         HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
-        for (int l = 0; l < g.Ny; ++l) {
-            hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS,
-                                 helm::launch_factor3_plane_f32(a, l, static_cast<float2*>(F), (size_t)g.Ny * BB,
-                                                                work32, H->d_err, H->st));
-            if (e != hipSuccess) { dfree(F); HIPCHK(e); }
-        }
+        // the slabs are independent: the first half runs on the handle's stream, the second
+        // on a second one, so that one half's latency-bound diagonal inverses overlap the
+        // other half's update GEMMs (both streams at the default priority)
+        if (!H->st2) HIPCHK(hipStreamCreateWithFlags(&H->st2, hipStreamNonBlocking));
+        hipEvent_t fork = nullptr, join = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } ev{fork, join};
+        const int half = (g.J + 1) / 2;
+        float2* F32 = static_cast<float2*>(F);
+        const size_t stride = (size_t)g.Ny * BB;
+        hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS, [&]() -> hipError_t {
+            hipError_t r = hipEventRecord(fork, H->st);
+            if (r == hipSuccess) r = hipStreamWaitEvent(H->st2, fork, 0);
+            for (int l = 0; l < g.Ny && r == hipSuccess; ++l) {
+                r = helm::launch_factor3_plane_f32(a, l, F32, stride, work32, H->d_err, H->st, 0, half);
+                if (r == hipSuccess && g.J > half)
+                    r = helm::launch_factor3_plane_f32(a, l, F32, stride, work32, H->d_err, H->st2, half,
+                                                       g.J - half);
+            }
+            if (r == hipSuccess) r = hipEventRecord(join, H->st2);
+            if (r == hipSuccess) r = hipStreamWaitEvent(H->st, join, 0);
+            return r;
+        }());
+        if (e != hipSuccess) { dfree(F); HIPCHK(e); }
         HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
         HIPCHK(hipStreamSynchronize(H->st));
         H->factor_path = herr ? 0 : 1;
@@ -1073,13 +1093,17 @@ helm_status factor3(helm_t H) {
         return st;
     }
     HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
-    for (int l = 0; l < g.Ny; ++l) {
-        void* out = static_cast<char*>(F) + (size_t)l * BB * esz;
-        hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS,
-                             helm::launch_factor3_plane(a, l, l > 0 ? G64 : nullptr, S, Tm, Cm, perm, pi,
-                                                        H->d_err, G64, out, single, (size_t)g.Ny * BB, H->st));
-        if (e != hipSuccess) { dfree(F); HIPCHK(e); }
-    }
+    // timed as one unit, like the complex64 route
+    hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS, [&]() -> hipError_t {
+        hipError_t r = hipSuccess;
+        for (int l = 0; l < g.Ny && r == hipSuccess; ++l) {
+            void* out = static_cast<char*>(F) + (size_t)l * BB * esz;
+            r = helm::launch_factor3_plane(a, l, l > 0 ? G64 : nullptr, S, Tm, Cm, perm, pi, H->d_err, G64, out,
+                                           single, (size_t)g.Ny * BB, H->st);
+        }
+        return r;
+    }());
+    if (e != hipSuccess) { dfree(F); HIPCHK(e); }
     herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
@@ -1481,6 +1505,7 @@ void helm_destroy(helm_t H) {
     else (void)hipDeviceSynchronize();
     if (H->ap_exec) (void)hipGraphExecDestroy(H->ap_exec);
     if (H->cap_st) (void)hipStreamDestroy(H->cap_st);
+    if (H->st2) (void)hipStreamDestroy(H->st2);
     free_work(H->wk);
     delete H->timer;
     if (H->F != H->F64) dfree(H->F);

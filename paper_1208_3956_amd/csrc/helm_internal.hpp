@@ -226,10 +226,11 @@ hipError_t launch_factor3_plane(const Fac3Args& a, int l, const double2* Gprev, 
                                 hipStream_t st);
 size_t factor3_panel_width();
 // complex64 slab factorisation (mixed precision): blocked Gauss-Jordan in place in the
-// stored factor F ([slab][plane][Bp*Bp], slab stride `stride`), one plane per call
+// stored factor F ([slab][plane][Bp*Bp], slab stride `stride`), one plane of the slabs
+// s0 .. s0 + ns - 1 per call (disjoint slab sets may run on different streams)
 size_t factor3_f32_work_bytes(int J, int Bp);
 hipError_t launch_factor3_plane_f32(const Fac3Args& a, int l, float2* F, size_t stride, void* work, int* err,
-                                    hipStream_t st);
+                                    hipStream_t st, int s0, int ns);
 template <typename T>
 hipError_t launch_strip_solve3(const Solve3Args<T>& a, hipStream_t st, KTimer* kt);
 

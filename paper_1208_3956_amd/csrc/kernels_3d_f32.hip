@@ -33,8 +33,9 @@ constexpr double COND_MAX = 1e6;   // largest accepted 1-norm condition of a dia
 
 // S_l = T_l - c_l b_{l-1} G_{l-1} into the plane-l slot of every slab (identity on the
 // padding); G_{l-1} is the previous plane's slot (already inverted).  T in FP64, rounded.
-__global__ void __launch_bounds__(256) k3f_build_S(Fac3Args a, int l, float2* __restrict__ F, size_t stride) {
-    const int s = blockIdx.y;
+__global__ void __launch_bounds__(256) k3f_build_S(Fac3Args a, int l, float2* __restrict__ F, size_t stride,
+                                                  int s0) {
+    const int s = s0 + blockIdx.y;
     const size_t BB = (size_t)a.Bp * a.Bp;
     const int W = a.sW[s], B = W * a.Nz;
     float2* S = F + s * stride + (size_t)l * BB;
@@ -81,10 +82,10 @@ __global__ void __launch_bounds__(256) k3f_build_S(Fac3Args a, int l, float2* __
 // complex64.  err bit 1: zero or non-finite pivot; bit 2: 1-norm condition above COND_MAX.
 __global__ void __launch_bounds__(256) k3f_diag_inv(const float2* __restrict__ F, size_t stride, int l, int Bp,
                                                    int k0, double2* __restrict__ Pd, float2* __restrict__ Pf,
-                                                   int* __restrict__ err) {
+                                                   int* __restrict__ err, int s0) {
     __shared__ GJShared sh;
     __shared__ double na[64], np[64];
-    const int s = blockIdx.x;
+    const int s = s0 + blockIdx.x;
     const float2* A = F + s * stride + (size_t)l * Bp * Bp;
     const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
     double2 M[16];
@@ -121,10 +122,10 @@ __global__ void __launch_bounds__(256) k3f_diag_inv(const float2* __restrict__ F
 // The 64 x 64 x 64 product runs on FMA with both operands in LDS.
 __global__ void __launch_bounds__(256) k3f_rc(const float2* __restrict__ F, size_t stride, int l, int Bp, int k0,
                                              const float2* __restrict__ Pf, float2* __restrict__ Cb,
-                                             float2* __restrict__ Rb) {
+                                             float2* __restrict__ Rb, int s0) {
     __shared__ float2 Ps[64][65];      // Ps[m][k] = P(k, m)
     __shared__ float2 As[64][65];      // As[j][m] = A(k0 + m, J0 + j)
-    const int s = blockIdx.y, J0 = blockIdx.x * NBF, t = threadIdx.x;
+    const int s = s0 + blockIdx.y, J0 = blockIdx.x * NBF, t = threadIdx.x;
     const float2* A = F + s * stride + (size_t)l * Bp * Bp;
     float2* cb = Cb + (size_t)s * NBF * Bp;
     float2* rb = Rb + (size_t)s * NBF * Bp;
@@ -182,13 +183,13 @@ __global__ void __launch_bounds__(256) k3f_rc(const float2* __restrict__ F, size
 // C(l % 16, l / 16), B operand R(l / 16, l % 16), accumulator rows 4 (l / 16) + j, column
 // l % 16), one k-step ahead.
 __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t stride, int l, int Bp, int k0,
-                                                 int J, const float2* __restrict__ Cb,
-                                                 const float2* __restrict__ Rb) {
+                                                 int ns, const float2* __restrict__ Cb,
+                                                 const float2* __restrict__ Rb, int s0) {
     const int nb = Bp / NBF, nt = nb * nb;
-    const int total = J * nt, per = (total + 7) / 8;
+    const int total = ns * nt, per = (total + 7) / 8;
     const int gi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (gi >= total) return;
-    const int s = gi / nt, tt = gi % nt, it = tt % nb, jt = tt / nb;
+    const int s = s0 + gi / nt, tt = gi % nt, it = tt % nb, jt = tt / nb;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 15, q4 = lane >> 4;
     const int I0 = it * NBF + 32 * (w & 1), J0 = jt * NBF + 32 * (w >> 1);
     float2* A = F + s * stride + (size_t)l * Bp * Bp;
@@ -270,20 +271,20 @@ size_t factor3_f32_work_bytes(int J, int Bp) {
 }
 
 hipError_t launch_factor3_plane_f32(const Fac3Args& a, int l, float2* F, size_t stride, void* work, int* err,
-                                    hipStream_t st) {
+                                    hipStream_t st, int s0, int ns) {
     const size_t BB = (size_t)a.Bp * a.Bp;
     double2* Pd = static_cast<double2*>(work);
     float2* Pf = reinterpret_cast<float2*>(Pd + (size_t)a.J * BLK);
     float2* Cb = Pf + (size_t)a.J * BLK;
     float2* Rb = Cb + (size_t)a.J * NBF * a.Bp;
     const unsigned nbs = (unsigned)std::min<size_t>((BB + 255) / 256, 4096);
-    hipLaunchKernelGGL(k3f_build_S, dim3(nbs, a.J), dim3(256), 0, st, a, l, F, stride);
+    hipLaunchKernelGGL(k3f_build_S, dim3(nbs, ns), dim3(256), 0, st, a, l, F, stride, s0);
     const int nb = a.Bp / NBF;
-    const int total = a.J * nb * nb, per = (total + 7) / 8;
+    const int total = ns * nb * nb, per = (total + 7) / 8;
     for (int k0 = 0; k0 < a.Bp; k0 += NBF) {
-        hipLaunchKernelGGL(k3f_diag_inv, dim3(a.J), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pd, Pf, err);
-        hipLaunchKernelGGL(k3f_rc, dim3(nb, a.J), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pf, Cb, Rb);
-        hipLaunchKernelGGL(k3f_update, dim3(8 * per), dim3(256), 0, st, F, stride, l, a.Bp, k0, a.J, Cb, Rb);
+        hipLaunchKernelGGL(k3f_diag_inv, dim3(ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pd, Pf, err, s0);
+        hipLaunchKernelGGL(k3f_rc, dim3(nb, ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pf, Cb, Rb, s0);
+        hipLaunchKernelGGL(k3f_update, dim3(8 * per), dim3(256), 0, st, F, stride, l, a.Bp, k0, ns, Cb, Rb, s0);
     }
     return hipGetLastError();
 }
