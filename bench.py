@@ -152,7 +152,7 @@ def cpu_baseline(wl, iters_mean, budget_s=10.0):
 
 
 KERNEL_SOURCES = ("paper_1208_3956_amd/csrc/kernels_solve.hip",
-                  "paper_1208_3956_amd/csrc/kernels_factor.hip",
+                  "paper_1208_3956_amd/csrc/kernels_vec.hip",
                   "paper_1208_3956_amd/csrc/helm_internal.hpp")
 
 
@@ -165,25 +165,26 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def profiled_traffic(cls, wl, nrhs, prec):
+def profiled_traffic(cls, wl, nrhs, prec, prefix=""):
     """HBM bytes per launch of kernel class `cls` from the committed counter summary of this
     workload, or None when there is none or the kernel sources changed since it was taken.
     The summary holds FETCH_SIZE and WRITE_SIZE per dispatch already scaled by the copy
-    calibration, and the sha256 of the kernel sources it was measured on."""
+    calibration, and the sha256 of the kernel sources it was measured on; `prefix` selects
+    another kernel's entries in the same summary (the stencil's: "stencil_")."""
     import re
     path = os.path.join(ROOT, "profiles", f"{cls}_hbm_traffic_{wl.name}_nrhs{nrhs}_{prec}.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
     want = {}
-    for key in ("source_sha256", "fetch_bytes_per_launch", "write_bytes_per_launch"):
+    for key in ("source_sha256", f"{prefix}fetch_bytes_per_launch", f"{prefix}write_bytes_per_launch"):
         m = re.search(rf"^{key}:\s*(\S+)\s*$", text, re.M)
         if not m:
             return None
         want[key] = m.group(1)
     if want["source_sha256"] != kernel_source_hash():
         return None
-    return float(want["fetch_bytes_per_launch"]) + float(want["write_bytes_per_launch"])
+    return float(want[f"{prefix}fetch_bytes_per_launch"]) + float(want[f"{prefix}write_bytes_per_launch"])
 
 
 def algorithmic_bytes(H, nrhs, prec):
@@ -447,7 +448,8 @@ def main():
         "kernel_ms_per_step_from": "one untimed step with every class timed",
         "roofline": roof,
         "factor_roofline": factor_roof,
-        "stencil_roofline": stencil_roofline(H, wl, f),
+        "stencil_roofline": dict(stencil_roofline(H, wl, f),
+                                 traffic=profiled_traffic("phase_a", wl, nrhs, args.prec, "stencil_")),
     }
     H.close()
     if args.prec == "mixed" and not args.no_c128_leg:
