@@ -22,7 +22,8 @@ EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm
            "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
            "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
-           "helm_solve_batch", "helm_get_dims3", "helm_autotune", "helm_get_factor_path"]
+           "helm_solve_batch", "helm_get_dims3", "helm_autotune", "helm_get_factor_path",
+           "helm_get_factor_slots"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -82,6 +83,7 @@ def lib() -> ctypes.CDLL:
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
     L.helm_autotune.argtypes = [vp, ci, vp, pint, ci, ci, pint, pdbl]
     L.helm_get_factor_path.argtypes = [vp, pint]
+    L.helm_get_factor_slots.argtypes = [vp, pint]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
     L.helm_get_dims3.argtypes = [vp, pint, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
@@ -220,6 +222,12 @@ def helm_get_chunks(hdl):
 def helm_get_factor_path(hdl) -> int:
     p = ctypes.c_int()
     check(lib().helm_get_factor_path(hdl, ctypes.byref(p)), hdl)
+    return p.value
+
+
+def helm_get_factor_slots(hdl) -> int:
+    p = ctypes.c_int()
+    check(lib().helm_get_factor_slots(hdl, ctypes.byref(p)), hdl)
     return p.value
 
 

@@ -105,6 +105,13 @@ struct helm_problem {
     double2* Fs64 = nullptr;    // FP64 propagators (idem)
     int fac_m = 0;              // rows per chunk the factor buffers were laid out for
     int factor_path = 0;        // 3-D: 1 = complex64 blocked Gauss-Jordan, 0 = FP64 inverses
+    // strips with identical operators share one factorisation: fidx[s] is the factor slot
+    // of strip s; the factor kernels run on the slots' representative strips (tf, gf: the
+    // per-strip tables and the geometry restricted to the representatives)
+    std::vector<int> fidx;
+    int nfac = 0;
+    helm::DevTables tf;
+    helm::Geom gf;
     bool factored = false;
     int* d_err = nullptr;
     Work wk;
@@ -304,7 +311,8 @@ helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
     const auto* Fc = static_cast<const helm::cplx<T>*>(H->Fc);
     const auto* Fs = static_cast<const helm::cplx<T>*>(H->Fs);
     auto* Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
-    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, F, Fc, Fs, Yw, nrhs, io, H->st, H->kt()));
+    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, H->fidx[s], F, Fc, Fs, Yw, nrhs, io, H->st,
+                                       H->kt()));
     return HELM_OK;
 }
 
@@ -978,6 +986,53 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         if (S.rpad)
             for (int k = 0; k < 3; ++k) tcol[(size_t)s * 8 + 3 + k] = g.beta[s + 1] - 2 + k - S.a;
     }
+    // strips whose operators coincide share one factorisation (2-D): the same width, PML
+    // tables and target columns, and the same k^2 on every row of corresponding columns
+    // (an x-invariant medium makes every interior strip of one width alike)
+    std::vector<int> urep;
+    H->fidx.assign(J, 0);
+    auto same_strip = [&](int a, int b) {
+        if (sW[a] != sW[b]) return false;
+        const int W = sW[a];
+        for (int q = 0; q < W; ++q) {
+            const double2 x = sax[(size_t)a * WP + q], y = sax[(size_t)b * WP + q];
+            if (x.x != y.x || x.y != y.y) return false;
+        }
+        for (int q = 0; q <= W; ++q) {
+            const double2 x = saxh[(size_t)a * (WP + 1) + q], y = saxh[(size_t)b * (WP + 1) + q];
+            if (x.x != y.x || x.y != y.y) return false;
+        }
+        for (int k = 0; k < 8; ++k)
+            if (tcol[(size_t)a * 8 + k] != tcol[(size_t)b * 8 + k]) return false;
+        for (int q = 0; q < W; ++q) {
+            const int ca = scol[(size_t)a * WP + q], cb = scol[(size_t)b * WP + q];
+            if (ca == cb) continue;
+            for (int l = 0; l < Ny; ++l)
+                if (k2[(size_t)l * Nx + ca] != k2[(size_t)l * Nx + cb]) return false;
+        }
+        return true;
+    };
+    for (int s = 0; s < J; ++s) {
+        int u = 0;
+        if (dim == 2)
+            while (u < (int)urep.size() && !same_strip(s, urep[u])) ++u;
+        else
+            u = (int)urep.size();
+        if (u == (int)urep.size()) urep.push_back(s);
+        H->fidx[s] = u;
+    }
+    H->nfac = (int)urep.size();
+    std::vector<double2> fsax((size_t)H->nfac * WP), fsaxh((size_t)H->nfac * (WP + 1));
+    std::vector<int> fscol((size_t)H->nfac * WP), fsW(H->nfac), ftcol((size_t)H->nfac * 8);
+    for (int u = 0; u < H->nfac; ++u) {
+        const int r = urep[u];
+        fsW[u] = sW[r];
+        std::copy(sax.begin() + (size_t)r * WP, sax.begin() + (size_t)(r + 1) * WP, fsax.begin() + (size_t)u * WP);
+        std::copy(saxh.begin() + (size_t)r * (WP + 1), saxh.begin() + (size_t)(r + 1) * (WP + 1),
+                  fsaxh.begin() + (size_t)u * (WP + 1));
+        std::copy(scol.begin() + (size_t)r * WP, scol.begin() + (size_t)(r + 1) * WP, fscol.begin() + (size_t)u * WP);
+        std::copy(tcol.begin() + (size_t)r * 8, tcol.begin() + (size_t)(r + 1) * 8, ftcol.begin() + (size_t)u * 8);
+    }
     auto& t = H->t;
     helm_status st = HELM_OK;
     struct Guard {
@@ -998,6 +1053,16 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if ((st = upload(H, (void**)&t.rcols, rcols.data(), rcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.redcols, redcols.data(), redcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.tcol, tcol.data(), tcol.size() * sizeof(int))) != HELM_OK) return st;
+    H->tf = t;
+    if ((st = upload(H, (void**)&H->tf.sax, fsax.data(), fsax.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&H->tf.saxh, fsaxh.data(), fsaxh.size() * sizeof(double2))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&H->tf.scol, fscol.data(), fscol.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&H->tf.sW, fsW.data(), fsW.size() * sizeof(int))) != HELM_OK) return st;
+    if ((st = upload(H, (void**)&H->tf.tcol, ftcol.data(), ftcol.size() * sizeof(int))) != HELM_OK) return st;
+    H->gf = g;
+    H->gf.J = H->nfac;
+    H->gf.strips.clear();
+    for (int u = 0; u < H->nfac; ++u) H->gf.strips.push_back(g.strips[urep[u]]);
     if ((st = upload(H, (void**)&t.bw, bw.data(), bw.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.k2w, k2w.data(), k2w.size() * sizeof(double))) != HELM_OK) return st;
     if (dim == 3) {
@@ -1134,9 +1199,9 @@ helm_status helm_factor(helm_t H) {
     // cleared: slots no factorisation writes must read as zero) once, and every later
     // factorisation overwrites the same slots.  The complex64 path keeps the FP64 factor as
     // workspace and receives each block rounded as it is stored.
-    const size_t nel = (size_t)g.J * g.Ny * NSLOT * BLK;
-    const size_t nsel = H->ch.G >= 2 ? (size_t)g.J * (H->ch.P - 1) * 2 * BLK : 0;
-    const size_t ncomp = (size_t)g.J * g.Ny * 2 * 8 * WP;
+    const size_t nel = (size_t)H->nfac * g.Ny * NSLOT * BLK;
+    const size_t nsel = H->ch.G >= 2 ? (size_t)H->nfac * (H->ch.P - 1) * 2 * BLK : 0;
+    const size_t ncomp = (size_t)H->nfac * g.Ny * 2 * 8 * WP;
     const bool single = H->prec != HELM_C128;
     const size_t esz = single ? sizeof(float2) : sizeof(double2);
     if (!H->F64) {
@@ -1164,18 +1229,20 @@ helm_status helm_factor(helm_t H) {
     double2* F64 = H->F64;
     float2* F32 = single ? static_cast<float2*>(H->F) : nullptr;
     HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
-    HIPCHK(TIMED(H, helm::K_FACTOR_CHUNKS, helm::launch_factor_chunks(H->t, g, H->ch, F64, F32, H->d_err, H->st)));
-    HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_separators(H->t, g, H->ch, F64, F32, H->d_err, H->st)));
+    // one factorisation per distinct strip operator (factor slots 0 .. nfac - 1)
+    const auto& gf = H->gf;
+    HIPCHK(TIMED(H, helm::K_FACTOR_CHUNKS, helm::launch_factor_chunks(H->tf, gf, H->ch, F64, F32, H->d_err, H->st)));
+    HIPCHK(TIMED(H, helm::K_FACTOR_SEPS, helm::launch_factor_separators(H->tf, gf, H->ch, F64, F32, H->d_err, H->st)));
     if (nsel)
         HIPCHK(TIMED(H, helm::K_FACTOR_SEPS,
-                     helm::launch_factor_propagators(H->t, g, H->ch, F64, H->Fs64,
+                     helm::launch_factor_propagators(H->tf, gf, H->ch, F64, H->Fs64,
                                                      single ? static_cast<float2*>(H->Fs) : nullptr, H->st)));
     if (single)
         HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<float2>(F32, static_cast<float2*>(H->Fc),
-                                                                           H->t.tcol, g, H->ch, H->st)));
+                                                                           H->tf.tcol, gf, H->ch, H->st)));
     else
         HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<double2>(F64, static_cast<double2*>(H->Fc),
-                                                                            H->t.tcol, g, H->ch, H->st)));
+                                                                            H->tf.tcol, gf, H->ch, H->st)));
     int herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
@@ -1459,6 +1526,13 @@ helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* sol
     if (ap_applies) *ap_applies = H->stat_ap;
     if (restarts) *restarts = H->stat_restarts;
     if (solve_ms) *solve_ms = H->stat_ms;
+    return HELM_OK;
+}
+
+helm_status helm_get_factor_slots(helm_t H, int* slots) {
+    if (!H || !slots) return HELM_EINVAL;
+    if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
+    *slots = H->nfac;
     return HELM_OK;
 }
 

@@ -178,7 +178,8 @@ hipError_t launch_extract_targets(const V* F, V* Fc, const int* tcol, const Geom
                                   const Chunks& ch, hipStream_t st);
 
 template <typename T>
-hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
+// strip s with its factors in slot fs of F, Fc, Fs (identical strips share a slot)
+hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
                               const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
                               int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt = nullptr);
 

@@ -1101,15 +1101,15 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
 }  // namespace
 
 template <typename T>
-hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s,
+hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
                               const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
                               int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt) {
     SolveArgs<T> a;
-    a.F = F + (size_t)s * g.Ny * NSLOT * BLK;
-    a.Fs = Fs ? Fs + (size_t)s * (ch.P - 1) * 2 * BLK : nullptr;
+    a.F = F + (size_t)fs * g.Ny * NSLOT * BLK;
+    a.Fs = Fs ? Fs + (size_t)fs * (ch.P - 1) * 2 * BLK : nullptr;
     a.q = ch.q;
     a.G = ch.G;
-    a.Fc = Fc ? Fc + (size_t)s * g.Ny * 2 * 8 * WP : nullptr;
+    a.Fc = Fc ? Fc + (size_t)fs * g.Ny * 2 * 8 * WP : nullptr;
     a.tcol = t.tcol + s * 8;
     a.Yw = Yw;
     a.cy = t.cy;
@@ -1131,10 +1131,10 @@ hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& c
     return run<T, 16>(a, targets, st, kt);
 }
 
-template hipError_t launch_strip_solve<float>(const DevTables&, const Geom&, const Chunks&, int,
+template hipError_t launch_strip_solve<float>(const DevTables&, const Geom&, const Chunks&, int, int,
                                               const float2*, const float2*, const float2*, float2*, int,
                                               const IOSpec&, hipStream_t, KTimer*);
-template hipError_t launch_strip_solve<double>(const DevTables&, const Geom&, const Chunks&, int,
+template hipError_t launch_strip_solve<double>(const DevTables&, const Geom&, const Chunks&, int, int,
                                                const double2*, const double2*, const double2*, double2*,
                                                int, const IOSpec&, hipStream_t, KTimer*);
 

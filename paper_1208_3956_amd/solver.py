@@ -154,6 +154,11 @@ class Helmholtz:
         return {"chunk_rows": best, "ms_per_apply": times, "cached": hit is not None}
 
     @property
+    def factor_slots(self) -> int:
+        """Number of stored factorisations (identical 2-D strips share one)."""
+        return L.helm_get_factor_slots(self.h)
+
+    @property
     def factor_path(self) -> int:
         """3-D: 1 when the slab inverses came from the complex64 blocked Gauss-Jordan, 0
         when from the FP64 one (always 0 in 2-D)."""

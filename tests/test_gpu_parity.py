@@ -218,3 +218,36 @@ def test_shape_checks_before_launch(case):
     with pytest.raises(TypeError):
         H.apply_P(torch.zeros((1, g.N_y, g.N_x), dtype=torch.complex64, device=DEV))
     H.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_identical_strips_share_factors(prec):
+    """An x-invariant (layered) medium makes every interior strip of one width alike: those
+    share one factorisation; every strip's solve and the preconditioner still match the
+    oracle, which factors each strip on its own.  A medium that varies with x keeps one
+    factorisation per strip."""
+    n, J = 60, 6
+    cy = 1.0 + 0.5 * np.random.default_rng(3).random(n)
+    wl = _wl(n=n, J=J, c=np.repeat(cy[:, None], n, 1))
+    g = geometry_from_workload(wl)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    H = _gpu(wl, prec=prec, chunk=7)
+    widths = [st.W for st in g.strips]
+    # first and last strips see the outer PML; the interior ones differ only by width
+    assert H.factor_slots == 2 + len(set(widths[1:-1])) < J
+    tol = TOL_STRIP_C128 if prec == "c128" else TOL_P_C64
+    rng = np.random.default_rng(12)
+    for s, st in enumerate(g.strips):
+        r = _rand(rng, (2, g.N_y, st.W))
+        x = H.strip_solve(s, _t(r)).cpu().numpy()
+        ref = np.stack([S.solve(s, rk) for rk in r])
+        assert _rel(x, ref) < tol, (s, _rel(x, ref))
+    f = _rand(rng, (2, g.N_y, g.N_x))
+    pf = H.apply_P(_t(f)).cpu().numpy()
+    ref = np.stack([apply_P(g, S, A, fk) for fk in f])
+    assert _rel(pf, ref) < (TOL_P_C128 if prec == "c128" else TOL_P_C64)
+    H.close()
+    H = _gpu(_wl(n=n, J=J), prec=prec, chunk=7)
+    assert H.factor_slots == J
+    H.close()
