@@ -438,6 +438,7 @@ def main():
                    "pml_outer": wl.w_out, "pml_iface": wl.w, "prec": args.prec,
                    "mode": args.mode, "chunk_rows": H.chunk_rows, "tol": args.tol,
                    "autotune": tuned, "factor_path": H.factor_path if wl.dim == 3 else None,
+                   "factor_slots": H.factor_slots,
                    "step": "helm_factor + helm_solve"},
         "solve_only_value": pts / (solve_ms / 1e3), "solve_ms": solve_ms,
         "factor_ms": t_fac * 1e3 / args.steps,
