@@ -82,7 +82,9 @@ def phase_flops(H, wl, nrhs):
     P = -(-Ny // m)
     n_int = Ny - (P - 1)                    # interior rows over all chunks
     W2 = sum(w * w for w in H.strip_width) / len(H.strip_width)
-    W3 = sum(w ** 3 for w in H.strip_width)
+    # identical strips share one factorisation: the factor work covers one strip per slot
+    slot = H.strip_factor_slot
+    W3 = sum(H.strip_width[slot.index(u)] ** 3 for u in range(max(slot) + 1))
     fl = {
         # forward + backward block substitution: one W x W matvec per interior row each way
         "phase_a": 8.0 * W2 * nrhs * (2 * n_int - P),
@@ -91,7 +93,7 @@ def phase_flops(H, wl, nrhs):
         # spike corrections X~ x_above + Y~ x_below on every interior row that has them
         "phase_c": 8.0 * W2 * nrhs * (2 * n_int - (m - 1) - (Ny - (P - 1) * m)) if P > 1 else 0.0,
         # inverse (Gauss-Jordan, W^3) + top spike (2 W^3) + bottom spike (W^3) per interior row
-        "factor_chunks": 8.0 * (W3 / len(H.strip_width)) * len(H.strip_width) * n_int * 4.0,
+        "factor_chunks": 8.0 * W3 * n_int * 4.0,
         "factor_separators": 8.0 * W3 * (P - 1) * 3.0,
     }
     return fl

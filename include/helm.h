@@ -237,13 +237,15 @@ helm_status helm_get_dims3(helm_t H, int* N_x, int* N_y, int* N_z, int* J);
 helm_status helm_get_dims(helm_t H, int* N_x, int* N_y, int* J);
 helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip_width);
 
-/* Number of factorisations the handle stores (host int).  2-D strips whose operators
+/* Number of factorisations the handle stores (host int) and, if strip_slot is not NULL,
+ * the slot each of the J strips uses (host, J ints, slots numbered by first use).  2-D
+ * strips whose operators
  * coincide (the same width, PML tables and reduced-form target columns, and the same k^2
  * on every row of corresponding columns: e.g. the interior strips of one width in a medium
  * that does not vary with x; the paper notes that a constant medium needs one
  * factorisation, Sec. 4.3) share one; 3-D slabs are factored one by one (J).
  * HELM_ESTATE if helm_setup did not complete. */
-helm_status helm_get_factor_slots(helm_t H, int* slots);
+helm_status helm_get_factor_slots(helm_t H, int* slots, int* strip_slot);
 
 /* Which factorisation produced the stored 3-D slab inverses (host int):
  *   1  complex64 blocked Gauss-Jordan with pivoting inside the 64 x 64 diagonal blocks

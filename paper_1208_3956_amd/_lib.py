@@ -83,7 +83,7 @@ def lib() -> ctypes.CDLL:
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
     L.helm_autotune.argtypes = [vp, ci, vp, pint, ci, ci, pint, pdbl]
     L.helm_get_factor_path.argtypes = [vp, pint]
-    L.helm_get_factor_slots.argtypes = [vp, pint]
+    L.helm_get_factor_slots.argtypes = [vp, pint, pint]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
     L.helm_get_dims3.argtypes = [vp, pint, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
@@ -225,10 +225,12 @@ def helm_get_factor_path(hdl) -> int:
     return p.value
 
 
-def helm_get_factor_slots(hdl) -> int:
+def helm_get_factor_slots(hdl, J: int):
+    """Returns (number of stored factorisations, the slot of each strip)."""
     p = ctypes.c_int()
-    check(lib().helm_get_factor_slots(hdl, ctypes.byref(p)), hdl)
-    return p.value
+    sl = (ctypes.c_int * J)()
+    check(lib().helm_get_factor_slots(hdl, ctypes.byref(p), sl), hdl)
+    return p.value, list(sl)
 
 
 def helm_get_stats(hdl):

@@ -1529,10 +1529,12 @@ helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* sol
     return HELM_OK;
 }
 
-helm_status helm_get_factor_slots(helm_t H, int* slots) {
+helm_status helm_get_factor_slots(helm_t H, int* slots, int* strip_slot) {
     if (!H || !slots) return HELM_EINVAL;
     if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
     *slots = H->nfac;
+    if (strip_slot)
+        for (int s = 0; s < H->g.J; ++s) strip_slot[s] = H->fidx[s];
     return HELM_OK;
 }
 

@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) k3f_diag_inv(const float2* __restrict__ F
                                                    int k0, double2* __restrict__ Pd, float2* __restrict__ Pf,
                                                    int* __restrict__ err, int s0) {
     __shared__ GJShared sh;
-    __shared__ double na[64], np[64];
+    __shared__ double na[4][64], np[4][64];
     const int s = s0 + blockIdx.x;
     const float2* A = F + s * stride + (size_t)l * Bp * Bp;
     const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -96,34 +96,43 @@ __global__ void __launch_bounds__(256) k3f_diag_inv(const float2* __restrict__ F
     }
     double2* pd = Pd + (size_t)s * BLK;
     gj_invert_store(M, WP, sh, pd, Pf + (size_t)s * BLK, err);
-    if (threadIdx.x < 64) {
-        const int t = threadIdx.x;
+    {
+        // column sums of |A_KK| and |P|: thread (column c, quarter h) sums 16 rows
+        const int c = threadIdx.x & 63, h = threadIdx.x >> 6;
         double sa = 0.0, sp = 0.0;
-        for (int r = 0; r < 64; ++r) {
-            const float2 v = A[(size_t)(k0 + t) * Bp + k0 + r];
+#pragma unroll 4
+        for (int r = 16 * h; r < 16 * h + 16; ++r) {
+            const float2 v = A[(size_t)(k0 + c) * Bp + k0 + r];
             sa += sqrt((double)v.x * v.x + (double)v.y * v.y);
-            const double2 p = pd[(size_t)t * WP + r];
+            const double2 p = pd[(size_t)c * WP + r];
             sp += sqrt(p.x * p.x + p.y * p.y);
         }
-        na[t] = sa;
-        np[t] = sp;
+        na[h][c] = sa;
+        np[h][c] = sp;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double ma = 0.0, mp = 0.0;
-        for (int t = 0; t < 64; ++t) { ma = fmax(ma, na[t]); mp = fmax(mp, np[t]); }
-        if (!(ma * mp <= COND_MAX)) atomicOr(err, 2);
+    if (threadIdx.x < 64) {
+        // the maxima over the columns by one wave
+        const int c = threadIdx.x;
+        double ma = na[0][c] + na[1][c] + na[2][c] + na[3][c];
+        double mp = np[0][c] + np[1][c] + np[2][c] + np[3][c];
+        for (int off = 32; off > 0; off >>= 1) {
+            ma = fmax(ma, __shfl_xor(ma, off));
+            mp = fmax(mp, __shfl_xor(mp, off));
+        }
+        if (c == 0 && !(ma * mp <= COND_MAX)) atomicOr(err, 2);
     }
 }
 
 // The operands of the update for column block k0 (grid: column tiles x slabs):
 //   C(i, k) = A(i, k0 + k) - [i = k0 + k]     rows of tile jt,  stored Cb[s][k][Bp]
 //   R(k, j) = sum_m P(k, m) A(k0 + m, j)      columns of tile jt, R(:, K) = P, Rb[s][k][Bp]
-// The 64 x 64 x 64 product runs on FMA with both operands in LDS.
+// The 64 x 64 x 64 product runs on v_mfma_f32_16x16x4f32: wave w computes rows
+// 16w .. 16w + 15 of R for the tile's 64 columns, P read in lane layout from global
+// memory, the A block from LDS (staged column by column, coalesced).
 __global__ void __launch_bounds__(256) k3f_rc(const float2* __restrict__ F, size_t stride, int l, int Bp, int k0,
                                              const float2* __restrict__ Pf, float2* __restrict__ Cb,
                                              float2* __restrict__ Rb, int s0) {
-    __shared__ float2 Ps[64][65];      // Ps[m][k] = P(k, m)
     __shared__ float2 As[64][65];      // As[j][m] = A(k0 + m, J0 + j)
     const int s = s0 + blockIdx.y, J0 = blockIdx.x * NBF, t = threadIdx.x;
     const float2* A = F + s * stride + (size_t)l * Bp * Bp;
@@ -145,34 +154,32 @@ __global__ void __launch_bounds__(256) k3f_rc(const float2* __restrict__ F, size
         return;
     }
     for (int e = t; e < NBF * NBF; e += 256) {
-        const int m = e / NBF, kk = e % NBF;
-        Ps[m][kk] = P[(size_t)m * WP + kk];
         const int jj = e / NBF, mm = e % NBF;
         As[jj][mm] = A[(size_t)(J0 + jj) * Bp + k0 + mm];
     }
     __syncthreads();
-    // thread: rows k = (t & 15) + 16 a, columns j = (t >> 4) + 16 b, a, b = 0..3
-    const int tk = t & 15, tj = t >> 4;
-    float2 acc[4][4];
+    const int lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
+    mf4 re[4], im[4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int jb = 0; jb < 4; ++jb) { re[jb] = mf4{0.f, 0.f, 0.f, 0.f}; im[jb] = re[jb]; }
+    const float2* pp = P + (size_t)q4 * WP + 16 * w + n;     // P(16w + n, 4 ks + q4)
+#pragma unroll 4
+    for (int ks = 0; ks < NBF / 4; ++ks) {
+        const float2 a = pp[(size_t)4 * ks * WP];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = make_float2(0.f, 0.f);
-    for (int m = 0; m < NBF; ++m) {
-        float2 pv[4], av[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) pv[a] = Ps[m][tk + 16 * a];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) av[b] = As[tj + 16 * b][m];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) cfma(acc[a][b], pv[a], av[b]);
+        for (int jb = 0; jb < 4; ++jb) {
+            const float2 b = As[16 * jb + n][4 * ks + q4];
+            re[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, re[jb], 0, 0, 0);
+            im[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, im[jb], 0, 0, 0);
+            re[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, re[jb], 0, 0, 0);
+            im[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, im[jb], 0, 0, 0);
+        }
     }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) rb[(size_t)(tk + 16 * a) * Bp + J0 + tj + 16 * b] = acc[a][b];
+        for (int j = 0; j < 4; ++j)
+            rb[(size_t)(16 * w + 4 * q4 + j) * Bp + J0 + 16 * jb + n] = make_float2(re[jb][j], im[jb][j]);
 }
 
 // A := A_mod - C R on every 64 x 64 tile of every slab.  The tiles are spread over the

@@ -156,7 +156,12 @@ class Helmholtz:
     @property
     def factor_slots(self) -> int:
         """Number of stored factorisations (identical 2-D strips share one)."""
-        return L.helm_get_factor_slots(self.h)
+        return L.helm_get_factor_slots(self.h, self.J)[0]
+
+    @property
+    def strip_factor_slot(self) -> list:
+        """The factorisation slot of every strip."""
+        return L.helm_get_factor_slots(self.h, self.J)[1]
 
     @property
     def factor_path(self) -> int:

@@ -236,6 +236,9 @@ def test_identical_strips_share_factors(prec):
     widths = [st.W for st in g.strips]
     # first and last strips see the outer PML; the interior ones differ only by width
     assert H.factor_slots == 2 + len(set(widths[1:-1])) < J
+    slot = H.strip_factor_slot
+    assert slot[0] == 0 and all((slot[a] == slot[b]) == (widths[a] == widths[b])
+                                for a in range(1, J - 1) for b in range(1, J - 1))
     tol = TOL_STRIP_C128 if prec == "c128" else TOL_P_C64
     rng = np.random.default_rng(12)
     for s, st in enumerate(g.strips):
