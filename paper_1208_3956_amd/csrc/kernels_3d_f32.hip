@@ -12,7 +12,8 @@
 // holds S^{-1} with no permutation to undo.  The rows of block K are written as R
 // directly rather than through the product (in FP32 that form would cancel to an error of
 // order eps cond(A_KK)).  The update is a rank-64 complex GEMM on
-// v_mfma_f32_16x16x4f32 (four real products per complex one), accumulated in FP32.
+// v_mfma_f32_16x16x4f32 with three real products per complex one (Gauss's form),
+// accumulated in FP32.
 // Without a search over the whole column the elimination relies on well-conditioned
 // diagonal blocks: every inverted block's 1-norm condition number is checked, and the
 // factorisation reports it (err bit 2) so that the caller can redo the slab factor with
@@ -221,7 +222,9 @@ __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t
             }
         return;
     }
-    mf4 re[2][2], im[2][2];
+    // complex products by three real ones (x1 = -sum Cr Rr, x2 = sum Ci Ri,
+    // x3 = -sum (Cr + Ci)(Rr + Ri)):  Re = A.r + x1 + x2,  Im = A.i + x3 - x1 + x2
+    float2 av[2][2][4];
 #pragma unroll
     for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
@@ -230,12 +233,17 @@ __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int row = I0 + 16 * ia + 4 * q4 + j;
-                float2 v;
-                if (kcol) v = make_float2(row == col ? 1.f : 0.f, 0.f);
-                else v = A[(size_t)col * Bp + row];
-                re[ia][jb][j] = v.x;
-                im[ia][jb][j] = v.y;
+                av[ia][jb][j] = kcol ? make_float2(row == col ? 1.f : 0.f, 0.f) : A[(size_t)col * Bp + row];
             }
+        }
+    mf4 x1[2][2], x2[2][2], x3[2][2];
+#pragma unroll
+    for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+        for (int jb = 0; jb < 2; ++jb) {
+            x1[ia][jb] = mf4{0.f, 0.f, 0.f, 0.f};
+            x2[ia][jb] = x1[ia][jb];
+            x3[ia][jb] = x1[ia][jb];
         }
     float2 c[2], r[2], cn[2], rn[2];
 #pragma unroll
@@ -244,15 +252,16 @@ __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t
         const size_t nx = (size_t)(kb + 1 < NBF / 4 ? kb + 1 : kb) * 4 * Bp;
 #pragma unroll
         for (int u = 0; u < 2; ++u) { cn[u] = cp[nx + 16 * u]; rn[u] = rp[nx + 16 * u]; }
+        float cs[2], rs[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) { cs[u] = c[u].x + c[u].y; rs[u] = r[u].x + r[u].y; }
 #pragma unroll
         for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
             for (int jb = 0; jb < 2; ++jb) {
-                // out = A_mod - C R:  re += (-Cr) Rr + Ci Ri,  im += (-Cr) Ri + (-Ci) Rr
-                re[ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-c[ia].x, r[jb].x, re[ia][jb], 0, 0, 0);
-                im[ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-c[ia].x, r[jb].y, im[ia][jb], 0, 0, 0);
-                re[ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(c[ia].y, r[jb].y, re[ia][jb], 0, 0, 0);
-                im[ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-c[ia].y, r[jb].x, im[ia][jb], 0, 0, 0);
+                x1[ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-c[ia].x, r[jb].x, x1[ia][jb], 0, 0, 0);
+                x2[ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(c[ia].y, r[jb].y, x2[ia][jb], 0, 0, 0);
+                x3[ia][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-cs[ia], rs[jb], x3[ia][jb], 0, 0, 0);
             }
 #pragma unroll
         for (int u = 0; u < 2; ++u) { c[u] = cn[u]; r[u] = rn[u]; }
@@ -265,7 +274,9 @@ __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int row = I0 + 16 * ia + 4 * q4 + j;
-                A[(size_t)col * Bp + row] = make_float2(re[ia][jb][j], im[ia][jb][j]);
+                const float2 a0 = av[ia][jb][j];
+                const float p1 = x1[ia][jb][j], p2 = x2[ia][jb][j], p3 = x3[ia][jb][j];
+                A[(size_t)col * Bp + row] = make_float2(a0.x + p1 + p2, a0.y + p3 - p1 + p2);
             }
         }
 }
