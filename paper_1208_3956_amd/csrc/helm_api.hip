@@ -91,6 +91,14 @@ struct EventTimer : helm::KTimer {
     ~EventTimer() override { for (hipEvent_t e : pool) (void)hipEventDestroy(e); }
 };
 
+// slab groups (one stream each) of the 3-D complex64 factorisation
+#ifndef FAC3_GROUPS
+#define FAC3_GROUPS 2
+#endif
+#ifndef FAC3_BATCH
+#define FAC3_BATCH 0      // slabs per group; 0: the slabs split evenly over the streams
+#endif
+
 struct helm_problem {
     helm::Geom g;
     helm::Chunks ch;
@@ -123,7 +131,7 @@ struct helm_problem {
     int dev = 0;                // HIP device of the handle
     int use_graph = 1;          // replay Algorithm 3 from a captured HIP graph (REDUCED)
     hipGraphExec_t ap_exec = nullptr;
-    hipStream_t st2 = nullptr;     // second stream of the 3-D complex64 factorisation
+    hipStream_t st_fac[FAC3_GROUPS - 1] = {};   // group streams of the 3-D complex64 factorisation
     hipStream_t cap_st = nullptr;  // private stream the graph is captured on (capture is not
                                    // allowed on the legacy default stream); replays go to st
     int ap_nrhs = 0;
@@ -1110,28 +1118,49 @@ helm_status factor3(helm_t H) {
         // Gauss-Jordan with partial pivoting over the whole column below
         if ((st = alloc(&work32, helm::factor3_f32_work_bytes(g.J, g.Bp))) != HELM_OK) { dfree(F); return st; }
         HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
-        // the slabs are independent: the first half runs on the handle's stream, the second
-        // on a second one, so that one half's latency-bound diagonal inverses overlap the
-        // other half's update GEMMs (both streams at the default priority)
-        if (!H->st2) HIPCHK(hipStreamCreateWithFlags(&H->st2, hipStreamNonBlocking));
-        hipEvent_t fork = nullptr, join = nullptr;
-        HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-        struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } ev{fork, join};
-        const int half = (g.J + 1) / 2;
+        // the slabs are independent.  FAC3_GROUPS streams (the handle's and streams of their
+        // own, default priority) each factor one group of slabs at a time, all planes of a
+        // group before the next, so that one stream's latency-bound diagonal inverses
+        // overlap the other streams' update GEMMs.  Measured at 80^3 (16 slabs, 2 streams):
+        // groups of 8 slabs 1130 ms, of 4 1226 ms, of 2 1590 ms (smaller groups keep the
+        // updated matrices in the last-level cache but launch too few tiles), one stream
+        // 1425 ms; 4 or 8 streams with one group each changed nothing
+        constexpr int NGR = FAC3_GROUPS;
+        const int batch = FAC3_BATCH > 0 ? std::min(FAC3_BATCH, g.J) : (g.J + NGR - 1) / NGR;
+        const int ngroups = (g.J + batch - 1) / batch;
+        const int nst = std::min(NGR, ngroups);
+        hipStream_t sts[NGR];
+        sts[0] = H->st;
+        for (int q = 1; q < nst; ++q) {
+            if (!H->st_fac[q - 1]) HIPCHK(hipStreamCreateWithFlags(&H->st_fac[q - 1], hipStreamNonBlocking));
+            sts[q] = H->st_fac[q - 1];
+        }
+        hipEvent_t evs[NGR] = {};
+        struct Evs {
+            hipEvent_t* e; int n;
+            ~Evs() { for (int q = 0; q < n; ++q) if (e[q]) (void)hipEventDestroy(e[q]); }
+        } evguard{evs, NGR};
+        for (int q = 0; q < nst; ++q) HIPCHK(hipEventCreateWithFlags(&evs[q], hipEventDisableTiming));
         float2* F32 = static_cast<float2*>(F);
         const size_t stride = (size_t)g.Ny * BB;
         hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS, [&]() -> hipError_t {
-            hipError_t r = hipEventRecord(fork, H->st);
-            if (r == hipSuccess) r = hipStreamWaitEvent(H->st2, fork, 0);
-            for (int l = 0; l < g.Ny && r == hipSuccess; ++l) {
-                r = helm::launch_factor3_plane_f32(a, l, F32, stride, work32, H->d_err, H->st, 0, half);
-                if (r == hipSuccess && g.J > half)
-                    r = helm::launch_factor3_plane_f32(a, l, F32, stride, work32, H->d_err, H->st2, half,
-                                                       g.J - half);
+            // fork: every group stream waits for the work queued so far on the handle's
+            hipError_t r = hipEventRecord(evs[0], H->st);
+            for (int q = 1; q < nst && r == hipSuccess; ++q) r = hipStreamWaitEvent(sts[q], evs[0], 0);
+            for (int g0 = 0; g0 < ngroups && r == hipSuccess; g0 += nst)
+                for (int l = 0; l < g.Ny && r == hipSuccess; ++l)
+                    for (int q = 0; q < nst && r == hipSuccess; ++q) {
+                        const int gi = g0 + q;
+                        if (gi >= ngroups) continue;
+                        const int s0 = gi * batch;
+                        const int ns = std::min(batch, g.J - s0);
+                        r = helm::launch_factor3_plane_f32(a, l, F32, stride, work32, H->d_err, sts[q], s0, ns);
+                    }
+            // join
+            for (int q = 1; q < nst && r == hipSuccess; ++q) {
+                r = hipEventRecord(evs[q], sts[q]);
+                if (r == hipSuccess) r = hipStreamWaitEvent(H->st, evs[q], 0);
             }
-            if (r == hipSuccess) r = hipEventRecord(join, H->st2);
-            if (r == hipSuccess) r = hipStreamWaitEvent(H->st, join, 0);
             return r;
         }());
         if (e != hipSuccess) { dfree(F); HIPCHK(e); }
@@ -1581,7 +1610,8 @@ void helm_destroy(helm_t H) {
     else (void)hipDeviceSynchronize();
     if (H->ap_exec) (void)hipGraphExecDestroy(H->ap_exec);
     if (H->cap_st) (void)hipStreamDestroy(H->cap_st);
-    if (H->st2) (void)hipStreamDestroy(H->st2);
+    for (hipStream_t q : H->st_fac)
+        if (q) (void)hipStreamDestroy(q);
     free_work(H->wk);
     delete H->timer;
     if (H->F != H->F64) dfree(H->F);
