@@ -1,6 +1,6 @@
-// Gauss-Jordan inversion of a 64 x 64 complex block held in registers (FP64), shared by
-// the strip factorisation (2-D) and the complex64 slab factorisation (3-D), where it
-// inverts the diagonal blocks.
+// Gauss-Jordan inversion of a 64 x 64 complex block held in registers (FP64) and a
+// 64 x 64 complex block product on FP64 MFMA, shared by the strip factorisation (2-D) and
+// the complex64 slab factorisation (3-D), where they invert the diagonal blocks.
 #pragma once
 #include "helm_internal.hpp"
 
@@ -110,6 +110,56 @@ __device__ inline void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, do
         dst[(size_t)pj * WP + my_step] = v;
         if (dst32) dst32[(size_t)pj * WP + my_step] = make_float2((float)v.x, (float)v.y);
     }
+    __syncthreads();
+}
+
+
+// C = alpha * A * B (+ D) on v_mfma_f64_16x16x4f64: full WP x WP, column-major with leading
+// dimensions, operands in LDS or global memory, C may alias A, B or D.  Wave w computes rows
+// 16 w .. 16 w + 15 in four 16-column tiles; a complex product is four real ones.  Lane
+// layout (one 16x16x4 block of doubles): A[l % 16][l / 16], B[l / 16][l % 16] and
+// C[l / 16 + 4 j][l % 16] in component j (rows interleaved by 4, unlike the FP32 block).
+typedef double md4 __attribute__((ext_vector_type(4)));
+
+__device__ __attribute__((always_inline)) inline void gemm64_mfma(double2* C, int ldc, const double2* A, int lda, const double2* B, int ldb,
+                            double2 alpha, const double2* D, int ldd) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 15, q4 = lane >> 4;
+    double2 av[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) av[s] = A[(16 * w + n) + (size_t)(4 * s + q4) * lda];
+    md4 cr[4], ci[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) { cr[tt] = md4{0.0, 0.0, 0.0, 0.0}; ci[tt] = cr[tt]; }
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        double2 bv[4];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) bv[tt] = B[(4 * s + q4) + (size_t)(16 * tt + n) * ldb];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            cr[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[tt].x, cr[tt], 0, 0, 0);
+            ci[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].x, bv[tt].y, ci[tt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            cr[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[s].y, bv[tt].y, cr[tt], 0, 0, 0);
+            ci[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s].y, bv[tt].x, ci[tt], 0, 0, 0);
+        }
+    }
+    double2 v[4][4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double2 x = cmul(alpha, cmk<double2>(cr[tt][j], ci[tt][j]));
+            if (D) x = cadd(x, D[(16 * w + q4 + 4 * j) + (size_t)(16 * tt + n) * ldd]);
+            v[tt][j] = x;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) C[(16 * w + q4 + 4 * j) + (size_t)(16 * tt + n) * ldc] = v[tt][j];
     __syncthreads();
 }
 

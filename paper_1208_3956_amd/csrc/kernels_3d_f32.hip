@@ -29,8 +29,12 @@ using namespace gjr;
 
 typedef float mf4 __attribute__((ext_vector_type(4)));
 
-constexpr int NBF = 64;            // block width
 constexpr double COND_MAX = 1e6;   // largest accepted 1-norm condition of a diagonal block
+// per-slab strides of the work arrays (the same for 64- and 128-wide blocks, so that slab
+// groups on different streams never share a region)
+constexpr size_t WSTR = 8 * (size_t)BLK;   // FP64 scratch blocks
+constexpr size_t PSTR = 128 * 128;         // P
+__host__ __device__ inline size_t cstr(int Bp) { return (size_t)128 * Bp; }   // C and R
 
 // S_l = T_l - c_l b_{l-1} G_{l-1} into the plane-l slot of every slab (identity on the
 // padding); G_{l-1} is the previous plane's slot (already inverted).  T in FP64, rounded.
@@ -95,8 +99,8 @@ __global__ void __launch_bounds__(256) k3f_diag_inv(const float2* __restrict__ F
         const float2 v = A[(size_t)(k0 + g + 4 * r) * Bp + k0 + i];
         M[r] = make_double2(v.x, v.y);
     }
-    double2* pd = Pd + (size_t)s * BLK;
-    gj_invert_store(M, WP, sh, pd, Pf + (size_t)s * BLK, err);
+    double2* pd = Pd + (size_t)s * WSTR;
+    gj_invert_store(M, WP, sh, pd, Pf + (size_t)s * PSTR, err);
     {
         // column sums of |A_KK| and |P|: thread (column c, quarter h) sums 16 rows
         const int c = threadIdx.x & 63, h = threadIdx.x >> 6;
@@ -125,62 +129,150 @@ __global__ void __launch_bounds__(256) k3f_diag_inv(const float2* __restrict__ F
     }
 }
 
-// The operands of the update for column block k0 (grid: column tiles x slabs):
+// P = A_KK^{-1} for a 128 x 128 diagonal block from its 64 x 64 blocks [A11 A12; A21 A22]:
+//     P11 = A11^{-1},  S = A22 - A21 P11 A12,  P22 = S^{-1},
+//     P12 = -P11 A12 P22,  P21 = -P22 A21 P11,  P11 <- P11 - P12 A21 P11
+// (pivoting inside the two 64 x 64 inverses), in FP64, one workgroup per slab, with eight
+// 64 x 64 scratch blocks per slab in global memory; P is stored complex64, column-major
+// (leading dimension 128).  err bits as in the 64-wide kernel.
+__global__ void __launch_bounds__(256) k3f_diag_inv128(const float2* __restrict__ F, size_t stride, int l, int Bp,
+                                                      int k0, double2* __restrict__ Wd, float2* __restrict__ Pf,
+                                                      int* __restrict__ err, int s0) {
+    __shared__ GJShared sh;
+    __shared__ double na[2][128], np[2][128];
+    const int s = s0 + blockIdx.x, t = threadIdx.x;
+    const float2* A = F + s * stride + (size_t)l * Bp * Bp;
+    double2* W = Wd + (size_t)s * WSTR;
+    double2 *A12 = W, *A21 = W + BLK, *A22 = W + 2 * BLK, *P11 = W + 3 * BLK;
+    double2 *T1 = W + 4 * BLK, *P22 = W + 5 * BLK, *T2 = W + 6 * BLK, *P12 = W + 7 * BLK;
+    auto at = [&](int r, int c) {
+        const float2 v = A[(size_t)(k0 + c) * Bp + k0 + r];
+        return make_double2(v.x, v.y);
+    };
+    for (int e = t; e < BLK; e += 256) {
+        const int r = e % WP, c = e / WP;
+        A12[e] = at(r, 64 + c);
+        A21[e] = at(64 + r, c);
+        A22[e] = at(64 + r, 64 + c);
+    }
+    const int i = t & 63, g = t >> 6;
+    const double2 one = make_double2(1.0, 0.0), mone = make_double2(-1.0, 0.0);
+    double2 M[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) M[r] = at(i, g + 4 * r);
+    gj_invert_store(M, WP, sh, P11, nullptr, err);                 // ends with a barrier
+    gemm64_mfma(T1, WP, P11, WP, A12, WP, one, nullptr, 0);        // T1 = P11 A12
+    gemm64_mfma(A22, WP, A21, WP, T1, WP, mone, A22, WP);          // S = A22 - A21 T1
+#pragma unroll
+    for (int r = 0; r < 16; ++r) M[r] = A22[(size_t)(g + 4 * r) * WP + i];
+    gj_invert_store(M, WP, sh, P22, nullptr, err);
+    gemm64_mfma(P12, WP, T1, WP, P22, WP, mone, nullptr, 0);       // P12 = -T1 P22
+    gemm64_mfma(T2, WP, A21, WP, P11, WP, one, nullptr, 0);        // T2 = A21 P11
+    gemm64_mfma(A21, WP, P22, WP, T2, WP, mone, nullptr, 0);       // P21 = -P22 T2 (over A21)
+    gemm64_mfma(P11, WP, P12, WP, T2, WP, mone, P11, WP);          // P11 = P11 - P12 T2
+    float2* P = Pf + (size_t)s * PSTR;
+    for (int e = t; e < 128 * 128; e += 256) {
+        const int r = e % 128, c = e / 128;
+        const double2* src = r < 64 ? (c < 64 ? P11 : P12) : (c < 64 ? A21 : P22);
+        const double2 v = src[(size_t)(c & 63) * WP + (r & 63)];
+        P[e] = make_float2((float)v.x, (float)v.y);
+    }
+    __syncthreads();
+    {
+        // column sums of |A_KK| and |P|: thread (column c, half h) sums 64 rows
+        const int c = t & 127, h = t >> 7;
+        double sa = 0.0, sp = 0.0;
+#pragma unroll 4
+        for (int r = 64 * h; r < 64 * h + 64; ++r) {
+            const double2 v = at(r, c);
+            sa += sqrt(v.x * v.x + v.y * v.y);
+            const float2 q = P[(size_t)c * 128 + r];
+            sp += sqrt((double)q.x * q.x + (double)q.y * q.y);
+        }
+        na[h][c] = sa;
+        np[h][c] = sp;
+    }
+    __syncthreads();
+    if (t < 64) {
+        double ma = fmax(na[0][t] + na[1][t], na[0][t + 64] + na[1][t + 64]);
+        double mp = fmax(np[0][t] + np[1][t], np[0][t + 64] + np[1][t + 64]);
+        for (int off = 32; off > 0; off >>= 1) {
+            ma = fmax(ma, __shfl_xor(ma, off));
+            mp = fmax(mp, __shfl_xor(mp, off));
+        }
+        if (t == 0 && !(ma * mp <= COND_MAX)) atomicOr(err, 2);
+    }
+}
+
+// The operands of the update for the column block K = k0 .. k0 + NB - 1 (grid: 64-column
+// tiles x slabs):
 //   C(i, k) = A(i, k0 + k) - [i = k0 + k]     rows of tile jt,  stored Cb[s][k][Bp]
 //   R(k, j) = sum_m P(k, m) A(k0 + m, j)      columns of tile jt, R(:, K) = P, Rb[s][k][Bp]
-// The 64 x 64 x 64 product runs on v_mfma_f32_16x16x4f32: wave w computes rows
-// 16w .. 16w + 15 of R for the tile's 64 columns, P read in lane layout from global
-// memory, the A block from LDS (staged column by column, coalesced).
+// P is NB x NB, column-major (leading dimension NB).  The NB x 64 x NB product runs on
+// v_mfma_f32_16x16x4f32: wave w computes rows NB/4 w .. of R for the tile's 64 columns, P
+// read in lane layout from global memory, the A block from LDS (staged column by column).
+template <int NB>
 __global__ void __launch_bounds__(256) k3f_rc(const float2* __restrict__ F, size_t stride, int l, int Bp, int k0,
                                              const float2* __restrict__ Pf, float2* __restrict__ Cb,
                                              float2* __restrict__ Rb, int s0) {
-    __shared__ float2 As[64][65];      // As[j][m] = A(k0 + m, J0 + j)
-    const int s = s0 + blockIdx.y, J0 = blockIdx.x * NBF, t = threadIdx.x;
+    constexpr int RW = NB / 64;        // 16-row MFMA tiles per wave
+    __shared__ float2 As[64][NB + 1];  // As[j][m] = A(k0 + m, J0 + j)
+    const int s = s0 + blockIdx.y, J0 = blockIdx.x * 64, t = threadIdx.x;
     const float2* A = F + s * stride + (size_t)l * Bp * Bp;
-    float2* cb = Cb + (size_t)s * NBF * Bp;
-    float2* rb = Rb + (size_t)s * NBF * Bp;
-    const float2* P = Pf + (size_t)s * BLK;
+    float2* cb = Cb + (size_t)s * cstr(Bp);
+    float2* rb = Rb + (size_t)s * cstr(Bp);
+    const float2* P = Pf + (size_t)s * PSTR;
     // C rows of this tile
-    for (int e = t; e < NBF * NBF; e += 256) {
-        const int k = e / NBF, ii = e % NBF, i = J0 + ii;
+    for (int e = t; e < NB * 64; e += 256) {
+        const int k = e / 64, ii = e % 64, i = J0 + ii;
         float2 v = A[(size_t)(k0 + k) * Bp + i];
         if (i == k0 + k) v.x -= 1.0f;
         cb[(size_t)k * Bp + i] = v;
     }
-    if (J0 == k0) {
-        for (int e = t; e < NBF * NBF; e += 256) {
-            const int k = e / NBF, jj = e % NBF;
-            rb[(size_t)k * Bp + J0 + jj] = P[(size_t)jj * WP + k];
+    if (J0 >= k0 && J0 < k0 + NB) {
+        for (int e = t; e < NB * 64; e += 256) {
+            const int k = e / 64, jj = e % 64;
+            rb[(size_t)k * Bp + J0 + jj] = P[(size_t)(J0 - k0 + jj) * NB + k];
         }
         return;
     }
-    for (int e = t; e < NBF * NBF; e += 256) {
-        const int jj = e / NBF, mm = e % NBF;
+    for (int e = t; e < NB * 64; e += 256) {
+        const int jj = e / NB, mm = e % NB;
         As[jj][mm] = A[(size_t)(J0 + jj) * Bp + k0 + mm];
     }
     __syncthreads();
     const int lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
-    mf4 re[4], im[4];
+    mf4 re[RW][4], im[RW][4];
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb) { re[jb] = mf4{0.f, 0.f, 0.f, 0.f}; im[jb] = re[jb]; }
-    const float2* pp = P + (size_t)q4 * WP + 16 * w + n;     // P(16w + n, 4 ks + q4)
-#pragma unroll 4
-    for (int ks = 0; ks < NBF / 4; ++ks) {
-        const float2 a = pp[(size_t)4 * ks * WP];
+    for (int ra = 0; ra < RW; ++ra)
+#pragma unroll
+        for (int jb = 0; jb < 4; ++jb) { re[ra][jb] = mf4{0.f, 0.f, 0.f, 0.f}; im[ra][jb] = re[ra][jb]; }
+    const float2* pp = P + (size_t)q4 * NB + 16 * RW * w + n;     // P(16 (RW w + ra) + n, 4 ks + q4)
+#pragma unroll 2
+    for (int ks = 0; ks < NB / 4; ++ks) {
+        float2 a[RW];
+#pragma unroll
+        for (int ra = 0; ra < RW; ++ra) a[ra] = pp[(size_t)4 * ks * NB + 16 * ra];
 #pragma unroll
         for (int jb = 0; jb < 4; ++jb) {
             const float2 b = As[16 * jb + n][4 * ks + q4];
-            re[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, re[jb], 0, 0, 0);
-            im[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, im[jb], 0, 0, 0);
-            re[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.y, b.y, re[jb], 0, 0, 0);
-            im[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, im[jb], 0, 0, 0);
+#pragma unroll
+            for (int ra = 0; ra < RW; ++ra) {
+                re[ra][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ra].x, b.x, re[ra][jb], 0, 0, 0);
+                im[ra][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ra].x, b.y, im[ra][jb], 0, 0, 0);
+                re[ra][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[ra].y, b.y, re[ra][jb], 0, 0, 0);
+                im[ra][jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[ra].y, b.x, im[ra][jb], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb)
+    for (int ra = 0; ra < RW; ++ra)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            rb[(size_t)(16 * w + 4 * q4 + j) * Bp + J0 + 16 * jb + n] = make_float2(re[jb][j], im[jb][j]);
+        for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                rb[(size_t)(16 * (RW * w + ra) + 4 * q4 + j) * Bp + J0 + 16 * jb + n] =
+                    make_float2(re[ra][jb][j], im[ra][jb][j]);
 }
 
 // A := A_mod - C R on every 64 x 64 tile of every slab.  The tiles are spread over the
@@ -190,25 +282,26 @@ __global__ void __launch_bounds__(256) k3f_rc(const float2* __restrict__ F, size
 // tiles; operands are read straight from global memory in the MFMA lane layout (A operand
 // C(l % 16, l / 16), B operand R(l / 16, l % 16), accumulator rows 4 (l / 16) + j, column
 // l % 16), one k-step ahead.
+template <int NB>
 __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t stride, int l, int Bp, int k0,
                                                  int ns, const float2* __restrict__ Cb,
                                                  const float2* __restrict__ Rb, int s0) {
-    const int nb = Bp / NBF, nt = nb * nb;
+    const int nb = Bp / 64, nt = nb * nb;
     const int total = ns * nt, per = (total + 7) / 8;
     const int gi = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (gi >= total) return;
     const int s = s0 + gi / nt, tt = gi % nt, it = tt % nb, jt = tt / nb;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, n = lane & 15, q4 = lane >> 4;
-    const int I0 = it * NBF + 32 * (w & 1), J0 = jt * NBF + 32 * (w >> 1);
+    const int I0 = it * 64 + 32 * (w & 1), J0 = jt * 64 + 32 * (w >> 1);
     float2* A = F + s * stride + (size_t)l * Bp * Bp;
-    const float2* cp = Cb + (size_t)s * NBF * Bp + (size_t)q4 * Bp + I0 + n;
-    const float2* rp = Rb + (size_t)s * NBF * Bp + (size_t)q4 * Bp + J0 + n;
-    const bool kcol = jt * NBF == k0;
-    if (it * NBF == k0) {
+    const float2* cp = Cb + (size_t)s * cstr(Bp) + (size_t)q4 * Bp + I0 + n;
+    const float2* rp = Rb + (size_t)s * cstr(Bp) + (size_t)q4 * Bp + J0 + n;
+    const bool kcol = jt * 64 >= k0 && jt * 64 < k0 + NB;
+    if (it * 64 >= k0 && it * 64 < k0 + NB) {
         // the rows of block K become R(:, J) = P A(K, J): written directly, since forming
         // them as A(K, J) - (A_KK - I) R(:, J) would cancel A(K, J) against A_KK P A(K, J)
         // and leave an FP32 error of order eps cond(A_KK)
-        const float2* rr = Rb + (size_t)s * NBF * Bp;
+        const float2* rr = Rb + (size_t)s * cstr(Bp);
 #pragma unroll
         for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
@@ -248,8 +341,8 @@ __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t
     float2 c[2], r[2], cn[2], rn[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) { c[u] = cp[16 * u]; r[u] = rp[16 * u]; }
-    for (int kb = 0; kb < NBF / 4; ++kb) {
-        const size_t nx = (size_t)(kb + 1 < NBF / 4 ? kb + 1 : kb) * 4 * Bp;
+    for (int kb = 0; kb < NB / 4; ++kb) {
+        const size_t nx = (size_t)(kb + 1 < NB / 4 ? kb + 1 : kb) * 4 * Bp;
 #pragma unroll
         for (int u = 0; u < 2; ++u) { cn[u] = cp[nx + 16 * u]; rn[u] = rp[nx + 16 * u]; }
         float cs[2], rs[2];
@@ -284,25 +377,39 @@ __global__ void __launch_bounds__(256) k3f_update(float2* __restrict__ F, size_t
 }  // namespace
 
 size_t factor3_f32_work_bytes(int J, int Bp) {
-    // Pd (FP64) + Pf + Cb + Rb per slab
-    return (size_t)J * (BLK * sizeof(double2) + BLK * sizeof(float2) + 2 * (size_t)NBF * Bp * sizeof(float2));
+    // per slab: eight FP64 64 x 64 scratch blocks (the 64-wide inverse uses the first),
+    // P (complex64, up to 128 x 128), C and R (up to 128 x Bp each)
+    return (size_t)J * (WSTR * sizeof(double2) + PSTR * sizeof(float2) + 2 * cstr(Bp) * sizeof(float2));
 }
 
+// One plane of the slabs s0 .. s0 + ns - 1: column blocks of 128 (a last block of 64 when
+// Bp is an odd multiple of 64).  A 128-wide block halves the passes of the update over the
+// matrices (the update is bound by HBM and MFMA about equally at 64).
 hipError_t launch_factor3_plane_f32(const Fac3Args& a, int l, float2* F, size_t stride, void* work, int* err,
                                     hipStream_t st, int s0, int ns) {
     const size_t BB = (size_t)a.Bp * a.Bp;
-    double2* Pd = static_cast<double2*>(work);
-    float2* Pf = reinterpret_cast<float2*>(Pd + (size_t)a.J * BLK);
-    float2* Cb = Pf + (size_t)a.J * BLK;
-    float2* Rb = Cb + (size_t)a.J * NBF * a.Bp;
+    double2* Wd = static_cast<double2*>(work);
+    float2* Pf = reinterpret_cast<float2*>(Wd + (size_t)a.J * WSTR);
+    float2* Cb = Pf + (size_t)a.J * PSTR;
+    float2* Rb = Cb + (size_t)a.J * cstr(a.Bp);
     const unsigned nbs = (unsigned)std::min<size_t>((BB + 255) / 256, 4096);
     hipLaunchKernelGGL(k3f_build_S, dim3(nbs, ns), dim3(256), 0, st, a, l, F, stride, s0);
-    const int nb = a.Bp / NBF;
+    const int nb = a.Bp / 64;
     const int total = ns * nb * nb, per = (total + 7) / 8;
-    for (int k0 = 0; k0 < a.Bp; k0 += NBF) {
-        hipLaunchKernelGGL(k3f_diag_inv, dim3(ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pd, Pf, err, s0);
-        hipLaunchKernelGGL(k3f_rc, dim3(nb, ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pf, Cb, Rb, s0);
-        hipLaunchKernelGGL(k3f_update, dim3(8 * per), dim3(256), 0, st, F, stride, l, a.Bp, k0, ns, Cb, Rb, s0);
+    for (int k0 = 0; k0 < a.Bp;) {
+        if (k0 + 128 <= a.Bp) {
+            hipLaunchKernelGGL(k3f_diag_inv128, dim3(ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Wd, Pf, err, s0);
+            hipLaunchKernelGGL(k3f_rc<128>, dim3(nb, ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pf, Cb, Rb, s0);
+            hipLaunchKernelGGL(k3f_update<128>, dim3(8 * per), dim3(256), 0, st, F, stride, l, a.Bp, k0, ns, Cb, Rb,
+                               s0);
+            k0 += 128;
+        } else {
+            hipLaunchKernelGGL(k3f_diag_inv, dim3(ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Wd, Pf, err, s0);
+            hipLaunchKernelGGL(k3f_rc<64>, dim3(nb, ns), dim3(256), 0, st, F, stride, l, a.Bp, k0, Pf, Cb, Rb, s0);
+            hipLaunchKernelGGL(k3f_update<64>, dim3(8 * per), dim3(256), 0, st, F, stride, l, a.Bp, k0, ns, Cb, Rb,
+                               s0);
+            k0 += 64;
+        }
     }
     return hipGetLastError();
 }
