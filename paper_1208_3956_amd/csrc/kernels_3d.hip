@@ -435,8 +435,9 @@ __global__ void __launch_bounds__(256) k3_rhs0(Solve3Args<T> a, cplx<T>* __restr
 // SIMD hide the load latency; each wave also loads its next block before it multiplies
 // the current one).  The NW3 partial tiles are added through LDS.  Returns, for thread
 // t < 256, the entry (row t / 16, column t % 16) of the tile.
-// complex64: v_mfma_f32_16x16x4f32, four real products per complex one (lane layout
-// A[l % 16][l / 16], B[l / 16][l % 16], C[4 (l / 16) + j][l % 16] in component j).
+// complex64: v_mfma_f32_16x16x4f32, three real products per complex one (Gauss's form;
+// lane layout A[l % 16][l / 16], B[l / 16][l % 16], C[4 (l / 16) + j][l % 16] in
+// component j).
 constexpr int NW3 = 16;
 constexpr int NT3 = 64 * NW3;
 
@@ -444,7 +445,10 @@ __device__ inline float2 tile_product(const float2* __restrict__ G, const float2
                                       int RP, int i0, int r0, float2 (*red)[16][16]) {
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
     const int nblk = Bp / 16;
-    mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+    // complex products from three real ones: x1 = sum Gr Xr, x2 = sum Gi Xi,
+    // x3 = sum (Gr + Gi)(Xr + Xi); Re = x1 - x2, Im = x3 - x1 - x2 (two chains of each for
+    // independent MFMAs)
+    mf4 x1a = {0.f, 0.f, 0.f, 0.f}, x2a = x1a, x3a = x1a, x1b = x1a, x2b = x1a, x3b = x1a;
     const float2* gp = G + (size_t)q4 * Bp + i0 + n;
     const float2* xp = X + (size_t)q4 * RP + r0 + n;
     float2 g[4], x[4], gn[4], xn[4];
@@ -461,20 +465,21 @@ __device__ inline float2 tile_product(const float2* __restrict__ G, const float2
         load(bn, gn, xn);
 #pragma unroll
         for (int u = 0; u < 4; u += 2) {
-            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].x, x[u].x, aR0, 0, 0, 0);
-            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].x, x[u].y, aI0, 0, 0, 0);
-            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].x, x[u + 1].x, aR1, 0, 0, 0);
-            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].x, x[u + 1].y, aI1, 0, 0, 0);
-            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g[u].y, x[u].y, aR0, 0, 0, 0);
-            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].y, x[u].x, aI0, 0, 0, 0);
-            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g[u + 1].y, x[u + 1].y, aR1, 0, 0, 0);
-            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].y, x[u + 1].x, aI1, 0, 0, 0);
+            x1a = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].x, x[u].x, x1a, 0, 0, 0);
+            x2a = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].y, x[u].y, x2a, 0, 0, 0);
+            x3a = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u].x + g[u].y, x[u].x + x[u].y, x3a, 0, 0, 0);
+            x1b = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].x, x[u + 1].x, x1b, 0, 0, 0);
+            x2b = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].y, x[u + 1].y, x2b, 0, 0, 0);
+            x3b = __builtin_amdgcn_mfma_f32_16x16x4f32(g[u + 1].x + g[u + 1].y, x[u + 1].x + x[u + 1].y, x3b, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) { g[u] = gn[u]; x[u] = xn[u]; }
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) red[w][4 * q4 + j][n] = make_float2(aR0[j] + aR1[j], aI0[j] + aI1[j]);
+    for (int j = 0; j < 4; ++j) {
+        const float p1 = x1a[j] + x1b[j], p2 = x2a[j] + x2b[j], p3 = x3a[j] + x3b[j];
+        red[w][4 * q4 + j][n] = make_float2(p1 - p2, p3 - p1 - p2);
+    }
     __syncthreads();
     float2 z = make_float2(0.f, 0.f);
     if (t < 256) {
