@@ -147,20 +147,16 @@ def test_factor_path_by_precision(case):
     H.close()
 
 
-@pytest.fixture(scope="module")
-def smooth40():
-    wl = W.smooth_3d(n=40, nsrc=4)
-    g = geometry_from_workload(wl)
-    return wl, g
-
-
-@pytest.mark.parametrize("s", [7, 15])
-def test_complex64_slab_factor_multiblock(smooth40, s):
-    """40^3 smooth medium (blocks of 14 x 64 unknowns after padding): slab solves of the
-    complex64 blocked Gauss-Jordan factor against the oracle's SuperLU slab solves."""
+@pytest.mark.parametrize("n,J,s", [(40, 16, 7), (40, 16, 15), (20, 4, 1)])
+def test_complex64_slab_factor_multiblock(n, J, s):
+    """Smooth media: 40^3 (blocks of 840-896 unknowns padded to 896, seven 128-wide column
+    blocks) and 20^3 (648 padded to 704: five 128-wide blocks and a last 64-wide one).  Slab
+    solves of the complex64 blocked Gauss-Jordan factor against the oracle's SuperLU slab
+    solves."""
     from oracle.assemble import assemble_strip
     import scipy.sparse.linalg as spla
-    wl, g = smooth40
+    wl = W.smooth_3d(n=n, nsrc=4, J=J)
+    g = geometry_from_workload(wl)
     H = _gpu(wl, prec="mixed")
     assert H.factor_path == 1
     st = g.strips[s]
