@@ -73,18 +73,18 @@ def phase_flops(H, wl, nrhs):
     B = W N_z) and one timed factor unit is the whole factorisation (B^3 multiply-adds of
     Gauss-Jordan per slab and plane)."""
     Ny = H.N_y
+    slot = H.strip_factor_slot               # identical strips share one factorisation
+    reps = [slot.index(u) for u in range(max(slot) + 1)]
     if H.dim == 3:
         B = [w * H.N_z for w in H.strip_width]
         B2 = sum(b * b for b in B) / len(B)
         return {"phase_a": 8.0 * B2 * nrhs * (2 * Ny - 1), "phase_b": 0.0, "phase_c": 0.0,
-                "factor_chunks": 8.0 * sum(b ** 3 for b in B) * Ny, "factor_separators": 0.0}
+                "factor_chunks": 8.0 * sum(B[r] ** 3 for r in reps) * Ny, "factor_separators": 0.0}
     m = H.chunk_rows
     P = -(-Ny // m)
     n_int = Ny - (P - 1)                    # interior rows over all chunks
     W2 = sum(w * w for w in H.strip_width) / len(H.strip_width)
-    # identical strips share one factorisation: the factor work covers one strip per slot
-    slot = H.strip_factor_slot
-    W3 = sum(H.strip_width[slot.index(u)] ** 3 for u in range(max(slot) + 1))
+    W3 = sum(H.strip_width[r] ** 3 for r in reps)
     fl = {
         # forward + backward block substitution: one W x W matvec per interior row each way
         "phase_a": 8.0 * W2 * nrhs * (2 * n_int - P),

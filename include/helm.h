@@ -238,12 +238,13 @@ helm_status helm_get_dims(helm_t H, int* N_x, int* N_y, int* J);
 helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip_width);
 
 /* Number of factorisations the handle stores (host int) and, if strip_slot is not NULL,
- * the slot each of the J strips uses (host, J ints, slots numbered by first use).  2-D
- * strips whose operators
+ * the slot each of the J strips uses (host, J ints, slots numbered by first use).  Strips
+ * whose operators
  * coincide (the same width, PML tables and reduced-form target columns, and the same k^2
  * on every row of corresponding columns: e.g. the interior strips of one width in a medium
  * that does not vary with x; the paper notes that a constant medium needs one
- * factorisation, Sec. 4.3) share one; 3-D slabs are factored one by one (J).
+ * factorisation, Sec. 4.3) share one; so do 3-D slabs (the same comparison over every
+ * z-plane).
  * HELM_ESTATE if helm_setup did not complete. */
 helm_status helm_get_factor_slots(helm_t H, int* slots, int* strip_slot);
 

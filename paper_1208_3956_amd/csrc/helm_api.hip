@@ -295,7 +295,7 @@ template <typename T>
 helm_status strip_solve3(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
     const auto& g = H->g;
     helm::Solve3Args<T> a;
-    a.F = static_cast<const helm::cplx<T>*>(H->F) + (size_t)s * g.Ny * g.Bp * g.Bp;
+    a.F = static_cast<const helm::cplx<T>*>(H->F) + (size_t)H->fidx[s] * g.Ny * g.Bp * g.Bp;
     a.Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
     a.cy = H->t.cy;
     a.by = H->t.by;
@@ -994,9 +994,10 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         if (S.rpad)
             for (int k = 0; k < 3; ++k) tcol[(size_t)s * 8 + 3 + k] = g.beta[s + 1] - 2 + k - S.a;
     }
-    // strips whose operators coincide share one factorisation (2-D): the same width, PML
-    // tables and target columns, and the same k^2 on every row of corresponding columns
-    // (an x-invariant medium makes every interior strip of one width alike)
+    // strips (slabs) whose operators coincide share one factorisation: the same width, PML
+    // tables and target columns, and the same k^2 on every row (and z-plane) of
+    // corresponding columns (a medium that does not vary with x makes every interior strip
+    // of one width alike)
     std::vector<int> urep;
     H->fidx.assign(J, 0);
     auto same_strip = [&](int a, int b) {
@@ -1015,17 +1016,14 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         for (int q = 0; q < W; ++q) {
             const int ca = scol[(size_t)a * WP + q], cb = scol[(size_t)b * WP + q];
             if (ca == cb) continue;
-            for (int l = 0; l < Ny; ++l)
-                if (k2[(size_t)l * Nx + ca] != k2[(size_t)l * Nx + cb]) return false;
+            for (size_t row = 0; row < (size_t)Nz * Ny; ++row)
+                if (k2[row * Nx + ca] != k2[row * Nx + cb]) return false;
         }
         return true;
     };
     for (int s = 0; s < J; ++s) {
         int u = 0;
-        if (dim == 2)
-            while (u < (int)urep.size() && !same_strip(s, urep[u])) ++u;
-        else
-            u = (int)urep.size();
+        while (u < (int)urep.size() && !same_strip(s, urep[u])) ++u;
         if (u == (int)urep.size()) urep.push_back(s);
         H->fidx[s] = u;
     }
@@ -1090,7 +1088,8 @@ helm_status factor3(helm_t H) {
     const bool single = H->prec != HELM_C128;
     const size_t esz = single ? sizeof(float2) : sizeof(double2);
     void* F = nullptr;
-    CHK(dmalloc(H, &F, (size_t)g.J * g.Ny * BB * esz));
+    const int nf = H->nfac;               // one factorisation per distinct slab operator
+    CHK(dmalloc(H, &F, (size_t)nf * g.Ny * BB * esz));
     struct Bufs {
         std::vector<void*> p;
         ~Bufs() { for (void* q : p) dfree(q); }
@@ -1106,8 +1105,8 @@ helm_status factor3(helm_t H) {
     void* work32 = nullptr;
     helm_status st;
     helm::Fac3Args a;
-    a.J = g.J; a.Ny = g.Ny; a.Nz = g.Nz; a.Nx = g.Nx; a.Bp = g.Bp;
-    a.sW = H->t.sW; a.sax = H->t.sax; a.saxh = H->t.saxh; a.scol = H->t.scol;
+    a.J = nf; a.Ny = g.Ny; a.Nz = g.Nz; a.Nx = g.Nx; a.Bp = g.Bp;
+    a.sW = H->tf.sW; a.sax = H->tf.sax; a.saxh = H->tf.saxh; a.scol = H->tf.scol;
     a.ay = H->t.ay; a.ayh = H->t.ayh; a.az = H->t.az; a.azh = H->t.azh;
     a.cy = H->t.cy; a.by = H->t.by; a.k2 = H->t.k2;
     a.ih2 = 1.0 / (g.h * g.h);
@@ -1116,7 +1115,7 @@ helm_status factor3(helm_t H) {
         // complex64 blocked Gauss-Jordan in place in the stored factor; a diagonal block
         // that is singular or ill-conditioned sends the whole factorisation to the FP64
         // Gauss-Jordan with partial pivoting over the whole column below
-        if ((st = alloc(&work32, helm::factor3_f32_work_bytes(g.J, g.Bp))) != HELM_OK) { dfree(F); return st; }
+        if ((st = alloc(&work32, helm::factor3_f32_work_bytes(nf, g.Bp))) != HELM_OK) { dfree(F); return st; }
         HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
         // the slabs are independent.  FAC3_GROUPS streams (the handle's and streams of their
         // own, default priority) each factor one group of slabs at a time, all planes of a
@@ -1126,8 +1125,8 @@ helm_status factor3(helm_t H) {
         // updated matrices in the last-level cache but launch too few tiles), one stream
         // 1425 ms; 4 or 8 streams with one group each changed nothing
         constexpr int NGR = FAC3_GROUPS;
-        const int batch = FAC3_BATCH > 0 ? std::min(FAC3_BATCH, g.J) : (g.J + NGR - 1) / NGR;
-        const int ngroups = (g.J + batch - 1) / batch;
+        const int batch = FAC3_BATCH > 0 ? std::min(FAC3_BATCH, nf) : (nf + NGR - 1) / NGR;
+        const int ngroups = (nf + batch - 1) / batch;
         const int nst = std::min(NGR, ngroups);
         hipStream_t sts[NGR];
         sts[0] = H->st;
@@ -1153,7 +1152,7 @@ helm_status factor3(helm_t H) {
                         const int gi = g0 + q;
                         if (gi >= ngroups) continue;
                         const int s0 = gi * batch;
-                        const int ns = std::min(batch, g.J - s0);
+                        const int ns = std::min(batch, nf - s0);
                         r = helm::launch_factor3_plane_f32(a, l, F32, stride, work32, H->d_err, sts[q], s0, ns);
                     }
             // join
@@ -1177,12 +1176,12 @@ helm_status factor3(helm_t H) {
         }
     }
     H->factor_path = 0;
-    if ((st = alloc((void**)&S, g.J * BB * sizeof(double2))) != HELM_OK ||
-        (st = alloc((void**)&G64, g.J * BB * sizeof(double2))) != HELM_OK ||
-        (st = alloc((void**)&Tm, (size_t)g.J * g.Bp * nb * sizeof(double2))) != HELM_OK ||
-        (st = alloc((void**)&Cm, (size_t)g.J * g.Bp * nb * sizeof(double2))) != HELM_OK ||
-        (st = alloc((void**)&perm, (size_t)g.J * g.Bp * sizeof(int))) != HELM_OK ||
-        (st = alloc((void**)&pi, (size_t)g.J * g.Bp * sizeof(int))) != HELM_OK) {
+    if ((st = alloc((void**)&S, nf * BB * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&G64, nf * BB * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&Tm, (size_t)nf * g.Bp * nb * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&Cm, (size_t)nf * g.Bp * nb * sizeof(double2))) != HELM_OK ||
+        (st = alloc((void**)&perm, (size_t)nf * g.Bp * sizeof(int))) != HELM_OK ||
+        (st = alloc((void**)&pi, (size_t)nf * g.Bp * sizeof(int))) != HELM_OK) {
         dfree(F);
         return st;
     }

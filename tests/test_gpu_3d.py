@@ -141,6 +141,7 @@ def test_factor_path_by_precision(case):
     wl, g, A, S = case
     H = _gpu(wl, prec="mixed")
     assert H.factor_path == 1
+    assert H.factor_slots == wl.J          # a medium that varies with x: one per slab
     H.close()
     H = _gpu(wl, prec="c128")
     assert H.factor_path == 0

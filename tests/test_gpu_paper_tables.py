@@ -51,7 +51,9 @@ def test_table3_const3d_100(w):
     res = H.solve(f, 1e-6)
     want = row["w_pml"][str(w)]
     print(f"Table 3 n={n} J={J} w_pml={w}: {res.iters[0]} iterations (paper: {want}), "
-          f"factor path {H.factor_path}", flush=True)
+          f"factor path {H.factor_path}, {H.factor_slots} factorisations", flush=True)
+    # a constant medium: the interior slabs share one factorisation (Sec. 4.3)
+    assert H.factor_slots == 3
     H.close()
     assert res.status == 0 and res.relres[0] <= 1e-6
     assert abs(res.iters[0] - want) <= 2
