@@ -41,6 +41,7 @@ struct Work {
     double2* y = nullptr;
     double2* red = nullptr;
     double2* apin = nullptr;    // fixed input of the captured reduced operator
+    double2* psi0 = nullptr;    // restart: correction taken from the previous cycle's space
 };
 
 // Event-pair timing of kernel launches (helm_set_kernel_timing).
@@ -241,7 +242,7 @@ helm_status upload(helm_t H, void** dptr, const void* src, size_t bytes) {
 // ---------------------------------------------------------------- workspaces
 void free_work(Work& w) {
     void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Vw, w.Gw, w.Ww, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
-                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin};
+                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin, w.psi0};
     for (void* p : ps) dfree(p);
     w = Work();
 }
@@ -551,8 +552,8 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     Work& w = H->wk;
     if (w.basis && w.n == n && w.mcap >= mwant) return HELM_OK;
     dfree(w.basis); dfree(w.w); dfree(w.h1); dfree(w.h2); dfree(w.nrm); dfree(w.partial);
-    dfree(w.npartial); dfree(w.y); dfree(w.red); dfree(w.apin);
-    w.basis = w.w = w.h1 = w.h2 = w.y = w.red = w.apin = w.partial = nullptr;
+    dfree(w.npartial); dfree(w.y); dfree(w.red); dfree(w.apin); dfree(w.psi0);
+    w.basis = w.w = w.h1 = w.h2 = w.y = w.red = w.apin = w.partial = w.psi0 = nullptr;
     w.nrm = w.npartial = nullptr;
     H->ws_epoch += 1;
     size_t freeb = 0, totb = 0;
@@ -565,6 +566,7 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     CHK(dmalloc(H, &w.w, vb));
     CHK(dmalloc(H, &w.red, vb));
     CHK(dmalloc(H, &w.apin, vb));
+    CHK(dmalloc(H, &w.psi0, vb));
     CHK(dmalloc(H, &w.h1, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.h2, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.y, (size_t)nrhs * (m + 1) * sizeof(double2)));
@@ -629,7 +631,8 @@ helm_status norms(helm_t H, const double2* v, int nrhs, long n, std::vector<doub
 // iteration counts.  active[r] == false rhs take no part (y = 0).
 helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std::vector<double>& bnorm,
                         const std::vector<double>& target, int maxit, double2* yout,
-                        std::vector<int>& its, std::vector<double>& resid) {
+                        std::vector<int>& its, std::vector<double>& resid,
+                        std::vector<std::vector<cd>>* hess = nullptr) {
     Work& w = H->wk;
     const int m = std::min(maxit, w.mcap);
     const size_t vs = (size_t)nrhs * n;
@@ -637,6 +640,8 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
     std::vector<double> scale(nrhs);
     its.assign(nrhs, 0);
     resid.assign(nrhs, 0.0);
+    // Hessenberg columns of each right-hand side, column k with entries 0 .. k + 1
+    if (hess) hess->assign(nrhs, std::vector<cd>());
     bool all = true;
     for (int r = 0; r < nrhs; ++r) {
         gv[r].init(m, bnorm[r]);
@@ -678,6 +683,10 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
                     const double2 a = hh1[(size_t)r * nv + i], c2 = hh2[(size_t)r * nv + i];
                     col[i] = cd(a.x + c2.x, a.y + c2.y);
                 }
+                if (hess) {
+                    for (int i = 0; i < nv; ++i) (*hess)[r].push_back(col[i]);
+                    (*hess)[r].push_back(cd(nr[r], 0.0));
+                }
                 G.push(col.data(), nr[r]);
                 its[r] = G.k;
                 resid[r] = G.res;
@@ -700,6 +709,75 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
     HIPCHK(hipMemcpyAsync(w.y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
     HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(w.basis, nvec, w.y, yout, nrhs, n, 0, H->st)));
     HIPCHK(hipStreamSynchronize(H->st));
+    return HELM_OK;
+}
+
+// Restart in reduced mode: the previous cycle left its Krylov basis V (in w.basis, k_r + 1
+// vectors for right-hand side r) and Hessenberg matrix H_r with M V_k = V_{k+1} H_r for the
+// reduced operator M.  The new right-hand side b is first reduced by its best correction
+// from that space: z_r = argmin ||V^H b - H_r z|| (small least squares on the host),
+// psi0 = V_k z_r, b <- b - V_{k+1} H_r z_r (= b - M psi0 up to the rounding of the Arnoldi
+// relation, far below the restart's target).  The slowly converging directions the first
+// cycle already found are thereby removed before the new cycle starts.
+helm_status project_previous(helm_t H, int nrhs, long n, double2* b, const std::vector<std::vector<cd>>& hess,
+                             const std::vector<int>& kprev, bool& have_psi0) {
+    Work& w = H->wk;
+    int kmax = 0;
+    for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, kprev[r]);
+    have_psi0 = false;
+    if (kmax < 1 || (int)hess.size() != nrhs) return HELM_OK;
+    const int nv = kmax + 1;
+    const int nb = helm::dots_blocks(n);
+    std::vector<double2> c((size_t)nrhs * nv);
+    HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_dots(w.basis, nv, b, nrhs, n, w.partial, nb, w.h1, H->st)));
+    HIPCHK(hipMemcpyAsync(c.data(), w.h1, c.size() * sizeof(double2), hipMemcpyDeviceToHost, H->st));
+    HIPCHK(hipStreamSynchronize(H->st));
+    std::vector<double2> zt((size_t)nrhs * nv, make_double2(0, 0)), tt((size_t)nrhs * nv, make_double2(0, 0));
+    for (int r = 0; r < nrhs; ++r) {
+        const int k = kprev[r];
+        if (k < 1 || (int)hess[r].size() < k * (k + 3) / 2) continue;
+        // column j of H_r holds entries 0 .. j + 1 (stored consecutively)
+        std::vector<cd> Hm((size_t)(k + 1) * k, 0.0), rhs(k + 1);
+        size_t pos = 0;
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i <= j + 1; ++i) Hm[(size_t)j * (k + 1) + i] = hess[r][pos++];
+        for (int i = 0; i <= k; ++i) rhs[i] = cd(c[(size_t)r * nv + i].x, c[(size_t)r * nv + i].y);
+        // least squares by Givens rotations on the Hessenberg matrix
+        std::vector<cd> R = Hm, g = rhs;
+        for (int j = 0; j < k; ++j) {
+            const cd a = R[(size_t)j * (k + 1) + j], bb = R[(size_t)j * (k + 1) + j + 1];
+            const double t = std::hypot(std::abs(a), std::abs(bb));
+            if (!(t > 0.0)) continue;
+            const cd cs = a / t, sn = bb / t;          // rotation mapping (a, b) to (t, 0)
+            for (int q = j; q < k; ++q) {
+                const cd x = R[(size_t)q * (k + 1) + j], y = R[(size_t)q * (k + 1) + j + 1];
+                R[(size_t)q * (k + 1) + j] = std::conj(cs) * x + std::conj(sn) * y;
+                R[(size_t)q * (k + 1) + j + 1] = -sn * x + cs * y;
+            }
+            const cd x = g[j], y = g[j + 1];
+            g[j] = std::conj(cs) * x + std::conj(sn) * y;
+            g[j + 1] = -sn * x + cs * y;
+        }
+        std::vector<cd> z(k);
+        for (int i = k - 1; i >= 0; --i) {
+            cd sacc = g[i];
+            for (int j = i + 1; j < k; ++j) sacc -= R[(size_t)j * (k + 1) + i] * z[j];
+            const cd d = R[(size_t)i * (k + 1) + i];
+            z[i] = std::abs(d) > 0.0 ? sacc / d : 0.0;
+        }
+        for (int i = 0; i <= k; ++i) {
+            cd acc = 0.0;
+            for (int j = 0; j < k; ++j) acc += Hm[(size_t)j * (k + 1) + i] * z[j];
+            tt[(size_t)r * nv + i] = make_double2(acc.real(), acc.imag());
+        }
+        for (int j = 0; j < k; ++j) zt[(size_t)r * nv + j] = make_double2(z[j].real(), z[j].imag());
+    }
+    HIPCHK(hipMemcpyAsync(w.h2, tt.data(), tt.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
+    HIPCHK(hipMemcpyAsync(w.y, zt.data(), zt.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
+    HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_update(w.basis, nv, w.h2, b, nrhs, n, H->st)));
+    HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(w.basis, nv, w.y, w.psi0, nrhs, n, 0, H->st)));
+    HIPCHK(hipStreamSynchronize(H->st));
+    have_psi0 = true;
     return HELM_OK;
 }
 
@@ -727,6 +805,8 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     bool ok = false;
     std::vector<double> est0;      // GMRES residual estimates at the end of the first cycle
     bool floor_used = false;       // the first cycle ended at the recorded floor
+    std::vector<std::vector<cd>> hess;   // Hessenberg columns of the last cycle (reduced)
+    bool have_psi0 = false;        // w.psi0 holds a correction for the coming cycle
     for (int cycle = 0; used < H->max_iter; ++cycle) {
         // explicit FP64 residual of the current iterate (u = 0 in cycle 0: r = f)
         if (cycle == 0)
@@ -778,6 +858,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
             b = w.red;
+            if (cycle > 0) CHK(project_previous(H, nrhs, n, w.red, hess, its, have_psi0));
         }
         CHK(norms(H, b, nrhs, n, bn));
         if (trace_on())
@@ -795,7 +876,16 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
             }
         }
         // GMRES on op(y) = b; the solution increment is P y (+ u~)
-        CHK(gmres_cycle(H, nrhs, n, b, bn, target, H->max_iter - used, w.w, its, resid));
+        CHK(gmres_cycle(H, nrhs, n, b, bn, target, H->max_iter - used, w.w, its, resid,
+                        reduced ? &hess : nullptr));
+        if (have_psi0) {
+            // the correction taken from the previous cycle's space joins this cycle's psi
+            std::vector<double2> ones(nrhs, make_double2(1.0, 0.0));
+            HIPCHK(hipMemcpyAsync(w.h1, ones.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, H->st));
+            HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(w.psi0, 1, w.h1, w.w, nrhs, n, 1, H->st)));
+            HIPCHK(hipStreamSynchronize(H->st));
+            have_psi0 = false;
+        }
         if (cycle == 0) est0 = resid;
         int kmax = 0;
         for (int r = 0; r < nrhs; ++r) { total[r] += its[r]; kmax = std::max(kmax, its[r]); }
