@@ -41,7 +41,8 @@ struct Work {
     double2* y = nullptr;
     double2* red = nullptr;
     double2* apin = nullptr;    // fixed input of the captured reduced operator
-    double2* psi0 = nullptr;    // restart: correction taken from the previous cycle's space
+    double2* basis_old = nullptr;   // the previous cycle's basis, kept through a restart
+    int mcap_old = 0;
 };
 
 // Event-pair timing of kernel launches (helm_set_kernel_timing).
@@ -242,7 +243,7 @@ helm_status upload(helm_t H, void** dptr, const void* src, size_t bytes) {
 // ---------------------------------------------------------------- workspaces
 void free_work(Work& w) {
     void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Vw, w.Gw, w.Ww, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
-                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin, w.psi0};
+                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin, w.basis_old};
     for (void* p : ps) dfree(p);
     w = Work();
 }
@@ -552,8 +553,9 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     Work& w = H->wk;
     if (w.basis && w.n == n && w.mcap >= mwant) return HELM_OK;
     dfree(w.basis); dfree(w.w); dfree(w.h1); dfree(w.h2); dfree(w.nrm); dfree(w.partial);
-    dfree(w.npartial); dfree(w.y); dfree(w.red); dfree(w.apin); dfree(w.psi0);
-    w.basis = w.w = w.h1 = w.h2 = w.y = w.red = w.apin = w.partial = w.psi0 = nullptr;
+    dfree(w.npartial); dfree(w.y); dfree(w.red); dfree(w.apin); dfree(w.basis_old);
+    w.basis = w.w = w.h1 = w.h2 = w.y = w.red = w.apin = w.partial = w.basis_old = nullptr;
+    w.mcap_old = 0;
     w.nrm = w.npartial = nullptr;
     H->ws_epoch += 1;
     size_t freeb = 0, totb = 0;
@@ -566,7 +568,6 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     CHK(dmalloc(H, &w.w, vb));
     CHK(dmalloc(H, &w.red, vb));
     CHK(dmalloc(H, &w.apin, vb));
-    CHK(dmalloc(H, &w.psi0, vb));
     CHK(dmalloc(H, &w.h1, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.h2, (size_t)nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.y, (size_t)nrhs * (m + 1) * sizeof(double2)));
@@ -626,13 +627,29 @@ helm_status norms(helm_t H, const double2* v, int nrhs, long n, std::vector<doub
     return HELM_OK;
 }
 
+// Recycled space of a restart (reduced mode): the previous cycle's basis V (nv vectors per
+// right-hand side block; k_r + 1 of them used by right-hand side r) with M V_k = V_{k+1} Hr.
+// With Hr = Qh R (Qh orthonormal columns), C = V_{k+1} Qh is orthonormal and M U = C for
+// U = V_k R^{-1}.  The new cycle runs Arnoldi on (I - C C^H) M (B_j = C^H M v_j recorded per
+// step) and its solution gains U (a - B y), a = C^H b of the starting residual: GMRES over
+// span(U) + the new Krylov space (the GCRO form of augmented restarting).
+struct Aug {
+    const double2* V = nullptr;
+    int nv = 0;
+    std::vector<int> k;                   // per rhs: size of the recycled space
+    std::vector<std::vector<cd>> Qh;      // per rhs (k + 1) x k, column-major
+    std::vector<std::vector<cd>> R;       // per rhs k x k upper triangular, column-major
+    std::vector<std::vector<cd>> a;       // per rhs C^H b
+    std::vector<std::vector<cd>> B;       // per rhs, k entries per Arnoldi step
+};
+
 // One GMRES(m) cycle on op(y) = b.  b is copied into the basis.  Each right-hand side
 // stops when its residual is <= target[r]; returns y (device, [nrhs][n]) and per-rhs
 // iteration counts.  active[r] == false rhs take no part (y = 0).
 helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std::vector<double>& bnorm,
                         const std::vector<double>& target, int maxit, double2* yout,
                         std::vector<int>& its, std::vector<double>& resid,
-                        std::vector<std::vector<cd>>* hess = nullptr) {
+                        std::vector<std::vector<cd>>* hess = nullptr, Aug* aug = nullptr) {
     Work& w = H->wk;
     const int m = std::min(maxit, w.mcap);
     const size_t vs = (size_t)nrhs * n;
@@ -657,11 +674,43 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
     }
     int k = 0;
     std::vector<double2> hh1((size_t)nrhs * (m + 1)), hh2((size_t)nrhs * (m + 1));
+    std::vector<double2> aug_d, aug_e;
     std::vector<double> nr(nrhs);
     const int nb = helm::dots_blocks(n);
     while (!all && k < m) {
         double2* vk = w.basis + (size_t)k * vs;
         CHK(apply_op(H, nrhs, vk, w.w));
+        if (aug) {
+            // w <- (I - C C^H) w: B_j = C^H w = Qh^H (V^H w), w -= V (Qh B_j)
+            const int anv = aug->nv;
+            HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_dots(aug->V, anv, w.w, nrhs, n, w.partial, nb, w.h1, H->st)));
+            // host buffers outlive the step (the upload below completes at the step's sync)
+            std::vector<double2>& d = aug_d;
+            std::vector<double2>& e = aug_e;
+            d.assign((size_t)nrhs * anv, make_double2(0, 0));
+            e.assign((size_t)nrhs * anv, make_double2(0, 0));
+            HIPCHK(hipMemcpyAsync(d.data(), w.h1, d.size() * sizeof(double2), hipMemcpyDeviceToHost, H->st));
+            HIPCHK(hipStreamSynchronize(H->st));
+            for (int r = 0; r < nrhs; ++r) {
+                const int kr = aug->k[r];
+                if (gv[r].done || kr < 1) continue;
+                const std::vector<cd>& Q = aug->Qh[r];
+                for (int i = 0; i < kr; ++i) {
+                    cd bj = 0.0;
+                    for (int q = 0; q <= kr; ++q)
+                        bj += std::conj(Q[(size_t)i * (kr + 1) + q]) * cd(d[(size_t)r * anv + q].x, d[(size_t)r * anv + q].y);
+                    aug->B[r].push_back(bj);
+                }
+                const cd* bj = aug->B[r].data() + aug->B[r].size() - kr;
+                for (int q = 0; q <= kr; ++q) {
+                    cd acc = 0.0;
+                    for (int i = 0; i < kr; ++i) acc += Q[(size_t)i * (kr + 1) + q] * bj[i];
+                    e[(size_t)r * anv + q] = make_double2(acc.real(), acc.imag());
+                }
+            }
+            HIPCHK(hipMemcpyAsync(w.h2, e.data(), e.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
+            HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_update(aug->V, anv, w.h2, w.w, nrhs, n, H->st)));
+        }
         const int nv = k + 1;
         // classical Gram-Schmidt, twice
         HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_dots(w.basis, nv, w.w, nrhs, n, w.partial, nb, w.h1, H->st)));
@@ -709,75 +758,124 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
     HIPCHK(hipMemcpyAsync(w.y, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
     HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(w.basis, nvec, w.y, yout, nrhs, n, 0, H->st)));
     HIPCHK(hipStreamSynchronize(H->st));
+    if (aug) {
+        // + U (a - B y) = V_k R^{-1} (a - B y)
+        const int anv = aug->nv;
+        std::vector<double2> gco((size_t)nrhs * anv, make_double2(0, 0));
+        for (int r = 0; r < nrhs; ++r) {
+            const int kr = aug->k[r];
+            if (kr < 1) continue;
+            std::vector<cd> y = gv[r].solve(gv[r].k);
+            std::vector<cd> t = aug->a[r];
+            for (int j = 0; j < (int)y.size() && (size_t)(j + 1) * kr <= aug->B[r].size(); ++j)
+                for (int i = 0; i < kr; ++i) t[i] -= aug->B[r][(size_t)j * kr + i] * y[j];
+            const std::vector<cd>& R = aug->R[r];
+            for (int i = kr - 1; i >= 0; --i) {
+                cd acc = t[i];
+                for (int j = i + 1; j < kr; ++j) acc -= R[(size_t)j * kr + i] * t[j];
+                t[i] = acc / R[(size_t)i * kr + i];
+            }
+            for (int i = 0; i < kr; ++i) gco[(size_t)r * anv + i] = make_double2(t[i].real(), t[i].imag());
+        }
+        HIPCHK(hipMemcpyAsync(w.y, gco.data(), gco.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
+        HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(aug->V, anv, w.y, yout, nrhs, n, 1, H->st)));
+        HIPCHK(hipStreamSynchronize(H->st));
+    }
     return HELM_OK;
 }
 
-// Restart in reduced mode: the previous cycle left its Krylov basis V (in w.basis, k_r + 1
-// vectors for right-hand side r) and Hessenberg matrix H_r with M V_k = V_{k+1} H_r for the
-// reduced operator M.  The new right-hand side b is first reduced by its best correction
-// from that space: z_r = argmin ||V^H b - H_r z|| (small least squares on the host),
-// psi0 = V_k z_r, b <- b - V_{k+1} H_r z_r (= b - M psi0 up to the rounding of the Arnoldi
-// relation, far below the restart's target).  The slowly converging directions the first
-// cycle already found are thereby removed before the new cycle starts.
-helm_status project_previous(helm_t H, int nrhs, long n, double2* b, const std::vector<std::vector<cd>>& hess,
-                             const std::vector<int>& kprev, bool& have_psi0) {
+// Restart in reduced mode: from the previous cycle's basis V (in w.basis) and Hessenberg
+// matrices, the recycled space of the coming cycle (see Aug): Hr = Qh R by modified
+// Gram-Schmidt on the host (the space is cut where R loses rank), a = C^H b, and the new
+// starting residual b <- b - C a.  The previous basis is then moved to w.basis_old so that
+// the coming cycle builds its own in w.basis.  Returns with aug.nv = 0 (no recycling) when
+// there is nothing to recycle or no memory for the second basis.
+helm_status build_aug(helm_t H, int nrhs, long n, double2* b, const std::vector<std::vector<cd>>& hess,
+                      const std::vector<int>& kprev, Aug& aug) {
     Work& w = H->wk;
+    aug = Aug();
     int kmax = 0;
     for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, kprev[r]);
-    have_psi0 = false;
     if (kmax < 1 || (int)hess.size() != nrhs) return HELM_OK;
+    if (!w.basis_old || w.mcap_old < w.mcap) {
+        dfree(w.basis_old);
+        w.basis_old = nullptr;
+        w.mcap_old = 0;
+        if (hipMalloc((void**)&w.basis_old, (size_t)nrhs * n * sizeof(double2) * (w.mcap + 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            w.basis_old = nullptr;
+            return HELM_OK;                      // no room: a plain restart
+        }
+        w.mcap_old = w.mcap;
+    }
     const int nv = kmax + 1;
     const int nb = helm::dots_blocks(n);
     std::vector<double2> c((size_t)nrhs * nv);
     HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_dots(w.basis, nv, b, nrhs, n, w.partial, nb, w.h1, H->st)));
     HIPCHK(hipMemcpyAsync(c.data(), w.h1, c.size() * sizeof(double2), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
-    std::vector<double2> zt((size_t)nrhs * nv, make_double2(0, 0)), tt((size_t)nrhs * nv, make_double2(0, 0));
+    aug.k.assign(nrhs, 0);
+    aug.Qh.assign(nrhs, {});
+    aug.R.assign(nrhs, {});
+    aug.a.assign(nrhs, {});
+    aug.B.assign(nrhs, {});
+    std::vector<double2> e((size_t)nrhs * nv, make_double2(0, 0));
     for (int r = 0; r < nrhs; ++r) {
-        const int k = kprev[r];
+        int k = kprev[r];
         if (k < 1 || (int)hess[r].size() < k * (k + 3) / 2) continue;
-        // column j of H_r holds entries 0 .. j + 1 (stored consecutively)
-        std::vector<cd> Hm((size_t)(k + 1) * k, 0.0), rhs(k + 1);
+        std::vector<cd> Hm((size_t)(k + 1) * k, 0.0);
         size_t pos = 0;
         for (int j = 0; j < k; ++j)
             for (int i = 0; i <= j + 1; ++i) Hm[(size_t)j * (k + 1) + i] = hess[r][pos++];
-        for (int i = 0; i <= k; ++i) rhs[i] = cd(c[(size_t)r * nv + i].x, c[(size_t)r * nv + i].y);
-        // least squares by Givens rotations on the Hessenberg matrix
-        std::vector<cd> R = Hm, g = rhs;
+        // modified Gram-Schmidt: Hm = Q R
+        double hnorm = 0.0;
+        for (const cd& v : Hm) hnorm = std::max(hnorm, std::abs(v));
+        std::vector<cd> Q = Hm, R((size_t)k * k, 0.0);
+        int kk = 0;
         for (int j = 0; j < k; ++j) {
-            const cd a = R[(size_t)j * (k + 1) + j], bb = R[(size_t)j * (k + 1) + j + 1];
-            const double t = std::hypot(std::abs(a), std::abs(bb));
-            if (!(t > 0.0)) continue;
-            const cd cs = a / t, sn = bb / t;          // rotation mapping (a, b) to (t, 0)
-            for (int q = j; q < k; ++q) {
-                const cd x = R[(size_t)q * (k + 1) + j], y = R[(size_t)q * (k + 1) + j + 1];
-                R[(size_t)q * (k + 1) + j] = std::conj(cs) * x + std::conj(sn) * y;
-                R[(size_t)q * (k + 1) + j + 1] = -sn * x + cs * y;
+            cd* qj = Q.data() + (size_t)j * (k + 1);
+            for (int i = 0; i < j; ++i) {
+                const cd* qi = Q.data() + (size_t)i * (k + 1);
+                cd dot = 0.0;
+                for (int q = 0; q <= k; ++q) dot += std::conj(qi[q]) * qj[q];
+                R[(size_t)j * k + i] = dot;
+                for (int q = 0; q <= k; ++q) qj[q] -= dot * qi[q];
             }
-            const cd x = g[j], y = g[j + 1];
-            g[j] = std::conj(cs) * x + std::conj(sn) * y;
-            g[j + 1] = -sn * x + cs * y;
+            double nrm = 0.0;
+            for (int q = 0; q <= k; ++q) nrm += std::norm(qj[q]);
+            nrm = std::sqrt(nrm);
+            if (!(nrm > 1e-12 * hnorm)) break;   // rank lost: recycle the leading j columns
+            R[(size_t)j * k + j] = nrm;
+            for (int q = 0; q <= k; ++q) qj[q] /= nrm;
+            kk = j + 1;
         }
-        std::vector<cd> z(k);
-        for (int i = k - 1; i >= 0; --i) {
-            cd sacc = g[i];
-            for (int j = i + 1; j < k; ++j) sacc -= R[(size_t)j * (k + 1) + i] * z[j];
-            const cd d = R[(size_t)i * (k + 1) + i];
-            z[i] = std::abs(d) > 0.0 ? sacc / d : 0.0;
+        if (kk < 1) continue;
+        // keep the leading kk columns; V_{kk+1} spans them (Hessenberg structure)
+        std::vector<cd> Qk((size_t)(kk + 1) * kk), Rk((size_t)kk * kk);
+        for (int j = 0; j < kk; ++j) {
+            for (int q = 0; q <= kk; ++q) Qk[(size_t)j * (kk + 1) + q] = Q[(size_t)j * (k + 1) + q];
+            for (int i = 0; i <= j; ++i) Rk[(size_t)j * kk + i] = R[(size_t)j * k + i];
         }
-        for (int i = 0; i <= k; ++i) {
+        std::vector<cd> av(kk, 0.0);
+        for (int i = 0; i < kk; ++i)
+            for (int q = 0; q <= kk; ++q)
+                av[i] += std::conj(Qk[(size_t)i * (kk + 1) + q]) * cd(c[(size_t)r * nv + q].x, c[(size_t)r * nv + q].y);
+        for (int q = 0; q <= kk; ++q) {
             cd acc = 0.0;
-            for (int j = 0; j < k; ++j) acc += Hm[(size_t)j * (k + 1) + i] * z[j];
-            tt[(size_t)r * nv + i] = make_double2(acc.real(), acc.imag());
+            for (int i = 0; i < kk; ++i) acc += Qk[(size_t)i * (kk + 1) + q] * av[i];
+            e[(size_t)r * nv + q] = make_double2(acc.real(), acc.imag());
         }
-        for (int j = 0; j < k; ++j) zt[(size_t)r * nv + j] = make_double2(z[j].real(), z[j].imag());
+        aug.k[r] = kk;
+        aug.Qh[r] = std::move(Qk);
+        aug.R[r] = std::move(Rk);
+        aug.a[r] = std::move(av);
     }
-    HIPCHK(hipMemcpyAsync(w.h2, tt.data(), tt.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
-    HIPCHK(hipMemcpyAsync(w.y, zt.data(), zt.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
+    HIPCHK(hipMemcpyAsync(w.h2, e.data(), e.size() * sizeof(double2), hipMemcpyHostToDevice, H->st));
     HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_update(w.basis, nv, w.h2, b, nrhs, n, H->st)));
-    HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(w.basis, nv, w.y, w.psi0, nrhs, n, 0, H->st)));
     HIPCHK(hipStreamSynchronize(H->st));
-    have_psi0 = true;
+    std::swap(w.basis, w.basis_old);
+    aug.V = w.basis_old;
+    aug.nv = nv;
     return HELM_OK;
 }
 
@@ -806,7 +904,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     std::vector<double> est0;      // GMRES residual estimates at the end of the first cycle
     bool floor_used = false;       // the first cycle ended at the recorded floor
     std::vector<std::vector<cd>> hess;   // Hessenberg columns of the last cycle (reduced)
-    bool have_psi0 = false;        // w.psi0 holds a correction for the coming cycle
+    Aug aug;                       // recycled space of a restart (reduced)
     for (int cycle = 0; used < H->max_iter; ++cycle) {
         // explicit FP64 residual of the current iterate (u = 0 in cycle 0: r = f)
         if (cycle == 0)
@@ -858,7 +956,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
             b = w.red;
-            if (cycle > 0) CHK(project_previous(H, nrhs, n, w.red, hess, its, have_psi0));
+            if (cycle > 0) CHK(build_aug(H, nrhs, n, w.red, hess, its, aug));
         }
         CHK(norms(H, b, nrhs, n, bn));
         if (trace_on())
@@ -877,15 +975,8 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
         }
         // GMRES on op(y) = b; the solution increment is P y (+ u~)
         CHK(gmres_cycle(H, nrhs, n, b, bn, target, H->max_iter - used, w.w, its, resid,
-                        reduced ? &hess : nullptr));
-        if (have_psi0) {
-            // the correction taken from the previous cycle's space joins this cycle's psi
-            std::vector<double2> ones(nrhs, make_double2(1.0, 0.0));
-            HIPCHK(hipMemcpyAsync(w.h1, ones.data(), nrhs * sizeof(double2), hipMemcpyHostToDevice, H->st));
-            HIPCHK(TIMED(H, helm::K_GMRES, helm::launch_lincomb(w.psi0, 1, w.h1, w.w, nrhs, n, 1, H->st)));
-            HIPCHK(hipStreamSynchronize(H->st));
-            have_psi0 = false;
-        }
+                        reduced ? &hess : nullptr, aug.nv > 0 ? &aug : nullptr));
+        aug = Aug();
         if (cycle == 0) est0 = resid;
         int kmax = 0;
         for (int r = 0; r < nrhs; ++r) { total[r] += its[r]; kmax = std::max(kmax, its[r]); }
