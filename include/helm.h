@@ -113,10 +113,11 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
  * elimination, plane after plane (the blocks of all slabs of one plane together).  2-D:
  * computed in FP64, stored in FP64 (HELM_C128) or rounded to complex64.  3-D HELM_C128:
  * FP64 with partial pivoting over the whole column.  3-D HELM_MIXED_C64: complex64 with
- * FP32 accumulation, pivoting inside the 64 x 64 diagonal blocks only (their inverses in
- * FP64); if a diagonal block is singular or its 1-norm condition exceeds 1e6 the
- * factorisation is redone by the FP64 route and rounded (helm_get_factor_path tells
- * which ran).
+ * FP32 accumulation over column blocks of 128, each diagonal block inverted in FP64 from
+ * its 64 x 64 sub-blocks with pivoting inside those only; if a diagonal block is singular
+ * or its 1-norm condition exceeds 1e6 the factorisation is redone by the FP64 route and
+ * rounded (helm_get_factor_path tells which ran).  Strips or slabs with identical
+ * operators share one factorisation in every mode (helm_get_factor_slots).
  * HELM_ESINGULAR if a pivot is zero or not finite.
  */
 helm_status helm_factor(helm_t H);
@@ -150,7 +151,9 @@ helm_status helm_autotune(helm_t H, int nrhs, const void* rhs, const int* cand, 
  * cycle starts from u~ = P r instead of the strip solves of Algorithm 2: r - A P r lives
  * on the same interface columns (Sec. 2.1), and the sweep also removes what the
  * complex64 strip solves leave off those columns; this application of P counts as one
- * iteration.
+ * iteration.  When the first cycle ran 16 or more iterations, a later cycle also keeps
+ * its new directions orthogonal to the images of the previous cycle's Krylov basis and
+ * minimises over both spaces (Krylov recycling; fewer iterations, same stopping rule).
  *   rhs     device, nrhs * N_y * N_x complex128 (padded grid)
  *   u       device, same shape, output
  *   iters   host, nrhs ints (may be NULL): GMRES iterations (applications of A P, plus
@@ -249,8 +252,9 @@ helm_status helm_get_partition(helm_t H, int* beta, int* strip_first, int* strip
 helm_status helm_get_factor_slots(helm_t H, int* slots, int* strip_slot);
 
 /* Which factorisation produced the stored 3-D slab inverses (host int):
- *   1  complex64 blocked Gauss-Jordan with pivoting inside the 64 x 64 diagonal blocks
- *      (HELM_MIXED_C64, every diagonal block inverted with a 1-norm condition <= 1e6),
+ *   1  complex64 blocked Gauss-Jordan with pivoting inside the 64 x 64 diagonal
+ *      sub-blocks (HELM_MIXED_C64, every diagonal block inverted with a 1-norm
+ *      condition <= 1e6),
  *   0  FP64 Gauss-Jordan with partial pivoting over the whole column (HELM_C128, a
  *      complex64 attempt that met a singular or ill-conditioned diagonal block, and 2-D).
  * HELM_ESTATE before helm_factor. */
