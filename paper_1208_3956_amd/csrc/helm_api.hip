@@ -1297,6 +1297,15 @@ helm_status factor3(helm_t H) {
     a.cy = H->t.cy; a.by = H->t.by; a.k2 = H->t.k2;
     a.ih2 = 1.0 / (g.h * g.h);
     int herr = 0;
+    // the sweeps read the stored complex64 inverses in 16-row panels (one contiguous run per
+    // 16-row tile of a plane product instead of 16-entry pieces of every column)
+    auto panelize = [&](void* Fp, void* work) -> hipError_t {
+        auto run = [&]() {
+            return helm::launch_factor3_panelize(static_cast<float2*>(Fp), (size_t)g.Ny * BB, nf, g.Ny, g.Bp,
+                                                 static_cast<float2*>(work), H->st);
+        };
+        return TIMED(H, helm::K_FACTOR_CHUNKS, run());
+    };
     if (single) {
         // complex64 blocked Gauss-Jordan in place in the stored factor; a diagonal block
         // that is singular or ill-conditioned sends the whole factorisation to the FP64
@@ -1356,6 +1365,10 @@ helm_status factor3(helm_t H) {
             std::fprintf(stderr, "[helm] 3-D complex64 blocked Gauss-Jordan: %s\n",
                          herr ? "ill-conditioned diagonal block, redone in FP64" : "accepted");
         if (!herr) {
+            void* pw = nullptr;
+            if ((st = alloc(&pw, (size_t)nf * BB * sizeof(float2))) != HELM_OK) { dfree(F); return st; }
+            if ((e = panelize(F, pw)) != hipSuccess) { dfree(F); HIPCHK(e); }
+            HIPCHK(hipStreamSynchronize(H->st));
             H->F = F;
             H->factored = true;
             return HELM_OK;
@@ -1386,6 +1399,11 @@ helm_status factor3(helm_t H) {
     herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
+    if (single && !herr) {
+        // S (nf Bp^2 complex128 entries) is free now and holds the panel scratch
+        if ((e = panelize(F, S)) != hipSuccess) { dfree(F); HIPCHK(e); }
+        HIPCHK(hipStreamSynchronize(H->st));
+    }
     H->F = F;
     if (herr) return fail(H, HELM_ESINGULAR, "zero or non-finite pivot in a slab factorisation");
     H->factored = true;

@@ -230,6 +230,10 @@ size_t factor3_panel_width();
 // stored factor F ([slab][plane][Bp*Bp], slab stride `stride`), one plane of the slabs
 // s0 .. s0 + ns - 1 per call (disjoint slab sets may run on different streams)
 size_t factor3_f32_work_bytes(int J, int Bp);
+// stored complex64 slab inverses (J slots of Ny planes, slot stride `stride`) rewritten,
+// plane by plane, from column-major into the 16-row panels the sweeps read; work holds
+// J Bp^2 complex64 entries
+hipError_t launch_factor3_panelize(float2* F, size_t stride, int J, int Ny, int Bp, float2* work, hipStream_t st);
 hipError_t launch_factor3_plane_f32(const Fac3Args& a, int l, float2* F, size_t stride, void* work, int* err,
                                     hipStream_t st, int s0, int ns);
 template <typename T>

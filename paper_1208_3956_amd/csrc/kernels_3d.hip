@@ -430,7 +430,9 @@ __global__ void __launch_bounds__(256) k3_rhs0(Solve3Args<T> a, cplx<T>* __restr
     Tw[e] = (i < a.B && r < a.nrhs) ? gather3<T>(a, r, 0, i) : cmk<cplx<T>>(0, 0);
 }
 
-// Z = G X for a 16-row x 16-column tile: G column-major Bp x Bp, X [k][RP].  The k range
+// Z = G X for a 16-row x 16-column tile: G Bp x Bp, column-major (complex128) or in 16-row
+// panels (complex64: entry (i, k) at (i / 16) 16 Bp + 16 k + i % 16, so that the 16 rows of
+// a tile are one contiguous run of 16 Bp entries), X [k][RP].  The k range
 // is cut into blocks of 16; wave w of NW3 takes blocks w, w + NW3, ... (several waves per
 // SIMD hide the load latency; each wave also loads its next block before it multiplies
 // the current one).  The NW3 partial tiles are added through LDS.  Returns, for thread
@@ -449,13 +451,13 @@ __device__ inline float2 tile_product(const float2* __restrict__ G, const float2
     // x3 = sum (Gr + Gi)(Xr + Xi); Re = x1 - x2, Im = x3 - x1 - x2 (two chains of each for
     // independent MFMAs)
     mf4 x1a = {0.f, 0.f, 0.f, 0.f}, x2a = x1a, x3a = x1a, x1b = x1a, x2b = x1a, x3b = x1a;
-    const float2* gp = G + (size_t)q4 * Bp + i0 + n;
+    const float2* gp = G + (size_t)(i0 / 16) * 16 * Bp + 16 * q4 + n;
     const float2* xp = X + (size_t)q4 * RP + r0 + n;
     float2 g[4], x[4], gn[4], xn[4];
     auto load = [&](int b, float2 (&gg)[4], float2 (&xx)[4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            gg[u] = gp[(size_t)(16 * b + 4 * u) * Bp];
+            gg[u] = gp[(size_t)(16 * b + 4 * u) * 16];
             xx[u] = xp[(size_t)(16 * b + 4 * u) * RP];
         }
     };
@@ -564,7 +566,40 @@ __global__ void __launch_bounds__(NT3) k3_bwd(Solve3Args<T> a, int l) {
     if (i < a.B && r < a.nrhs) scatter3<T>(a, r, l, i, x);
 }
 
+// The complex64 inverses of plane l of the J slots (column-major, slot stride `stride`)
+// written to dst[s][Bp^2] in the 16-row panel layout of the sweeps (destination order:
+// panel, column, row within the panel; the reads are 16-entry runs of a column).
+__global__ void __launch_bounds__(256) k3_panelize(const float2* __restrict__ F, size_t stride, int l, int Bp,
+                                                  float2* __restrict__ dst) {
+    const size_t BB = (size_t)Bp * Bp, PW = (size_t)16 * Bp;
+    const float2* src = F + blockIdx.y * stride + (size_t)l * BB;
+    float2* d = dst + blockIdx.y * BB;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < BB; e += (size_t)gridDim.x * 256) {
+        const size_t p = e / PW, k = (e % PW) / 16, ii = e % 16;
+        d[e] = src[k * Bp + 16 * p + ii];
+    }
+}
+
+// dst[s][Bp^2] back into plane l of slot s
+__global__ void __launch_bounds__(256) k3_plane_back(float2* __restrict__ F, size_t stride, int l, int Bp,
+                                                    const float2* __restrict__ src) {
+    const size_t BB = (size_t)Bp * Bp;
+    float2* d = F + blockIdx.y * stride + (size_t)l * BB;
+    const float2* q = src + blockIdx.y * BB;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < BB; e += (size_t)gridDim.x * 256) d[e] = q[e];
+}
+
 }  // namespace
+
+hipError_t launch_factor3_panelize(float2* F, size_t stride, int J, int Ny, int Bp, float2* work, hipStream_t st) {
+    const size_t BB = (size_t)Bp * Bp;
+    const unsigned nb = (unsigned)std::min<size_t>((BB + 255) / 256, 2048);
+    for (int l = 0; l < Ny; ++l) {
+        hipLaunchKernelGGL(k3_panelize, dim3(nb, J), dim3(256), 0, st, F, stride, l, Bp, work);
+        hipLaunchKernelGGL(k3_plane_back, dim3(nb, J), dim3(256), 0, st, F, stride, l, Bp, work);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_factor3_plane(const Fac3Args& a, int l, const double2* Gprev, double2* S,
                                 double2* Tm, double2* Cm, int* perm, int* pi, int* err,
