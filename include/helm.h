@@ -116,7 +116,8 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
  * FP32 accumulation over column blocks of 128, each diagonal block inverted in FP64 from
  * its 64 x 64 sub-blocks with pivoting inside those only; if a diagonal block is singular
  * or its 1-norm condition exceeds 1e6 the factorisation is redone by the FP64 route and
- * rounded (helm_get_factor_path tells which ran).  Strips or slabs with identical
+ * rounded (helm_get_factor_path tells which ran; the environment variable
+ * HELM_FACTOR3_FP64=1 selects that route from the start).  Strips or slabs with identical
  * operators share one factorisation in every mode (helm_get_factor_slots).
  * HELM_ESINGULAR if a pivot is zero or not finite.
  */

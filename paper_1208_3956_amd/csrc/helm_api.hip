@@ -1308,7 +1308,10 @@ helm_status factor3(helm_t H) {
         // one timed unit
         return TIMED(H, helm::K_OTHER, run());
     };
-    if (single) {
+    // HELM_FACTOR3_FP64=1 sends a complex64 factorisation straight to the FP64 route (the one
+    // an ill-conditioned diagonal block would take), so that route can be exercised
+    const char* force = std::getenv("HELM_FACTOR3_FP64");
+    if (single && !(force && force[0] == '1')) {
         // complex64 blocked Gauss-Jordan in place in the stored factor; a diagonal block
         // that is singular or ill-conditioned sends the whole factorisation to the FP64
         // Gauss-Jordan with partial pivoting over the whole column below

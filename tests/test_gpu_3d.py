@@ -169,3 +169,27 @@ def test_complex64_slab_factor_multiblock(n, J, s):
     ref = np.stack([lu.solve(rk.ravel()).reshape(rk.shape) for rk in r])
     assert _rel(x, ref) < TOL_C64, _rel(x, ref)
     H.close()
+
+
+def test_complex64_fp64_route_rounded(case, monkeypatch):
+    """The route a complex64 factorisation takes after an ill-conditioned diagonal block
+    (FP64 Gauss-Jordan with pivoting over the whole column, rounded to complex64, then
+    stored in the 16-row panels of the sweeps), forced from the start: slab solves against
+    the oracle's and a solve against the direct solution, at the complex64 bars."""
+    wl, g, A, S = case
+    monkeypatch.setenv("HELM_FACTOR3_FP64", "1")
+    H = _gpu(wl, prec="mixed", mode="reduced")
+    assert H.factor_path == 0
+    rng = np.random.default_rng(9)
+    for s in range(g.J):
+        r = _rand(rng, (3,) + g.strip_shape(g.strips[s]))
+        x = H.strip_solve(s, _t(r)).cpu().numpy()
+        ref = np.stack([S.solve(s, rk) for rk in r])
+        assert _rel(x, ref) < TOL_C64, (s, _rel(x, ref))
+    f = wl.rhs()
+    res = H.solve(_t(f), tol=1e-6)
+    ud = solve_direct(g, f, A)
+    assert res.status == 0 and max(res.relres) <= 1e-6
+    for k in range(f.shape[0]):
+        assert _rel(res.u.cpu().numpy()[k], ud[k]) < TOL_FIELD
+    H.close()
