@@ -10,7 +10,12 @@ Conventions (0-based; the paper counts from 1):
     paper gives no profile; the reading used here is sigma(xi) = sigma_max
     (xi/(w h))^p with depth xi measured from the layer's inner edge, the edge at a
     half-point, layer points at xi = (m - 1/2) h and half-points at xi = m h, and
-    sigma_max = s0 c_ref / (w h) with c_ref the largest wave speed.
+    sigma_max = s0 c_ref / (w h) with c_ref the largest wave speed.  The outer PML
+    (which belongs to the global operator A and so to the solution) and the interface
+    pads (which belong only to the strip operators A^(j), i.e. to the preconditioner)
+    take their own strengths: s0 and s0_iface.  Unless given, s0_iface = 2.5 w: the pads
+    then have the same damping per cell whatever their width, sigma_max h / c_ref = 2.5
+    (chosen with this oracle on the constant-medium study of Table 4, Sec. 4.4).
   * Strips (Sec. 2.2): interfaces at half-points.  beta[0] = 0, beta[J] = N_x and, for
     0 < s < J, strip s-1 ends at column beta[s]-1 and strip s starts at column beta[s]
     (the paper's b_j = x_{beta_j + 1/2} in 1-based counting).  Core of strip s (0-based
@@ -28,6 +33,10 @@ from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
 
 import numpy as np
+
+
+# interface pads: sigma_max h / c_ref unless their strength is given
+PAD_S0_PER_CELL = 2.5
 
 
 def _sigma(depth_cells: np.ndarray, width: int, h: float, sigma_max: float, power: float) -> np.ndarray:
@@ -73,6 +82,8 @@ class Geometry:
     beta: np.ndarray = None        # length J+1
     strips: List[StripGeom] = field(default_factory=list)
     cref: Optional[float] = None   # PML reference speed; None -> max(c)
+    s0_iface: Optional[float] = None  # strength of the interface pads (strip operators
+                                      # only); None: PAD_S0_PER_CELL * w
     n_z: int = 0                   # 3-D (Sec. 2.2, 7-point stencil): interior points along z;
                                    # 0 for the 2-D problem.  c is then (n_z, n_y, n_x)
 
@@ -122,8 +133,14 @@ class Geometry:
         return (li[:, None] * self.n_x + ii[None, :])
 
     # ---------------------------------------------------------------- PML tables
-    def sigma_max(self, width: int) -> float:
-        return self.s0 * self.c_ref / (width * self.h) if width > 0 else 0.0
+    @property
+    def s0_pad(self) -> float:
+        """Strength s0 of the interface pads."""
+        return PAD_S0_PER_CELL * self.w if self.s0_iface is None else float(self.s0_iface)
+
+    def sigma_max(self, width: int, s0: Optional[float] = None) -> float:
+        s0 = self.s0 if s0 is None else s0
+        return s0 * self.c_ref / (width * self.h) if width > 0 else 0.0
 
     def outer_depth(self, pos: np.ndarray, N: int) -> np.ndarray:
         """Depth (in cells) of position `pos` (points integer, half-points x.5) inside the
@@ -148,7 +165,7 @@ class Geometry:
             pos = st.a + np.arange(st.W, dtype=float)
         depth_out = self.outer_depth(pos, self.N_x)
         sig = _sigma(depth_out, self.w_out, self.h, self.sigma_max(self.w_out), self.power)
-        smax_pad = self.sigma_max(self.w)
+        smax_pad = self.sigma_max(self.w, self.s0_pad)
         if st.left_pad:
             edge = st.core[0] - 0.5
             m = pos < edge
@@ -202,7 +219,8 @@ def partition(n_x: int, w_out: int, J: int, w: int, rule: str = "interior") -> n
 
 def make_geometry(c: np.ndarray, omega: float, h: float, w_out: int, w: int, J: int,
                   power: float = 2.0, s0: float = 10.0, beta: Optional[Sequence[int]] = None,
-                  rule: str = "interior", cref: Optional[float] = None) -> Geometry:
+                  rule: str = "interior", cref: Optional[float] = None,
+                  s0_iface: Optional[float] = None) -> Geometry:
     c = np.asarray(c, dtype=float)
     n_z = 0
     if c.ndim == 3:
@@ -224,7 +242,8 @@ def make_geometry(c: np.ndarray, omega: float, h: float, w_out: int, w: int, J: 
     for s in range(1, J):
         if b[s] - 1 < w_out or b[s] + 1 > w_out + n_x - 1:
             raise ValueError("interfaces must lie inside the interior (outside the outer PML)")
-    g = Geometry(n_x, n_y, w_out, w, J, h, omega, c, power, s0, b, cref=cref, n_z=n_z)
+    g = Geometry(n_x, n_y, w_out, w, J, h, omega, c, power, s0, b, cref=cref, n_z=n_z,
+                 s0_iface=s0_iface)
     for s in range(J):
         lp = s > 0
         rp = s < J - 1
@@ -239,4 +258,4 @@ def make_geometry(c: np.ndarray, omega: float, h: float, w_out: int, w: int, J: 
 
 def geometry_from_workload(wl) -> Geometry:
     return make_geometry(wl.c, wl.omega, wl.h, wl.w_out, wl.w, wl.J, wl.pml_power, wl.pml_s0,
-                         wl.beta)
+                         wl.beta, s0_iface=wl.pml_iface_s0)

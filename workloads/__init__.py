@@ -38,7 +38,9 @@ class Workload:
     J        : number of strips along x
     src      : list of (i, l) interior source indices; f = 1/h^2 at each
     pml_power, pml_s0 : PML profile sigma(xi) = sigma_max (xi/(w h))^p with
-               sigma_max = s0 c_ref / (w h); p = pml_power, s0 = pml_s0
+               sigma_max = s0 c_ref / (w h); p = pml_power, s0 = pml_s0 (outer PML)
+    pml_iface_s0 : s0 of the interface pads (they enter only the strip operators);
+               None: the library's default, 2.5 times the pad width
     """
     name: str
     c: np.ndarray
@@ -51,6 +53,7 @@ class Workload:
     pml_power: float = 2.0
     pml_s0: float = 10.0
     tol: float = 1e-6
+    pml_iface_s0: Optional[float] = None
     precision: str = "c128"
     beta: Optional[List[int]] = None
     extra: dict = field(default_factory=dict)
