@@ -6,10 +6,11 @@
 One step = factor every padded strip (helm_factor) + solve all right-hand sides to a
 1e-6 relative residual (helm_solve): the whole hot path on the inputs already resident
 in HBM.  Metric: right-hand sides x interior grid points per second.  Prints one JSON
-line.  One untimed step with HIP events around every hot-kernel launch gives the per-class
-breakdown and names the dominant kernel class; during the timed steps only that class is
-bracketed with events on the solver's stream (helm_set_kernel_timing), so its average
-launch duration is measured live over the timed region while the rest runs undisturbed.
+line.  The timed steps run the configured path untouched (in reduced mode each GMRES
+iteration replays Algorithm 3 from a HIP graph).  Then one step with HIP events around
+every hot-kernel launch gives the per-class breakdown and names the dominant kernel class,
+and a few more steps bracket only that class with events on the solver's stream
+(helm_set_kernel_timing) for its average launch duration.
 """
 from __future__ import annotations
 
@@ -44,7 +45,14 @@ def parse():
     p.add_argument("--tune-candidates", default="16,24,32,40,48",
                    help="chunk sizes the autotuner times (2-D)")
     p.add_argument("--tol", type=float, default=1e-6)
+    p.add_argument("--roofline-steps", type=int, default=2,
+                   help="steps run after the timed ones with the dominant kernel class event-timed")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-baseline", default="sample", choices=["sample", "full"],
+                   help="sample: re-time a bounded oracle sample and scale the committed record of the "
+                        "oracle's whole job; full: run the oracle's whole job now (minutes)")
+    p.add_argument("--oracle-record-out", default=None,
+                   help="with --cpu-baseline full: also write the job record (Markdown) here")
     p.add_argument("--no-c128-leg", action="store_true",
                    help="skip the complex128 comparison legs (batched and one RHS per solve)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -99,58 +107,170 @@ def phase_flops(H, wl, nrhs):
     return fl
 
 
-def cpu_baseline(wl, iters_mean, budget_s=10.0):
-    """The FP64 oracle on a bounded sample of the same workload, scaled to the job.
+def _oracle_solve_one(k):
+    """Worker of the all-cores leg: the oracle's DD-GMRES on right-hand side k with the
+    factorisations inherited from the parent (fork)."""
+    from oracle.solve import solve_dd_reduced
+    g, A, S, f = _ORACLE_CTX
+    t = time.time()
+    r = solve_dd_reduced(g, f[k], 1e-6, S=S, A=A)
+    return k, time.time() - t, r.iters, r.relres
 
-    Sample: assemble the global operator, factor padded strips with SuperLU (two solves
-    each) for about `budget_s` seconds, and time 2 global residual evaluations.  One application of Algorithm 3
-    is 2(J-1) strip solves plus 2 residual evaluations; the job is J strip factorisations
-    plus, per right-hand side, (mean GPU iterations + 2) applications (the +2 standing for
-    Algorithms 2 and 4)."""
+
+_ORACLE_CTX = None
+
+
+def _strip_pieces(g, k2, strips, nsolve=2):
+    """SuperLU factorisation of the given strips and nsolve solves each (seconds, means)."""
     import numpy as np
     import scipy.sparse.linalg as spla
-    from oracle.assemble import assemble_global, assemble_strip
+    from oracle.assemble import assemble_strip
+    rng = np.random.default_rng(0)
+    tf, ts = [], []
+    for s in strips:
+        st = g.strips[s]
+        ta = time.time()
+        lu = spla.splu(assemble_strip(g, st, k2).tocsc(), permc_spec="COLAMD")
+        tf.append(time.time() - ta)
+        for _ in range(nsolve):
+            r = rng.standard_normal(int(np.prod(g.strip_shape(st)))) + 0j
+            ta = time.time()
+            lu.solve(r)
+            ts.append(time.time() - ta)
+    return float(np.mean(tf)), float(np.mean(ts))
+
+
+SAMPLE_STRIPS = (0, 1, 2)
+
+
+def oracle_job(wl, max_cores=16):
+    """The FP64 oracle's whole job on the host, as it stands (scipy SuperLU, one thread per
+    process): assemble the global operator, factor every padded strip (StripSolvers), then
+    the reduced DD-GMRES of Algorithm 5 on right-hand side 0 end to end with its own
+    iteration count (1 core); then C = min(cores, max_cores) processes forked after the
+    factorisation each solve one further right-hand side (all cores).  Also times the
+    bounded sample the default run re-times (SAMPLE_STRIPS factorisations and solves)."""
+    global _ORACLE_CTX
+    import multiprocessing as mp
+    from oracle.assemble import assemble_global
+    from oracle.dd import StripSolvers
     from oracle.grid import geometry_from_workload
+    from oracle.solve import solve_dd_reduced
 
     t0 = time.time()
     g = geometry_from_workload(wl)
     A = assemble_global(g)
-    k2 = g.k2()
-    rng = np.random.default_rng(0)
-    t_fac, t_ss = [], []
-    # strips in a fixed order until the sample has run about `budget_s` seconds (at least 2)
-    order = [(k * 7919) % g.J for k in range(g.J)]
-    for s in order:
-        st = g.strips[s]
-        ta = time.time()
-        lu = spla.splu(assemble_strip(g, st, k2).tocsc(), permc_spec="COLAMD")
-        t_fac.append(time.time() - ta)
-        for _ in range(2):
-            r = rng.standard_normal(int(np.prod(g.strip_shape(st)))) + 0j
-            ta = time.time()
-            lu.solve(r)
-            t_ss.append(time.time() - ta)
-        if len(t_fac) >= 2 and time.time() - t0 > budget_s:
-            break
-    u = rng.standard_normal(int(np.prod(g.field_shape))) + 0j
+    t_asm = time.time() - t0
+    t_sfac, t_ssol = _strip_pieces(g, g.k2(), SAMPLE_STRIPS)
     ta = time.time()
-    for _ in range(2):
-        _ = u - A @ u
-    t_res = (time.time() - ta) / 2
-    t_fac_s = float(np.mean(t_fac))
-    t_ss_s = float(np.mean(t_ss))
-    t_ap = 2 * (g.J - 1) * t_ss_s + 2 * t_res
-    est = t_fac_s * g.J + wl.nrhs * (iters_mean + 2.0) * t_ap
-    return {
-        "value": wl.nrhs * wl.n_points / est, "unit": "RHS*gridpts/s", "cores": 1,
-        "kind": "oracle",
-        "sample": (f"oracle (scipy SuperLU, single thread) pieces on {wl.name}: {len(t_fac)} of {g.J} strip "
-                   f"factorisations ({t_fac_s:.2f} s each), {len(t_ss)} strip solves ({t_ss_s * 1e3:.1f} ms each), "
-                   f"2 global residuals ({t_res * 1e3:.0f} ms each); scaled to J factorisations + "
-                   f"nrhs x (mean GPU iterations {iters_mean:.1f} + 2) x [2(J-1) solves + 2 residuals]"),
-        "est_job_s": est,
-        "sample_wall_s": time.time() - t0,
-    }
+    S = StripSolvers(g)
+    t_fac = time.time() - ta
+    cores = max(1, min(max_cores, os.cpu_count() or 1))
+    nsolve = min(wl.nrhs, cores + 1)
+    f = wl.rhs(list(range(nsolve)))
+    ta = time.time()
+    r0 = solve_dd_reduced(g, f[0], 1e-6, S=S, A=A)
+    t_one = time.time() - ta
+    print(f"# oracle: assemble {t_asm:.1f} s, factor {g.J} strips {t_fac:.1f} s, one RHS {t_one:.1f} s "
+          f"({r0.iters} iterations)", file=sys.stderr, flush=True)
+    C = min(cores, nsolve - 1)
+    t_par, it_par = None, []
+    if C >= 2:
+        _ORACLE_CTX = (g, A, S, f)
+        old = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS")}
+        os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = "1"
+        try:
+            ta = time.time()
+            with mp.get_context("fork").Pool(C) as pool:
+                res = pool.map(_oracle_solve_one, range(1, C + 1))
+            t_par = time.time() - ta
+            it_par = [r[2] for r in res]
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+            _ORACLE_CTX = None
+        print(f"# oracle: {C} RHS on {C} processes in {t_par:.1f} s", file=sys.stderr, flush=True)
+    return {"workload": wl.name, "nrhs": wl.nrhs, "n_points": wl.n_points, "J": g.J,
+            "t_assemble_s": t_asm, "t_factor_all_s": t_fac, "t_one_rhs_s": t_one, "iters_rhs0": r0.iters,
+            "relres_rhs0": r0.relres, "cores": C if t_par else 1, "t_wall_C_rhs_s": t_par,
+            "iters_C_rhs": it_par, "sample_strips": list(SAMPLE_STRIPS), "sample_factor_s": t_sfac,
+            "sample_solve_s": t_ssol, "host_cpus": os.cpu_count(), "wall_s": time.time() - t0}
+
+
+def _job_values(rec, scale=1.0):
+    """Right-hand sides x points per second of the recorded oracle job (times x scale): one
+    core (solves one after another) and C cores (C solves at a time)."""
+    t_common = (rec["t_assemble_s"] + rec["t_factor_all_s"]) * scale
+    job1 = t_common + rec["nrhs"] * rec["t_one_rhs_s"] * scale
+    out = {"one_core": {"value": rec["nrhs"] * rec["n_points"] / job1, "cores": 1, "est_job_s": job1}}
+    if rec.get("t_wall_C_rhs_s"):
+        C = rec["cores"]
+        jobc = t_common + math.ceil(rec["nrhs"] / C) * rec["t_wall_C_rhs_s"] * scale
+        out["all_cores"] = {"value": rec["nrhs"] * rec["n_points"] / jobc, "cores": C, "est_job_s": jobc}
+    return out
+
+
+def oracle_record_path(wl):
+    return os.path.join(ROOT, "profiles", f"oracle_job_{wl.name}.md")
+
+
+def read_oracle_record(path):
+    """The JSON block of a recorded oracle job summary (Markdown)."""
+    text = open(path).read()
+    a = text.index("```json") + len("```json")
+    return json.loads(text[a:text.index("```", a)])
+
+
+def write_oracle_record(path, rec, argv):
+    with open(path, "w") as fh:
+        fh.write(f"# The CPU oracle's whole job on {rec['workload']}\n\n"
+                 f"command: `python {' '.join(argv)}` (host of the GPU box, {rec['host_cpus']} CPUs visible)\n\n"
+                 "Assembly of the global operator, SuperLU factorisation of every strip, reduced DD-GMRES "
+                 "to 1e-6 on right-hand side 0 (one process), then one right-hand side per forked process "
+                 "on `cores` processes.  `sample_*`: the bounded sample the default bench run re-times.\n\n"
+                 "```json\n" + json.dumps(rec, indent=1) + "\n```\n")
+
+
+def cpu_baseline(wl, mode):
+    """cpu_baseline of the bench line.  mode "full": the oracle's whole job now (several
+    minutes at 2000^2).  mode "sample": a bounded sample (SuperLU factorisation and solves of
+    SAMPLE_STRIPS, about 10 s) re-timed now, and the committed record of the whole oracle job
+    on this workload (profiles/oracle_job_<workload>.md, written by --cpu-baseline full on
+    the same kind of host) scaled by the ratio of the sample's time now to the same sample's
+    time in the record."""
+    if mode == "full":
+        rec = oracle_job(wl)
+        vals = _job_values(rec)
+        best = vals.get("all_cores", vals["one_core"])
+        return dict(value=best["value"], unit="RHS*gridpts/s", cores=best["cores"], kind="oracle",
+                    sample=(f"the oracle's whole job on {wl.name}, measured now: assembly, SuperLU factorisation "
+                            f"of all {rec['J']} strips, reduced DD-GMRES to 1e-6 on right-hand side 0 end to end "
+                            f"({rec['iters_rhs0']} iterations, 1 core), then right-hand sides 1..{rec['cores']} on "
+                            f"{rec['cores']} forked processes; scaled to {rec['nrhs']} right-hand sides"),
+                    **vals, record=rec)
+    path = oracle_record_path(wl)
+    t0 = time.time()
+    from oracle.grid import geometry_from_workload
+    g = geometry_from_workload(wl)
+    t_sfac, t_ssol = _strip_pieces(g, g.k2(), SAMPLE_STRIPS)
+    if not os.path.exists(path):
+        return {"value": None, "unit": "RHS*gridpts/s", "cores": 1, "kind": "oracle",
+                "sample": f"no record of the oracle's whole job on {wl.name} ({path} missing)"}
+    rec = read_oracle_record(path)
+    scale = (t_sfac + 2 * t_ssol) / (rec["sample_factor_s"] + 2 * rec["sample_solve_s"])
+    vals = _job_values(rec, scale)
+    best = vals.get("all_cores", vals["one_core"])
+    return dict(value=best["value"], unit="RHS*gridpts/s", cores=best["cores"], kind="oracle",
+                sample=(f"SuperLU factorisation and 2 solves of strips {list(SAMPLE_STRIPS)} of {wl.name} re-timed "
+                        f"now ({time.time() - t0:.1f} s; {scale:.2f}x their time in the record), scaling the "
+                        f"recorded whole oracle job: assembly, all {rec['J']} strip factorisations, reduced "
+                        f"DD-GMRES on right-hand side 0 ({rec['iters_rhs0']} iterations, 1 core) and right-hand "
+                        f"sides 1..{rec['cores']} on {rec['cores']} processes, scaled to {rec['nrhs']} right-hand "
+                        f"sides"),
+                **vals, host_scale=scale)
 
 
 KERNEL_SOURCES = ("paper_1208_3956_amd/csrc/kernels_solve.hip",
@@ -243,6 +363,7 @@ def c128_legs(wl, f, tol, plain_rhs=2):
     import torch
     from paper_1208_3956_amd import Helmholtz
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                  pml_iface_s0=wl.pml_iface_s0,
                   prec="c128", mode="reduced", device="cuda:0")
     if wl.dim == 2:
         H.autotune(f, reps=1, cache=None)     # factors with its own best chunk size
@@ -288,6 +409,7 @@ def batch_main(args):
     fs = [torch.from_numpy(wl.rhs()).to(dev) for wl in wls]
     streams = [torch.cuda.Stream(dev) for _ in wls]
     Hs = [Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                    pml_iface_s0=wl.pml_iface_s0,
                     prec=args.prec, mode=args.mode, chunk=args.chunk, device=dev, stream=s)
           for wl, s in zip(wls, streams)]
     pts = sum(f.shape[0] * wl.n_x * wl.n_y for wl, f in zip(wls, fs))
@@ -359,6 +481,7 @@ def main():
     print(f"# {wl.name}: padded {wl.N_x}x{wl.N_y}, J={wl.J}, nrhs={nrhs}, {args.prec}/{args.mode}",
           file=sys.stderr, flush=True)
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                  pml_iface_s0=wl.pml_iface_s0,
                   prec=args.prec, mode=args.mode, chunk=args.chunk, device=dev)
     tuned = None
     if args.chunk == 0 and wl.dim == 2:
@@ -374,14 +497,8 @@ def main():
         res = H.solve(f, args.tol)
         print(f"# warmup {k}: iters {sorted(set(res.iters))} relres {max(res.relres):.2e}",
               file=sys.stderr, flush=True)
-    # breakdown step: every hot-kernel class timed, names the dominant one
-    H.set_kernel_timing(True)
-    H.factor()
-    H.solve(f, args.tol)
-    torch.cuda.synchronize()
-    kt_all = H.kernel_times()
-    dom = max(PHASES, key=lambda k: kt_all[k][1])
-    H.set_kernel_timing(True, classes=[dom])
+    # timed steps: the configured path as a user runs it (reduced operator replayed from its
+    # HIP graph, no event timing)
     torch.cuda.synchronize()
     t_fac = 0.0
     t0 = time.perf_counter()
@@ -395,9 +512,24 @@ def main():
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    # breakdown step: every hot-kernel class timed with HIP events (kernel by kernel: the
+    # durations of events inside a graph replay cannot be read), names the dominant class
+    H.set_kernel_timing(True)
+    H.factor()
+    H.solve(f, args.tol)
+    torch.cuda.synchronize()
+    kt_all = H.kernel_times()
+    dom = max(PHASES, key=lambda k: kt_all[k][1])
+    # launch duration of the dominant class: further steps with only that class bracketed by
+    # events on the solver's stream, the rest undisturbed
+    H.set_kernel_timing(True, classes=[dom])
+    for k in range(args.roofline_steps):
+        H.factor()
+        H.solve(f, args.tol)
+    torch.cuda.synchronize()
     kt = H.kernel_times()
     H.set_kernel_timing(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
     pts = nrhs * wl.n_points
     value = pts / (ms_step / 1e3)
     solve_ms = ms_step - t_fac * 1e3 / args.steps
@@ -418,7 +550,10 @@ def main():
     roof = {"kernel": dom, "bound": "mfma", "arith": "fp32" if arith == "c64" else "fp64",
             "achieved": ach, "peak": peak, "unit": "TFLOP/s",
             "frac": ach / peak, "traffic": profiled_traffic(dom, wl, nrhs, args.prec),
-            "launches": cnt, "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl[dom]}
+            "launches": cnt, "avg_launch_us": avg_s * 1e6, "flops_per_launch": fl[dom],
+            "avg_launch_from": (f"HIP events around every {dom} launch on the solver's stream during "
+                                f"{args.roofline_steps} steps run after the timed ones (same inputs and "
+                                "kernels, reduced operator launched kernel by kernel)")}
     if dom == "phase_a":
         roof["algorithmic_bytes_per_launch"] = algorithmic_bytes(H, nrhs, args.prec)
     # the factorisation's MFMA use, from the breakdown step (whatever class dominates)
@@ -440,7 +575,8 @@ def main():
                    "pml_outer": wl.w_out, "pml_iface": wl.w, "prec": args.prec,
                    "mode": args.mode, "chunk_rows": H.chunk_rows, "tol": args.tol,
                    "autotune": tuned, "factor_path": H.factor_path if wl.dim == 3 else None,
-                   "factor_slots": H.factor_slots,
+                   "factor_slots": H.factor_slots, "pml_iface_s0": wl.pml_iface_s0 if wl.pml_iface_s0 is not None else "2.5 per pad cell",
+                   "graph_replay": args.mode == "reduced",
                    "step": "helm_factor + helm_solve"},
         "solve_only_value": pts / (solve_ms / 1e3), "solve_ms": solve_ms,
         "factor_ms": t_fac * 1e3 / args.steps,
@@ -461,7 +597,9 @@ def main():
         out["mixed_vs_c128_plain"] = (out["solve_only_value"]
                                       / out["c128"]["plain_one_rhs_per_solve"]["solve_only_value"])
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, float(np.mean(res.iters)))
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_baseline)
+        if args.cpu_baseline == "full" and args.oracle_record_out:
+            write_oracle_record(args.oracle_record_out, out["cpu_baseline"]["record"], sys.argv)
     print(json.dumps(out), flush=True)
 
 

@@ -64,7 +64,9 @@ typedef struct {
     int pml_outer;      /* outer PML width in cells, all faces (>= 1)                     */
     int pml_iface;      /* interface PML width w: pads on internal strip sides (>= 1)     */
     double pml_power;   /* profile sigma(xi) = sigma_max (xi / (w h))^power; default 2    */
-    double pml_s0;      /* sigma_max = pml_s0 * c_ref / (w h); default 10                */
+    double pml_s0;      /* outer PML: sigma_max = pml_s0 * c_ref / (w_out h); default 10.
+                           The outer PML is part of the global operator A, so it changes
+                           the solution u                                               */
     double pml_cref;    /* c_ref; <= 0 selects max(c)                                     */
     const int* beta;    /* host; NULL, or J-1 interface columns (0-based padded-grid
                            column where strip j+1 starts, strictly increasing)           */
@@ -83,6 +85,12 @@ typedef struct {
                            it in every GMRES iteration (its input is first copied into a
                            fixed buffer); 0: launch kernel by kernel.  Graphs are not used
                            while kernel timing is enabled                               */
+    double pml_iface_s0; /* interface pads: sigma_max = pml_iface_s0 * c_ref / (w h);
+                           < 0 (the default) selects 2.5 w, i.e. the same damping per cell
+                           sigma_max h / c_ref = 2.5 for every pad width.  The pads belong
+                           only to the strip operators A^(j) (Sec. 2.1, definition of
+                           Omega^(j)), i.e. to the preconditioner P: they change the
+                           iteration count, never the solution                          */
 } helm_opts;
 
 /* Default options for a 2-D problem of n_x x n_y interior points. */
@@ -283,6 +291,8 @@ helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* sol
  * enable is a bit mask of the classes to time (bit c = class c, 0xFF = all); launches of
  * the other classes are still counted.  0 disables timing.  Every timed launch costs two
  * event records on the stream, so timing only the classes of interest disturbs less.
+ * While timing is enabled the reduced operator is launched kernel by kernel, not replayed
+ * from its graph (the durations of events recorded by graph nodes cannot be read).
  */
 helm_status helm_set_kernel_timing(helm_t H, int enable);
 helm_status helm_get_kernel_times(helm_t H, int nclass, int* launches, double* total_ms);

@@ -45,6 +45,7 @@ class HelmOpts(ctypes.Structure):
         ("chunk", ctypes.c_int),
         ("stream", ctypes.c_void_p),
         ("graph", ctypes.c_int),
+        ("pml_iface_s0", ctypes.c_double),
     ]
 
 

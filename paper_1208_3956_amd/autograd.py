@@ -26,7 +26,8 @@ class HelmMisfit(torch.autograd.Function):
         c = (1.0 / torch.sqrt(m.detach())).cpu().numpy()
         H = Helmholtz(c, cfg["omega"], cfg["h"], cfg["J"], cfg.get("pml_outer", 16),
                       cfg.get("pml_iface", 8), cfg.get("pml_power", 2.0), cfg.get("pml_s0", 10.0),
-                      pml_cref=cfg["pml_cref"], prec=cfg.get("prec", "c128"),
+                      pml_cref=cfg["pml_cref"], pml_iface_s0=cfg.get("pml_iface_s0"),
+                      prec=cfg.get("prec", "c128"),
                       mode=cfg.get("mode", "full"), chunk=cfg.get("chunk", 0), device=src.device)
         try:
             H.factor()
@@ -44,5 +45,5 @@ class HelmMisfit(torch.autograd.Function):
 
 def misfit(m: torch.Tensor, src: torch.Tensor, rec, d: torch.Tensor, **cfg) -> torch.Tensor:
     """J(m) as a differentiable scalar; cfg: omega, h, J, pml_cref (required), pml_outer,
-    pml_iface, pml_power, pml_s0, prec, mode, chunk, tol."""
+    pml_iface, pml_power, pml_s0, pml_iface_s0, prec, mode, chunk, tol."""
     return HelmMisfit.apply(m, src, torch.as_tensor(rec, dtype=torch.int64), d, cfg)

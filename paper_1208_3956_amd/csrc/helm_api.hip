@@ -28,8 +28,10 @@ struct Work {
             *Hf = nullptr, *Ut = nullptr, *R = nullptr, *Tup = nullptr, *Tdn = nullptr;
     // interface-window fields of the reduced operator (v, g = psi - A v, w)
     double2 *Vw = nullptr, *Gw = nullptr, *Ww = nullptr;
-    // GMRES
-    int mcap = 0;
+    // GMRES.  gnrhs is the right-hand-side capacity of every buffer below and of R, Ut:
+    // they are laid out for the nrhs of each call ([k][nrhs][n]) and reallocated when a
+    // call brings more right-hand sides than they were sized for
+    int mcap = 0, gnrhs = 0;
     long n = 0;
     double2* basis = nullptr;
     double2* w = nullptr;
@@ -215,19 +217,20 @@ double outer_depth(const helm::Geom& g, double pos, int N) {
     const double lo = g.wout - 0.5, hi = N - g.wout - 0.5;
     return std::max(std::max(lo - pos, pos - hi), 0.0);
 }
-double smax_of(const helm::Geom& g, int width) {
-    return width > 0 ? g.s0 * g.cref / (width * g.h) : 0.0;
+double smax_of(const helm::Geom& g, int width, double s0) {
+    return width > 0 ? s0 * g.cref / (width * g.h) : 0.0;
 }
 cd alpha_outer(const helm::Geom& g, double pos, int N) {
-    return alpha_of(sigma_of(outer_depth(g, pos, N), g.wout, smax_of(g, g.wout), g.power), g.omega);
+    return alpha_of(sigma_of(outer_depth(g, pos, N), g.wout, smax_of(g, g.wout, g.s0), g.power), g.omega);
 }
 // alpha_x of the padded strip operator at global position pos (points integer, half-points
 // x.5): pad profile left of the left pad edge / right of the right pad edge, else global.
+// The pads take their own strength s0i: they enter only the strip operators.
 cd alpha_strip(const helm::Geom& g, const helm::Strip& s, double pos) {
     if (s.lpad && pos < s.core_lo - 0.5)
-        return alpha_of(sigma_of(s.core_lo - 0.5 - pos, g.w, smax_of(g, g.w), g.power), g.omega);
+        return alpha_of(sigma_of(s.core_lo - 0.5 - pos, g.w, smax_of(g, g.w, g.s0i), g.power), g.omega);
     if (s.rpad && pos > s.dom_hi - 0.5)
-        return alpha_of(sigma_of(pos - (s.dom_hi - 0.5), g.w, smax_of(g, g.w), g.power), g.omega);
+        return alpha_of(sigma_of(pos - (s.dom_hi - 0.5), g.w, smax_of(g, g.w, g.s0i), g.power), g.omega);
     return alpha_outer(g, pos, g.Nx);
 }
 
@@ -293,12 +296,13 @@ struct TimedScope {
 #define TIMED(H, cls, expr) ([&]() { TimedScope ts_(H, cls); return (expr); }())
 
 // ---------------------------------------------------------------- sweeps
+// yw: the strip solver's workspace (null: the handle's own, H->wk.Yw); kt: kernel timer
 template <typename T>
-helm_status strip_solve3(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
+helm_status strip_solve3(helm_t H, int s, int nrhs, const helm::IOSpec& io, void* yw, helm::KTimer* kt) {
     const auto& g = H->g;
     helm::Solve3Args<T> a;
     a.F = static_cast<const helm::cplx<T>*>(H->F) + (size_t)H->fidx[s] * g.Ny * g.Bp * g.Bp;
-    a.Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
+    a.Yw = static_cast<helm::cplx<T>*>(yw ? yw : H->wk.Yw);
     a.cy = H->t.cy;
     a.by = H->t.by;
     a.io = io;
@@ -310,25 +314,34 @@ helm_status strip_solve3(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
     a.Ny = g.Ny; a.Nz = g.Nz; a.W = g.strips[s].W; a.B = a.W * g.Nz; a.Bp = g.Bp;
     a.nrhs = nrhs; a.RP = rhs_pad16(nrhs); a.Nrow = g.Nrow();
     a.Tw = a.Yw + (size_t)g.Ny * g.Bp * a.RP;     // two planes after the Ny planes of Yw
-    HIPCHK(helm::launch_strip_solve3<T>(a, H->st, H->kt()));
+    HIPCHK(helm::launch_strip_solve3<T>(a, H->st, kt));
     return HELM_OK;
 }
 
 template <typename T>
-helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
-    if (H->g.dim == 3) return strip_solve3<T>(H, s, nrhs, io);
+helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io, void* yw, helm::KTimer* kt) {
+    if (H->g.dim == 3) return strip_solve3<T>(H, s, nrhs, io, yw, kt);
     const auto* F = static_cast<const helm::cplx<T>*>(H->F);
     const auto* Fc = static_cast<const helm::cplx<T>*>(H->Fc);
     const auto* Fs = static_cast<const helm::cplx<T>*>(H->Fs);
-    auto* Yw = static_cast<helm::cplx<T>*>(H->wk.Yw);
-    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, H->fidx[s], F, Fc, Fs, Yw, nrhs, io, H->st,
-                                       H->kt()));
+    auto* Yw = static_cast<helm::cplx<T>*>(yw ? yw : H->wk.Yw);
+    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, H->fidx[s], F, Fc, Fs, Yw, nrhs, io, H->st, kt));
     return HELM_OK;
 }
 
-helm_status strip_solve_any(helm_t H, int s, int nrhs, const helm::IOSpec& io) {
-    return H->prec == HELM_C128 ? strip_solve<double>(H, s, nrhs, io)
-                                : strip_solve<float>(H, s, nrhs, io);
+helm_status strip_solve_any(helm_t H, int s, int nrhs, const helm::IOSpec& io, void* yw = nullptr,
+                            bool timed = true) {
+    helm::KTimer* kt = timed ? H->kt() : nullptr;
+    return H->prec == HELM_C128 ? strip_solve<double>(H, s, nrhs, io, yw, kt)
+                                : strip_solve<float>(H, s, nrhs, io, yw, kt);
+}
+
+// Bytes of strip-solver workspace a solve of nrhs right-hand sides needs (the Yw buffer of
+// ensure_sweep_ws: 2-D [nrhs][Ny][WP]; 3-D Ny + 2 planes of [Bp][nrhs rounded up to 16])
+size_t strip_ws_bytes(helm_t H, int nrhs) {
+    const auto& g = H->g;
+    const size_t esz = H->prec == HELM_C128 ? sizeof(double2) : sizeof(float2);
+    return g.dim == 3 ? (size_t)(g.Ny + 2) * g.Bp * rhs_pad16(nrhs) * esz : (size_t)nrhs * g.Ny * WP * esz;
 }
 
 double2* trace(double2* base, int s, int k, int nrhs, long Nrow) {
@@ -551,11 +564,14 @@ struct Givens {
 
 helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     Work& w = H->wk;
-    if (w.basis && w.n == n && w.mcap >= mwant) return HELM_OK;
+    if (w.basis && w.n == n && w.mcap >= mwant && w.gnrhs >= nrhs) return HELM_OK;
     dfree(w.basis); dfree(w.w); dfree(w.h1); dfree(w.h2); dfree(w.nrm); dfree(w.partial);
     dfree(w.npartial); dfree(w.y); dfree(w.red); dfree(w.apin); dfree(w.basis_old);
+    dfree(w.R); dfree(w.Ut);
     w.basis = w.w = w.h1 = w.h2 = w.y = w.red = w.apin = w.partial = w.basis_old = nullptr;
+    w.R = w.Ut = nullptr;
     w.mcap_old = 0;
+    w.gnrhs = 0;
     w.nrm = w.npartial = nullptr;
     H->ws_epoch += 1;
     size_t freeb = 0, totb = 0;
@@ -575,8 +591,20 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     const int nb = helm::dots_blocks(std::max(n, H->g.Nrow() * H->g.Nx));
     CHK(dmalloc(H, &w.partial, (size_t)nb * nrhs * (m + 1) * sizeof(double2)));
     CHK(dmalloc(H, &w.npartial, (size_t)nb * nrhs * sizeof(double)));
+    CHK(dmalloc(H, &w.R, field_bytes(H, nrhs)));
+    CHK(dmalloc(H, &w.Ut, field_bytes(H, nrhs)));
     w.mcap = m;
     w.n = n;
+    w.gnrhs = nrhs;
+    return HELM_OK;
+}
+
+// Destroys the captured reduced operator once its last replay has completed.
+helm_status drop_graph(helm_t H) {
+    if (!H->ap_exec) return HELM_OK;
+    HIPCHK(H->st ? hipStreamSynchronize(H->st) : hipDeviceSynchronize());
+    HIPCHK(hipGraphExecDestroy(H->ap_exec));
+    H->ap_exec = nullptr;
     return HELM_OK;
 }
 
@@ -588,6 +616,8 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
         HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, H->g, nrhs, H->wk.PF, nullptr, out, H->st)));
         return HELM_OK;
     }
+    // kernel timing brackets launches with events, which a graph replay cannot time here
+    // (hipEventElapsedTime rejects events recorded by graph nodes): timed runs go eagerly
     if (!H->use_graph || H->timer) return apply_AP_reduced(H, nrhs, x, out);
     // graph replay: the captured launches read the fixed buffer apin and write `out`
     Work& w = H->wk;
@@ -595,7 +625,7 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
     const size_t bytes = (size_t)nrhs * H->g.Nrow() * 2 * (H->g.J - 1) * sizeof(double2);
     HIPCHK(hipMemcpyAsync(w.apin, x, bytes, hipMemcpyDeviceToDevice, H->st));
     if (!H->ap_exec || H->ap_nrhs != nrhs || H->ap_out != out || H->ap_epoch != H->ws_epoch) {
-        if (H->ap_exec) { HIPCHK(hipGraphExecDestroy(H->ap_exec)); H->ap_exec = nullptr; }
+        CHK(drop_graph(H));
         if (!H->cap_st) HIPCHK(hipStreamCreateWithFlags(&H->cap_st, hipStreamNonBlocking));
         // the captured work only reads buffers written before the replay on st; nothing is
         // executed during the capture itself
@@ -806,7 +836,8 @@ helm_status build_aug(helm_t H, int nrhs, long n, double2* b, const std::vector<
         dfree(w.basis_old);
         w.basis_old = nullptr;
         w.mcap_old = 0;
-        if (hipMalloc((void**)&w.basis_old, (size_t)nrhs * n * sizeof(double2) * (w.mcap + 1)) != hipSuccess) {
+        // the same capacity as w.basis (the two buffers are swapped below)
+        if (hipMalloc((void**)&w.basis_old, (size_t)w.gnrhs * n * sizeof(double2) * (w.mcap + 1)) != hipSuccess) {
             (void)hipGetLastError();
             w.basis_old = nullptr;
             return HELM_OK;                      // no room: a plain restart
@@ -894,10 +925,6 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     const bool reduced = H->mode == HELM_REDUCED && nred > 0;
     const long n = reduced ? g.Nrow() * nred : nfull;
     CHK(ensure_gmres_ws(H, nrhs, n, std::min(H->max_iter, reduced ? 60 : 30)));
-    if (!w.R) {
-        CHK(dmalloc(H, &w.R, field_bytes(H, nrhs)));
-        CHK(dmalloc(H, &w.Ut, field_bytes(H, nrhs)));
-    }
     std::vector<double> fn, rn;
     CHK(norms(H, f, nrhs, nfull, fn));
     // u is first written at the end of cycle 0 (u = correction), so it starts unset
@@ -910,6 +937,9 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     bool floor_used = false;       // the first cycle ended at the recorded floor
     std::vector<std::vector<cd>> hess;   // Hessenberg columns of the last cycle (reduced)
     Aug aug;                       // recycled space of a restart (reduced)
+    // an augmented cycle's Hessenberg matrix describes the projected operator
+    // (I - C C^H) M, not M, so only a cycle that was not itself augmented is recycled
+    bool prev_aug = false;
     for (int cycle = 0; used < H->max_iter; ++cycle) {
         // explicit FP64 residual of the current iterate (u = 0 in cycle 0: r = f)
         if (cycle == 0)
@@ -961,7 +991,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
             b = w.red;
-            if (cycle > 0) CHK(build_aug(H, nrhs, n, w.red, hess, its, aug));
+            if (cycle > 0 && !prev_aug) CHK(build_aug(H, nrhs, n, w.red, hess, its, aug));
         }
         CHK(norms(H, b, nrhs, n, bn));
         if (trace_on())
@@ -981,6 +1011,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
         // GMRES on op(y) = b; the solution increment is P y (+ u~)
         CHK(gmres_cycle(H, nrhs, n, b, bn, target, H->max_iter - used, w.w, its, resid,
                         reduced ? &hess : nullptr, aug.nv > 0 ? &aug : nullptr));
+        prev_aug = aug.nv > 0;
         aug = Aug();
         if (cycle == 0) est0 = resid;
         int kmax = 0;
@@ -1014,6 +1045,36 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
 
 }  // namespace
 
+// ---------------------------------------------------------------- shared with other entry points
+namespace helm {
+
+size_t strip_workspace_bytes(helm_t H, int nrhs) { return strip_ws_bytes(H, nrhs); }
+
+// x = A^(j)^{-1} r for strip `strip` ([rhs][row][strip-local column] layout of
+// helm_strip_solve).  ws: the strip-solver workspace, at least strip_workspace_bytes(H, nrhs)
+// bytes (null: the handle's own, which must already be sized for nrhs); a caller-supplied
+// workspace solve is never event-timed.
+helm_status strip_solve_into(helm_t H, int strip, int nrhs, const void* r, void* x, void* ws) {
+    const auto& g = H->g;
+    const int W = g.strips[strip].W;
+    helm::IOSpec io;
+    io.src = static_cast<const double2*>(r);
+    io.src_rs = g.Nrow() * W; io.src_ls = W; io.src_off = 0;
+    io.src_lo = 0; io.src_hi = W;
+    io.dst = static_cast<double2*>(x);
+    io.dst_rs = g.Nrow() * W; io.dst_ls = W; io.dst_off[0] = io.dst_off[1] = 0;
+    io.o_lo[0] = 0; io.o_hi[0] = W;
+    return strip_solve_any(H, strip, nrhs, io, ws, ws == nullptr);
+}
+
+hipStream_t handle_stream(helm_t H) { return H->st; }
+int handle_device(helm_t H) { return H->dev; }
+bool handle_factored(helm_t H) { return H->factored; }
+int handle_strips(helm_t H) { return H->g.J; }
+helm_status handle_fail(helm_t H, helm_status code, const std::string& msg) { return fail(H, code, msg); }
+
+}  // namespace helm
+
 // =====================================================================================
 extern "C" {
 
@@ -1028,6 +1089,7 @@ void helm_default_opts(helm_opts* o, int n_x, int n_y) {
     o->prec = HELM_C128; o->mode = HELM_FULL; o->max_iter = 200; o->chunk = 0;
     o->stream = nullptr;
     o->graph = 1;
+    o->pml_iface_s0 = -1.0;     // 2.5 per cell of the pad
 }
 
 helm_status helm_setup(const double* c, double omega, double h, const helm_opts* opts, int J,
@@ -1066,6 +1128,9 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     g.h = h; g.omega = omega;
     g.power = opts->pml_power > 0 ? opts->pml_power : 2.0;
     g.s0 = opts->pml_s0 >= 0 ? opts->pml_s0 : 10.0;
+    // interface pads: unless given, the same damping per cell for every width,
+    // sigma_max h / c_ref = 2.5 (s0 = 2.5 w)
+    g.s0i = opts->pml_iface_s0 >= 0 ? opts->pml_iface_s0 : 2.5 * g.w;
     g.cref = opts->pml_cref > 0 ? opts->pml_cref : cmax;
     // ---- partition (Sec. 2.2; eq. define_beta_j for rule 1)
     g.beta.assign(J + 1, 0);
@@ -1276,6 +1341,12 @@ helm_status factor3(helm_t H) {
     void* F = nullptr;
     const int nf = H->nfac;               // one factorisation per distinct slab operator
     CHK(dmalloc(H, &F, (size_t)nf * g.Ny * BB * esz));
+    // F is freed on every early return (HIP errors included) unless it was handed to H
+    struct FOwner {
+        void*& p; bool kept = false;
+        ~FOwner() { if (!kept) dfree(p); }
+    } fown{F};
+    auto keep_F = [&]() { H->F = F; fown.kept = true; };
     struct Bufs {
         std::vector<void*> p;
         ~Bufs() { for (void* q : p) dfree(q); }
@@ -1315,7 +1386,7 @@ helm_status factor3(helm_t H) {
         // complex64 blocked Gauss-Jordan in place in the stored factor; a diagonal block
         // that is singular or ill-conditioned sends the whole factorisation to the FP64
         // Gauss-Jordan with partial pivoting over the whole column below
-        if ((st = alloc(&work32, helm::factor3_f32_work_bytes(nf, g.Bp))) != HELM_OK) { dfree(F); return st; }
+        if ((st = alloc(&work32, helm::factor3_f32_work_bytes(nf, g.Bp))) != HELM_OK) return st;
         HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
         // the slabs are independent.  FAC3_GROUPS streams (the handle's and streams of their
         // own, default priority) each factor one group of slabs at a time, all planes of a
@@ -1362,7 +1433,7 @@ helm_status factor3(helm_t H) {
             }
             return r;
         }());
-        if (e != hipSuccess) { dfree(F); HIPCHK(e); }
+        HIPCHK(e);
         HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
         HIPCHK(hipStreamSynchronize(H->st));
         H->factor_path = herr ? 0 : 1;
@@ -1371,10 +1442,10 @@ helm_status factor3(helm_t H) {
                          herr ? "ill-conditioned diagonal block, redone in FP64" : "accepted");
         if (!herr) {
             void* pw = nullptr;
-            if ((st = alloc(&pw, (size_t)nf * BB * sizeof(float2))) != HELM_OK) { dfree(F); return st; }
-            if ((e = panelize(F, pw)) != hipSuccess) { dfree(F); HIPCHK(e); }
+            if ((st = alloc(&pw, (size_t)nf * BB * sizeof(float2))) != HELM_OK) return st;
+            HIPCHK(panelize(F, pw));
             HIPCHK(hipStreamSynchronize(H->st));
-            H->F = F;
+            keep_F();
             H->factored = true;
             return HELM_OK;
         }
@@ -1385,10 +1456,8 @@ helm_status factor3(helm_t H) {
         (st = alloc((void**)&Tm, (size_t)nf * g.Bp * nb * sizeof(double2))) != HELM_OK ||
         (st = alloc((void**)&Cm, (size_t)nf * g.Bp * nb * sizeof(double2))) != HELM_OK ||
         (st = alloc((void**)&perm, (size_t)nf * g.Bp * sizeof(int))) != HELM_OK ||
-        (st = alloc((void**)&pi, (size_t)nf * g.Bp * sizeof(int))) != HELM_OK) {
-        dfree(F);
+        (st = alloc((void**)&pi, (size_t)nf * g.Bp * sizeof(int))) != HELM_OK)
         return st;
-    }
     HIPCHK(hipMemsetAsync(H->d_err, 0, sizeof(int), H->st));
     // timed as one unit, like the complex64 route
     hipError_t e = TIMED(H, helm::K_FACTOR_CHUNKS, [&]() -> hipError_t {
@@ -1400,16 +1469,16 @@ helm_status factor3(helm_t H) {
         }
         return r;
     }());
-    if (e != hipSuccess) { dfree(F); HIPCHK(e); }
+    HIPCHK(e);
     herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
     if (single && !herr) {
         // S (nf Bp^2 complex128 entries) is free now and holds the panel scratch
-        if ((e = panelize(F, S)) != hipSuccess) { dfree(F); HIPCHK(e); }
+        HIPCHK(panelize(F, S));
         HIPCHK(hipStreamSynchronize(H->st));
     }
-    H->F = F;
+    keep_F();
     if (herr) return fail(H, HELM_ESINGULAR, "zero or non-finite pivot in a slab factorisation");
     H->factored = true;
     return HELM_OK;
@@ -1421,10 +1490,7 @@ helm_status helm_factor(helm_t H) {
     const auto& g = H->g;
     // the captured reduced operator holds the factor addresses in its kernel arguments:
     // drop it before the factors are freed (it is captured again on the next solve)
-    if (H->ap_exec) {
-        HIPCHK(hipGraphExecDestroy(H->ap_exec));
-        H->ap_exec = nullptr;
-    }
+    CHK(drop_graph(H));
     HIPCHK(hipStreamSynchronize(H->st));    // no queued work may still read the old factors
     H->factored = false;
     if (g.dim == 3) {
@@ -1712,16 +1778,7 @@ helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void*
     if (strip < 0 || strip >= H->g.J || nrhs < 1 || !r || !x)
         return fail(H, HELM_EINVAL, "bad arguments");
     CHK(ensure_sweep_ws(H, nrhs));
-    const auto& g = H->g;
-    const int W = g.strips[strip].W;
-    helm::IOSpec io;
-    io.src = static_cast<const double2*>(r);
-    io.src_rs = g.Nrow() * W; io.src_ls = W; io.src_off = 0;
-    io.src_lo = 0; io.src_hi = W;
-    io.dst = static_cast<double2*>(x);
-    io.dst_rs = g.Nrow() * W; io.dst_ls = W; io.dst_off[0] = io.dst_off[1] = 0;
-    io.o_lo[0] = 0; io.o_hi[0] = W;
-    return strip_solve_any(H, strip, nrhs, io);
+    return helm::strip_solve_into(H, strip, nrhs, r, x, nullptr);
 }
 
 helm_status helm_get_dims3(helm_t H, int* N_x, int* N_y, int* N_z, int* J) {

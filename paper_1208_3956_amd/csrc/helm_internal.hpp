@@ -63,6 +63,7 @@ struct Geom {
     // rows of a field: fields are [rhs][row][x] with row = z * Ny + y
     long Nrow() const { return (long)Nz * Ny; }
     double h = 0, omega = 0, power = 2, s0 = 10, cref = 0;
+    double s0i = 0;              // strength of the interface pads (strip operators only)
     std::vector<int> beta;       // J+1 entries
     std::vector<Strip> strips;
 };
@@ -238,6 +239,17 @@ hipError_t launch_factor3_plane_f32(const Fac3Args& a, int l, float2* F, size_t 
                                     hipStream_t st, int s0, int ns);
 template <typename T>
 hipError_t launch_strip_solve3(const Solve3Args<T>& a, hipStream_t st, KTimer* kt);
+
+// ---- host core (helm_api.hip) shared with other entry points
+// bytes of strip-solver workspace one strip solve of nrhs right-hand sides needs
+size_t strip_workspace_bytes(helm_t H, int nrhs);
+// helm_strip_solve with the workspace ws (>= strip_workspace_bytes; null: the handle's own)
+helm_status strip_solve_into(helm_t H, int strip, int nrhs, const void* r, void* x, void* ws);
+hipStream_t handle_stream(helm_t H);
+int handle_device(helm_t H);
+bool handle_factored(helm_t H);
+int handle_strips(helm_t H);
+helm_status handle_fail(helm_t H, helm_status code, const std::string& msg);
 
 // ---- misfit and adjoint gradient (kernels_grad.hip)
 hipError_t launch_rec_residual(const double2* u, long field, const long* rec, int nrec,

@@ -34,6 +34,11 @@ class Helmholtz:
     omega, h   angular frequency and grid spacing
     J          number of strips along x
     pml_outer  outer PML width (cells); pml_iface: interface PML width w
+    pml_s0     strength of the outer PML (part of A: changes the solution)
+    pml_iface_s0  strength of the interface pads (part of P only: changes iterations);
+               None = 2.5 x pml_iface (the same damping per cell for every width)
+    beta_rule  partition when beta is None: 0 = even split of the interior,
+               1 = the paper's rule (eq. define_beta_j)
     prec       "c128" or "mixed" (complex64 strip factors and sweeps, FP64 GMRES)
     mode       "full" or "reduced" (GMRES on the interface columns, Algorithms 2-5)
     chunk      rows per chunk of the y-partitioned strip solver (0 = library default)
@@ -45,7 +50,9 @@ class Helmholtz:
                  pml_iface: int = 8, pml_power: float = 2.0, pml_s0: float = 10.0,
                  pml_cref: float = 0.0, prec: str = "c128", mode: str = "full",
                  max_iter: int = 200, chunk: int = 0, beta: Optional[Sequence[int]] = None,
-                 device="cuda:0", stream=None, graph: bool = True):
+                 device="cuda:0", stream=None, graph: bool = True,
+                 pml_iface_s0: Optional[float] = None,
+                 beta_rule: int = 0):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the solver runs on a HIP device (cuda:N in torch)")
@@ -60,6 +67,8 @@ class Helmholtz:
             o.n[2] = int(self._c.shape[0])
         o.pml_outer, o.pml_iface = int(pml_outer), int(pml_iface)
         o.pml_power, o.pml_s0, o.pml_cref = float(pml_power), float(pml_s0), float(pml_cref)
+        o.pml_iface_s0 = -1.0 if pml_iface_s0 is None else float(pml_iface_s0)
+        o.beta_rule = int(beta_rule)
         o.prec = {"c128": L.HELM_C128, "mixed": L.HELM_MIXED_C64, "c64": L.HELM_MIXED_C64}[prec]
         o.mode = {"full": L.HELM_FULL, "reduced": L.HELM_REDUCED}[mode]
         o.max_iter = int(max_iter)

@@ -23,6 +23,7 @@ def test_autotune_choice_and_solution(prec, mode, tmp_path):
     wl = W.small(n=60, J=4, w_out=7, w=5, c=c, nsrc=3, seed=32)
     f = torch.from_numpy(wl.rhs()).to(DEV)
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                  pml_iface_s0=wl.pml_iface_s0,
                   prec=prec, mode=mode, chunk=9, device=DEV)
     cache = str(tmp_path / "tune.json")
     cand = (5, 12, 30, 80)
@@ -40,6 +41,7 @@ def test_autotune_choice_and_solution(prec, mode, tmp_path):
         assert np.linalg.norm(u[k] - ud[k]) / np.linalg.norm(ud[k]) < 1e-5
     # a second handle of the same shape takes the cached choice without timing
     H2 = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                   pml_iface_s0=wl.pml_iface_s0,
                    prec=prec, mode=mode, chunk=9, device=DEV)
     out2 = H2.autotune(f, candidates=cand, reps=1, cache=cache)
     assert out2["cached"] and out2["chunk_rows"] == out["chunk_rows"]
@@ -55,6 +57,7 @@ def test_autotune_3d_is_one_chunk():
     wl = W.small3(n=10, J=2, w_out=4, w=3, nsrc=1)
     f = torch.from_numpy(wl.rhs()).to(DEV)
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                  pml_iface_s0=wl.pml_iface_s0,
                   prec="mixed", mode="reduced", device=DEV)
     out = H.autotune(f, candidates=(8, 16), reps=1, cache=None)
     assert out["chunk_rows"] == H.N_y and H.factored

@@ -29,6 +29,7 @@ def _wl(n, J, seed):
 def _H(wl, prec, graph, stream=None, chunk=9):
     from paper_1208_3956_amd import Helmholtz
     return Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                     pml_iface_s0=wl.pml_iface_s0,
                      prec=prec, mode="reduced", chunk=chunk, device=DEV, stream=stream,
                      graph=graph).factor()
 

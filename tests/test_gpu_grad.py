@@ -39,6 +39,7 @@ def case():
 def _H(wl, g0, prec, mode, chunk=9):
     from paper_1208_3956_amd import Helmholtz
     return Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                     pml_iface_s0=wl.pml_iface_s0,
                      pml_cref=g0.c_ref, prec=prec, mode=mode, chunk=chunk, device=DEV).factor()
 
 

@@ -38,6 +38,7 @@ def case():
 def _H(wl, g0, c, prec, mode="reduced"):
     from paper_1208_3956_amd import Helmholtz
     return Helmholtz(c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                     pml_iface_s0=wl.pml_iface_s0,
                      pml_cref=g0.c_ref, prec=prec, mode=mode, device=DEV).factor()
 
 

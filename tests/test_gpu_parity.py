@@ -40,6 +40,7 @@ def _wl(n=40, J=3, w_out=8, w=6, c=None, nsrc=3, seed=5):
 def _gpu(wl, prec="c128", mode="full", chunk=9):
     from paper_1208_3956_amd import Helmholtz
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                  pml_iface_s0=wl.pml_iface_s0,
                   prec=prec, mode=mode, chunk=chunk, device=DEV)
     return H.factor()
 
@@ -50,6 +51,25 @@ def _t(x):
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _close(x, ref, tol, what="", rows=None):
+    """Every right-hand side (leading index) within tol in relative L2 and in relative
+    max-norm (max |x - ref| / max |ref|); with rows = m, also every block of m rows (the
+    strip solver's y-chunks) within 5 tol in relative L2, so that an error confined to one
+    right-hand-side group, chunk or row cannot hide under a norm over everything."""
+    assert x.shape == ref.shape, (what, x.shape, ref.shape)
+    for k in range(ref.shape[0]):
+        d = x[k] - ref[k]
+        l2 = np.linalg.norm(d) / np.linalg.norm(ref[k])
+        mx = np.abs(d).max() / np.abs(ref[k]).max()
+        assert l2 < tol and mx < tol, (what, k, l2, mx)
+        if rows:
+            for r0 in range(0, ref.shape[1], rows):
+                nb = np.linalg.norm(ref[k][r0:r0 + rows])
+                if nb > 0:
+                    eb = np.linalg.norm(d[r0:r0 + rows]) / nb
+                    assert eb < 5 * tol, (what, k, r0, eb)
 
 
 def _rand(rng, shape):
@@ -80,9 +100,9 @@ def test_stencil_apply(case):
     f = _rand(rng, (3, g.N_y, g.N_x))
     out = H.apply_A(_t(u), _t(f)).cpu().numpy()
     ref = np.stack([fk - (A @ uk.ravel()).reshape(uk.shape) for uk, fk in zip(u, f)])
-    assert _rel(out, ref) < TOL_A
+    _close(out, ref, TOL_A, "f - A u")
     out2 = H.apply_A(_t(u)).cpu().numpy()
-    assert _rel(out2, f - ref) < TOL_A
+    _close(out2, f - ref, TOL_A, "A u")
     H.close()
 
 
@@ -96,7 +116,7 @@ def test_strip_solve_c128(case, chunk, nrhs):
         r = _rand(rng, (nrhs, g.N_y, st.W))
         x = H.strip_solve(s, _t(r)).cpu().numpy()
         ref = np.stack([S.solve(s, rk) for rk in r])
-        assert _rel(x, ref) < TOL_STRIP_C128, (s, _rel(x, ref))
+        _close(x, ref, TOL_STRIP_C128, f"strip {s}", rows=H.chunk_rows)
     H.close()
 
 
@@ -112,7 +132,7 @@ def test_strip_solve_mixed(case, chunk, nrhs):
         r = _rand(rng, (nrhs, g.N_y, st.W))
         x = H.strip_solve(s, _t(r)).cpu().numpy()
         ref = np.stack([S.solve(s, rk) for rk in r])
-        assert _rel(x, ref) < TOL_P_C64, (s, _rel(x, ref))
+        _close(x, ref, TOL_P_C64, f"strip {s}", rows=H.chunk_rows)
     H.close()
 
 
@@ -124,7 +144,7 @@ def test_apply_P(case, prec, tol):
     f = _rand(rng, (6, g.N_y, g.N_x))
     pf = H.apply_P(_t(f)).cpu().numpy()
     ref = np.stack([apply_P(g, S, A, fk) for fk in f])
-    assert _rel(pf, ref) < tol, _rel(pf, ref)
+    _close(pf, ref, tol, "P")
     H.close()
 
 
@@ -136,7 +156,7 @@ def test_apply_AP_reduced(case, prec, tol):
     psi = _rand(rng, (4, g.N_y, 2 * (g.J - 1)))
     out = H.apply_AP_reduced(_t(psi)).cpu().numpy()
     ref = np.stack([apply_AP_reduced(g, S, A, pk) for pk in psi])
-    assert _rel(out, ref) < tol, _rel(out, ref)
+    _close(out, ref, tol, "reduced A P")
     H.close()
 
 
@@ -151,8 +171,7 @@ def test_solve_matches_direct(case, mode, prec):
     ud = solve_direct(g, f, A)
     assert res.status == 0
     assert max(res.relres) <= 1e-6
-    for k in range(f.shape[0]):
-        assert _rel(u[k], ud[k]) < TOL_FIELD, (k, _rel(u[k], ud[k]))
+    _close(u, ud, TOL_FIELD, "field")
     # iteration counts against the oracle's DD-GMRES (MGS vs CGS2 and the mixed
     # precision may move the crossing of the tolerance by one step)
     solver = solve_dd if mode == "full" else solve_dd_reduced
@@ -181,7 +200,7 @@ def test_homogeneous_100_plain_c128():
     ud = solve_direct(g, f, A)
     ref = solve_dd(g, f[0], 1e-6, A=A)
     assert res.relres[0] <= 1e-6
-    assert _rel(res.u.cpu().numpy()[0], ud[0]) < TOL_FIELD
+    _close(res.u.cpu().numpy(), ud, TOL_FIELD, "field")
     assert abs(res.iters[0] - ref.iters) <= 1
     H.close()
 
@@ -245,11 +264,11 @@ def test_identical_strips_share_factors(prec):
         r = _rand(rng, (2, g.N_y, st.W))
         x = H.strip_solve(s, _t(r)).cpu().numpy()
         ref = np.stack([S.solve(s, rk) for rk in r])
-        assert _rel(x, ref) < tol, (s, _rel(x, ref))
+        _close(x, ref, tol, f"strip {s}", rows=7)
     f = _rand(rng, (2, g.N_y, g.N_x))
     pf = H.apply_P(_t(f)).cpu().numpy()
     ref = np.stack([apply_P(g, S, A, fk) for fk in f])
-    assert _rel(pf, ref) < (TOL_P_C128 if prec == "c128" else TOL_P_C64)
+    _close(pf, ref, TOL_P_C128 if prec == "c128" else TOL_P_C64, "P")
     H.close()
     H = _gpu(_wl(n=n, J=J), prec=prec, chunk=7)
     assert H.factor_slots == J
