@@ -163,7 +163,11 @@ def oracle_job(wl, max_cores=16):
     t_asm = time.time() - t0
     t_sfac, t_ssol = _strip_pieces(g, g.k2(), SAMPLE_STRIPS)
     ta = time.time()
-    S = StripSolvers(g)
+
+    def progress(done, J):
+        if done % 8 == 0 or done == J:
+            print(f"# oracle: {done}/{J} strips factored ({time.time() - ta:.0f} s)", file=sys.stderr, flush=True)
+    S = StripSolvers(g, progress=progress)
     t_fac = time.time() - ta
     cores = max(1, min(max_cores, os.cpu_count() or 1))
     nsolve = min(wl.nrhs, cores + 1)
@@ -181,8 +185,12 @@ def oracle_job(wl, max_cores=16):
         os.environ["OMP_NUM_THREADS"] = os.environ["OPENBLAS_NUM_THREADS"] = "1"
         try:
             ta = time.time()
+            res = []
             with mp.get_context("fork").Pool(C) as pool:
-                res = pool.map(_oracle_solve_one, range(1, C + 1))
+                for r in pool.imap_unordered(_oracle_solve_one, range(1, C + 1)):
+                    res.append(r)
+                    print(f"# oracle: right-hand side {r[0]} done in {r[1]:.0f} s ({r[2]} iterations)",
+                          file=sys.stderr, flush=True)
             t_par = time.time() - ta
             it_par = [r[2] for r in res]
         finally:

@@ -27,13 +27,16 @@ from .grid import Geometry
 class StripSolvers:
     """SuperLU factorisations of all padded strip operators A^(j) (Algorithm 1)."""
 
-    def __init__(self, g: Geometry, k2=None):
+    def __init__(self, g: Geometry, k2=None, progress=None):
+        """progress: optional callable(strips done, J), called after each factorisation."""
         self.g = g
         k2 = g.k2() if k2 is None else k2
         self.lu = []
         for st in g.strips:
             As = assemble_strip(g, st, k2).tocsc()
             self.lu.append(spla.splu(As, permc_spec="COLAMD"))
+            if progress is not None:
+                progress(len(self.lu), g.J)
 
     def solve(self, s: int, rhs: np.ndarray) -> np.ndarray:
         st = self.g.strips[s]
