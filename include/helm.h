@@ -241,6 +241,24 @@ helm_status helm_apply_A(helm_t H, int nrhs, const void* u, const void* f, void*
  */
 helm_status helm_strip_solve(helm_t H, int strip, int nrhs, const void* r, void* x);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): helm_strip_solve without any
+ * allocation.  The strip solver's workspace is a static 64 MiB device array of the
+ * library, one per GPU, held until the process ends, instead of a buffer of the handle;
+ * the factors are those helm_factor stored.  Same arguments, layout and result as
+ * helm_strip_solve (the same kernels).  The workspace holds 64 MiB: a 2-D strip solve needs
+ * nrhs * N_y * 64 complex values (8 B in HELM_MIXED_C64, 16 B in HELM_C128), a 3-D slab
+ * solve (N_y + 2) * Bp * (nrhs rounded up to 16) values (Bp = padded slab block); larger
+ * calls return HELM_EINVAL without launching anything.  The handle's device must be
+ * current (HELM_EINVAL otherwise).  Every call on one GPU shares that GPU's workspace, and
+ * the part a call uses is cleared by a kernel at its start: calls that overlap on one GPU
+ * (other streams, other handles, other threads) race and must be ordered by the caller.
+ * The call launches kernels only (no allocation, no memset, no event), so it may be
+ * captured into a HIP graph.  HELM_ESTATE before helm_factor.
+ */
+helm_status helm_strip_solve_noalloc(helm_t H, int strip, int nrhs, const void* r, void* x);
+
 /* N_x, N_y, N_z (1 in 2-D) and J. */
 helm_status helm_get_dims3(helm_t H, int* N_x, int* N_y, int* N_z, int* J);
 

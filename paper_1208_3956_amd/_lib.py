@@ -23,7 +23,7 @@ EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
            "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
            "helm_solve_batch", "helm_get_dims3", "helm_autotune", "helm_get_factor_path",
-           "helm_get_factor_slots"]
+           "helm_get_factor_slots", "helm_strip_solve_noalloc"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -82,6 +82,7 @@ def lib() -> ctypes.CDLL:
     L.helm_grad.argtypes = [vp, ci, vp, ci, vp, vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                             vp, pint]
     L.helm_strip_solve.argtypes = [vp, ci, ci, vp, vp]
+    L.helm_strip_solve_noalloc.argtypes = [vp, ci, ci, vp, vp]
     L.helm_autotune.argtypes = [vp, ci, vp, pint, ci, ci, pint, pdbl]
     L.helm_get_factor_path.argtypes = [vp, pint]
     L.helm_get_factor_slots.argtypes = [vp, pint, pint]
@@ -198,6 +199,12 @@ def helm_apply_A(hdl, nrhs: int, u_ptr: int, f_ptr, out_ptr: int) -> None:
 def helm_strip_solve(hdl, strip: int, nrhs: int, r_ptr: int, x_ptr: int) -> None:
     check(lib().helm_strip_solve(hdl, int(strip), int(nrhs), ctypes.c_void_p(r_ptr),
                                  ctypes.c_void_p(x_ptr)), hdl)
+
+
+def helm_strip_solve_noalloc(hdl, strip: int, nrhs: int, r_ptr: int, x_ptr: int) -> int:
+    """Returns the status (HELM_EINVAL for a call larger than the static workspace)."""
+    return lib().helm_strip_solve_noalloc(hdl, int(strip), int(nrhs), ctypes.c_void_p(r_ptr),
+                                          ctypes.c_void_p(x_ptr))
 
 
 def helm_get_dims(hdl):
