@@ -151,3 +151,102 @@ def apply_P_reduced(g: Geometry, S: StripSolvers, A, psi_red: np.ndarray, ut: np
     psi = from_reduced(g, psi_red)
     v, w, _ = sweep(g, S, A, psi, up_from=1, dn_from=g.J - 2)
     return v + w + ut
+
+
+# ------------------------------------------------------------------ concurrent double sweep
+#
+# The paper observes (Sec. 1 and the end of Sec. 3.1) that the upward and downward sequences
+# of solves can run at the same time if the point where they cross is handled with care; it
+# shows this only for its 1-D model.  The 2-D form used here needs no crossing point at all:
+#   upward  (as in eq. solve_upward)          v^(j)  = A^(j)^{-1}(f^(j)  - 2 delta(x - b_{j-1}) d_x v^(j-1))
+#   downward on f instead of the residual     w'^(j) = A^(j)^{-1}(f~^(j) + 2 delta(x - b~_j) d_x w'^(j+1))
+#   the strip's own sources, in both          z^(j)  = A^(j)^{-1}(f on D^(j) and D~^(j))
+#   P_c f = v^(j) + w'^(j) - z^(j) on D^(j)
+# v^(j) carries the field of every source left of b_j, w'^(j) that of every source right of
+# b_{j-1} (the transmission reproduces the incoming wave, Sec. 3.2), so their sum counts the
+# sources of D^(j) and D~^(j) twice and z^(j) removes one copy.  For a medium independent of x
+# and perfect PML layers P_c f is the solution (the argument of Theorem 1 in each direction).
+# The two chains do not depend on each other, and the z^(j) on nothing.
+
+def sweep_concurrent(g: Geometry, S: StripSolvers, f: np.ndarray):
+    """Both sweeps of the concurrent form on f; returns (v, w', z) on the whole grid, each
+    restricted to the columns of D^(j) of its strip j."""
+    J, h = g.J, g.h
+    delta = 1.0 / (2.0 * h)
+    v = np.zeros_like(f)
+    wd = np.zeros_like(f)
+    z = np.zeros_like(f)
+    prev = None
+    for s in range(J):                                   # upward, as in sweep()
+        st = g.strips[s]
+        rhs = np.zeros(g.strip_shape(st), dtype=np.complex128)
+        lo, hi = st.core
+        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]
+        if prev is not None:
+            b = g.beta[s]
+            pst, px = prev
+            dxv = (px[..., b - pst.a] - px[..., b - 1 - pst.a]) / h
+            rhs[..., b - 1 - st.a] += -2.0 * delta * dxv
+            rhs[..., b - st.a] += -2.0 * delta * dxv
+        x = S.solve(s, rhs)
+        v[..., lo:hi] = x[..., lo - st.a:hi - st.a]
+        prev = (st, x)
+    nxt = None
+    for s in range(J - 1, -1, -1):                       # downward on f
+        st = g.strips[s]
+        rhs = np.zeros(g.strip_shape(st), dtype=np.complex128)
+        lo, hi = st.keep_dn
+        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]        # f~^(j): f on D~^(j)
+        if nxt is not None:
+            b = g.beta[s + 1]
+            nst, nx_ = nxt
+            dxw = (nx_[..., b + 1 - nst.a] - nx_[..., b - nst.a]) / h
+            rhs[..., b - st.a] += 2.0 * delta * dxw
+            rhs[..., b + 1 - st.a] += 2.0 * delta * dxw
+        x = S.solve(s, rhs)
+        clo, chi = st.core
+        wd[..., clo:chi] = x[..., clo - st.a:chi - st.a]
+        nxt = (st, x)
+    for s, st in enumerate(g.strips):                    # the strips' own sources
+        rhs = np.zeros(g.strip_shape(st), dtype=np.complex128)
+        lo, hi = max(st.core[0], st.keep_dn[0]), min(st.core[1], st.keep_dn[1])
+        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]
+        x = S.solve(s, rhs)
+        clo, chi = st.core
+        z[..., clo:chi] = x[..., clo - st.a:chi - st.a]
+    return v, wd, z
+
+
+def apply_P_concurrent(g: Geometry, S: StripSolvers, f: np.ndarray) -> np.ndarray:
+    """P_c f = v + w' - z (the concurrent double sweep)."""
+    v, wd, z = sweep_concurrent(g, S, f)
+    return v + wd - z
+
+
+def concurrent_columns(g: Geometry) -> np.ndarray:
+    """Columns where f - A P_c f can be non-zero: beta_j - 1 and beta_j of every internal
+    interface (the two columns next to b_j)."""
+    return g.residual_columns()
+
+
+def reduced_setup_concurrent(g: Geometry, S: StripSolvers, A, f: np.ndarray):
+    """The reduced form's starting point for P_c: u~ from independent strip solves of f on
+    D^(j), kept on D^(j); phi = f - A u~ then lives on the concurrent columns."""
+    ut = np.zeros_like(f)
+    for s, st in enumerate(g.strips):
+        rhs = np.zeros(g.strip_shape(st), dtype=np.complex128)
+        lo, hi = st.core
+        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]
+        x = S.solve(s, rhs)
+        ut[..., lo:hi] = x[..., lo - st.a:hi - st.a]
+    phi = f - (A @ ut.ravel()).reshape(f.shape)
+    return ut, phi
+
+
+def apply_AP_concurrent_reduced(g: Geometry, S: StripSolvers, A, psi_red: np.ndarray) -> np.ndarray:
+    """(A P_c psi) restricted to the concurrent columns, for psi given there."""
+    cols = concurrent_columns(g)
+    psi = np.zeros(g.field_shape, dtype=np.complex128)
+    psi[..., cols] = psi_red
+    out = (A @ apply_P_concurrent(g, S, psi).ravel()).reshape(psi.shape)
+    return out[..., cols].copy()

@@ -468,3 +468,102 @@ def test_adjoint_identity_via_complex_symmetry():
     assert abs(lhs - rhs) < 1e-10 * abs(lhs)
     via_sym = np.conj(Ainv(D * np.conj(b)) / D)
     assert np.linalg.norm(via_sym - AHinv_b) < 1e-10 * np.linalg.norm(AHinv_b)
+
+
+# ------------------------------------------------------------------ concurrent double sweep
+
+def _pc_defect(w, mutate=None, layered=True):
+    from oracle.dd import apply_P_concurrent
+    import oracle.dd as dd
+    n = 48
+    rng = np.random.default_rng(4)
+    cy = 1.0 + 0.5 * rng.random(n)
+    c = np.repeat(cy[:, None], n, 1) if layered else np.ones((n, n))
+    g = make_geometry(c, 2 * math.pi / (10 / n), 1.0 / n, 10, w, 4, s0_iface=10.0)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    f = np.zeros((g.N_y, g.N_x), complex)
+    f[g.N_y // 2, 15] = f[g.N_y // 3, 45] = f[g.N_y // 4, 22] = n * n   # 22: on an interface
+    if mutate is None:
+        pf = apply_P_concurrent(g, S, f)
+    else:
+        v, wd, z = mutate(g, S, f)
+        pf = v + wd - z
+    return np.linalg.norm(f - (A @ pf.ravel()).reshape(f.shape)) / np.linalg.norm(f)
+
+
+def test_concurrent_sweep_theorem1():
+    """The concurrent double sweep (both sweeps on f, each strip's own sources removed once)
+    is exact for an x-invariant medium up to the pad reflection, like P (Theorem 1,
+    Sec. 3.2): the defect of A P_c falls as the pads widen."""
+    e = [_pc_defect(w) for w in (3, 6, 12)]
+    assert e[0] > e[1] > e[2]
+    assert e[2] < 0.01
+
+
+def _mutated_concurrent(old, new):
+    import inspect
+    from oracle import dd
+    src = inspect.getsource(dd.sweep_concurrent)
+    assert old in src
+    ns = dict(vars(dd))
+    exec(compile(src.replace(old, new), "mutant", "exec"), ns)
+    return ns["sweep_concurrent"]
+
+
+@pytest.mark.parametrize("old,new", [
+    ("x = S.solve(s, rhs)\n        clo, chi = st.core\n        z[", "x = 0 * S.solve(s, rhs)\n        clo, chi = st.core\n        z["),   # no z
+    ("lo, hi = max(st.core[0], st.keep_dn[0]), min(st.core[1], st.keep_dn[1])",
+     "lo, hi = st.core"),                                                            # z over D
+    ("rhs[..., b - st.a] += 2.0 * delta * dxw", "rhs[..., b - st.a] += -2.0 * delta * dxw"),  # sign
+    ("lo, hi = st.keep_dn\n        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]        # f~",
+     "lo, hi = st.core\n        rhs[..., lo - st.a:hi - st.a] = f[..., lo:hi]        # f~"),   # f on D, not D~
+])
+def test_concurrent_sweep_planted_mistakes(old, new):
+    """Each plausible slip in the concurrent form (dropping z, taking z or the downward
+    sources over D instead of D~, a transmission sign) breaks the x-invariant exactness."""
+    good = _pc_defect(8)
+    bad = _pc_defect(8, mutate=_mutated_concurrent(old, new))
+    assert bad > 10 * good, (good, bad)
+
+
+def test_concurrent_sweep_J1_and_support():
+    """One strip: P_c = A^{-1}.  Several: f - A P_c f lives on the columns beta_j - 1,
+    beta_j (the two columns next to each b_j), so a GMRES reduced to them is the same
+    method; the reduced operator equals A P_c restricted there."""
+    from oracle.dd import apply_P_concurrent, apply_AP_concurrent_reduced, concurrent_columns
+    g1 = _geom(n=24, J=1, w_out=6, w=4)
+    A1 = assemble_global(g1)
+    rng = np.random.default_rng(17)
+    f = _rand_field(rng, (g1.N_y, g1.N_x))
+    pf = apply_P_concurrent(g1, StripSolvers(g1), f)
+    assert np.linalg.norm(f - (A1 @ pf.ravel()).reshape(f.shape)) < 1e-12 * np.linalg.norm(f)
+    g = _geom(n=36, J=4, w_out=6, w=5)
+    A = assemble_global(g)
+    S = StripSolvers(g)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    r = f - (A @ apply_P_concurrent(g, S, f).ravel()).reshape(f.shape)
+    mask = np.ones(g.N_x, bool)
+    mask[concurrent_columns(g)] = False
+    assert np.linalg.norm(r[:, mask]) < 1e-12 * np.linalg.norm(f)
+    assert np.linalg.norm(r[:, ~mask]) > 1e-3 * np.linalg.norm(f)
+    psi = _rand_field(rng, (g.N_y, len(concurrent_columns(g))))
+    full = np.zeros((g.N_y, g.N_x), complex)
+    full[:, concurrent_columns(g)] = psi
+    ref = (A @ apply_P_concurrent(g, S, full).ravel()).reshape(full.shape)
+    out = apply_AP_concurrent_reduced(g, S, A, psi)
+    assert np.linalg.norm(out - ref[:, concurrent_columns(g)]) < 1e-12 * np.linalg.norm(ref)
+    assert np.linalg.norm(ref[:, mask]) < 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("mode", ["full", "reduced"])
+def test_concurrent_dd_gmres_reaches_direct_solution(mode):
+    from oracle.solve import solve_dd_concurrent
+    g = _geom(n=30, J=3, w_out=6, w=5)
+    A = assemble_global(g)
+    rng = np.random.default_rng(23)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    ud = solve_direct(g, f, A)
+    res = solve_dd_concurrent(g, f, 1e-10, A=A, mode=mode)
+    assert res.relres < 1e-9
+    assert np.linalg.norm(res.u - ud) < 1e-7 * np.linalg.norm(ud)
