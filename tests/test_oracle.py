@@ -9,6 +9,7 @@ import types
 import numpy as np
 import pytest
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 import workloads as W
 from oracle import grid as ogrid
@@ -567,3 +568,80 @@ def test_concurrent_dd_gmres_reaches_direct_solution(mode):
     res = solve_dd_concurrent(g, f, 1e-10, A=A, mode=mode)
     assert res.relres < 1e-9
     assert np.linalg.norm(res.u - ud) < 1e-7 * np.linalg.norm(ud)
+
+
+# ------------------------------------------------------------------ Robin double sweep
+
+def test_robin_one_subdomain_is_the_global_operator():
+    """J = 1: the single Robin subdomain has no internal side, so it is the global
+    operator and the preconditioner is A^{-1}."""
+    from oracle.robin import RobinSolvers, apply_P_robin, assemble_robin_strip
+    g = _geom(n=20, J=1, w_out=5, w=4)
+    A = assemble_global(g)
+    assert abs(assemble_robin_strip(g, 0) - A).max() == 0.0
+    rng = np.random.default_rng(2)
+    f = _rand_field(rng, (g.N_y, g.N_x))
+    pf = apply_P_robin(g, RobinSolvers(g), A, f)
+    assert np.linalg.norm(f - (A @ pf.ravel()).reshape(f.shape)) < 1e-12 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("s", [0, 1, 2])
+def test_robin_ghost_elimination_is_consistent(s):
+    """Eliminating the ghost column of a Robin side is an identity: for any field U, the
+    Robin subdomain solve with right-hand side (A U) on its columns plus the data terms
+    (U_out - rho U_in) / h^2 taken from U itself returns U on the subdomain.  (A sign or
+    factor slip in the diagonal term or in the data breaks it.)"""
+    from oracle.robin import assemble_robin_strip, robin_rho, robin_span
+    g = _geom(n=30, J=3, w_out=6, w=4)
+    A = assemble_global(g)
+    rng = np.random.default_rng(40 + s)
+    U = _rand_field(rng, (g.N_y, g.N_x))
+    AU = (A @ U.ravel()).reshape(U.shape)
+    lo, hi = robin_span(g, s)
+    st = g.strips[s]
+    rhs = AU[:, lo:hi].copy()
+    ih2 = 1.0 / g.h ** 2
+    if st.left_pad:
+        rhs[:, 0] += (U[:, lo - 1] - robin_rho(g, lo) * U[:, lo]) * ih2
+    if st.right_pad:
+        rhs[:, -1] += (U[:, hi] - robin_rho(g, hi - 1) * U[:, hi - 1]) * ih2
+    x = spla.spsolve(assemble_robin_strip(g, s).tocsc(), rhs.ravel()).reshape(rhs.shape)
+    assert np.linalg.norm(x - U[:, lo:hi]) < 1e-10 * np.linalg.norm(U[:, lo:hi])
+    # and the oracle's rho continues a boundary value outward like an outgoing wave,
+    # rho ~ e^{i k h} (error O((k h)^3)), row by row
+    kh = np.sqrt(g.k2()[:, lo]) * g.h
+    assert np.all(np.abs(robin_rho(g, lo) - np.exp(1j * kh)) < 0.1 * kh ** 3)
+
+
+def test_robin_condition_lets_outgoing_waves_through():
+    """The discrete right-side condition (-d_x + i k) u = 0 at a half-point, with d_x the
+    two-point difference and u the two-point mean, nearly annihilates a wave travelling
+    out through it (residual O((k h)^2) of the wave's i k) and not one coming in: the
+    rho of the ghost elimination encodes the outgoing direction (Sec. 4.4; time convention
+    e^{-i omega t}, so e^{+ikx} travels towards +x)."""
+    for kh in (0.2, 0.4, 0.628):
+        k, h = kh, 1.0
+        out = np.exp(1j * k * np.array([0.0, h]))        # e^{ikx} at the columns b, b + 1
+        inc = np.conj(out)                                # e^{-ikx}
+        cond = lambda u: -(u[1] - u[0]) / h + 1j * k * (u[1] + u[0]) / 2
+        assert abs(cond(out)) < 0.5 * kh ** 2 * k
+        assert abs(cond(inc)) > 1.5 * k
+        # the ghost rule: a boundary value u_b continues outward as rho u_b
+        rho = (1 + 0.5j * k * h) / (1 - 0.5j * k * h)
+        assert abs(rho - np.exp(1j * k * h)) < 0.1 * kh ** 3
+
+
+def test_paper_table4_robin_column_soft():
+    """Table 4 (Sec. 4.4), Robin column: the Robin double sweep needs 9 and 13 iterations
+    at 100^2 and 200^2 (constant medium, J = n/10, 10 points per wavelength).  The paper's
+    discretisation of the Robin conditions is not stated; soft pin, +-1."""
+    from oracle.solve import solve_dd_robin
+    rows = json.load(open(os.path.join(HERE, "golden", "table4_robin_const2d.json")))["rows"]
+    for row in rows[:2]:
+        n, J = row["n"], row["J"]
+        h = 1.0 / n
+        g = make_geometry(np.ones((n, n)), 2 * math.pi / (10 * h), h, 10, 8, J)
+        f = np.zeros((g.N_y, g.N_x), complex)
+        f[g.N_y // 2, g.N_x // 2] = 1 / h ** 2
+        res = solve_dd_robin(g, f, 1e-6)
+        assert abs(res.iters - row["iterations"]) <= 1, (n, res.iters)
