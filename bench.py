@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--prec", default="mixed", choices=["mixed", "c128"])
     p.add_argument("--mode", default="reduced", choices=["reduced", "full"])
+    p.add_argument("--sweep", default="double", choices=["double", "concurrent"],
+                   help="double: the paper's P; concurrent: P_c (both sweeps on f at once)")
     p.add_argument("--chunk", type=int, default=0,
                    help="rows per chunk of the strip solver; 0 = autotuned before the timed steps")
     p.add_argument("--tune-candidates", default="16,24,32,40,48",
@@ -53,6 +55,8 @@ def parse():
                         "oracle's whole job; full: run the oracle's whole job now (minutes)")
     p.add_argument("--oracle-record-out", default=None,
                    help="with --cpu-baseline full: also write the job record (Markdown) here")
+    p.add_argument("--no-lens-leg", action="store_true",
+                   help="skip the 1000^2 Gaussian-lens leg (complex64-mixed and complex128)")
     p.add_argument("--no-c128-leg", action="store_true",
                    help="skip the complex128 comparison legs (batched and one RHS per solve)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -403,6 +407,47 @@ def c128_legs(wl, f, tol, plain_rhs=2):
     }
 
 
+def lens_leg(tol, reps=2):
+    """The 1000^2 Gaussian-lens workload (16 sources, J = 32), a medium that varies with x
+    (every strip has its own factorisation), in complex64-mixed and complex128: factor and
+    solve times (mean of `reps` timed passes after one untimed pass) and iteration counts."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1208_3956_amd import Helmholtz
+    wl = W.lens_1000()
+    f = torch.from_numpy(wl.rhs()).to("cuda:0")
+    out = {"workload": wl.name, "nrhs": f.shape[0], "J": wl.J}
+    for prec in ("mixed", "c128"):
+        H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                      pml_iface_s0=wl.pml_iface_s0, prec=prec, mode="reduced", device="cuda:0")
+        H.factor()
+        res = H.solve(f, tol)
+        torch.cuda.synchronize()
+        tf = ts = 0.0
+        for _ in range(reps):
+            ta = time.perf_counter()
+            H.factor()
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            res = H.solve(f, tol)
+            torch.cuda.synchronize()
+            tf += tb - ta
+            ts += time.perf_counter() - tb
+        slots = H.factor_slots
+        H.close()
+        ms = (tf + ts) / reps * 1e3
+        out[prec] = {"ms_per_step": ms, "factor_ms": tf / reps * 1e3, "solve_ms": ts / reps * 1e3,
+                     "value": f.shape[0] * wl.n_points / (ms / 1e3), "factor_slots": slots,
+                     "iters": {"min": min(res.iters), "max": max(res.iters),
+                               "mean": float(np.mean(res.iters))},
+                     "relres_max": max(res.relres)}
+        print(f"# lens {prec}: {ms:.0f} ms per step, iterations {sorted(set(res.iters))}",
+              file=sys.stderr, flush=True)
+    out["mixed_vs_c128"] = out["mixed"]["value"] / out["c128"]["value"]
+    return out
+
+
 def batch_main(args):
     """Eight uneven layered problems (500^2 ... 2000^2, 8 RHS each): one step = factor all +
     solve all concurrently (helm_solve_batch, one stream per problem); the same handles are
@@ -489,7 +534,7 @@ def main():
     print(f"# {wl.name}: padded {wl.N_x}x{wl.N_y}, J={wl.J}, nrhs={nrhs}, {args.prec}/{args.mode}",
           file=sys.stderr, flush=True)
     H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
-                  pml_iface_s0=wl.pml_iface_s0,
+                  pml_iface_s0=wl.pml_iface_s0, sweep=args.sweep,
                   prec=args.prec, mode=args.mode, chunk=args.chunk, device=dev)
     tuned = None
     if args.chunk == 0 and wl.dim == 2:
@@ -584,13 +629,14 @@ def main():
                    "mode": args.mode, "chunk_rows": H.chunk_rows, "tol": args.tol,
                    "autotune": tuned, "factor_path": H.factor_path if wl.dim == 3 else None,
                    "factor_slots": H.factor_slots, "pml_iface_s0": wl.pml_iface_s0 if wl.pml_iface_s0 is not None else "2.5 per pad cell",
-                   "graph_replay": args.mode == "reduced",
+                   "graph_replay": args.mode == "reduced", "sweep": args.sweep,
                    "step": "helm_factor + helm_solve"},
         "solve_only_value": pts / (solve_ms / 1e3), "solve_ms": solve_ms,
         "factor_ms": t_fac * 1e3 / args.steps,
         "iters": {"min": min(res.iters), "max": max(res.iters),
                   "mean": float(np.mean(res.iters))},
         "relres_max": max(res.relres), "restarts": res.restarts,
+        "preconditioner_applications": res.ap_applies,
         "kernel_ms_per_step": {k: v[1] for k, v in kt_all.items()},
         "kernel_ms_per_step_from": "one untimed step with every class timed",
         "roofline": roof,
@@ -604,6 +650,8 @@ def main():
         out["mixed_vs_c128_batched"] = out["solve_only_value"] / out["c128"]["batched"]["solve_only_value"]
         out["mixed_vs_c128_plain"] = (out["solve_only_value"]
                                       / out["c128"]["plain_one_rhs_per_solve"]["solve_only_value"])
+    if wl.dim == 2 and wl.name.startswith("layers") and not args.no_lens_leg:
+        out["lens_1000"] = lens_leg(args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_baseline)
         if args.cpu_baseline == "full" and args.oracle_record_out:

@@ -91,6 +91,29 @@ typedef struct {
                            only to the strip operators A^(j) (Sec. 2.1, definition of
                            Omega^(j)), i.e. to the preconditioner P: they change the
                            iteration count, never the solution                          */
+    int sweep;          /* 0 (default): the double sweep P of the paper, upward then
+                           downward on the residual (Sec. 2.1).  1: the concurrent double
+                           sweep P_c (the paper's remark that both sequences can run at the
+                           same time, Sec. 1 and 3.1, in a 2-D form with no crossing point):
+                           an upward sweep on f, a downward sweep on f on a stream of its
+                           own, and the strip solves of f on D^(j) and D~^(j) (sources both
+                           sweeps contain) on a third; P_c f = v + w' - z on every core.
+                           Half the sequential depth and 1.5 times the strip solves of P,
+                           exact for media that do not vary with x, weaker than P where they
+                           do.  Its reduced form keeps the columns beta_j - 1, beta_j        */
+    int transmission;   /* 0 (default): PML transmission, the strips padded with PML
+                           (Sec. 2.1).  1: Robin transmission, the comparison method of
+                           Sec. 4.4: subdomains D^(j) plus the extra column, unpadded, with
+                           first-order absorbing conditions d_n u + i k u on their internal
+                           sides; a ghost column beyond each side is eliminated, which adds
+                           -alpha_x(b) alpha_x(b +- 1/2) rho / h^2, rho = (1 + i k h/2) /
+                           (1 - i k h/2) with k at the side's column b, to that column's
+                           diagonal and puts the neighbour's data (V_o - rho V_i) / h^2 on
+                           it.  2-D, sweep 0 and HELM_FULL only (else HELM_EINVAL);
+                           pml_iface and pml_iface_s0 are then unused                        */
+    int restart;        /* GMRES cycle length (basis vectors kept before a restart); 0
+                           (default): 60 in HELM_REDUCED, 30 in HELM_FULL, whose basis
+                           vectors are whole fields.  Capped at max_iter                     */
 } helm_opts;
 
 /* Default options for a 2-D problem of n_x x n_y interior points. */
@@ -127,7 +150,9 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
  * rounded (helm_get_factor_path tells which ran; the environment variable
  * HELM_FACTOR3_FP64=1 selects that route from the start).  Strips or slabs with identical
  * operators share one factorisation in every mode (helm_get_factor_slots).
- * HELM_ESINGULAR if a pivot is zero or not finite.
+ * HELM_ESINGULAR if a pivot is zero or not finite, or (2-D) if a block inverted in the
+ * factorisation has a 1-norm condition estimate ||S||_1 ||S^-1||_1 above 1e13 (numerically
+ * singular in FP64: the strip operator is at or near a resonance, e.g. without PML).
  */
 helm_status helm_factor(helm_t H);
 
@@ -156,17 +181,21 @@ helm_status helm_autotune(helm_t H, int nrhs, const void* rhs, const int* cand, 
  * start (Sec. 4: reduction by 1e-6, capped at tol ||f||), then checking the true
  * residual ||f - A u|| / ||f|| in FP64 and, while it exceeds tol, running another GMRES
  * cycle on that residual r (iterative refinement; right-hand sides that already meet tol
- * take no part), up to max_iter applications of A P in total.  In REDUCED mode such a
- * cycle starts from u~ = P r instead of the strip solves of Algorithm 2: r - A P r lives
- * on the same interface columns (Sec. 2.1), and the sweep also removes what the
- * complex64 strip solves leave off those columns; this application of P counts as one
- * iteration.  When the first cycle ran 16 or more iterations, a later cycle also keeps
+ * take no part), up to max_iter applications of the preconditioner in total.  In REDUCED
+ * mode such a cycle starts from u~ = P r instead of the strip solves of Algorithm 2:
+ * r - A P r lives on the same interface columns (Sec. 2.1), and the sweep also removes
+ * what the complex64 strip solves leave off those columns.  HELM_MIXED_C64 ends its first
+ * cycle at three times the rounding noise that Algorithm 2 leaves off the reduced columns
+ * (the true residual cannot fall below about that level before the restart), measured
+ * per right-hand side in each solve, so that a solve does not depend on earlier ones.
+ * When the first cycle ran 16 or more iterations, a later cycle also keeps
  * its new directions orthogonal to the images of the previous cycle's Krylov basis and
  * minimises over both spaces (Krylov recycling; fewer iterations, same stopping rule).
  *   rhs     device, nrhs * N_y * N_x complex128 (padded grid)
  *   u       device, same shape, output
- *   iters   host, nrhs ints (may be NULL): GMRES iterations (applications of A P, plus
- *           one per REDUCED restart)
+ *   iters   host, nrhs ints (may be NULL): GMRES iterations of every cycle, the paper's
+ *           count (Sec. 4); the applications of P that start a REDUCED restart, like
+ *           Algorithm 2 and 4, are not iterations (helm_get_stats counts every application)
  *   relres  host, nrhs doubles (may be NULL): explicit ||f - A u|| / ||f||
  * HELM_ESTATE before helm_factor; HELM_ENOCONV if some right-hand side missed tol after
  * max_iter (u and relres still hold the best iterate).
@@ -217,7 +246,8 @@ helm_status helm_grad(helm_t H, int nsrc, const void* src, int nrec, const int64
 
 /*
  * The preconditioner alone (Sec. 2.1, end): out = P f = v + w for nrhs fields, computed
- * in the handle's precision.  f, out: device, nrhs * N_y * N_x complex128.
+ * in the handle's precision (opts.sweep = 1: P_c f = v + w' - z).  f, out: device,
+ * nrhs * N_y * N_x complex128.
  */
 helm_status helm_apply_P(helm_t H, int nrhs, const void* f, void* out);
 
@@ -225,7 +255,8 @@ helm_status helm_apply_P(helm_t H, int nrhs, const void* f, void* out);
  * Algorithm 3 on the reduced unknowns (Sec. 2.3): out = (A P psi) restricted to the
  * columns beta_j, beta_j + 1 of every internal interface.  psi, out: device,
  * nrhs * N_y * 2(J-1) complex128, [rhs][y][interface column], interface columns ordered
- * beta_1, beta_1+1, beta_2, beta_2+1, ...
+ * beta_1, beta_1+1, beta_2, beta_2+1, ...  With opts.sweep = 1: (A P_c psi) on the
+ * columns beta_j - 1, beta_j, ordered beta_1 - 1, beta_1, beta_2 - 1, ...
  */
 helm_status helm_apply_AP_reduced(helm_t H, int nrhs, const void* psi, void* out);
 
@@ -291,7 +322,9 @@ helm_status helm_get_factor_path(helm_t H, int* path);
  * last is a separator) and the number of chunks (host ints). */
 helm_status helm_get_chunks(helm_t H, int* rows_per_chunk, int* nchunks);
 
-/* Counters of the last helm_solve: total A P applications and restarts (host). */
+/* Counters of the last helm_solve: applications of the preconditioner (the GMRES
+ * iterations of the batch plus one per REDUCED restart; Algorithms 2 and 4 not counted),
+ * restarts, and the solve's wall time in milliseconds (host). */
 helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* solve_ms);
 
 /*

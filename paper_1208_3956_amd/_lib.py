@@ -46,6 +46,9 @@ class HelmOpts(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("graph", ctypes.c_int),
         ("pml_iface_s0", ctypes.c_double),
+        ("sweep", ctypes.c_int),
+        ("transmission", ctypes.c_int),
+        ("restart", ctypes.c_int),
     ]
 
 

@@ -21,7 +21,27 @@ struct GJShared {
     double2 fcol[2][WP];     // pivot column of the step (double-buffered: one barrier per step)
     int piv[2];
     int perm[WP];
+    double nrm[2][4];        // per wave: largest column 1-norm of the block, of its inverse
 };
+
+// A block whose 1-norm condition estimate ||S||_1 ||S^-1||_1 exceeds this is numerically
+// singular in FP64 (its inverse has no correct digit): the factorisation reports it
+constexpr double GJ_COND_MAX = 1e13;
+
+// sum over the 64 lanes of a wavefront (butterfly, every lane gets the sum)
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// largest column 1-norm over this wave's 16 register columns (rows i >= W are zero)
+__device__ inline double wave_colnorm_max(const double2 (&M)[16]) {
+    double best = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) best = fmax(best, wave_sum(sqrt(M[r].x * M[r].x + M[r].y * M[r].y)));
+    return best;
+}
 
 // wavefront maximum (device library; declared by the HIP headers only on request)
 extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_max_u64(unsigned long long);
@@ -40,7 +60,8 @@ __device__ inline double readlane_f64(double v, int lane) {
 
 // Inverse of the leading W x W block of the matrix in M (zero elsewhere), written column-major
 // with leading dimension WP to dst (zero outside the leading block); ends with a barrier so
-// that dst can be read back by the workgroup.  Sets err when a pivot is zero or not finite.
+// that dst can be read back by the workgroup.  Sets bit 1 of err when a pivot is zero or not
+// finite, bit 2 when the 1-norm condition estimate exceeds GJ_COND_MAX.
 __device__ inline void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, double2* __restrict__ dst,
                                 float2* __restrict__ dst32, int* err) {
     const int i = threadIdx.x & (WP - 1), g = threadIdx.x >> 6;
@@ -48,6 +69,10 @@ __device__ inline void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, do
     int my_step = i;                               // rows beyond W keep their position
     double2 my_inv = cmk<double2>(1.0, 0.0);
     int rot = 0;                                   // rotations done: M[r] holds column g + 4 (r + rot)
+    {
+        const double cn = wave_colnorm_max(M);
+        if ((threadIdx.x & 63) == 0) sh.nrm[0][g] = cn;
+    }
     for (int kk = 0; 4 * kk < W; ++kk) {
 #pragma unroll
         for (int gg = 0; gg < 4; ++gg) {
@@ -102,15 +127,28 @@ __device__ inline void gj_invert_store(double2 (&M)[16], int W, GJShared& sh, do
         M[15] = m0;
         ++rot;
     }
+    double2 out[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int j = g + 4 * ((r + rot) & 15);
         const int pj = j < W ? sh.perm[j] : j;
         const double2 v = cmul(M[r], my_inv);
+        out[r] = j < W ? v : cmk<double2>(0.0, 0.0);
         dst[(size_t)pj * WP + my_step] = v;
         if (dst32) dst32[(size_t)pj * WP + my_step] = make_float2((float)v.x, (float)v.y);
     }
+    // permuting rows and columns leaves the set of column 1-norms unchanged: the largest
+    // over the stored array is ||S^-1||_1 (the identity outside the leading block excluded)
+    {
+        const double cn = wave_colnorm_max(out);
+        if ((threadIdx.x & 63) == 0) sh.nrm[1][g] = cn;
+    }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < 4; ++q) { a = fmax(a, sh.nrm[0][q]); b = fmax(b, sh.nrm[1][q]); }
+        if (!(a * b <= GJ_COND_MAX)) atomicOr(err, 2);
+    }
 }
 
 

@@ -26,8 +26,16 @@ struct Work {
     void* Yw = nullptr;
     double2 *V = nullptr, *G = nullptr, *PF = nullptr, *Psi = nullptr, *Wf = nullptr,
             *Hf = nullptr, *Ut = nullptr, *R = nullptr, *Tup = nullptr, *Tdn = nullptr;
-    // interface-window fields of the reduced operator (v, g = psi - A v, w)
+    // interface-window fields of the reduced operator (v, g = psi - A v, w; concurrent sweep:
+    // v, z, w')
     double2 *Vw = nullptr, *Gw = nullptr, *Ww = nullptr;
+    // concurrent sweep: strip-solver workspaces of the downward chain and of the z solves, and
+    // the input field of its reduced operator (zero off the reduced columns)
+    void *Yw2 = nullptr, *Yw3 = nullptr;
+    double2* PsiC = nullptr;
+    // Robin transmission: [2][nrhs][Nrow], a zero half and the data (V_o - rho V_i) / h^2 of
+    // the strip being solved (the transmission source is coef * (second half - first half))
+    double2* Rob = nullptr;
     // GMRES.  gnrhs is the right-hand-side capacity of every buffer below and of R, Ut:
     // they are laid out for the nrhs of each call ([k][nrhs][n]) and reallocated when a
     // call brings more right-hand sides than they were sized for
@@ -128,13 +136,14 @@ struct helm_problem {
     int* d_err = nullptr;
     Work wk;
     int stat_ap = 0, stat_restarts = 0;
-    // complex64 path: relative residual the first GMRES cycle left behind although its own
-    // estimate was far lower (the rounding floor of the complex64 preconditioner); later
-    // solves end their first cycle near it instead of iterating below it
-    double floor_rel = 0.0;
     int dev = 0;                // HIP device of the handle
     int use_graph = 1;          // replay Algorithm 3 from a captured HIP graph (REDUCED)
     hipGraphExec_t ap_exec = nullptr;
+    int sweep = 0;              // 0: the double sweep P; 1: the concurrent double sweep P_c
+    int trans = 0;              // 0: PML transmission; 1: Robin transmission (Sec. 4.4)
+    int restart = 0;            // GMRES cycle length (0: by mode)
+    hipStream_t st_c[2] = {};   // concurrent sweep: streams of the downward chain and the z solves
+    hipEvent_t ev_c[3] = {};    // fork / join events of the concurrent sweep
     hipStream_t st_fac[FAC3_GROUPS - 1] = {};   // group streams of the 3-D complex64 factorisation
     hipStream_t cap_st = nullptr;  // private stream the graph is captured on (capture is not
                                    // allowed on the legacy default stream); replays go to st
@@ -246,7 +255,8 @@ helm_status upload(helm_t H, void** dptr, const void* src, size_t bytes) {
 // ---------------------------------------------------------------- workspaces
 void free_work(Work& w) {
     void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Vw, w.Gw, w.Ww, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
-                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin, w.basis_old};
+                  w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin, w.basis_old,
+                  w.Yw2, w.Yw3, w.PsiC, w.Rob};
     for (void* p : ps) dfree(p);
     w = Work();
 }
@@ -265,6 +275,17 @@ helm_status ensure_sweep_ws(helm_t H, int nrhs) {
     const size_t yw = g.dim == 3 ? (size_t)(g.Ny + 2) * g.Bp * rhs_pad16(nrhs) * sizeof(double2)
                                  : (size_t)nrhs * g.Ny * WP * sizeof(double2);
     CHK(dmalloc(H, &w.Yw, yw));
+    if (H->sweep == 1) {
+        CHK(dmalloc(H, &w.Yw2, yw));
+        CHK(dmalloc(H, &w.Yw3, yw));
+        CHK(dmalloc(H, &w.PsiC, fb));
+        HIPCHK(hipMemsetAsync(w.PsiC, 0, fb, H->st));
+    }
+    if (H->trans == 1) {
+        const size_t rb = (size_t)2 * nrhs * g.Nrow() * sizeof(double2);
+        CHK(dmalloc(H, &w.Rob, rb));
+        HIPCHK(hipMemsetAsync(w.Rob, 0, rb, H->st));
+    }
     double2** fields[] = {&w.V, &w.G, &w.PF, &w.Psi, &w.Wf, &w.Hf};
     for (double2** f : fields) {
         CHK(dmalloc(H, f, fb));
@@ -364,6 +385,26 @@ bool win_off(const helm::Geom& g, int s, int j, int x0, int n, int* off) {
     return x0 >= w0 && x0 + n <= w0 + helm::IWIN;
 }
 
+// Robin transmission source of a strip (Sec. 4.4): the ghost beyond its boundary column
+// q_t carries the neighbour field's Robin data, which moves (V_o - rho_j V_i) / h^2 onto
+// column q_t; rho_j of interface j (column beta_j), V_o / V_i the neighbour's traces at the
+// columns outside / inside the strip.
+helm_status robin_source(helm_t H, int nrhs, int j, const double2* vo, const double2* vi, int q_t,
+                         helm::IOSpec& io) {
+    const auto& g = H->g;
+    Work& w = H->wk;
+    const long plane = (long)nrhs * g.Nrow();
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_robin_data(vo, vi, H->t.rho + (size_t)(j - 1) * g.Nrow(),
+                                                           w.Rob + plane, nrhs, g.Nrow(),
+                                                           1.0 / (g.h * g.h), H->st)));
+    io.trA = w.Rob;
+    io.trB = w.Rob + plane;
+    io.q_t = q_t;
+    io.t_cols = 1;
+    io.coef = 1.0;
+    return HELM_OK;
+}
+
 // Upward sweep (eq. solve_upward) for strips s0..J-1.  full: keep v^(j) on its whole core;
 // otherwise only the columns the interface residuals read.  src = input field.
 helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
@@ -384,7 +425,11 @@ helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
             io.src = src;
             io.src_lo = S.core_lo - S.a; io.src_hi = S.core_hi - S.a;
         }
-        if (s > s0) {
+        if (s > s0 && H->trans == 1) {
+            // Robin data of v^(j-1) at its columns beta_s - 1 (outside) and beta_s (inside)
+            CHK(robin_source(H, nrhs, s, trace(w.Tup, s - 1, 0, nrhs, g.Nrow()),
+                             trace(w.Tup, s - 1, 1, nrhs, g.Nrow()), 0, io));
+        } else if (s > s0) {
             io.trA = trace(w.Tup, s - 1, 0, nrhs, g.Nrow());
             io.trB = trace(w.Tup, s - 1, 1, nrhs, g.Nrow());
             io.q_t = g.beta[s] - 1 - S.a;
@@ -437,7 +482,12 @@ helm_status sweep_down(helm_t H, int nrhs, double2* dst, bool full) {
                 return fail(H, HELM_EINVAL, "columns outside the interface window");
             io.dst_rs = g.Nrow() * wrow; io.dst_ls = (int)wrow;
         }
-        if (s < g.J - 2) {
+        if (s < g.J - 2 && H->trans == 1) {
+            // Robin data of w^(j+1) at its columns beta_{s+1} + 1 (outside) and beta_{s+1}
+            // (inside)
+            CHK(robin_source(H, nrhs, s + 1, trace(w.Tdn, s + 1, 1, nrhs, g.Nrow()),
+                             trace(w.Tdn, s + 1, 0, nrhs, g.Nrow()), S.W - 1, io));
+        } else if (s < g.J - 2) {
             io.trA = trace(w.Tdn, s + 1, 0, nrhs, g.Nrow());
             io.trB = trace(w.Tdn, s + 1, 1, nrhs, g.Nrow());
             io.q_t = g.beta[s + 1] - S.a;
@@ -495,6 +545,199 @@ helm_status apply_AP_reduced(helm_t H, int nrhs, const double2* psi, double2* ou
     // h = g - A w on the reduced columns; output psi - h
     HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_stencil_win(1, H->t, g, nrhs, w.Ww, psi, w.Gw, out, H->st)));
     return HELM_OK;
+}
+
+// ---------------------------------------------------------------- concurrent double sweep
+// P_c f = v + w' - z on every core D^(j): v the upward sweep on f (eq. solve_upward), w' a
+// downward sweep on f (eq. solve_downward with f~^(j) in place of the residual), z^(j) the
+// strip solve of f on D^(j) and D~^(j) (the sources both chains contain).  The upward chain
+// runs on the handle's stream, the downward chain and the z solves on two streams of their
+// own, each with its own strip-solver workspace; f - A P_c f lives on the columns
+// beta_j - 1, beta_j, where the reduced form of this sweep keeps its unknowns.
+
+// strip solve of strip s on stream q with workspace yw
+helm_status solve_on(helm_t H, hipStream_t q, int s, int nrhs, const helm::IOSpec& io, void* yw) {
+    const hipStream_t keep = H->st;
+    H->st = q;
+    helm_status r = strip_solve_any(H, s, nrhs, io, yw);
+    H->st = keep;
+    return r;
+}
+
+helm_status conc_streams(helm_t H) {
+    for (hipStream_t& q : H->st_c)
+        if (!q) HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+    for (hipEvent_t& e : H->ev_c)
+        if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return HELM_OK;
+}
+
+// Window outputs of a strip: its first two core columns into the window of interface s
+// (s >= 1), its last two into that of interface s + 1 (s <= J - 2).
+helm_status conc_windows(helm_t H, int s, helm::IOSpec& io) {
+    const auto& g = H->g;
+    const auto& S = g.strips[s];
+    const long wrow = (long)(g.J - 1) * helm::IWIN;
+    io.dst_rs = g.Nrow() * wrow; io.dst_ls = (int)wrow;
+    io.targets_only = 1;
+    int k = 0;
+    bool in = true;
+    if (s >= 1) {
+        io.o_lo[k] = S.core_lo - S.a; io.o_hi[k] = io.o_lo[k] + 2;
+        in = in && win_off(g, s, s, S.core_lo, 2, &io.dst_off[k]);
+        ++k;
+    }
+    if (s <= g.J - 2) {
+        io.o_lo[k] = S.core_hi - 2 - S.a; io.o_hi[k] = S.core_hi - S.a;
+        in = in && win_off(g, s, s + 1, S.core_hi - 2, 2, &io.dst_off[k]);
+        ++k;
+    }
+    if (!in) return fail(H, HELM_EINVAL, "core columns outside the interface window");
+    return HELM_OK;
+}
+
+// The three parts of P_c src.  full: v, w', z on whole cores into dv, dw, dz (full fields);
+// otherwise (src zero off the reduced columns) on the interface windows Vw, Ww, Gw.
+helm_status sweep_concurrent(helm_t H, int nrhs, const double2* src, bool full, double2* dv, double2* dw,
+                             double2* dz) {
+    const auto& g = H->g;
+    Work& w = H->wk;
+    const int J = g.J;
+    const double ih2 = 1.0 / (g.h * g.h);
+    CHK(conc_streams(H));
+    const hipStream_t qa = H->st, qb = H->st_c[0], qc = H->st_c[1];
+    HIPCHK(hipEventRecord(H->ev_c[0], qa));
+    HIPCHK(hipStreamWaitEvent(qb, H->ev_c[0], 0));
+    HIPCHK(hipStreamWaitEvent(qc, H->ev_c[0], 0));
+    // reduced input: strip J - 1 has no source on D~^(J) (so w'^(J) = 0) nor on D and D~
+    const int dn_first = full ? J - 1 : J - 2;
+    const int z_last = full ? J - 1 : J - 2;
+    for (int i = 0; i < J; ++i) {
+        {   // upward, strip i
+            const int s = i;
+            const auto& S = g.strips[s];
+            helm::IOSpec io = field_io(H, s);
+            io.src = src; io.src_lo = S.core_lo - S.a; io.src_hi = S.core_hi - S.a;
+            if (s > 0) {
+                io.trA = trace(w.Tup, s - 1, 0, nrhs, g.Nrow());
+                io.trB = trace(w.Tup, s - 1, 1, nrhs, g.Nrow());
+                io.q_t = g.beta[s] - 1 - S.a;
+                io.coef = -ih2;
+            }
+            if (s < J - 1) {
+                io.tro0 = trace(w.Tup, s, 0, nrhs, g.Nrow());
+                io.tro1 = trace(w.Tup, s, 1, nrhs, g.Nrow());
+                io.qo0 = g.beta[s + 1] - 1 - S.a;
+                io.qo1 = g.beta[s + 1] - S.a;
+            }
+            if (full) {
+                io.dst = dv; io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = S.core_hi - S.a;
+            } else {
+                io.dst = w.Vw;
+                CHK(conc_windows(H, s, io));
+            }
+            CHK(solve_on(H, qa, s, nrhs, io, w.Yw));
+        }
+        if (dn_first - i >= 0) {   // downward, strip dn_first - i
+            const int s = dn_first - i;
+            const auto& S = g.strips[s];
+            helm::IOSpec io = field_io(H, s);
+            io.src = src; io.src_lo = S.kdn_lo - S.a; io.src_hi = S.kdn_hi - S.a;
+            if (s < dn_first) {
+                io.trA = trace(w.Tdn, s + 1, 0, nrhs, g.Nrow());
+                io.trB = trace(w.Tdn, s + 1, 1, nrhs, g.Nrow());
+                io.q_t = g.beta[s + 1] - S.a;
+                io.coef = ih2;
+            }
+            if (s > 0) {
+                io.tro0 = trace(w.Tdn, s, 0, nrhs, g.Nrow());
+                io.tro1 = trace(w.Tdn, s, 1, nrhs, g.Nrow());
+                io.qo0 = g.beta[s] - S.a;
+                io.qo1 = g.beta[s] + 1 - S.a;
+            }
+            if (full) {
+                io.dst = dw; io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = S.core_hi - S.a;
+            } else {
+                io.dst = w.Ww;
+                CHK(conc_windows(H, s, io));
+            }
+            CHK(solve_on(H, qb, s, nrhs, io, w.Yw2));
+        }
+        if (i <= z_last) {   // the strip's own sources, strip i
+            const int s = i;
+            const auto& S = g.strips[s];
+            helm::IOSpec io = field_io(H, s);
+            io.src = src;
+            io.src_lo = std::max(S.core_lo, S.kdn_lo) - S.a;
+            io.src_hi = std::min(S.core_hi, S.kdn_hi) - S.a;
+            if (full) {
+                io.dst = dz; io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = S.core_hi - S.a;
+            } else {
+                io.dst = w.Gw;
+                CHK(conc_windows(H, s, io));
+            }
+            CHK(solve_on(H, qc, s, nrhs, io, w.Yw3));
+        }
+    }
+    HIPCHK(hipEventRecord(H->ev_c[1], qb));
+    HIPCHK(hipEventRecord(H->ev_c[2], qc));
+    HIPCHK(hipStreamWaitEvent(qa, H->ev_c[1], 0));
+    HIPCHK(hipStreamWaitEvent(qa, H->ev_c[2], 0));
+    return HELM_OK;
+}
+
+// out = P_c f on the whole grid
+helm_status apply_Pc_full(helm_t H, int nrhs, const double2* f, double2* out) {
+    CHK(ensure_sweep_ws(H, nrhs));
+    Work& w = H->wk;
+    CHK(sweep_concurrent(H, nrhs, f, true, w.V, w.Wf, w.G));
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_sum_diff(w.V, w.Wf, w.G, out, (long)nrhs * H->g.Nrow() * H->g.Nx, H->st)));
+    return HELM_OK;
+}
+
+// out = (A P_c psi) on the columns beta_j - 1, beta_j, for psi given there
+helm_status apply_APc_reduced(helm_t H, int nrhs, const double2* psi, double2* out) {
+    CHK(ensure_sweep_ws(H, nrhs));
+    const auto& g = H->g;
+    Work& w = H->wk;
+    if (g.J < 2) return HELM_OK;
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(psi, H->t.rcols, 2 * (g.J - 1), nrhs, g.Nrow(), g.Nx, w.PsiC, H->st)));
+    CHK(sweep_concurrent(H, nrhs, w.PsiC, false, nullptr, nullptr, nullptr));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_stencil_win(2, H->t, g, nrhs, w.Vw, w.Ww, w.Gw, out, H->st)));
+    return HELM_OK;
+}
+
+// The starting point of the reduced form of P_c: u~ from independent strip solves of f on
+// D^(j), kept on D^(j) (f - A u~ then lives on the columns beta_j - 1, beta_j); the solves
+// go round the three streams
+helm_status conc_setup(helm_t H, int nrhs, const double2* f, double2* ut) {
+    const auto& g = H->g;
+    Work& w = H->wk;
+    CHK(conc_streams(H));
+    const hipStream_t qs[3] = {H->st, H->st_c[0], H->st_c[1]};
+    void* yws[3] = {w.Yw, w.Yw2, w.Yw3};
+    HIPCHK(hipEventRecord(H->ev_c[0], H->st));
+    HIPCHK(hipStreamWaitEvent(qs[1], H->ev_c[0], 0));
+    HIPCHK(hipStreamWaitEvent(qs[2], H->ev_c[0], 0));
+    for (int s = 0; s < g.J; ++s) {
+        const auto& S = g.strips[s];
+        helm::IOSpec io = field_io(H, s);
+        io.src = f;
+        io.src_lo = S.core_lo - S.a; io.src_hi = S.core_hi - S.a;
+        io.dst = ut;
+        io.o_lo[0] = io.src_lo; io.o_hi[0] = io.src_hi;
+        CHK(solve_on(H, qs[s % 3], s, nrhs, io, yws[s % 3]));
+    }
+    HIPCHK(hipEventRecord(H->ev_c[1], qs[1]));
+    HIPCHK(hipEventRecord(H->ev_c[2], qs[2]));
+    HIPCHK(hipStreamWaitEvent(H->st, H->ev_c[1], 0));
+    HIPCHK(hipStreamWaitEvent(H->st, H->ev_c[2], 0));
+    return HELM_OK;
+}
+
+// the preconditioner of the handle's sweep on whole fields
+helm_status apply_P_any(helm_t H, int nrhs, const double2* f, double2* out) {
+    return H->sweep == 1 ? apply_Pc_full(H, nrhs, f, out) : apply_P_full(H, nrhs, f, out);
 }
 
 // Algorithm 2: u~ on D~^(j) from independent strip solves with f on D~^(j).
@@ -599,6 +842,14 @@ helm_status ensure_gmres_ws(helm_t H, int nrhs, long n, int mwant) {
     return HELM_OK;
 }
 
+// the reduced operator of the handle's sweep (Algorithm 3, or its concurrent counterpart)
+helm_status apply_AP_red(helm_t H, int nrhs, const double2* x, double2* out) {
+    return H->sweep == 1 ? apply_APc_reduced(H, nrhs, x, out) : apply_AP_reduced(H, nrhs, x, out);
+}
+
+// columns of the reduced unknowns: beta_j, beta_j + 1 (P), beta_j - 1, beta_j (P_c)
+const int* red_cols(helm_t H) { return H->sweep == 1 ? H->t.rcols : H->t.redcols; }
+
 // Destroys the captured reduced operator once its last replay has completed.
 helm_status drop_graph(helm_t H) {
     if (!H->ap_exec) return HELM_OK;
@@ -612,13 +863,13 @@ helm_status drop_graph(helm_t H) {
 helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
     H->stat_ap += 1;
     if (H->mode == HELM_FULL) {
-        CHK(apply_P_full(H, nrhs, x, H->wk.PF));
+        CHK(apply_P_any(H, nrhs, x, H->wk.PF));
         HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, H->g, nrhs, H->wk.PF, nullptr, out, H->st)));
         return HELM_OK;
     }
     // kernel timing brackets launches with events, which a graph replay cannot time here
     // (hipEventElapsedTime rejects events recorded by graph nodes): timed runs go eagerly
-    if (!H->use_graph || H->timer) return apply_AP_reduced(H, nrhs, x, out);
+    if (!H->use_graph || H->timer) return apply_AP_red(H, nrhs, x, out);
     // graph replay: the captured launches read the fixed buffer apin and write `out`
     Work& w = H->wk;
     CHK(ensure_sweep_ws(H, nrhs));
@@ -633,7 +884,7 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
         const hipStream_t user_st = H->st;
         HIPCHK(hipStreamBeginCapture(H->cap_st, hipStreamCaptureModeRelaxed));
         H->st = H->cap_st;
-        helm_status cs = apply_AP_reduced(H, nrhs, w.apin, out);
+        helm_status cs = apply_AP_red(H, nrhs, w.apin, out);
         H->st = user_st;
         hipError_t ce = hipStreamEndCapture(H->cap_st, &graph);
         if (cs != HELM_OK) { if (graph) (void)hipGraphDestroy(graph); return cs; }
@@ -915,6 +1166,15 @@ helm_status build_aug(helm_t H, int nrhs, long n, double2* b, const std::vector<
     return HELM_OK;
 }
 
+// first-cycle stop of the complex64 path, relative to the rounding noise Algorithm 2 leaves
+// off the reduced columns.  The true residual after a first cycle run to tol stalls at 4 to
+// 7 times that noise (2000^2 layers: noise 9.1e-6, stall 6.4e-5; 1000^2 lens: 6.0e-6 and
+// 2.2e-5 of ||f||), so the cycle stops at 3 times it: iterating further gains nothing, the
+// restart starts from the stall anyway
+#ifndef FLOOR_PER_NOISE
+#define FLOOR_PER_NOISE 3.0
+#endif
+
 helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double tol,
                        int* iters, double* relres) {
     const auto& g = H->g;
@@ -924,7 +1184,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     const int nred = 2 * (g.J - 1);
     const bool reduced = H->mode == HELM_REDUCED && nred > 0;
     const long n = reduced ? g.Nrow() * nred : nfull;
-    CHK(ensure_gmres_ws(H, nrhs, n, std::min(H->max_iter, reduced ? 60 : 30)));
+    CHK(ensure_gmres_ws(H, nrhs, n, std::min(H->max_iter, H->restart > 0 ? H->restart : reduced ? 60 : 30)));
     std::vector<double> fn, rn;
     CHK(norms(H, f, nrhs, nfull, fn));
     // u is first written at the end of cycle 0 (u = correction), so it starts unset
@@ -933,8 +1193,6 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     int used = 0;
     H->stat_restarts = -1;
     bool ok = false;
-    std::vector<double> est0;      // GMRES residual estimates at the end of the first cycle
-    bool floor_used = false;       // the first cycle ended at the recorded floor
     std::vector<std::vector<cd>> hess;   // Hessenberg columns of the last cycle (reduced)
     Aug aug;                       // recycled space of a restart (reduced)
     // an augmented cycle's Hessenberg matrix describes the projected operator
@@ -947,14 +1205,6 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
         else
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, u, f, w.R, H->st)));
         CHK(norms(H, w.R, nrhs, nfull, rn));
-        if (cycle == 1 && H->prec != HELM_C128) {
-            // a first cycle that ran far below its true residual measures the floor; one
-            // that stopped at the recorded floor re-measures it
-            double fl = 0.0;
-            for (int r = 0; r < nrhs; ++r)
-                if (fn[r] > 0 && (floor_used || rn[r] > 4.0 * est0[r])) fl = std::max(fl, rn[r] / fn[r]);
-            if (fl > 0.0 || !floor_used) H->floor_rel = fl;
-        }
         bool conv = true;
         for (int r = 0; r < nrhs; ++r) conv = conv && (rn[r] <= tol * fn[r] || fn[r] == 0.0);
         if (trace_on())
@@ -977,23 +1227,37 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
             // reduced columns (Sec. 2.1, exact arithmetic), and the sweep removes the
             // complex64 rounding residual left off those columns (which the reduced GMRES
             // cannot see) together with its transmission across the interfaces, where
-            // strip solves alone would leave it on the interface columns.  This
-            // application of P is counted as an iteration.
+            // strip solves alone would leave it on the interface columns.
             if (cycle == 0) {
-                CHK(reduced_setup(H, nrhs, w.R, w.Ut));
+                if (H->sweep == 1) CHK(conc_setup(H, nrhs, w.R, w.Ut));
+                else CHK(reduced_setup(H, nrhs, w.R, w.Ut));
             } else {
+                // the restart's counterpart of Algorithm 2: an application of P, not a GMRES
+                // iteration (it is counted in the operator applications of helm_get_stats
+                // and against max_iter)
                 H->stat_ap += 1;
-                CHK(apply_P_full(H, nrhs, w.R, w.Ut));
-                for (int r = 0; r < nrhs; ++r)
-                    if (rn[r] > tol * fn[r]) total[r] += 1;
+                CHK(apply_P_any(H, nrhs, w.R, w.Ut));
                 used += 1;
             }
             HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
-            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, red_cols(H), nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
             b = w.red;
             if (cycle > 0 && !prev_aug) CHK(build_aug(H, nrhs, n, w.red, hess, its, aug));
         }
         CHK(norms(H, b, nrhs, n, bn));
+        // complex64, first cycle: f - A u~ off the reduced columns vanishes in exact arithmetic
+        // (Sec. 2.3), so what is there is the rounding noise of the complex64 strip solves:
+        // the level below which the reduced GMRES cannot lower the true residual.  Measured
+        // per right-hand side, so that even a handle's first solve stops its first cycle there
+        std::vector<double> noise(nrhs, 0.0);
+        if (reduced && cycle == 0 && H->prec != HELM_C128) {
+            std::vector<double> hn;
+            CHK(norms(H, w.Hf, nrhs, nfull, hn));
+            for (int r = 0; r < nrhs; ++r) noise[r] = std::sqrt(std::max(hn[r] * hn[r] - bn[r] * bn[r], 0.0));
+            if (trace_on())
+                std::fprintf(stderr, "[helm] complex64 noise of Algorithm 2 rhs0 %.3e relative\n",
+                             fn[0] > 0 ? noise[0] / fn[0] : 0.0);
+        }
         if (trace_on())
             std::fprintf(stderr, "[helm] cycle %d |b| rhs0 %.3e |f| %.3e\n", cycle, bn[0], fn[0]);
         for (int r = 0; r < nrhs; ++r) {
@@ -1003,28 +1267,25 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
             target[r] = cycle == 0 ? tol * std::min(bn[r], fn[r]) : tol * fn[r];
             // complex64: iterating the first cycle below the rounding floor of the
             // preconditioner gains nothing (the restart starts from the floor anyway)
-            if (cycle == 0 && H->floor_rel > 2.0 * tol) {
-                target[r] = std::max(target[r], 0.5 * H->floor_rel * fn[r]);
-                floor_used = true;
-            }
+            if (cycle == 0 && noise[r] > 2.0 * tol * fn[r])
+                target[r] = std::max(target[r], FLOOR_PER_NOISE * noise[r]);
         }
         // GMRES on op(y) = b; the solution increment is P y (+ u~)
         CHK(gmres_cycle(H, nrhs, n, b, bn, target, H->max_iter - used, w.w, its, resid,
                         reduced ? &hess : nullptr, aug.nv > 0 ? &aug : nullptr));
         prev_aug = aug.nv > 0;
         aug = Aug();
-        if (cycle == 0) est0 = resid;
         int kmax = 0;
         for (int r = 0; r < nrhs; ++r) { total[r] += its[r]; kmax = std::max(kmax, its[r]); }
         used += std::max(kmax, 1);
         if (reduced) {
             // Algorithm 4: u += P psi + u~   (psi scattered onto the reduced columns of Psi,
             // which is zero everywhere else: nothing but this scatter writes it)
-            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, H->t.redcols, nred, nrhs, g.Nrow(), g.Nx, w.Psi, H->st)));
-            CHK(apply_P_full(H, nrhs, w.Psi, w.Hf));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, red_cols(H), nred, nrhs, g.Nrow(), g.Nx, w.Psi, H->st)));
+            CHK(apply_P_any(H, nrhs, w.Psi, w.Hf));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_sum3(cycle == 0 ? nullptr : u, w.Hf, w.Ut, u, nrhs * nfull, H->st)));
         } else {
-            CHK(apply_P_full(H, nrhs, w.w, w.Hf));
+            CHK(apply_P_any(H, nrhs, w.w, w.Hf));
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_sum3(cycle == 0 ? nullptr : u, w.Hf, nullptr, u, nrhs * nfull, H->st)));
         }
     }
@@ -1090,6 +1351,9 @@ void helm_default_opts(helm_opts* o, int n_x, int n_y) {
     o->stream = nullptr;
     o->graph = 1;
     o->pml_iface_s0 = -1.0;     // 2.5 per cell of the pad
+    o->sweep = 0;
+    o->transmission = 0;
+    o->restart = 0;
 }
 
 helm_status helm_setup(const double* c, double omega, double h, const helm_opts* opts, int J,
@@ -1113,7 +1377,12 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if (!(h > 0) || !std::isfinite(h)) return bad("h must be positive and finite");
     if (J < 1) return bad("J must be >= 1");
     if (opts->pml_outer < 1) return bad("pml_outer must be >= 1");
-    if (J > 1 && opts->pml_iface < 1) return bad("pml_iface must be >= 1");
+    if (opts->transmission != 0 && opts->transmission != 1)
+        return bad("transmission must be 0 (PML) or 1 (Robin)");
+    const bool robin = opts->transmission == 1;
+    if (robin && (opts->dim != 2 || opts->sweep != 0 || opts->mode == HELM_REDUCED))
+        return bad("the Robin transmission is built for 2-D problems, the double sweep and the full form");
+    if (J > 1 && !robin && opts->pml_iface < 1) return bad("pml_iface must be >= 1");
     double cmax = 0.0;
     for (size_t i = 0; i < (size_t)nx * ny * nz; ++i) {
         if (!(c[i] > 0.0) || !std::isfinite(c[i])) return bad("c must be positive and finite");
@@ -1153,8 +1422,10 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         S.lpad = s > 0; S.rpad = s < J - 1;
         S.core_lo = g.beta[s]; S.core_hi = g.beta[s + 1];
         S.dom_lo = S.core_lo; S.dom_hi = S.core_hi + (S.rpad ? 1 : 0);
-        S.a = S.core_lo - (S.lpad ? g.w : 0);
-        S.W = S.dom_hi + (S.rpad ? g.w : 0) - S.a;
+        // Robin subdomains are D^(j) and the extra column, with no pads
+        const int pad = robin ? 0 : g.w;
+        S.a = S.core_lo - (S.lpad ? pad : 0);
+        S.W = S.dom_hi + (S.rpad ? pad : 0) - S.a;
         S.kdn_lo = S.core_lo + (S.lpad ? 1 : 0);
         S.kdn_hi = S.core_hi + (S.rpad ? 1 : 0);
         if (S.W > WP) return bad("padded strip " + std::to_string(s) + " is " + std::to_string(S.W) +
@@ -1175,6 +1446,11 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     H->max_iter = opts->max_iter > 0 ? opts->max_iter : 200;
     H->st = static_cast<hipStream_t>(opts->stream);
     H->use_graph = opts->graph ? 1 : 0;
+    if (opts->sweep != 0 && opts->sweep != 1) return bad("sweep must be 0 (double sweep) or 1 (concurrent)");
+    H->sweep = opts->sweep;
+    H->trans = opts->transmission;
+    if (opts->restart < 0) return bad("restart must be >= 0");
+    H->restart = opts->restart;
     if (hipGetDevice(&H->dev) != hipSuccess) H->dev = 0;
 
     // ---- tables (FP64 complex), Sec. 2.1-2.2
@@ -1218,6 +1494,35 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
             scol[(size_t)s * WP + q] = std::min(std::max(S.a + q, S.dom_lo), S.dom_hi - 1);
         }
         for (int q = 0; q <= S.W; ++q) saxh[(size_t)s * (WP + 1) + q] = d2(alpha_strip(g, S, S.a + q - 0.5));
+    }
+    // Robin transmission (Sec. 4.4): rho_j = (1 + i k h/2) / (1 - i k h/2) per row with k at
+    // column beta_j, and the ghost-elimination terms -alpha_x(b) alpha_x(b -+ 1/2) rho / h^2
+    // of the boundary columns b = beta_s (left side) and b = beta_{s+1} (right side)
+    std::vector<double2> rob, rho;
+    if (robin) {
+        auto rho_at = [&](int l, int col) {
+            const cd ikh2(0.0, 0.5 * std::sqrt(k2[(size_t)l * Nx + col]) * h);
+            return (1.0 + ikh2) / (1.0 - ikh2);
+        };
+        rob.assign((size_t)J * Ny * 2, make_double2(0, 0));
+        rho.assign((size_t)std::max(1, J - 1) * Ny, make_double2(0, 0));
+        for (int s = 1; s < J; ++s)
+            for (int l = 0; l < Ny; ++l) rho[(size_t)(s - 1) * Ny + l] = d2(rho_at(l, g.beta[s]));
+        for (int s = 0; s < J; ++s) {
+            const auto& S = g.strips[s];
+            for (int l = 0; l < Ny; ++l) {
+                if (S.lpad) {
+                    const int b = S.dom_lo;
+                    rob[((size_t)s * Ny + l) * 2] =
+                        d2(-alpha_outer(g, b, Nx) * alpha_outer(g, b - 0.5, Nx) * rho_at(l, b) * ih2);
+                }
+                if (S.rpad) {
+                    const int b = S.dom_hi - 1;
+                    rob[((size_t)s * Ny + l) * 2 + 1] =
+                        d2(-alpha_outer(g, b, Nx) * alpha_outer(g, b + 0.5, Nx) * rho_at(l, b) * ih2);
+                }
+            }
+        }
     }
     // pairs of adjacent columns per interface (the pair stencil kernel relies on it)
     std::vector<int> rcols, redcols;
@@ -1264,6 +1569,10 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
         }
         for (int k = 0; k < 8; ++k)
             if (tcol[(size_t)a * 8 + k] != tcol[(size_t)b * 8 + k]) return false;
+        for (size_t k = 0; robin && k < (size_t)Ny * 2; ++k) {
+            const double2 x = rob[(size_t)a * Ny * 2 + k], y = rob[(size_t)b * Ny * 2 + k];
+            if (x.x != y.x || x.y != y.y) return false;
+        }
         for (int q = 0; q < W; ++q) {
             const int ca = scol[(size_t)a * WP + q], cb = scol[(size_t)b * WP + q];
             if (ca == cb) continue;
@@ -1310,7 +1619,19 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if ((st = upload(H, (void**)&t.rcols, rcols.data(), rcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.redcols, redcols.data(), redcols.size() * sizeof(int))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&t.tcol, tcol.data(), tcol.size() * sizeof(int))) != HELM_OK) return st;
+    if (robin) {
+        if ((st = upload(H, (void**)&t.srob, rob.data(), rob.size() * sizeof(double2))) != HELM_OK) return st;
+        if ((st = upload(H, (void**)&t.rho, rho.data(), rho.size() * sizeof(double2))) != HELM_OK) return st;
+    }
     H->tf = t;
+    if (robin) {
+        std::vector<double2> frob((size_t)H->nfac * Ny * 2);
+        for (int u = 0; u < H->nfac; ++u)
+            std::copy(rob.begin() + (size_t)urep[u] * Ny * 2, rob.begin() + (size_t)(urep[u] + 1) * Ny * 2,
+                      frob.begin() + (size_t)u * Ny * 2);
+        if ((st = upload(H, (void**)&H->tf.srob, frob.data(), frob.size() * sizeof(double2))) != HELM_OK)
+            return st;
+    }
     if ((st = upload(H, (void**)&H->tf.sax, fsax.data(), fsax.size() * sizeof(double2))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&H->tf.saxh, fsaxh.data(), fsaxh.size() * sizeof(double2))) != HELM_OK) return st;
     if ((st = upload(H, (void**)&H->tf.scol, fscol.data(), fscol.size() * sizeof(int))) != HELM_OK) return st;
@@ -1549,7 +1870,10 @@ helm_status helm_factor(helm_t H) {
     int herr = 0;
     HIPCHK(hipMemcpyAsync(&herr, H->d_err, sizeof(int), hipMemcpyDeviceToHost, H->st));
     HIPCHK(hipStreamSynchronize(H->st));
-    if (herr) return fail(H, HELM_ESINGULAR, "zero or non-finite pivot in a strip factorisation");
+    if (herr & 1) return fail(H, HELM_ESINGULAR, "zero or non-finite pivot in a strip factorisation");
+    if (herr & 2)
+        return fail(H, HELM_ESINGULAR, "a strip block is numerically singular (1-norm condition estimate "
+                                       "above 1e13): the strip operator is at or near a resonance");
     H->factored = true;
     return HELM_OK;
 }
@@ -1596,7 +1920,7 @@ helm_status helm_autotune(helm_t H, int nrhs, const void* rhs, const int* cand, 
     CHK(dmalloc(H, &xin, in_bytes));
     CHK(dmalloc(H, &xout, in_bytes));
     if (reduced)
-        HIPCHK(helm::launch_gather_cols(static_cast<const double2*>(rhs), H->t.redcols, nred, nrhs, g.Nrow(),
+        HIPCHK(helm::launch_gather_cols(static_cast<const double2*>(rhs), red_cols(H), nred, nrhs, g.Nrow(),
                                         g.Nx, xin, H->st));
     else
         HIPCHK(hipMemcpyAsync(xin, rhs, in_bytes, hipMemcpyDeviceToDevice, H->st));
@@ -1605,8 +1929,8 @@ helm_status helm_autotune(helm_t H, int nrhs, const void* rhs, const int* cand, 
     HIPCHK(hipEventCreate(&e1));
     struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } ev{e0, e1};
     auto apply = [&]() -> helm_status {
-        if (reduced) return apply_AP_reduced(H, nrhs, xin, xout);
-        CHK(apply_P_full(H, nrhs, xin, H->wk.PF));
+        if (reduced) return apply_AP_red(H, nrhs, xin, xout);
+        CHK(apply_P_any(H, nrhs, xin, H->wk.PF));
         HIPCHK(helm::launch_apply_A(H->t, g, nrhs, H->wk.PF, nullptr, xout, H->st));
         return HELM_OK;
     };
@@ -1752,7 +2076,8 @@ helm_status helm_apply_P(helm_t H, int nrhs, const void* f, void* out) {
     if (!H) return HELM_EINVAL;
     if (!H->factored) return fail(H, HELM_ESTATE, "helm_apply_P before helm_factor");
     if (nrhs < 1 || !f || !out) return fail(H, HELM_EINVAL, "bad arguments");
-    return apply_P_full(H, nrhs, static_cast<const double2*>(f), static_cast<double2*>(out));
+    CHK(ensure_sweep_ws(H, nrhs));
+    return apply_P_any(H, nrhs, static_cast<const double2*>(f), static_cast<double2*>(out));
 }
 
 helm_status helm_apply_AP_reduced(helm_t H, int nrhs, const void* psi, void* out) {
@@ -1760,7 +2085,8 @@ helm_status helm_apply_AP_reduced(helm_t H, int nrhs, const void* psi, void* out
     if (!H->factored) return fail(H, HELM_ESTATE, "helm_apply_AP_reduced before helm_factor");
     if (nrhs < 1 || !psi || !out) return fail(H, HELM_EINVAL, "bad arguments");
     if (H->g.J < 2) return fail(H, HELM_EINVAL, "the reduced space is empty for J = 1");
-    return apply_AP_reduced(H, nrhs, static_cast<const double2*>(psi), static_cast<double2*>(out));
+    if (H->trans == 1) return fail(H, HELM_EINVAL, "the reduced form is built for the PML transmission");
+    return apply_AP_red(H, nrhs, static_cast<const double2*>(psi), static_cast<double2*>(out));
 }
 
 helm_status helm_apply_A(helm_t H, int nrhs, const void* u, const void* f, void* out) {
@@ -1875,6 +2201,10 @@ void helm_destroy(helm_t H) {
     else (void)hipDeviceSynchronize();
     if (H->ap_exec) (void)hipGraphExecDestroy(H->ap_exec);
     if (H->cap_st) (void)hipStreamDestroy(H->cap_st);
+    for (hipStream_t q : H->st_c)
+        if (q) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : H->ev_c)
+        if (e) (void)hipEventDestroy(e);
     for (hipStream_t q : H->st_fac)
         if (q) (void)hipStreamDestroy(q);
     free_work(H->wk);

@@ -98,7 +98,15 @@ struct IOSpec {
     // every requested column is one of the strip's 8 compact target columns: phase C may
     // compute only those (reduced form)
     int targets_only = 0;
+    // columns receiving the transmission source: 2 (q_t and q_t + 1, the PML transmission)
+    // or 1 (q_t only, a Robin side)
+    int t_cols = 2;
 };
+
+// Strip-local column q receives the transmission source of io.
+__host__ __device__ inline bool tr_col(const IOSpec& io, int q) {
+    return io.q_t >= 0 && (q == io.q_t || (io.t_cols == 2 && q == io.q_t + 1));
+}
 
 // Device tables of one problem.
 struct DevTables {
@@ -120,6 +128,10 @@ struct DevTables {
     double* k2w = nullptr;      // Nrow*(J-1)*IWIN  k^2 on the interface windows
     double2* az = nullptr;      // Nz       (3-D) alpha_z at points
     double2* azh = nullptr;     // Nz+1     (3-D) alpha_z at half-points
+    // Robin subdomains (2-D comparison method): diagonal terms of the first / last column,
+    // [strip][row][2]; rho = (1 + i k h/2)/(1 - i k h/2) of every interface, [J-1][row]
+    double2* srob = nullptr;
+    double2* rho = nullptr;
 };
 
 // Interface windows: the reduced form only ever touches the columns beta_j - 2 .. beta_j + 2
@@ -194,6 +206,8 @@ hipError_t launch_apply_A_pairs(const DevTables& t, const Geom& g, int nrhs, con
 // [nrhs][Nrow][2(J-1)] holding columns beta_j, beta_j + 1):
 //   mode 0: g = psi - A u on the window columns beta_j - 1, beta_j (psi is 0 on beta_j - 1)
 //   mode 1: out = psi - (g - A u) on beta_j, beta_j + 1
+//   mode 2: out = A (u + psi - g) on beta_j - 1, beta_j (psi, g: window fields too; the
+//           concurrent sweep's v, w' and z)
 hipError_t launch_stencil_win(int mode, const DevTables& t, const Geom& g, int nrhs, const double2* u,
                               const double2* psi, double2* gw, double2* out, hipStream_t st);
 
@@ -217,6 +231,12 @@ hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, i
 // out = x + y + z; x or z may be null
 hipError_t launch_sum3(const double2* x, const double2* y, const double2* z, double2* out, long n,
                        hipStream_t st);
+// Robin data of a neighbour field: out[r][row] = (vo - rho[row] vi)[r][row] / h^2
+hipError_t launch_robin_data(const double2* vo, const double2* vi, const double2* rho, double2* out, int nrhs,
+                             long Nrow, double ih2, hipStream_t st);
+// out = x + y - z (all non-null)
+hipError_t launch_sum_diff(const double2* x, const double2* y, const double2* z, double2* out, long n,
+                           hipStream_t st);
 int dots_blocks(long n);
 
 // one plane l of the 3-D slab factorisation for every slab: S = T_l - c_l b_{l-1} Gprev,

@@ -394,7 +394,7 @@ __device__ inline cplx<T> gather3(const Solve3Args<T>& a, int r, int l, int k) {
     double2 v = make_double2(0.0, 0.0);
     if (q >= io.src_lo && q < io.src_hi)
         v = io.src[(size_t)r * io.src_rs + rho * io.src_ls + (q + io.src_off)];
-    if (io.q_t >= 0 && (q == io.q_t || q == io.q_t + 1)) {
+    if (tr_col(io, q)) {
         const double2 ta = io.trA[(size_t)r * a.Nrow + rho], tb = io.trB[(size_t)r * a.Nrow + rho];
         v.x += io.coef * (tb.x - ta.x);
         v.y += io.coef * (tb.y - ta.y);

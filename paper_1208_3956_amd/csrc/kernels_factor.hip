@@ -41,6 +41,9 @@ struct FactorArgs {
     const double2* saxh;
     const int* scol;
     const int* sW;
+    // Robin subdomains (the comparison method of Sec. 4.4): [strip][row][2] terms added to
+    // the diagonal of the first / last column of every row (null: PML pads)
+    const double2* rob;
     int* err;
     int Nx, Ny, m, P;
     double inv_h2;
@@ -64,6 +67,10 @@ __device__ void build_T(double2* M, const FactorArgs& a, int s, int l, int W) {
         d = cadd(d, cmul(ayl, cadd(n, so)));
         d.x *= a.inv_h2; d.y *= a.inv_h2;
         d.x -= a.k2[(size_t)l * a.Nx + a.scol[(size_t)s * WP + t]];
+        if (a.rob) {
+            if (t == 0) d = cadd(d, a.rob[((size_t)s * a.Ny + l) * 2]);
+            if (t == W - 1) d = cadd(d, a.rob[((size_t)s * a.Ny + l) * 2 + 1]);
+        }
         M[t + t * LDM] = d;
         if (t + 1 < W) {
             double2 o = cmul(axq, e);
@@ -129,6 +136,10 @@ __global__ void __launch_bounds__(NT) k_factor_chunks(FactorArgs a) {
         double2 d = cadd(xd, cmul(a.ay[l], cadd(a.ayh[l + 1], a.ayh[l])));
         d.x *= a.inv_h2; d.y *= a.inv_h2;
         d.x -= a.k2[(size_t)l * a.Nx + col];
+        if (a.rob) {
+            if (i == 0) d = cadd(d, a.rob[((size_t)s * a.Ny + l) * 2]);
+            if (i == W - 1) d = cadd(d, a.rob[((size_t)s * a.Ny + l) * 2 + 1]);
+        }
         const double2 cb = l > r0 ? cmul(a.cy[l], a.by[l - 1]) : cmk<double2>(0.0, 0.0);
         const double2* Gp = slot(a, s, l > r0 ? l - 1 : l, 0);
 #pragma unroll
@@ -309,7 +320,7 @@ __global__ void k_extract_targets(const V* __restrict__ F, V* __restrict__ Fc,
 FactorArgs make_args(const DevTables& t, const Geom& g, const Chunks& ch, double2* F, float2* F32, int* err) {
     FactorArgs a;
     a.F = F; a.F32 = F32; a.k2 = t.k2; a.ay = t.ay; a.ayh = t.ayh; a.cy = t.cy; a.by = t.by;
-    a.sax = t.sax; a.saxh = t.saxh; a.scol = t.scol; a.sW = t.sW; a.err = err;
+    a.sax = t.sax; a.saxh = t.saxh; a.scol = t.scol; a.sW = t.sW; a.err = err; a.rob = t.srob;
     a.Nx = g.Nx; a.Ny = g.Ny; a.m = ch.m; a.P = ch.P; a.inv_h2 = 1.0 / (g.h * g.h);
     return a;
 }

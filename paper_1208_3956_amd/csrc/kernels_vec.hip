@@ -125,6 +125,8 @@ __global__ void __launch_bounds__(256) k_apply_A_pairs(StencilArgs s, const int*
 // side, then the next window), so no index needs a division.
 //   MODE 0: g[c] = psi(c) - (A u)[c], c = 1, 2, with psi(c) = psi[.., 2 j + c - 2] for c = 2, 0 for c = 1
 //   MODE 1: out[.., 2 j + k] = psi[.., 2 j + k] - (g[2 + k] - (A u)[2 + k]), k = 0, 1
+//   MODE 2: out[.., 2 j + k] = (A u)[1 + k], k = 0, 1, with u = u + psi - gw (three window
+//           fields: the concurrent sweep's v, w' and z; out on the columns beta_j - 1, beta_j)
 template <int MODE>
 __global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* __restrict__ bw,
                                                      const double* __restrict__ k2w, int NI, int nrhs,
@@ -139,12 +141,18 @@ __global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* _
     (void)nrhs;
     for (int q = threadIdx.x; q < 2 * NI; q += blockDim.x) {
         const int k = q & 1, j = q >> 1;
-        const int c = (MODE == 0 ? 1 : 2) + k;
+        const int c = (MODE == 1 ? 2 : 1) + k;
         const int i = bw[j] + c;
         const size_t b = rr * wrow + (size_t)j * IWIN + c;
-        const double2 uc = u[b], ue = u[b + 1], uw = u[b - 1];
-        const double2 un = (l + 1 < s.Ny) ? u[b + wrow] : cmk<double2>(0, 0);
-        const double2 us = (l > 0) ? u[b - wrow] : cmk<double2>(0, 0);
+        // the field at window offset d from b (MODE 2: the sum v + w' - z of three fields)
+        auto U = [&](long d) {
+            const size_t e = (size_t)((long)b + d);
+            if (MODE == 2) return csub(cadd(u[e], psi[e]), gw[e]);
+            return u[e];
+        };
+        const double2 uc = U(0), ue = U(1), uw = U(-1);
+        const double2 un = (l + 1 < s.Ny) ? U((long)wrow) : cmk<double2>(0, 0);
+        const double2 us = (l > 0) ? U(-(long)wrow) : cmk<double2>(0, 0);
         const double2 ae = s.axh[i + 1], aw = s.axh[i];
         const double2 an = s.ayh[l + 1], as = s.ayh[l];
         double2 xp = cadd(cmul(ae, csub(uc, ue)), cmul(aw, csub(uc, uw)));
@@ -154,8 +162,8 @@ __global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* _
         double2 a = cadd(xp, yp);
         if (s.Nz > 1) {
             const size_t pl = (size_t)s.Ny * wrow;
-            const double2 uu = (z + 1 < s.Nz) ? u[b + pl] : cmk<double2>(0, 0);
-            const double2 ud = (z > 0) ? u[b - pl] : cmk<double2>(0, 0);
+            const double2 uu = (z + 1 < s.Nz) ? U((long)pl) : cmk<double2>(0, 0);
+            const double2 ud = (z > 0) ? U(-(long)pl) : cmk<double2>(0, 0);
             double2 zp = cadd(cmul(s.azh[z + 1], csub(uc, uu)), cmul(s.azh[z], csub(uc, ud)));
             a = cadd(a, cmul(s.az[z], zp));
         }
@@ -167,8 +175,10 @@ __global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* _
         if (MODE == 0) {
             const double2 f = c >= 2 ? psi[pr] : cmk<double2>(0, 0);
             gw[b] = csub(f, a);
-        } else {
+        } else if (MODE == 1) {
             out[pr] = csub(psi[pr], csub(gw[b], a));
+        } else {
+            out[rr * (2 * (size_t)NI) + 2 * (size_t)j + k] = a;
         }
     }
 }
@@ -326,12 +336,22 @@ __global__ void k_scatter_cols(const double2* __restrict__ red, const int* __res
 
 // out = x + y + z (x or z may be null: treated as zero)
 __global__ void k_sum3(const double2* __restrict__ x, const double2* __restrict__ y,
-                       const double2* __restrict__ z, double2* __restrict__ out, long n) {
+                       const double2* __restrict__ z, double2* __restrict__ out, long n, double zs) {
     for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
         double2 v = y[q];
         if (x) v = cadd(x[q], v);
-        if (z) v = cadd(v, z[q]);
+        if (z) { v.x += zs * z[q].x; v.y += zs * z[q].y; }
         out[q] = v;
+    }
+}
+
+// Robin data: out[r][row] = (vo - rho[row] vi)[r][row] * ih2
+__global__ void k_robin_data(const double2* __restrict__ vo, const double2* __restrict__ vi,
+                             const double2* __restrict__ rho, double2* __restrict__ out, long n, long Nrow,
+                             double ih2) {
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < n; q += (long)gridDim.x * blockDim.x) {
+        const double2 d = csub(vo[q], cmul(rho[q % Nrow], vi[q]));
+        out[q] = make_double2(d.x * ih2, d.y * ih2);
     }
 }
 
@@ -375,8 +395,10 @@ hipError_t launch_stencil_win(int mode, const DevTables& t, const Geom& g, int n
     const dim3 grid((unsigned)g.Nrow(), (unsigned)nrhs);
     if (mode == 0)
         hipLaunchKernelGGL(k_stencil_win<0>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
-    else
+    else if (mode == 1)
         hipLaunchKernelGGL(k_stencil_win<1>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
+    else
+        hipLaunchKernelGGL(k_stencil_win<2>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
     return hipGetLastError();
 }
 
@@ -436,7 +458,20 @@ hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, i
 
 hipError_t launch_sum3(const double2* x, const double2* y, const double2* z, double2* out, long n,
                        hipStream_t st) {
-    hipLaunchKernelGGL(k_sum3, dim3(grid_for((size_t)n)), dim3(256), 0, st, x, y, z, out, n);
+    hipLaunchKernelGGL(k_sum3, dim3(grid_for((size_t)n)), dim3(256), 0, st, x, y, z, out, n, 1.0);
+    return hipGetLastError();
+}
+
+hipError_t launch_robin_data(const double2* vo, const double2* vi, const double2* rho, double2* out, int nrhs,
+                             long Nrow, double ih2, hipStream_t st) {
+    const long n = (long)nrhs * Nrow;
+    hipLaunchKernelGGL(k_robin_data, dim3(grid_for((size_t)n)), dim3(256), 0, st, vo, vi, rho, out, n, Nrow, ih2);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_diff(const double2* x, const double2* y, const double2* z, double2* out, long n,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_sum3, dim3(grid_for((size_t)n)), dim3(256), 0, st, x, y, z, out, n, -1.0);
     return hipGetLastError();
 }
 

@@ -39,6 +39,12 @@ class Helmholtz:
                None = 2.5 x pml_iface (the same damping per cell for every width)
     beta_rule  partition when beta is None: 0 = even split of the interior,
                1 = the paper's rule (eq. define_beta_j)
+    sweep      "double" (the paper's P) or "concurrent" (P_c: upward and downward sweeps
+               on f at the same time on separate streams)
+    transmission  "pml" (the paper's method) or "robin" (the comparison method of Sec. 4.4:
+               unpadded subdomains with first-order absorbing conditions; 2-D, double
+               sweep, full form)
+    restart    GMRES cycle length (0 = library default: 60 reduced, 30 full)
     prec       "c128" or "mixed" (complex64 strip factors and sweeps, FP64 GMRES)
     mode       "full" or "reduced" (GMRES on the interface columns, Algorithms 2-5)
     chunk      rows per chunk of the y-partitioned strip solver (0 = library default)
@@ -52,7 +58,8 @@ class Helmholtz:
                  max_iter: int = 200, chunk: int = 0, beta: Optional[Sequence[int]] = None,
                  device="cuda:0", stream=None, graph: bool = True,
                  pml_iface_s0: Optional[float] = None,
-                 beta_rule: int = 0):
+                 beta_rule: int = 0, sweep: str = "double", transmission: str = "pml",
+                 restart: int = 0):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the solver runs on a HIP device (cuda:N in torch)")
@@ -69,6 +76,9 @@ class Helmholtz:
         o.pml_power, o.pml_s0, o.pml_cref = float(pml_power), float(pml_s0), float(pml_cref)
         o.pml_iface_s0 = -1.0 if pml_iface_s0 is None else float(pml_iface_s0)
         o.beta_rule = int(beta_rule)
+        o.sweep = {"double": 0, "concurrent": 1}[sweep]
+        o.transmission = {"pml": 0, "robin": 1}[transmission]
+        o.restart = int(restart)
         o.prec = {"c128": L.HELM_C128, "mixed": L.HELM_MIXED_C64, "c64": L.HELM_MIXED_C64}[prec]
         o.mode = {"full": L.HELM_FULL, "reduced": L.HELM_REDUCED}[mode]
         o.max_iter = int(max_iter)

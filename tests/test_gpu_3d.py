@@ -205,3 +205,26 @@ def test_complex64_fp64_route_rounded(case, monkeypatch):
     for k in range(f.shape[0]):
         assert _rel(res.u.cpu().numpy()[k], ud[k]) < TOL_FIELD
     H.close()
+
+
+@pytest.mark.parametrize("n,s", [(60, 7)])
+def test_complex64_slab_solve_large(n, s):
+    """A sampled slab of the smooth 3-D medium at 60^3 (J = 16: blocks of 17 x 76 = 1292
+    unknowns, 98192 per slab), complex64 factor and solve against the oracle's SuperLU
+    solve, right-hand side by right-hand side, at the complex64 bar."""
+    from oracle.assemble import assemble_strip
+    import scipy.sparse.linalg as spla
+    wl = W.smooth_3d(n=n, nsrc=2, J=16)
+    g = geometry_from_workload(wl)
+    H = _gpu(wl, prec="mixed", mode="reduced")
+    assert H.factor_path == 1
+    st = g.strips[s]
+    lu = spla.splu(assemble_strip(g, st).tocsc(), permc_spec="COLAMD")
+    rng = np.random.default_rng(60 + s)
+    r = _rand(rng, (2,) + g.strip_shape(st))
+    x = H.strip_solve(s, _t(r)).cpu().numpy()
+    ref = np.stack([lu.solve(rk.ravel()).reshape(rk.shape) for rk in r])
+    err = _rel(x, ref)
+    print(f"{n}^3 slab {s} {g.strip_shape(st)}: worst relative error {err:.2e}", flush=True)
+    assert err < TOL_C64
+    H.close()

@@ -1,0 +1,109 @@
+"""The 1000^2 Gaussian-lens workload (J = 32, interface PML 12, 16 sources on row y = 0.1;
+complex128 and mixed precision), the one 2-D configuration whose medium varies with x, so
+that every strip has its own factorisation.  Checked against the oracle one output at a
+time: sampled strip solves against SuperLU, the preconditioner on one right-hand side
+against the oracle's sweeps, the solve's residual under the oracle's operator for sampled
+right-hand sides, and the iteration counts of the two precisions."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle.assemble import assemble_global, assemble_strip  # noqa: E402
+from oracle.dd import StripSolvers, apply_P  # noqa: E402
+from oracle.grid import geometry_from_workload  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _close(x, ref, tol, what="", rows=None):
+    """Every right-hand side within tol in relative L2 and relative max-norm; with rows = m
+    also every block of m rows (a y-chunk of the strip solver) within 5 tol."""
+    assert x.shape == ref.shape, (what, x.shape, ref.shape)
+    for k in range(ref.shape[0]):
+        d = x[k] - ref[k]
+        l2 = np.linalg.norm(d) / np.linalg.norm(ref[k])
+        mx = np.abs(d).max() / np.abs(ref[k]).max()
+        assert l2 < tol and mx < tol, (what, k, l2, mx)
+        if rows:
+            for r0 in range(0, ref.shape[1], rows):
+                nb = np.linalg.norm(ref[k][r0:r0 + rows])
+                if nb > 0:
+                    assert np.linalg.norm(d[r0:r0 + rows]) / nb < 5 * tol, (what, k, r0)
+
+
+@pytest.fixture(scope="module")
+def lens():
+    wl = W.lens_1000()
+    g = geometry_from_workload(wl)
+    return wl, g, assemble_global(g)
+
+
+def _H(wl, prec, mode="reduced"):
+    from paper_1208_3956_amd import Helmholtz
+    return Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                     pml_iface_s0=wl.pml_iface_s0, prec=prec, mode=mode, device=DEV).factor()
+
+
+def test_lens_every_strip_has_its_own_factorisation(lens):
+    wl, g, A = lens
+    H = _H(wl, "mixed")
+    assert H.factor_slots == wl.J
+    H.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed", 2e-4), ("c128", 1e-10)])
+def test_lens_strip_solves(lens, prec, tol):
+    import scipy.sparse.linalg as spla
+    wl, g, A = lens
+    H = _H(wl, prec)
+    k2 = g.k2()
+    rng = np.random.default_rng(11)
+    for s in (0, 13, 31):
+        st = g.strips[s]
+        lu = spla.splu(assemble_strip(g, st, k2).tocsc(), permc_spec="COLAMD")
+        r = rng.standard_normal((3, g.N_y, st.W)) + 1j * rng.standard_normal((3, g.N_y, st.W))
+        x = H.strip_solve(s, torch.from_numpy(r).to(DEV)).cpu().numpy()
+        ref = np.stack([lu.solve(rk.ravel()).reshape(rk.shape) for rk in r])
+        _close(x, ref, tol, f"strip {s}", rows=H.chunk_rows)
+    H.close()
+
+
+def test_lens_preconditioner_one_rhs(lens):
+    wl, g, A = lens
+    S = StripSolvers(g)
+    f = wl.rhs([7])
+    ref = apply_P(g, S, A, f[0])
+    for prec, tol in (("c128", 1e-10), ("mixed", 2e-4)):
+        H = _H(wl, prec, mode="full")
+        pf = H.apply_P(torch.from_numpy(f).to(DEV)).cpu().numpy()
+        _close(pf, ref[None], tol, f"P {prec}")
+        H.close()
+
+
+def test_lens_solves_and_iterations(lens):
+    wl, g, A = lens
+    f = wl.rhs()
+    ft = torch.from_numpy(f).to(DEV)
+    res = {}
+    for prec in ("c128", "mixed"):
+        H = _H(wl, prec)
+        res[prec] = H.solve(ft, tol=1e-6)
+        H.close()
+        r = res[prec]
+        print(f"lens {prec}: iterations {r.iters}, restarts {r.restarts}, {r.ms:.0f} ms", flush=True)
+        assert r.status == 0 and max(r.relres) <= 1e-6
+        for k in (0, 8, 15):
+            u = r.u[k].cpu().numpy()
+            rel = np.linalg.norm(f[k].ravel() - A @ u.ravel()) / np.linalg.norm(f[k])
+            assert rel <= 1e-6 * (1 + 1e-9), (prec, k, rel)
+            assert abs(rel - r.relres[k]) <= 1e-9 * rel + 1e-15, (prec, k, rel, r.relres[k])
+    assert all(m <= c + 1 for m, c in zip(res["mixed"].iters, res["c128"].iters)), \
+        list(zip(res["mixed"].iters, res["c128"].iters))
+    # the two precisions solve the same system: their fields agree to the field bar
+    u64 = res["mixed"].u.cpu().numpy()
+    u128 = res["c128"].u.cpu().numpy()
+    _close(u64, u128, 1e-5, "mixed vs complex128 fields")

@@ -144,3 +144,29 @@ def test_paper_partition_rule(prec, tol):
     assert res.status == 0 and max(res.relres) <= 1e-6
     _per_rhs(res.u.cpu().numpy(), solve_direct(g, f, A), 1e-5, "solve, paper partition")
     H.close()
+
+
+def test_resonant_strip_reports_esingular():
+    """Without PML (s0 = 0) a strip is a real Dirichlet problem; with k^2 at an eigenvalue of
+    its first y-block T = T_x + (2/h^2 - k^2) I (T_x the 1-D second difference over the W
+    columns, eigenvalues 4 sin^2(m pi / (2 (W + 1))) / h^2) that block is singular.  The
+    factorisation must report HELM_ESINGULAR instead of solving with a meaningless inverse;
+    k moved off the eigenvalue by 1% factors normally."""
+    import math
+    from paper_1208_3956_amd import Helmholtz
+    from paper_1208_3956_amd._lib import HelmError, HELM_ESINGULAR
+    n, w_out = 10, 1
+    h = 1.0 / n
+    W_ = n + 2 * w_out                                   # J = 1: the strip is the padded grid
+    k2 = 2.0 / h ** 2 + 4.0 * math.sin(math.pi / (2 * (W_ + 1))) ** 2 / h ** 2
+    for scale, singular in ((1.0, True), (1.01, False)):
+        H = Helmholtz(np.ones((n, n)), math.sqrt(k2 * scale), h, 1, pml_outer=w_out, pml_iface=1,
+                      pml_s0=0.0, prec="c128", mode="full", device=DEV)
+        if singular:
+            with pytest.raises(HelmError) as e:
+                H.factor()
+            assert e.value.status == HELM_ESINGULAR, e.value
+            print(f"resonant strip: {e.value}", flush=True)
+        else:
+            H.factor()
+        H.close()
