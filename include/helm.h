@@ -327,6 +327,14 @@ helm_status helm_get_chunks(helm_t H, int* rows_per_chunk, int* nchunks);
  * restarts, and the solve's wall time in milliseconds (host). */
 helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* solve_ms);
 
+/* Panel counters of the last helm_solve (host): right-hand sides that went through the
+ * GMRES operator, summed over its applications, and the same sum had converged right-hand
+ * sides stayed in the panel.  A right-hand side that has met its target leaves the panel:
+ * the unconverged ones are gathered into a panel of the next multiple of 16 (the strip
+ * kernels' right-hand-side group), so the strip solves of an application scale with the
+ * right-hand sides still iterating; the results are bitwise those of the full panel. */
+helm_status helm_get_panel_stats(helm_t H, long long* rhs_applied, long long* rhs_applied_full);
+
 /*
  * Kernel timing (profiling aid).  While enabled, every launch of the hot kernels is
  * bracketed by a pair of HIP events on the handle's stream (events are recorded

@@ -23,7 +23,7 @@ EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
            "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
            "helm_solve_batch", "helm_get_dims3", "helm_autotune", "helm_get_factor_path",
-           "helm_get_factor_slots", "helm_strip_solve_noalloc"]
+           "helm_get_factor_slots", "helm_strip_solve_noalloc", "helm_get_panel_stats"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -89,6 +89,7 @@ def lib() -> ctypes.CDLL:
     L.helm_autotune.argtypes = [vp, ci, vp, pint, ci, ci, pint, pdbl]
     L.helm_get_factor_path.argtypes = [vp, pint]
     L.helm_get_factor_slots.argtypes = [vp, pint, pint]
+    L.helm_get_panel_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
     L.helm_get_dims3.argtypes = [vp, pint, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
@@ -248,6 +249,13 @@ def helm_get_stats(hdl):
     a, r, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     check(lib().helm_get_stats(hdl, ctypes.byref(a), ctypes.byref(r), ctypes.byref(ms)), hdl)
     return a.value, r.value, ms.value
+
+
+def helm_get_panel_stats(hdl):
+    """(right-hand sides through the GMRES operator, the same without panel compaction)."""
+    a, b = ctypes.c_longlong(), ctypes.c_longlong()
+    check(lib().helm_get_panel_stats(hdl, ctypes.byref(a), ctypes.byref(b)), hdl)
+    return a.value, b.value
 
 
 def helm_set_kernel_timing(hdl, mask: int) -> None:

@@ -136,9 +136,24 @@ struct helm_problem {
     int* d_err = nullptr;
     Work wk;
     int stat_ap = 0, stat_restarts = 0;
+    // right-hand sides that went through the GMRES operator, and as many without dropping
+    // the converged ones from its panel
+    long long stat_panel = 0, stat_panel_full = 0;
     int dev = 0;                // HIP device of the handle
     int use_graph = 1;          // replay Algorithm 3 from a captured HIP graph (REDUCED)
-    hipGraphExec_t ap_exec = nullptr;
+    // captured reduced operators, one per right-hand-side count (the GMRES panel shrinks to
+    // the multiple of 16 that holds its unconverged right-hand sides): least recently used
+    // entry replaced
+    struct ApGraph {
+        hipGraphExec_t exec = nullptr;
+        int nrhs = 0;
+        const void* out = nullptr;
+        long epoch = -1;
+        unsigned long used = 0;
+    };
+    static constexpr int NGRAPH = 4;
+    ApGraph apg[NGRAPH];
+    unsigned long ap_tick = 0;
     int sweep = 0;              // 0: the double sweep P; 1: the concurrent double sweep P_c
     int trans = 0;              // 0: PML transmission; 1: Robin transmission (Sec. 4.4)
     int restart = 0;            // GMRES cycle length (0: by mode)
@@ -147,9 +162,7 @@ struct helm_problem {
     hipStream_t st_fac[FAC3_GROUPS - 1] = {};   // group streams of the 3-D complex64 factorisation
     hipStream_t cap_st = nullptr;  // private stream the graph is captured on (capture is not
                                    // allowed on the legacy default stream); replays go to st
-    int ap_nrhs = 0;
-    const void* ap_out = nullptr;
-    long ws_epoch = 0, ap_epoch = -1;  // workspace generation the graph was captured with
+    long ws_epoch = 0;          // workspace generation (graphs captured before it are stale)
     double stat_ms = 0.0;
     std::vector<void*> owned;   // table allocations
     EventTimer* timer = nullptr; // non-null while kernel timing is enabled
@@ -850,12 +863,18 @@ helm_status apply_AP_red(helm_t H, int nrhs, const double2* x, double2* out) {
 // columns of the reduced unknowns: beta_j, beta_j + 1 (P), beta_j - 1, beta_j (P_c)
 const int* red_cols(helm_t H) { return H->sweep == 1 ? H->t.rcols : H->t.redcols; }
 
-// Destroys the captured reduced operator once its last replay has completed.
-helm_status drop_graph(helm_t H) {
-    if (!H->ap_exec) return HELM_OK;
+// Destroys one captured reduced operator (every one: slot < 0) once its last replay has
+// completed.
+helm_status drop_graph(helm_t H, int slot = -1) {
+    bool any = false;
+    for (int i = 0; i < helm_problem::NGRAPH; ++i) any = any || ((slot < 0 || i == slot) && H->apg[i].exec);
+    if (!any) return HELM_OK;
     HIPCHK(H->st ? hipStreamSynchronize(H->st) : hipDeviceSynchronize());
-    HIPCHK(hipGraphExecDestroy(H->ap_exec));
-    H->ap_exec = nullptr;
+    for (int i = 0; i < helm_problem::NGRAPH; ++i) {
+        if ((slot >= 0 && i != slot) || !H->apg[i].exec) continue;
+        HIPCHK(hipGraphExecDestroy(H->apg[i].exec));
+        H->apg[i] = helm_problem::ApGraph();
+    }
     return HELM_OK;
 }
 
@@ -874,9 +893,16 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
     Work& w = H->wk;
     CHK(ensure_sweep_ws(H, nrhs));
     const size_t bytes = (size_t)nrhs * H->g.Nrow() * 2 * (H->g.J - 1) * sizeof(double2);
-    HIPCHK(hipMemcpyAsync(w.apin, x, bytes, hipMemcpyDeviceToDevice, H->st));
-    if (!H->ap_exec || H->ap_nrhs != nrhs || H->ap_out != out || H->ap_epoch != H->ws_epoch) {
-        CHK(drop_graph(H));
+    if (x != w.apin) HIPCHK(hipMemcpyAsync(w.apin, x, bytes, hipMemcpyDeviceToDevice, H->st));
+    int slot = -1, lru = 0;
+    for (int i = 0; i < helm_problem::NGRAPH; ++i) {
+        const auto& e = H->apg[i];
+        if (e.exec && e.nrhs == nrhs && e.out == out && e.epoch == H->ws_epoch) slot = i;
+        if (H->apg[i].used < H->apg[lru].used) lru = i;
+    }
+    if (slot < 0) {
+        slot = lru;
+        CHK(drop_graph(H, slot));
         if (!H->cap_st) HIPCHK(hipStreamCreateWithFlags(&H->cap_st, hipStreamNonBlocking));
         // the captured work only reads buffers written before the replay on st; nothing is
         // executed during the capture itself
@@ -889,12 +915,14 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
         hipError_t ce = hipStreamEndCapture(H->cap_st, &graph);
         if (cs != HELM_OK) { if (graph) (void)hipGraphDestroy(graph); return cs; }
         HIPCHK(ce);
-        hipError_t ie = hipGraphInstantiate(&H->ap_exec, graph, nullptr, nullptr, 0);
+        auto& e = H->apg[slot];
+        hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(ie);
-        H->ap_nrhs = nrhs; H->ap_out = out; H->ap_epoch = H->ws_epoch;
+        e.nrhs = nrhs; e.out = out; e.epoch = H->ws_epoch;
     }
-    HIPCHK(hipGraphLaunch(H->ap_exec, H->st));
+    H->apg[slot].used = ++H->ap_tick;
+    HIPCHK(hipGraphLaunch(H->apg[slot].exec, H->st));
     return HELM_OK;
 }
 
@@ -927,6 +955,43 @@ struct Aug {
 // One GMRES(m) cycle on op(y) = b.  b is copied into the basis.  Each right-hand side
 // stops when its residual is <= target[r]; returns y (device, [nrhs][n]) and per-rhs
 // iteration counts.  active[r] == false rhs take no part (y = 0).
+// w.w = op(v) for the right-hand sides still iterating; rows of converged ones are zero.
+// When their number fits fewer groups of 16 than nrhs, they are gathered into the fixed
+// input panel apin (rounded up to a multiple of 16, the padding zero: the operator is linear
+// and acts on every right-hand side alone, so each result is bitwise the one of the full
+// panel), the operator runs on that smaller panel, and the results move back to their rows
+// from the last one down (row i goes to act[i] >= i, never onto a row still to be read).
+helm_status apply_op_active(helm_t H, int nrhs, long n, const std::vector<Givens>& gv, const double2* v) {
+    Work& w = H->wk;
+    std::vector<int> act;
+    for (int r = 0; r < nrhs; ++r)
+        if (!gv[r].done) act.push_back(r);
+    const int nact = (int)act.size();
+    const int npad = std::min(nrhs, (nact + 15) / 16 * 16);
+    H->stat_panel_full += nrhs;
+    H->stat_panel += npad < nrhs && nact > 0 ? npad : nrhs;
+    if (npad >= nrhs || nact == 0) return apply_op(H, nrhs, v, w.w);
+    const size_t row = (size_t)n * sizeof(double2);
+    for (int i = 0; i < nact;) {                     // runs of consecutive right-hand sides
+        int e = i + 1;
+        while (e < nact && act[e] == act[e - 1] + 1) ++e;
+        HIPCHK(hipMemcpyAsync(w.apin + (size_t)i * n, v + (size_t)act[i] * n, row * (e - i),
+                              hipMemcpyDeviceToDevice, H->st));
+        i = e;
+    }
+    if (npad > nact) HIPCHK(hipMemsetAsync(w.apin + (size_t)nact * n, 0, row * (npad - nact), H->st));
+    CHK(apply_op(H, npad, w.apin, w.w));
+    for (int i = nact - 1; i >= 0; --i)
+        if (act[i] != i)
+            HIPCHK(hipMemcpyAsync(w.w + (size_t)act[i] * n, w.w + (size_t)i * n, row, hipMemcpyDeviceToDevice,
+                                  H->st));
+    for (int r = 0, i = 0; r < nrhs; ++r) {
+        if (i < nact && act[i] == r) { ++i; continue; }
+        HIPCHK(hipMemsetAsync(w.w + (size_t)r * n, 0, row, H->st));
+    }
+    return HELM_OK;
+}
+
 helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std::vector<double>& bnorm,
                         const std::vector<double>& target, int maxit, double2* yout,
                         std::vector<int>& its, std::vector<double>& resid,
@@ -960,7 +1025,7 @@ helm_status gmres_cycle(helm_t H, int nrhs, long n, const double2* b, const std:
     const int nb = helm::dots_blocks(n);
     while (!all && k < m) {
         double2* vk = w.basis + (size_t)k * vs;
-        CHK(apply_op(H, nrhs, vk, w.w));
+        CHK(apply_op_active(H, nrhs, n, gv, vk));
         if (aug) {
             // w <- (I - C C^H) w: B_j = C^H w = Qh^H (V^H w), w -= V (Qh B_j)
             const int anv = aug->nv;
@@ -1885,6 +1950,7 @@ helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
     if (nrhs < 1 || !rhs || !u) return fail(H, HELM_EINVAL, "nrhs >= 1 and non-null rhs, u required");
     if (!(tol > 0)) return fail(H, HELM_EINVAL, "tol must be positive");
     H->stat_ap = 0;
+    H->stat_panel = H->stat_panel_full = 0;
     const auto t0 = std::chrono::steady_clock::now();
     helm_status s = solve_impl(H, nrhs, static_cast<const double2*>(rhs), static_cast<double2*>(u),
                                tol, iters, relres);
@@ -2149,6 +2215,13 @@ helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* sol
     return HELM_OK;
 }
 
+helm_status helm_get_panel_stats(helm_t H, long long* rhs_applied, long long* rhs_applied_full) {
+    if (!H) return HELM_EINVAL;
+    if (rhs_applied) *rhs_applied = H->stat_panel;
+    if (rhs_applied_full) *rhs_applied_full = H->stat_panel_full;
+    return HELM_OK;
+}
+
 helm_status helm_get_factor_slots(helm_t H, int* slots, int* strip_slot) {
     if (!H || !slots) return HELM_EINVAL;
     if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
@@ -2199,7 +2272,8 @@ void helm_destroy(helm_t H) {
     if (!H) return;
     if (H->st) (void)hipStreamSynchronize(H->st);
     else (void)hipDeviceSynchronize();
-    if (H->ap_exec) (void)hipGraphExecDestroy(H->ap_exec);
+    for (auto& e : H->apg)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
     if (H->cap_st) (void)hipStreamDestroy(H->cap_st);
     for (hipStream_t q : H->st_c)
         if (q) (void)hipStreamDestroy(q);

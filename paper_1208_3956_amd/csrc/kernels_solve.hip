@@ -852,6 +852,91 @@ __global__ void __launch_bounds__(NT) k_phase_c(SolveArgs<T> a) {
     }
 }
 
+// ---------------------------------------------------------------- phase C (all columns), MFMA
+// complex64: per chunk and group of 16 right-hand sides, x_l = y_l - [X~_l Y~_l] [x_a; x_b]
+// for every row l of the chunk (the separator closing it is final after phase B and only
+// copied), one (64 x 128) by (128 x 16) product per row on v_mfma_f32_16x16x4f32 in three
+// real products.  The chunk's two separator vectors are the B operands of every row and stay
+// in registers; each lane loads its A operands (A[16w + n][4s + q4] of X~_l, then of Y~_l)
+// straight from global memory.  The 64 x 16 result is transposed through LDS so that the
+// scatter writes whole rows of one right-hand side (consecutive x positions) instead of
+// four-element pieces of sixteen right-hand sides.  Grid (chunks, right-hand-side groups,
+// row groups): row group z takes the chunk's rows z, z + gridDim.z, ...
+__global__ void __launch_bounds__(NT) k_phase_c_mfma(SolveArgs<float> a) {
+    using V = float2;
+    __shared__ V X[2 * WP][16];
+    __shared__ V O[16][WP + 1];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
+    const int c = blockIdx.x, rbase = blockIdx.y * 16;
+    const int r0 = c * a.m;
+    const bool has_a = c > 0, has_b = c < a.P - 1;
+    const int r1 = has_b ? c * a.m + a.m - 1 : a.Ny;     // separator closing the chunk, or Ny
+    const int nrow = r1 - r0 + (has_b ? 1 : 0);
+    const V zero = make_float2(0.f, 0.f);
+    for (int idx = t; idx < 2 * WP * 16; idx += NT) {
+        const int k = idx >> 4, q = idx & 15, r = rbase + q, kk = k & (WP - 1);
+        V v = zero;
+        if (r < a.nrhs && kk < a.W) {
+            if (k < WP) {
+                if (has_a) v = a.Yw[((size_t)r * a.Ny + (r0 - 1)) * WP + kk];
+            } else if (has_b) {
+                v = a.Yw[((size_t)r * a.Ny + r1) * WP + kk];
+            }
+        }
+        X[k][q] = v;
+    }
+    __syncthreads();
+    float xr[32], xi[32], xs[32];
+#pragma unroll
+    for (int s = 0; s < 32; ++s) {
+        const V v = X[4 * s + q4][n];
+        xr[s] = v.x; xi[s] = v.y; xs[s] = v.x + v.y;
+    }
+    const int rn = rbase + n;
+    const int qrow = 16 * w + 4 * q4;
+    const size_t ybase = (size_t)(rn < a.nrhs ? rn : 0) * a.Ny * WP + qrow;
+    for (int j = blockIdx.z; j < nrow; j += gridDim.z) {
+        const int l = r0 + j;
+        mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1;
+        if (!(has_b && l == r1)) {
+            if (has_a) {
+                const V* F = fslot(a, l, 1) + 16 * w + n;
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const V g = F[(4 * s + q4) * WP];
+                    m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x, xr[s], m1, 0, 0, 0);
+                    m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g.y, xi[s], m2, 0, 0, 0);
+                    m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x + g.y, xs[s], m3, 0, 0, 0);
+                }
+            }
+            if (has_b) {
+                const V* F = fslot(a, l, 2) + 16 * w + n;
+#pragma unroll
+                for (int s = 0; s < 16; ++s) {
+                    const V g = F[(4 * s + q4) * WP];
+                    m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x, xr[16 + s], m1, 0, 0, 0);
+                    m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g.y, xi[16 + s], m2, 0, 0, 0);
+                    m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g.x + g.y, xs[16 + s], m3, 0, 0, 0);
+                }
+            }
+        }
+        V y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = a.Yw[ybase + (size_t)l * WP + u];
+        __syncthreads();                                  // the previous row's scatter has read O
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float p1 = m1[u], p2 = m2[u], p3 = m3[u];
+            O[n][qrow + u] = make_float2(y[u].x - (p1 - p2), y[u].y - (p3 - p1 - p2));
+        }
+        __syncthreads();
+        for (int idx = t; idx < 16 * WP; idx += NT) {
+            const int q = idx >> 6, i = idx & (WP - 1), r = rbase + q;
+            if (r < a.nrhs && i < a.W) scatter<float>(a, r, l, i, O[q][i]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- phase C (target columns)
 // Only the 8 compact columns tcol[] of the strip; thread = (slot = t / 32, rhs = t % 32);
 // ROWS consecutive rows per workgroup share the separator vectors of their chunk.
@@ -1111,7 +1196,12 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
             hipLaunchKernelGGL((k_phase_c_targets<T>), dim3((a.Ny + CT_ROWS - 1) / CT_ROWS, (a.nrhs + 31) / 32),
                                dim3(NT), 0, st, a);
     }
-    else
+    else if constexpr (std::is_same<T, float>::value) {
+        // about four workgroups per CU: row groups split each chunk's rows
+        const int per = a.P * ((a.nrhs + 15) / 16);
+        const int TS = std::max(1, std::min(std::min(8, a.m), (1024 + per - 1) / per));
+        hipLaunchKernelGGL(k_phase_c_mfma, dim3(a.P, (a.nrhs + 15) / 16, TS), dim3(NT), 0, st, a);
+    } else
         hipLaunchKernelGGL((k_phase_c<T, R>), dim3(a.Ny, RG), dim3(NT), 0, st, a);
     if (kt) kt->end(K_PHASE_C, st);
     return hipGetLastError();

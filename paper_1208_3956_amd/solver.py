@@ -24,6 +24,10 @@ class SolveResult:
     ap_applies: int
     restarts: int
     ms: float
+    # right-hand sides through the GMRES operator (converged ones leave its panel), and the
+    # same count had they stayed
+    panel_rhs: int = 0
+    panel_rhs_full: int = 0
 
 
 class Helmholtz:
@@ -195,8 +199,9 @@ class Helmholtz:
         with torch.cuda.device(self.device):
             st, it, rel = L.helm_solve(self.h, f.shape[0], f.data_ptr(), u.data_ptr(), tol)
             ap, rs, ms = L.helm_get_stats(self.h)
+            pr, prf = L.helm_get_panel_stats(self.h)
         self._end()
-        return SolveResult(u, it, rel, st, ap, rs, ms)
+        return SolveResult(u, it, rel, st, ap, rs, ms, pr, prf)
 
     def grad(self, src: torch.Tensor, rec, d: torch.Tensor, tol: float = 1e-6):
         """Misfit 1/2 sum_s |R u_s - d_s|^2 and its gradient with respect to m = 1/c^2 on
@@ -312,6 +317,7 @@ def solve_batch(problems: Sequence[Helmholtz], rhs: Sequence[torch.Tensor], tol:
     for H, u, n in zip(problems, us, nr):
         H.stream.synchronize()
         ap, rs, ms = L.helm_get_stats(H.h)
-        out.append(SolveResult(u, its[k:k + n], rel[k:k + n], st, ap, rs, ms))
+        pr, prf = L.helm_get_panel_stats(H.h)
+        out.append(SolveResult(u, its[k:k + n], rel[k:k + n], st, ap, rs, ms, pr, prf))
         k += n
     return out
