@@ -57,6 +57,8 @@ def parse():
                    help="with --cpu-baseline full: also write the job record (Markdown) here")
     p.add_argument("--no-lens-leg", action="store_true",
                    help="skip the 1000^2 Gaussian-lens leg (complex64-mixed and complex128)")
+    p.add_argument("--no-3d-leg", action="store_true",
+                   help="skip the 80^3 smooth-medium leg (complex64-mixed, reduced)")
     p.add_argument("--no-c128-leg", action="store_true",
                    help="skip the complex128 comparison legs (batched and one RHS per solve)")
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -448,6 +450,47 @@ def lens_leg(tol, reps=2):
     return out
 
 
+def smooth3d_leg(tol, reps=1):
+    """The 80^3 smooth 3-D medium (32 sources, 16 slabs), complex64-mixed, reduced: factor
+    and solve times of `reps` timed steps after one untimed one, iterations, and the
+    complex64 slab factorisation's rate against the FP32 MFMA peak (algorithmic flops of
+    phase_flops: B^3 complex multiply-adds per plane of every stored slab factorisation)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_1208_3956_amd import Helmholtz
+    wl = W.smooth_3d()
+    f = torch.from_numpy(wl.rhs()).to("cuda:0")
+    H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                  pml_iface_s0=wl.pml_iface_s0, prec="mixed", mode="reduced", device="cuda:0")
+    H.factor()
+    res = H.solve(f, tol)
+    torch.cuda.synchronize()
+    tf = ts = 0.0
+    for _ in range(reps):
+        ta = time.perf_counter()
+        H.factor()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        res = H.solve(f, tol)
+        torch.cuda.synchronize()
+        tf += tb - ta
+        ts += time.perf_counter() - tb
+    slots, path = H.factor_slots, H.factor_path
+    fflops = phase_flops(H, wl, f.shape[0])["factor_chunks"]
+    H.close()
+    ms = (tf + ts) / reps * 1e3
+    out = {"workload": wl.name, "nrhs": f.shape[0], "J": wl.J, "ms_per_step": ms,
+           "factor_ms": tf / reps * 1e3, "solve_ms": ts / reps * 1e3,
+           "value": f.shape[0] * wl.n_points / (ms / 1e3), "factor_slots": slots, "factor_path": path,
+           "factor_tflops": fflops / (tf / reps) / 1e12, "factor_frac_fp32_peak": fflops / (tf / reps) / 1e12 / PEAK["c64"],
+           "iters": {"min": min(res.iters), "max": max(res.iters), "mean": float(np.mean(res.iters))},
+           "relres_max": max(res.relres)}
+    print(f"# smooth 3-D: {ms:.0f} ms per step (factor {out['factor_ms']:.0f} ms), iterations "
+          f"{sorted(set(res.iters))}", file=sys.stderr, flush=True)
+    return out
+
+
 def batch_main(args):
     """Eight uneven layered problems (500^2 ... 2000^2, 8 RHS each): one step = factor all +
     solve all concurrently (helm_solve_batch, one stream per problem); the same handles are
@@ -467,14 +510,24 @@ def batch_main(args):
           for wl, s in zip(wls, streams)]
     pts = sum(f.shape[0] * wl.n_x * wl.n_y for wl, f in zip(wls, fs))
 
+    solo_ms = [0.0] * len(Hs)
+
     def step(concurrent):
-        for H in Hs:
-            H.factor()
-        for H in Hs:
-            H.stream.synchronize()
         if concurrent:
+            for H in Hs:
+                H.factor()
+            for H in Hs:
+                H.stream.synchronize()
             return solve_batch(Hs, fs, args.tol)
-        return [H.solve(f, args.tol) for H, f in zip(Hs, fs)]
+        # one problem after another, each timed alone (factor + solve)
+        out = []
+        for k, (H, f) in enumerate(zip(Hs, fs)):
+            ta = time.perf_counter()
+            H.factor()
+            out.append(H.solve(f, args.tol))
+            H.stream.synchronize()
+            solo_ms[k] += (time.perf_counter() - ta) * 1e3
+        return out
 
     for k in range(args.warmup):
         print(f"# batch warmup {k}: concurrent", file=sys.stderr, flush=True)
@@ -494,6 +547,7 @@ def batch_main(args):
         res_s = step(False)
     torch.cuda.synchronize()
     t_s = (time.perf_counter() - t0) / args.steps
+    solo = [v / (args.steps + args.warmup) for v in solo_ms]
     for H in Hs:
         H.close()
     out = {
@@ -505,6 +559,10 @@ def batch_main(args):
                    "J": [wl.J for wl in wls], "nrhs_each": 8, "prec": args.prec, "mode": args.mode,
                    "step": "helm_factor (each) + helm_solve_batch"},
         "sequential_value": pts / t_s, "sequential_ms_per_step": t_s * 1e3,
+        # each problem's factor + solve alone; the concurrent step cannot be shorter than the
+        # slowest of them (the dependency chain of its sweeps and iterations)
+        "alone_ms_per_problem": solo, "slowest_alone_ms": max(solo),
+        "concurrent_over_slowest_alone": t_b * 1e3 / max(solo),
         "iters": [float(np.mean(r.iters)) for r in res],
         "relres_max": max(max(r.relres) for r in res + res_s),
     }
@@ -652,6 +710,8 @@ def main():
                                       / out["c128"]["plain_one_rhs_per_solve"]["solve_only_value"])
     if wl.dim == 2 and wl.name.startswith("layers") and not args.no_lens_leg:
         out["lens_1000"] = lens_leg(args.tol)
+    if wl.dim == 2 and wl.name.startswith("layers") and not args.no_3d_leg:
+        out["smooth_3d"] = smooth3d_leg(args.tol)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_baseline)
         if args.cpu_baseline == "full" and args.oracle_record_out:

@@ -50,7 +50,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for p in procs:
         _wait(p)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-pthread", "-o", tmp, *objs]
+    cmd = [hipcc, "-shared", f"--offload-arch={ARCH}", "-pthread", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout)

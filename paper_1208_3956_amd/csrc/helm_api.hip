@@ -2,6 +2,7 @@
 // (Algorithm 1), the double sweep P (eqs. solve_upward / solve_downward), its reduced form
 // (Algorithms 2-4) and right-preconditioned GMRES (Algorithm 5, Sec. 2.3).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -170,6 +171,14 @@ struct helm_problem {
 };
 
 namespace {
+
+// roctx range over a scope (host side; visible to rocprofv3 --marker-trace, free otherwise)
+struct Range {
+    explicit Range(const char* m) { roctxRangePushA(m); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 thread_local std::string g_setup_err;   // message of the last failed helm_setup
 
@@ -1277,6 +1286,7 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
                          fn[0] > 0 ? rn[0] / fn[0] : rn[0], used);
         if (cycle > 0 && conv) { ok = true; break; }
         H->stat_restarts += 1;
+        Range range(cycle == 0 ? "GMRES cycle 0 (Algorithms 2, 3, 4)" : "GMRES restart cycle");
         std::vector<double> bn, target(nrhs);
         // right-hand sides that already meet tol take no part in this cycle: their
         // residual is cleared so the correction (P y + u~) added to them is zero
@@ -1872,6 +1882,7 @@ helm_status factor3(helm_t H) {
 
 helm_status helm_factor(helm_t H) {
     if (!H) return HELM_EINVAL;
+    Range range("helm_factor");
     if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
     const auto& g = H->g;
     // the captured reduced operator holds the factor addresses in its kernel arguments:
@@ -1951,6 +1962,7 @@ helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
     if (!(tol > 0)) return fail(H, HELM_EINVAL, "tol must be positive");
     H->stat_ap = 0;
     H->stat_panel = H->stat_panel_full = 0;
+    Range range("helm_solve");
     const auto t0 = std::chrono::steady_clock::now();
     helm_status s = solve_impl(H, nrhs, static_cast<const double2*>(rhs), static_cast<double2*>(u),
                                tol, iters, relres);
