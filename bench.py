@@ -508,6 +508,10 @@ def batch_main(args):
                     pml_iface_s0=wl.pml_iface_s0,
                     prec=args.prec, mode=args.mode, chunk=args.chunk, device=dev, stream=s)
           for wl, s in zip(wls, streams)]
+    # the same problems with their strip solves fused into multi-problem launches
+    Hf = [Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
+                    pml_iface_s0=wl.pml_iface_s0, prec=args.prec, mode=args.mode, chunk=args.chunk,
+                    device=dev, stream=torch.cuda.Stream(dev), batch_fuse=True) for wl in wls]
     pts = sum(f.shape[0] * wl.n_x * wl.n_y for wl, f in zip(wls, fs))
 
     solo_ms = [0.0] * len(Hs)
@@ -548,7 +552,24 @@ def batch_main(args):
     torch.cuda.synchronize()
     t_s = (time.perf_counter() - t0) / args.steps
     solo = [v / (args.steps + args.warmup) for v in solo_ms]
-    for H in Hs:
+
+    def step_fused():
+        for H in Hf:
+            H.factor()
+        for H in Hf:
+            H.stream.synchronize()
+        return solve_batch(Hf, fs, args.tol)
+
+    for k in range(args.warmup):
+        step_fused()
+    torch.cuda.synchronize()
+    print("# batch timed: fused", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res_f = step_fused()
+    torch.cuda.synchronize()
+    t_f = (time.perf_counter() - t0) / args.steps
+    for H in Hs + Hf:
         H.close()
     out = {
         "metric": "RHS*gridpts/s to 1e-6 residual, uneven batch of 8 layered 2-D problems (500^2..2000^2, 8 RHS each)",
@@ -563,8 +584,11 @@ def batch_main(args):
         # slowest of them (the dependency chain of its sweeps and iterations)
         "alone_ms_per_problem": solo, "slowest_alone_ms": max(solo),
         "concurrent_over_slowest_alone": t_b * 1e3 / max(solo),
+        # strip solves fused into multi-problem launches (batch_fuse), lockstep rounds
+        "fused_value": pts / t_f, "fused_ms_per_step": t_f * 1e3,
+        "fused_launches": res_f[0].fused_launches, "unfused_launches": res_f[0].unfused_launches,
         "iters": [float(np.mean(r.iters)) for r in res],
-        "relres_max": max(max(r.relres) for r in res + res_s),
+        "relres_max": max(max(r.relres) for r in res + res_s + res_f),
     }
     print(json.dumps(out), flush=True)
 

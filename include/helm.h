@@ -114,6 +114,10 @@ typedef struct {
     int restart;        /* GMRES cycle length (basis vectors kept before a restart); 0
                            (default): 60 in HELM_REDUCED, 30 in HELM_FULL, whose basis
                            vectors are whole fields.  Capped at max_iter                     */
+    int batch_fuse;     /* 1: in helm_solve_batch, fuse this problem's strip solves with
+                           those of the other problems that set it (multi-problem launches,
+                           lockstep rounds; see helm_solve_batch).  0 (default): its own
+                           thread and stream                                                  */
 } helm_opts;
 
 /* Default options for a 2-D problem of n_x x n_y interior points. */
@@ -205,10 +209,19 @@ helm_status helm_solve(helm_t H, int nrhs, const void* rhs, void* u, double tol,
 
 /*
  * Several independent problems solved concurrently (uneven grids, e.g. a batch of
- * different sizes): problem p solves nrhs[p] right-hand sides rhs[p] into u[p] exactly as
+ * different sizes): problem p solves nrhs[p] right-hand sides rhs[p] into u[p] as
  * helm_solve(H[p], ...) would, each driven by its own host thread on its handle's stream,
- * so that the kernels of different problems share the GPU.  Give every handle its own
- * stream (handles that share a stream are still correct, only serialised).
+ * so that the kernels of different problems share the GPU (give each handle its own
+ * stream: handles that share a stream are serialised).  Problems whose options set
+ * batch_fuse (2-D, HELM_MIXED_C64, the double sweep; at least two of them, on one device,
+ * kernel timing off) fuse their strip solves instead: their threads meet in lockstep
+ * rounds, one strip solve of each per round, and a round launches the strips of up to 8
+ * problems as one launch per strip-solver phase (panels of more than 4 right-hand sides on
+ * the two-level separator solve, grouped by the form of phase C; other strip solves of the
+ * round launch one by one) on a stream of the call's own, ordered against each problem's
+ * stream by events; their reduced operator runs kernel by kernel, not from its graph.
+ * Every kernel treats each problem alone, so the results are bitwise those of helm_solve.
+ * The call returns when every problem has finished.
  *   H, nrhs, rhs, u   host arrays of nprob entries; rhs[p], u[p] device fields of H[p]
  *   iters, relres     host, sum(nrhs) entries each (may be NULL), problem by problem
  * Returns HELM_OK when every problem succeeded, else the status of the first failing
@@ -334,6 +347,11 @@ helm_status helm_get_stats(helm_t H, int* ap_applies, int* restarts, double* sol
  * kernels' right-hand-side group), so the strip solves of an application scale with the
  * right-hand sides still iterating; the results are bitwise those of the full panel. */
 helm_status helm_get_panel_stats(helm_t H, long long* rhs_applied, long long* rhs_applied_full);
+
+/* Strip-solve counters of the last helm_solve_batch the handle took part in (host):
+ * multi-problem launches (one launch per phase for the current strip of up to 8 problems)
+ * and strip solves launched on their own.  Both zero when the handle was not fused. */
+helm_status helm_get_fusion_stats(helm_t H, long long* fused, long long* unfused);
 
 /*
  * Kernel timing (profiling aid).  While enabled, every launch of the hot kernels is

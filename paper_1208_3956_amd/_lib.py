@@ -23,7 +23,8 @@ EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
            "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
            "helm_solve_batch", "helm_get_dims3", "helm_autotune", "helm_get_factor_path",
-           "helm_get_factor_slots", "helm_strip_solve_noalloc", "helm_get_panel_stats"]
+           "helm_get_factor_slots", "helm_strip_solve_noalloc", "helm_get_panel_stats",
+           "helm_get_fusion_stats"]
 KERNEL_CLASSES = ["phase_a", "phase_b", "phase_c", "factor_chunks", "factor_separators",
                   "stencil", "gmres_vectors", "other"]
 
@@ -49,6 +50,7 @@ class HelmOpts(ctypes.Structure):
         ("sweep", ctypes.c_int),
         ("transmission", ctypes.c_int),
         ("restart", ctypes.c_int),
+        ("batch_fuse", ctypes.c_int),
     ]
 
 
@@ -90,6 +92,7 @@ def lib() -> ctypes.CDLL:
     L.helm_get_factor_path.argtypes = [vp, pint]
     L.helm_get_factor_slots.argtypes = [vp, pint, pint]
     L.helm_get_panel_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
+    L.helm_get_fusion_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
     L.helm_get_dims.argtypes = [vp, pint, pint, pint]
     L.helm_get_dims3.argtypes = [vp, pint, pint, pint, pint]
     L.helm_get_partition.argtypes = [vp, pint, pint, pint]
@@ -255,6 +258,13 @@ def helm_get_panel_stats(hdl):
     """(right-hand sides through the GMRES operator, the same without panel compaction)."""
     a, b = ctypes.c_longlong(), ctypes.c_longlong()
     check(lib().helm_get_panel_stats(hdl, ctypes.byref(a), ctypes.byref(b)), hdl)
+    return a.value, b.value
+
+
+def helm_get_fusion_stats(hdl):
+    """(multi-problem strip-solve launches, strip solves launched alone) of the last batch."""
+    a, b = ctypes.c_longlong(), ctypes.c_longlong()
+    check(lib().helm_get_fusion_stats(hdl, ctypes.byref(a), ctypes.byref(b)), hdl)
     return a.value, b.value
 
 

@@ -12,7 +12,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <condition_variable>
+#include <mutex>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "helm_internal.hpp"
@@ -112,6 +115,8 @@ struct EventTimer : helm::KTimer {
 #define FAC3_BATCH 0      // slabs per group; 0: the slabs split evenly over the streams
 #endif
 
+struct Fuser;
+
 struct helm_problem {
     helm::Geom g;
     helm::Chunks ch;
@@ -140,6 +145,9 @@ struct helm_problem {
     // right-hand sides that went through the GMRES operator, and as many without dropping
     // the converged ones from its panel
     long long stat_panel = 0, stat_panel_full = 0;
+    // strip-solve rounds of the last helm_solve_batch this handle took part in: launched as
+    // one multi-problem launch per phase, or problem by problem
+    long long stat_fused = 0, stat_unfused = 0;
     int dev = 0;                // HIP device of the handle
     int use_graph = 1;          // replay Algorithm 3 from a captured HIP graph (REDUCED)
     // captured reduced operators, one per right-hand-side count (the GMRES panel shrinks to
@@ -158,6 +166,7 @@ struct helm_problem {
     int sweep = 0;              // 0: the double sweep P; 1: the concurrent double sweep P_c
     int trans = 0;              // 0: PML transmission; 1: Robin transmission (Sec. 4.4)
     int restart = 0;            // GMRES cycle length (0: by mode)
+    int batch_fuse = 0;         // join fused strip-solve launches in helm_solve_batch
     hipStream_t st_c[2] = {};   // concurrent sweep: streams of the downward chain and the z solves
     hipEvent_t ev_c[3] = {};    // fork / join events of the concurrent sweep
     hipStream_t st_fac[FAC3_GROUPS - 1] = {};   // group streams of the 3-D complex64 factorisation
@@ -167,7 +176,100 @@ struct helm_problem {
     double stat_ms = 0.0;
     std::vector<void*> owned;   // table allocations
     EventTimer* timer = nullptr; // non-null while kernel timing is enabled
+    Fuser* fuser = nullptr;     // set during helm_solve_batch: strip solves join fused launches
+    hipEvent_t fuse_ev = nullptr; // marks this handle's work before a fused strip solve
     helm::KTimer* kt() { return timer; }
+};
+
+// Strip solves of several problems' host threads in one launch per phase (helm_solve_batch).
+// Every participating thread deposits each strip solve and waits; when every thread that
+// has not finished its solve has deposited one, the last to arrive launches the round on
+// the fuser's stream and releases the others.  The round's jobs are grouped by the form of
+// their phase C (target columns or all); a group of two or more jobs that qualify is one
+// multi-problem launch per phase, the rest launch one by one.  Waiting for every unfinished
+// thread keeps the problems in lockstep, one strip of each per round (a thread between two
+// operator applications holds the round until it deposits again).  Each problem keeps its
+// own stream: the fuser's stream waits for an event recorded on the depositor's stream,
+// and the depositor's stream waits for an event recorded after the launch, so each
+// problem's work stays in its program order and its synchronisations wait for its own work.
+struct Fuser {
+    struct Pending {
+        helm::StripJob job;
+        hipStream_t st;
+        hipEvent_t ready;
+        hipError_t* result;
+    };
+    std::mutex mu;
+    std::condition_variable cv;
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    int active = 0;                  // participants that have not finished their solve
+    long round = 0;
+    std::vector<Pending> pend;
+    long fused_launches = 0, single_launches = 0;
+
+    void join() {
+        std::lock_guard<std::mutex> lk(mu);
+        ++active;
+    }
+    void leave() {
+        std::unique_lock<std::mutex> lk(mu);
+        --active;
+        if (!pend.empty() && (int)pend.size() >= active) launch_round();
+    }
+    hipError_t submit(const helm::StripJob& j, hipStream_t own, hipEvent_t ready) {
+        hipError_t e = hipEventRecord(ready, own);
+        if (e != hipSuccess) return e;
+        std::unique_lock<std::mutex> lk(mu);
+        pend.push_back(Pending{j, own, ready, &e});
+        const long my = round;
+        if ((int)pend.size() >= active) launch_round();
+        else cv.wait(lk, [&] { return round != my; });
+        return e;
+    }
+    // with mu held
+    void launch_round() {
+        const int n = (int)pend.size();
+        hipError_t e = hipSuccess;
+        for (const Pending& p : pend)
+            if (e == hipSuccess) e = hipStreamWaitEvent(st, p.ready, 0);
+        // groups: jobs that qualify alone for a multi-problem launch, by phase-C form
+        std::vector<helm::StripJob> grp[2], rest;
+        for (const Pending& p : pend) {
+            const helm::StripJob& j = p.job;
+            const int cls = (j.io.targets_only && j.Fc) ? 1 : 0;
+            helm::StripJob pair[2] = {j, j};
+            if (helm::strip_jobs_fusable(pair, 2)) grp[cls].push_back(j);
+            else rest.push_back(j);
+        }
+        auto single = [&](const helm::StripJob& j) {
+            ++single_launches;
+            return helm::launch_strip_solve<float>(
+                *j.t, *j.g, *j.ch, j.s, j.fs, static_cast<const float2*>(j.F),
+                static_cast<const float2*>(j.Fc), static_cast<const float2*>(j.Fs),
+                static_cast<float2*>(j.Yw), j.nrhs, j.io, st, nullptr);
+        };
+        for (auto& gj : grp)
+            for (size_t k0 = 0; k0 < gj.size() && e == hipSuccess; k0 += helm::MULTI_MAX) {
+                const int m = (int)std::min<size_t>(helm::MULTI_MAX, gj.size() - k0);
+                if (m >= 2) {
+                    e = helm::launch_strip_solve_multi(gj.data() + k0, m, st, nullptr);
+                    ++fused_launches;
+                } else {
+                    e = single(gj[k0]);
+                }
+            }
+        for (size_t k = 0; k < rest.size() && e == hipSuccess; ++k) e = single(rest[k]);
+        (void)n;
+        if (e == hipSuccess) e = hipEventRecord(done, st);
+        for (const Pending& p : pend) {
+            hipError_t w = e == hipSuccess ? hipStreamWaitEvent(p.st, done, 0) : e;
+            *p.result = w;
+        }
+        pend.clear();
+        ++round;
+        cv.notify_all();
+    }
 };
 
 namespace {
@@ -364,6 +466,15 @@ helm_status strip_solve3(helm_t H, int s, int nrhs, const helm::IOSpec& io, void
 template <typename T>
 helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io, void* yw, helm::KTimer* kt) {
     if (H->g.dim == 3) return strip_solve3<T>(H, s, nrhs, io, yw, kt);
+    if (H->fuser && std::is_same<T, float>::value) {
+        helm::StripJob j;
+        j.t = &H->t; j.g = &H->g; j.ch = &H->ch; j.s = s; j.fs = H->fidx[s]; j.f32 = true;
+        j.F = H->F; j.Fc = H->Fc; j.Fs = H->Fs; j.Yw = yw ? yw : H->wk.Yw;
+        j.nrhs = nrhs; j.io = io;
+        if (!H->fuse_ev) HIPCHK(hipEventCreateWithFlags(&H->fuse_ev, hipEventDisableTiming));
+        HIPCHK(H->fuser->submit(j, H->st, H->fuse_ev));
+        return HELM_OK;
+    }
     const auto* F = static_cast<const helm::cplx<T>*>(H->F);
     const auto* Fc = static_cast<const helm::cplx<T>*>(H->Fc);
     const auto* Fs = static_cast<const helm::cplx<T>*>(H->Fs);
@@ -897,7 +1008,7 @@ helm_status apply_op(helm_t H, int nrhs, const double2* x, double2* out) {
     }
     // kernel timing brackets launches with events, which a graph replay cannot time here
     // (hipEventElapsedTime rejects events recorded by graph nodes): timed runs go eagerly
-    if (!H->use_graph || H->timer) return apply_AP_red(H, nrhs, x, out);
+    if (!H->use_graph || H->timer || H->fuser) return apply_AP_red(H, nrhs, x, out);
     // graph replay: the captured launches read the fixed buffer apin and write `out`
     Work& w = H->wk;
     CHK(ensure_sweep_ws(H, nrhs));
@@ -1429,6 +1540,7 @@ void helm_default_opts(helm_opts* o, int n_x, int n_y) {
     o->sweep = 0;
     o->transmission = 0;
     o->restart = 0;
+    o->batch_fuse = 0;
 }
 
 helm_status helm_setup(const double* c, double omega, double h, const helm_opts* opts, int J,
@@ -1526,6 +1638,7 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     H->trans = opts->transmission;
     if (opts->restart < 0) return bad("restart must be >= 0");
     H->restart = opts->restart;
+    H->batch_fuse = opts->batch_fuse ? 1 : 0;
     if (hipGetDevice(&H->dev) != hipSuccess) H->dev = 0;
 
     // ---- tables (FP64 complex), Sec. 2.1-2.2
@@ -2048,11 +2161,38 @@ helm_status helm_solve_batch(int nprob, const helm_t* H, const int* nrhs, const 
         if (nrhs[p] < 1) return fail(H[p], HELM_EINVAL, "helm_solve_batch: nrhs must be >= 1");
         off[p + 1] = off[p] + nrhs[p];
     }
+    // 2-D complex64 problems on the double sweep fuse their strip solves: their host threads
+    // meet in a Fuser, which launches the strip solves of a round on a stream of its own
+    // (ordered against each problem's stream by events), one launch per phase
+    std::vector<int> fuse;
+    for (int p = 0; p < nprob; ++p)
+        if (H[p]->batch_fuse && H[p]->factored && H[p]->g.dim == 2 && H[p]->prec == HELM_MIXED_C64 &&
+            H[p]->sweep == 0 && !H[p]->timer && H[p]->dev == H[0]->dev)
+            fuse.push_back(p);
+    if (fuse.size() < 2) fuse.clear();
+    Fuser fz;
+    if (!fuse.empty()) {
+        if (hipSetDevice(H[fuse[0]]->dev) != hipSuccess) return fail(H[fuse[0]], HELM_EHIP, "hipSetDevice failed");
+        if (hipStreamCreateWithFlags(&fz.st, hipStreamNonBlocking) != hipSuccess)
+            return fail(H[fuse[0]], HELM_EHIP, "stream creation failed");
+        if (hipEventCreateWithFlags(&fz.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipStreamDestroy(fz.st);
+            return fail(H[fuse[0]], HELM_EHIP, "event creation failed");
+        }
+        for (int p : fuse) {
+            H[p]->fuser = &fz;
+            fz.join();
+        }
+    }
     std::vector<helm_status> st(nprob, HELM_OK);
     std::vector<std::thread> th;
     th.reserve(nprob);
     for (int p = 0; p < nprob; ++p) {
         th.emplace_back([&, p]() {
+            struct Leave {
+                Fuser* f;
+                ~Leave() { if (f) f->leave(); }
+            } leave{H[p]->fuser};
             if (hipSetDevice(H[p]->dev) != hipSuccess) {
                 st[p] = fail(H[p], HELM_EHIP, "hipSetDevice failed");
                 return;
@@ -2062,6 +2202,20 @@ helm_status helm_solve_batch(int nprob, const helm_t* H, const int* nrhs, const 
         });
     }
     for (auto& t : th) t.join();
+    for (int p = 0; p < nprob; ++p) H[p]->stat_fused = H[p]->stat_unfused = 0;
+    if (!fuse.empty()) {
+        hipError_t e = hipStreamSynchronize(fz.st);
+        for (int p : fuse) {
+            const hipError_t e2 = hipStreamSynchronize(H[p]->st);
+            if (e == hipSuccess) e = e2;
+            H[p]->fuser = nullptr;
+            H[p]->stat_fused = fz.fused_launches;
+            H[p]->stat_unfused = fz.single_launches;
+        }
+        (void)hipEventDestroy(fz.done);
+        (void)hipStreamDestroy(fz.st);
+        if (e != hipSuccess) return fail(H[fuse[0]], HELM_EHIP, hipGetErrorString(e));
+    }
     for (int p = 0; p < nprob; ++p)
         if (st[p] != HELM_OK) return st[p];
     return HELM_OK;
@@ -2234,6 +2388,13 @@ helm_status helm_get_panel_stats(helm_t H, long long* rhs_applied, long long* rh
     return HELM_OK;
 }
 
+helm_status helm_get_fusion_stats(helm_t H, long long* fused, long long* unfused) {
+    if (!H) return HELM_EINVAL;
+    if (fused) *fused = H->stat_fused;
+    if (unfused) *unfused = H->stat_unfused;
+    return HELM_OK;
+}
+
 helm_status helm_get_factor_slots(helm_t H, int* slots, int* strip_slot) {
     if (!H || !slots) return HELM_EINVAL;
     if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");
@@ -2286,6 +2447,7 @@ void helm_destroy(helm_t H) {
     else (void)hipDeviceSynchronize();
     for (auto& e : H->apg)
         if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (H->fuse_ev) (void)hipEventDestroy(H->fuse_ev);
     if (H->cap_st) (void)hipStreamDestroy(H->cap_st);
     for (hipStream_t q : H->st_c)
         if (q) (void)hipStreamDestroy(q);

@@ -103,6 +103,29 @@ struct IOSpec {
     int t_cols = 2;
 };
 
+// One strip solve of a multi-problem launch (one strip of each of several problems).
+constexpr int MULTI_MAX = 8;
+struct DevTables;
+struct KTimer;
+struct StripJob {
+    const DevTables* t = nullptr;
+    const Geom* g = nullptr;
+    const Chunks* ch = nullptr;
+    int s = 0, fs = 0;                   // strip and its factor slot
+    bool f32 = false;                    // complex64 factors and workspace
+    const void* F = nullptr;
+    const void* Fc = nullptr;
+    const void* Fs = nullptr;
+    void* Yw = nullptr;
+    int nrhs = 0;
+    IOSpec io;
+};
+// The jobs run as one launch per phase: 2 to MULTI_MAX of them, all complex64 2-D strips
+// with more than 4 right-hand sides on the two-level separator solve, and the same phase-C
+// form (target columns or all).
+bool strip_jobs_fusable(const StripJob* jobs, int n);
+hipError_t launch_strip_solve_multi(const StripJob* jobs, int n, hipStream_t st, KTimer* kt);
+
 // Strip-local column q receives the transmission source of io.
 __host__ __device__ inline bool tr_col(const IOSpec& io, int q) {
     return io.q_t >= 0 && (q == io.q_t || (io.t_cols == 2 && q == io.q_t + 1));

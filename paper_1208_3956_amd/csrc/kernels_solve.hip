@@ -41,6 +41,35 @@ struct SolveArgs {
     int q, G;             // separator groups (two-level separator solve when G >= 2)
 };
 
+// Block coordinates of a workgroup: the launch's own (one problem), or its place inside one
+// problem of a multi-problem launch (nz: the number of z blocks that problem uses).
+struct Blk {
+    int x, y, z, nz;
+};
+__device__ inline Blk own_blk() { return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z, (int)gridDim.z}; }
+
+// Several problems' strip solves in one launch (one strip of each): their arguments by value
+// in the kernel-argument block, x blocks [xs[k], xs[k+1]) belonging to problem k, which uses
+// ny[k] y blocks and nz[k] z blocks of the launch's maximum (the others return at once).
+template <typename T>
+struct MultiArgs {
+    SolveArgs<T> a[MULTI_MAX];
+    int xs[MULTI_MAX + 1];
+    int ny[MULTI_MAX], nz[MULTI_MAX];
+    int n;
+};
+static_assert(sizeof(MultiArgs<float>) <= 4096, "multi-problem arguments exceed the kernel-argument block");
+
+// problem of this workgroup and its block coordinates inside it; false: idle workgroup
+template <typename T>
+__device__ inline bool multi_blk(const MultiArgs<T>& m, int& k, Blk& b) {
+    const int bx = (int)blockIdx.x;
+    k = 0;
+    while (k + 1 < m.n && bx >= m.xs[k + 1]) ++k;
+    b = Blk{bx - m.xs[k], (int)blockIdx.y, (int)blockIdx.z, m.nz[k]};
+    return b.y < m.ny[k] && b.z < m.nz[k];
+}
+
 template <typename T>
 __device__ inline cplx<T> gather(const IOSpec& io, int r, int l, int q, int Ny) {
     double2 v = cmk<double2>(0.0, 0.0);
@@ -273,13 +302,13 @@ typedef float mf4 __attribute__((ext_vector_type(4)));
 // (64 x 16) goes through LDS, double-buffered, so a step has a single barrier.  Each lane
 // gathers the right-hand-side values of its own four output positions.
 template <int D>
-__global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
+__device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Blk& B) {
     using V = float2;
     constexpr int R = 16;
     __shared__ V Vs[2][WP][R];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int n = lane & 15, q4 = lane >> 4;            // MFMA column (rhs), row quad
-    const int c = blockIdx.x, rbase = blockIdx.y * R;
+    const int c = B.x, rbase = B.y * R;
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
     const int nr = r1 - r0;
@@ -434,6 +463,14 @@ __global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) {
     if constexpr (D > 1) { if (off == 1) bwd_loop(std::integral_constant<int, 1 % D>{}); }
     if constexpr (D > 2) { if (off == 2) bwd_loop(std::integral_constant<int, 2 % D>{}); }
     if constexpr (D > 3) { if (off == 3) bwd_loop(std::integral_constant<int, 3 % D>{}); }
+}
+template <int D>
+__global__ void __launch_bounds__(NT) k_phase_a_mfma(SolveArgs<float> a) { phase_a_mfma<D>(a, own_blk()); }
+template <int D>
+__global__ void __launch_bounds__(NT) k_phase_a_mfma_multi(MultiArgs<float> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) phase_a_mfma<D>(m.a[k], b);
 }
 
 // ---------------------------------------------------------------- phase B0
@@ -697,7 +734,7 @@ struct SepCtx {
     __shared__ V vecw[4][RB][WP];                                         \
     __shared__ V part[2][4][RB][WP];                                      \
     const int i = threadIdx.x & (WP - 1);                                 \
-    SepCtx<T> X{a, a.P - 1, (int)blockIdx.x * RB};                        \
+    SepCtx<T> X{a, a.P - 1, B.x * RB};                                    \
     bool okb[RB];                                                         \
     for (int b = 0; b < RB; ++b) okb[b] = X.ok(b);                        \
     auto vecs_at = [&](int c, V (&v)[RB]) {                               \
@@ -709,9 +746,9 @@ struct SepCtx {
 // the group's right-hand sides a_c = G'_c r^_c, r^_c = r_s - c_s y_{s-1} - b_s y_{s+1}
 // (s = sep(c)), independent per separator: wave w takes c0 + w, c0 + w + 4, ...
 template <typename T, int D>
-__global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) {
+__device__ __forceinline__ void sep_fwd_local(const SolveArgs<T>& a, const Blk& B) {
     SEPK_PROLOGUE
-    const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
+    const int g = B.y, c0 = X.first(g), c1 = X.last(g);
     {
         const int w = threadIdx.x >> 6;
         for (int c = c0 + w; c <= c1; c += 4) {
@@ -755,7 +792,7 @@ __global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) {
 
 // chain over the groups' last separators: z'_{last g} = zeta_{last g} + Phi_{last g} z'_{last g-1}
 template <typename T, int D>
-__global__ void __launch_bounds__(NT) k_sep_fwd_top(SolveArgs<T> a) {
+__device__ __forceinline__ void sep_fwd_top(const SolveArgs<T>& a, const Blk& B) {
     SEPK_PROLOGUE
     V v0[RB];
     vecs_at(X.last(0), v0);
@@ -767,9 +804,9 @@ __global__ void __launch_bounds__(NT) k_sep_fwd_top(SolveArgs<T> a) {
 // fix-up of the group's other separators, then its local backward chain
 // xi_c = z'_c - U'_c xi_{c+1} (the group's last separator starts it)
 template <typename T, int D>
-__global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) {
+__device__ __forceinline__ void sep_fix_bwd_local(const SolveArgs<T>& a, const Blk& B) {
     SEPK_PROLOGUE
-    const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
+    const int g = B.y, c0 = X.first(g), c1 = X.last(g);
     if (g >= 1) {
         V vf[RB];
         vecs_at(X.last(g - 1), vf);
@@ -786,7 +823,7 @@ __global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) {
 
 // chain over the groups' first separators: x_{first g} = xi_{first g} + Psi_{first g} x_{first g+1}
 template <typename T, int D>
-__global__ void __launch_bounds__(NT) k_sep_bwd_top(SolveArgs<T> a) {
+__device__ __forceinline__ void sep_bwd_top(const SolveArgs<T>& a, const Blk& B) {
     SEPK_PROLOGUE
     V v0[RB];
     vecs_at(X.first(a.G - 1), v0);
@@ -797,9 +834,9 @@ __global__ void __launch_bounds__(NT) k_sep_bwd_top(SolveArgs<T> a) {
 
 // fix-up of the group's other separators: x_c = xi_c + Psi_c x_{first g+1}
 template <typename T, int D>
-__global__ void __launch_bounds__(NT) k_sep_bwd_fix(SolveArgs<T> a) {
+__device__ __forceinline__ void sep_bwd_fix(const SolveArgs<T>& a, const Blk& B) {
     SEPK_PROLOGUE
-    const int g = blockIdx.y, c0 = X.first(g), c1 = X.last(g);
+    const int g = B.y, c0 = X.first(g), c1 = X.last(g);
     V vf[RB];
     vecs_at(X.first(g + 1), vf);
     sep_fix<T, RB>(c1 - c0, vf,
@@ -807,6 +844,46 @@ __global__ void __launch_bounds__(NT) k_sep_bwd_fix(SolveArgs<T> a) {
                    [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw);
 }
 #undef SEPK_PROLOGUE
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) { sep_fwd_local<T, D>(a, own_blk()); }
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fwd_local_multi(MultiArgs<T> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) sep_fwd_local<T, D>(m.a[k], b);
+}
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fwd_top(SolveArgs<T> a) { sep_fwd_top<T, D>(a, own_blk()); }
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fwd_top_multi(MultiArgs<T> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) sep_fwd_top<T, D>(m.a[k], b);
+}
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) { sep_fix_bwd_local<T, D>(a, own_blk()); }
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_fix_bwd_local_multi(MultiArgs<T> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) sep_fix_bwd_local<T, D>(m.a[k], b);
+}
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_bwd_top(SolveArgs<T> a) { sep_bwd_top<T, D>(a, own_blk()); }
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_bwd_top_multi(MultiArgs<T> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) sep_bwd_top<T, D>(m.a[k], b);
+}
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_bwd_fix(SolveArgs<T> a) { sep_bwd_fix<T, D>(a, own_blk()); }
+template <typename T, int D>
+__global__ void __launch_bounds__(NT) k_sep_bwd_fix_multi(MultiArgs<T> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) sep_bwd_fix<T, D>(m.a[k], b);
+}
 
 // ---------------------------------------------------------------- phase C (all columns)
 template <typename T, int R>
@@ -862,12 +939,12 @@ __global__ void __launch_bounds__(NT) k_phase_c(SolveArgs<T> a) {
 // scatter writes whole rows of one right-hand side (consecutive x positions) instead of
 // four-element pieces of sixteen right-hand sides.  Grid (chunks, right-hand-side groups,
 // row groups): row group z takes the chunk's rows z, z + gridDim.z, ...
-__global__ void __launch_bounds__(NT) k_phase_c_mfma(SolveArgs<float> a) {
+__device__ __forceinline__ void phase_c_mfma(const SolveArgs<float>& a, const Blk& B) {
     using V = float2;
     __shared__ V X[2 * WP][16];
     __shared__ V O[16][WP + 1];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
-    const int c = blockIdx.x, rbase = blockIdx.y * 16;
+    const int c = B.x, rbase = B.y * 16;
     const int r0 = c * a.m;
     const bool has_a = c > 0, has_b = c < a.P - 1;
     const int r1 = has_b ? c * a.m + a.m - 1 : a.Ny;     // separator closing the chunk, or Ny
@@ -895,7 +972,7 @@ __global__ void __launch_bounds__(NT) k_phase_c_mfma(SolveArgs<float> a) {
     const int rn = rbase + n;
     const int qrow = 16 * w + 4 * q4;
     const size_t ybase = (size_t)(rn < a.nrhs ? rn : 0) * a.Ny * WP + qrow;
-    for (int j = blockIdx.z; j < nrow; j += gridDim.z) {
+    for (int j = B.z; j < nrow; j += B.nz) {
         const int l = r0 + j;
         mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1;
         if (!(has_b && l == r1)) {
@@ -935,6 +1012,12 @@ __global__ void __launch_bounds__(NT) k_phase_c_mfma(SolveArgs<float> a) {
             if (r < a.nrhs && i < a.W) scatter<float>(a, r, l, i, O[q][i]);
         }
     }
+}
+__global__ void __launch_bounds__(NT) k_phase_c_mfma(SolveArgs<float> a) { phase_c_mfma(a, own_blk()); }
+__global__ void __launch_bounds__(NT) k_phase_c_mfma_multi(MultiArgs<float> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) phase_c_mfma(m.a[k], b);
 }
 
 // ---------------------------------------------------------------- phase C (target columns)
@@ -1001,12 +1084,12 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets(SolveArgs<T> a) {
 // tiles w + 4 z, w + 4 z + 4 gridDim.z, ...  Every workgroup stages the chunk's two separator
 // vectors; the separator row that closes the chunk is copied (its x is final after phase B)
 // by tile group 0.
-__global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a) {
+__device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, const Blk& B) {
     using V = float2;
     __shared__ V X[2 * WP][16];
     __shared__ V XF[2][WP][16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
-    const int c = blockIdx.x, rbase = blockIdx.y * 16;
+    const int c = B.x, rbase = B.y * 16;
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
     const int nr = r1 - r0;
@@ -1088,7 +1171,7 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
     V vb[32];
 #pragma unroll
     for (int s4 = 0; s4 < 32; ++s4) vb[s4] = X[4 * s4 + q4][n];
-    for (int tile = w + 4 * (int)blockIdx.z; tile < ntile; tile += 4 * (int)gridDim.z) {
+    for (int tile = w + 4 * B.z; tile < ntile; tile += 4 * B.nz) {
         // A operands: row rho = 16 tile + n (clamped), k = 4 s + q4
         const int rho = min(16 * tile + n, nrows - 1);
         const int l = r0 + (rho >> 3), tt = rho & 7;
@@ -1135,10 +1218,18 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a)
         }
     }
     // the separator row closing this chunk (its x, fixed up above if needed, is in X)
-    if (has_b && blockIdx.z == 0 && t < 8 * 16) {
+    if (has_b && B.z == 0 && t < 8 * 16) {
         const int tt = t >> 4, r = rbase + (t & 15), q = a.tcol[tt];
         if (q >= 0 && r < a.nrhs) scatter<float>(a, r, r1, q, X[WP + q][t & 15]);
     }
+}
+__global__ void __launch_bounds__(NT) k_phase_c_targets_mfma(SolveArgs<float> a) {
+    phase_c_targets_mfma(a, own_blk());
+}
+__global__ void __launch_bounds__(NT) k_phase_c_targets_mfma_multi(MultiArgs<float> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) phase_c_targets_mfma(m.a[k], b);
 }
 
 template <typename T> struct Depth { static constexpr int D = 2; };
@@ -1189,7 +1280,7 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
             // the 16-row tiles of a chunk are spread over TS workgroups (two tiles per wave
             // at m = 32: measured faster than one or four)
             const int tiles = ((a.m - 1) * 8 + 15) / 16;
-            const int TS = std::min(8, std::max(1, (tiles + 7) / 8));
+            const int TS = std::min(8, std::max(1, (tiles + 7) / 8));      // targets_groups
             hipLaunchKernelGGL(k_phase_c_targets_mfma, dim3(a.P, (a.nrhs + 15) / 16, TS), dim3(NT), 0, st, a);
         }
         else
@@ -1197,7 +1288,7 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
                                dim3(NT), 0, st, a);
     }
     else if constexpr (std::is_same<T, float>::value) {
-        // about four workgroups per CU: row groups split each chunk's rows
+        // about four workgroups per CU: row groups split each chunk's rows (phase_c_groups)
         const int per = a.P * ((a.nrhs + 15) / 16);
         const int TS = std::max(1, std::min(std::min(8, a.m), (1024 + per - 1) / per));
         hipLaunchKernelGGL(k_phase_c_mfma, dim3(a.P, (a.nrhs + 15) / 16, TS), dim3(NT), 0, st, a);
@@ -1207,12 +1298,10 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
     return hipGetLastError();
 }
 
-}  // namespace
-
 template <typename T>
-hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
-                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
-                              int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt) {
+SolveArgs<T> solve_args(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
+                        const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
+                        int nrhs, const IOSpec& io) {
     SolveArgs<T> a;
     a.F = F + (size_t)fs * g.Ny * NSLOT * BLK;
     a.Fs = Fs ? Fs + (size_t)fs * (ch.P - 1) * 2 * BLK : nullptr;
@@ -1235,9 +1324,107 @@ hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& c
     a.m = ch.m;
     a.P = ch.P;
     a.nrhs = nrhs;
+    return a;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
+                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
+                              int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt) {
+    const SolveArgs<T> a = solve_args<T>(t, g, ch, s, fs, F, Fc, Fs, Yw, nrhs, io);
     const bool targets = a.io.targets_only != 0;
     if (nrhs <= 4) return run<T, 4>(a, targets, st, kt);
     return run<T, 16>(a, targets, st, kt);
+}
+
+namespace {
+SolveArgs<float> job_args(const StripJob& j) {
+    return solve_args<float>(*j.t, *j.g, *j.ch, j.s, j.fs, static_cast<const float2*>(j.F),
+                             static_cast<const float2*>(j.Fc), static_cast<const float2*>(j.Fs),
+                             static_cast<float2*>(j.Yw), j.nrhs, j.io);
+}
+// rows of the full-column phase C per workgroup: about four workgroups per CU
+int phase_c_groups(const SolveArgs<float>& a) {
+    const int per = a.P * ((a.nrhs + 15) / 16);
+    return std::max(1, std::min(std::min(8, a.m), (1024 + per - 1) / per));
+}
+int targets_groups(const SolveArgs<float>& a) {
+    const int tiles = ((a.m - 1) * 8 + 15) / 16;
+    return std::min(8, std::max(1, (tiles + 7) / 8));
+}
+}  // namespace
+
+bool strip_jobs_fusable(const StripJob* jobs, int n) {
+    if (n < 2 || n > MULTI_MAX) return false;
+    int targets = -1;
+    for (int k = 0; k < n; ++k) {
+        const StripJob& j = jobs[k];
+        if (!j.f32 || j.g->dim != 2 || j.nrhs <= 4) return false;
+        if (!(j.ch->P > 2 && j.ch->G >= 2 && j.Fs)) return false;        // two-level separators
+        const int tk = (j.io.targets_only && j.Fc) ? 1 : 0;
+        if (targets >= 0 && tk != targets) return false;
+        targets = tk;
+    }
+    return true;
+}
+
+hipError_t launch_strip_solve_multi(const StripJob* jobs, int n, hipStream_t st, KTimer* kt) {
+    if (!strip_jobs_fusable(jobs, n)) return hipErrorInvalidValue;
+    MultiArgs<float> m{};
+    m.n = n;
+    for (int k = 0; k < n; ++k) m.a[k] = job_args(jobs[k]);
+    const bool targets = m.a[0].io.targets_only != 0;
+    // x blocks per problem, and per-problem y / z extents (the launch takes the largest)
+    auto shape = [&](auto xper, auto yper, auto zper, dim3& grid) {
+        m.xs[0] = 0;
+        int my = 1, mz = 1;
+        for (int k = 0; k < n; ++k) {
+            m.xs[k + 1] = m.xs[k] + xper(m.a[k]);
+            m.ny[k] = yper(m.a[k]);
+            m.nz[k] = zper(m.a[k]);
+            my = std::max(my, m.ny[k]);
+            mz = std::max(mz, m.nz[k]);
+        }
+        grid = dim3(m.xs[n], my, mz);
+    };
+    auto P = [](const SolveArgs<float>& a) { return a.P; };
+    auto RG = [](const SolveArgs<float>& a) { return (a.nrhs + 15) / 16; };
+    auto NR = [](const SolveArgs<float>& a) { return a.nrhs; };     // one right-hand side per block
+    auto G = [](const SolveArgs<float>& a) { return a.G; };
+    auto G1 = [](const SolveArgs<float>& a) { return a.G - 1; };
+    auto one = [](const SolveArgs<float>&) { return 1; };
+    constexpr int DS = Depth<float>::D;
+    dim3 grid;
+    if (kt) kt->begin(K_PHASE_A, st);
+    shape(P, RG, one, grid);
+    hipLaunchKernelGGL(k_phase_a_mfma_multi<2>, grid, dim3(NT), 0, st, m);
+    if (kt) kt->end(K_PHASE_A, st);
+    if (kt) kt->begin(K_PHASE_B, st);
+    shape(NR, G, one, grid);
+    hipLaunchKernelGGL((k_sep_fwd_local_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    shape(NR, one, one, grid);
+    hipLaunchKernelGGL((k_sep_fwd_top_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    shape(NR, G, one, grid);
+    hipLaunchKernelGGL((k_sep_fix_bwd_local_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    shape(NR, one, one, grid);
+    hipLaunchKernelGGL((k_sep_bwd_top_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    if (!targets) {
+        shape(NR, G1, one, grid);
+        hipLaunchKernelGGL((k_sep_bwd_fix_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    }
+    if (kt) kt->end(K_PHASE_B, st);
+    if (kt) kt->begin(K_PHASE_C, st);
+    if (targets) {
+        shape(P, RG, targets_groups, grid);
+        hipLaunchKernelGGL(k_phase_c_targets_mfma_multi, grid, dim3(NT), 0, st, m);
+    } else {
+        shape(P, RG, phase_c_groups, grid);
+        hipLaunchKernelGGL(k_phase_c_mfma_multi, grid, dim3(NT), 0, st, m);
+    }
+    if (kt) kt->end(K_PHASE_C, st);
+    return hipGetLastError();
 }
 
 template hipError_t launch_strip_solve<float>(const DevTables&, const Geom&, const Chunks&, int, int,

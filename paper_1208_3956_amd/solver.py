@@ -28,6 +28,9 @@ class SolveResult:
     # same count had they stayed
     panel_rhs: int = 0
     panel_rhs_full: int = 0
+    # solve_batch: multi-problem strip-solve launches and strip solves launched alone
+    fused_launches: int = 0
+    unfused_launches: int = 0
 
 
 class Helmholtz:
@@ -49,6 +52,8 @@ class Helmholtz:
                unpadded subdomains with first-order absorbing conditions; 2-D, double
                sweep, full form)
     restart    GMRES cycle length (0 = library default: 60 reduced, 30 full)
+    batch_fuse in solve_batch, fuse this problem's strip solves with the other problems
+               that set it (lockstep multi-problem launches) instead of its own stream
     prec       "c128" or "mixed" (complex64 strip factors and sweeps, FP64 GMRES)
     mode       "full" or "reduced" (GMRES on the interface columns, Algorithms 2-5)
     chunk      rows per chunk of the y-partitioned strip solver (0 = library default)
@@ -63,7 +68,7 @@ class Helmholtz:
                  device="cuda:0", stream=None, graph: bool = True,
                  pml_iface_s0: Optional[float] = None,
                  beta_rule: int = 0, sweep: str = "double", transmission: str = "pml",
-                 restart: int = 0):
+                 restart: int = 0, batch_fuse: bool = False):
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise ValueError("the solver runs on a HIP device (cuda:N in torch)")
@@ -83,6 +88,7 @@ class Helmholtz:
         o.sweep = {"double": 0, "concurrent": 1}[sweep]
         o.transmission = {"pml": 0, "robin": 1}[transmission]
         o.restart = int(restart)
+        o.batch_fuse = 1 if batch_fuse else 0
         o.prec = {"c128": L.HELM_C128, "mixed": L.HELM_MIXED_C64, "c64": L.HELM_MIXED_C64}[prec]
         o.mode = {"full": L.HELM_FULL, "reduced": L.HELM_REDUCED}[mode]
         o.max_iter = int(max_iter)
@@ -318,6 +324,7 @@ def solve_batch(problems: Sequence[Helmholtz], rhs: Sequence[torch.Tensor], tol:
         H.stream.synchronize()
         ap, rs, ms = L.helm_get_stats(H.h)
         pr, prf = L.helm_get_panel_stats(H.h)
-        out.append(SolveResult(u, its[k:k + n], rel[k:k + n], st, ap, rs, ms, pr, prf))
+        fu, un = L.helm_get_fusion_stats(H.h)
+        out.append(SolveResult(u, its[k:k + n], rel[k:k + n], st, ap, rs, ms, pr, prf, fu, un))
         k += n
     return out

@@ -96,6 +96,64 @@ def test_solve_batch_uneven_problems():
         H.close()
 
 
+def _fused_case(mode, precs, seeds=(51, 53, 55), sizes=((40, 3), (64, 5), (48, 4))):
+    """Problems of different sizes with 6 right-hand sides each (panels of more than 4 take
+    the fused launches), each problem also solved on its own by a second handle."""
+    from paper_1208_3956_amd import Helmholtz
+    wls, Hs, Hone = [], [], []
+    for (n, J), seed, prec in zip(sizes, seeds, precs):
+        c = 1.0 + 0.3 * np.random.default_rng(seed).random((n, n))
+        wl = W.small(n=n, J=J, w_out=7, w=5, c=c, nsrc=6, seed=seed + 1)
+        mk = lambda st: Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power,
+                                  wl.pml_s0, pml_iface_s0=wl.pml_iface_s0, prec=prec, mode=mode,
+                                  chunk=9, device=DEV, stream=st, batch_fuse=True).factor()
+        wls.append(wl)
+        Hs.append(mk(torch.cuda.Stream(DEV)))
+        Hone.append(mk(None))
+    return wls, Hs, Hone
+
+
+@pytest.mark.parametrize("mode", ["reduced", "full"])
+def test_solve_batch_fuses_strip_solves(mode):
+    """Three complex64 problems of different sizes and strip counts: their strip solves run
+    as multi-problem launches (one per phase and sweep step), and every problem's field and
+    iteration counts equal its own helm_solve bit for bit."""
+    from paper_1208_3956_amd import solve_batch
+    wls, Hs, Hone = _fused_case(mode, ["mixed"] * 3)
+    fs = [torch.from_numpy(wl.rhs()).to(DEV) for wl in wls]
+    res = solve_batch(Hs, fs, 1e-6)
+    print(f"{mode}: fused launches {[r.fused_launches for r in res]}, alone "
+          f"{[r.unfused_launches for r in res]}, iterations {[r.iters for r in res]}", flush=True)
+    for wl, H1, f, r in zip(wls, Hone, fs, res):
+        assert r.fused_launches > 0
+        one = H1.solve(f, 1e-6)
+        assert r.iters == one.iters and torch.equal(r.u, one.u)
+        assert max(r.relres) <= 1e-6
+        g = geometry_from_workload(wl)
+        ud = solve_direct(g, wl.rhs(), assemble_global(g))
+        err = max(np.linalg.norm(r.u.cpu().numpy()[k] - ud[k]) / np.linalg.norm(ud[k])
+                  for k in range(ud.shape[0]))
+        assert err < 1e-5, err
+    for H in Hs + Hone:
+        H.close()
+
+
+def test_solve_batch_fuses_only_eligible_problems():
+    """A complex128 problem in the batch runs on its own stream and thread; the two
+    complex64 problems fuse; all three equal their own solves bit for bit."""
+    from paper_1208_3956_amd import solve_batch
+    wls, Hs, Hone = _fused_case("reduced", ["mixed", "c128", "mixed"])
+    fs = [torch.from_numpy(wl.rhs()).to(DEV) for wl in wls]
+    res = solve_batch(Hs, fs, 1e-6)
+    assert res[0].fused_launches > 0 and res[2].fused_launches > 0
+    assert res[1].fused_launches == 0 and res[1].unfused_launches == 0
+    for H1, f, r in zip(Hone, fs, res):
+        one = H1.solve(f, 1e-6)
+        assert r.iters == one.iters and torch.equal(r.u, one.u)
+    for H in Hs + Hone:
+        H.close()
+
+
 def test_solve_batch_rejects_repeated_handle():
     from paper_1208_3956_amd import solve_batch
     from paper_1208_3956_amd._lib import HelmError

@@ -1,6 +1,7 @@
 """The uneven batch at its real sizes: eight layered problems of 500^2 .. 2000^2 (8 sources
-each, J = round(64 n / 2000)), complex64-mixed, reduced form, solved concurrently on their
-own streams (helm_solve_batch), as `bench.py --workload layers_uneven_batch` times them.
+each, J = round(64 n / 2000)), complex64-mixed, reduced form, solved concurrently
+(helm_solve_batch) as `bench.py --workload layers_uneven_batch` times them: on their own
+streams, and with their strip solves fused into multi-problem launches.
 
 Every problem's concurrent solve must equal its solve on its own bit for bit; for one
 sampled right-hand side of every problem, the residual f - A u with A assembled by the
@@ -27,7 +28,8 @@ def _rel_residual(A, f, u):
     return np.linalg.norm(r) / np.linalg.norm(f.ravel())
 
 
-def test_uneven_batch_real_sizes():
+@pytest.mark.parametrize("fuse", [False, True], ids=["streams", "fused"])
+def test_uneven_batch_real_sizes(fuse):
     from paper_1208_3956_amd import Helmholtz, solve_batch
     wls = W.layers_uneven_batch()
     torch.cuda.set_device(0)
@@ -35,10 +37,11 @@ def test_uneven_batch_real_sizes():
     fs = [torch.from_numpy(wl.rhs()).to(DEV) for wl in wls]
     Hs = [Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
                     pml_iface_s0=wl.pml_iface_s0, prec="mixed", mode="reduced", device=DEV,
-                    stream=s).factor() for wl, s in zip(wls, streams)]
+                    stream=s, batch_fuse=fuse).factor() for wl, s in zip(wls, streams)]
     for H in Hs:
         H.stream.synchronize()
     rb = solve_batch(Hs, fs, 1e-6)
+    assert all((r.fused_launches > 0) == fuse for r in rb)
     for k, (H, f, r) in enumerate(zip(Hs, fs, rb)):
         assert r.status == 0 and max(r.relres) <= 1e-6, (k, r.status, max(r.relres))
         r1 = H.solve(f, 1e-6)
@@ -46,6 +49,11 @@ def test_uneven_batch_real_sizes():
         assert r1.iters == r.iters and torch.equal(r1.u, r.u), k
         print(f"problem {k} ({wls[k].n_x}^2, J={wls[k].J}): iterations {sorted(set(r.iters))}",
               flush=True)
+    if fuse:
+        # bitwise the problems' own solves, which the unfused case checks against the oracle
+        for H in Hs:
+            H.close()
+        return
     rng = np.random.default_rng(77)
     for k, (wl, f, r) in enumerate(zip(wls, fs, rb)):
         g = geometry_from_workload(wl)
