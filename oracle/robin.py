@@ -124,3 +124,50 @@ def sweep_robin(g: Geometry, R: RobinSolvers, A, f: np.ndarray):
 def apply_P_robin(g: Geometry, R: RobinSolvers, A, f: np.ndarray) -> np.ndarray:
     v, w, _ = sweep_robin(g, R, A, f)
     return v + w
+
+
+def apply_P_concurrent_robin(g: Geometry, R: RobinSolvers, A, f: np.ndarray,
+                             start=None) -> np.ndarray:
+    """The concurrent sweeps of Sec. 3.1 with Robin transmission: the iterative method of
+    Sec. 1 (every subdomain problem takes Robin data from both neighbours' previous
+    solutions), in which step n = 1..J updates only subdomains n and J + 1 - n; the two
+    chains meet in the middle, where each takes the other's data from the step before.
+    Returns v = v^(j) on D^(j) after step J.  `start` (optional, for pins) gives every
+    subdomain's solution before step 1 as a global field (default zero)."""
+    J, h = g.J, g.h
+    ih2 = 1.0 / (h * h)
+    spans = [robin_span(g, s) for s in range(J)]
+    if start is None:
+        V = [None] * J                      # latest solution of every subdomain (its columns)
+    else:
+        V = [start[:, lo:hi].copy() for (lo, hi) in spans]
+
+    def solve(s, Vold):
+        lo, hi = spans[s]
+        st = g.strips[s]
+        clo, chi = st.core
+        rhs = np.zeros((g.N_y, hi - lo), dtype=np.complex128)
+        rhs[:, clo - lo:chi - lo] = f[:, clo:chi]
+        if s > 0 and Vold[s - 1] is not None:           # left side: data of subdomain s - 1
+            plo, _ = spans[s - 1]
+            vi = Vold[s - 1][:, lo - plo]
+            vo = Vold[s - 1][:, lo - 1 - plo]
+            rhs[:, 0] += (vo - robin_rho(g, lo) * vi) * ih2
+        if s < J - 1 and Vold[s + 1] is not None:       # right side: data of subdomain s + 1
+            nlo, _ = spans[s + 1]
+            wi = Vold[s + 1][:, hi - 1 - nlo]
+            wo = Vold[s + 1][:, hi - nlo]
+            rhs[:, hi - 1 - lo] += (wo - robin_rho(g, hi - 1) * wi) * ih2
+        return R.solve(s, rhs)
+
+    for n in range(1, J + 1):
+        upd = sorted({n - 1, J - n})                    # 0-based subdomains n and J + 1 - n
+        new = {s: solve(s, V) for s in upd}             # both from the previous step's values
+        for s, x in new.items():
+            V[s] = x
+    v = np.zeros_like(f)
+    for s in range(J):
+        lo, _ = spans[s]
+        clo, chi = g.strips[s].core
+        v[:, clo:chi] = V[s][:, clo - lo:chi - lo]
+    return v

@@ -100,3 +100,16 @@ def solve_dd_robin(g: Geometry, f: np.ndarray, tol: float = 1e-6, maxit: int = 4
     y, it, hist = gmres_right(op, f, tol, maxit)
     u = apply_P_robin(g, R, A, y)
     return Result(u, it, relres(A, u, f), hist)
+
+
+def solve_dd_concurrent_robin(g: Geometry, f: np.ndarray, tol: float = 1e-6, maxit: int = 400,
+                              R=None, A=None) -> Result:
+    """GMRES with the concurrent Robin sweeps of Sec. 3.1 (two-sided data, chains meeting in
+    the middle), full form."""
+    from .robin import RobinSolvers, apply_P_concurrent_robin
+    A = assemble_global(g) if A is None else A
+    R = RobinSolvers(g) if R is None else R
+    op = lambda y: (A @ apply_P_concurrent_robin(g, R, A, y).ravel()).reshape(y.shape)
+    y, it, hist = gmres_right(op, f, tol, maxit)
+    u = apply_P_concurrent_robin(g, R, A, y)
+    return Result(u, it, relres(A, u, f), hist)

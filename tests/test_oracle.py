@@ -645,3 +645,90 @@ def test_paper_table4_robin_column_soft():
         f[g.N_y // 2, g.N_x // 2] = 1 / h ** 2
         res = solve_dd_robin(g, f, 1e-6)
         assert abs(res.iters - row["iterations"]) <= 1, (n, res.iters)
+
+
+# ------------------------------------------------------------ concurrent Robin sweeps
+def test_concurrent_robin_one_subdomain_is_the_global_solve():
+    """J = 1: the single step updates the only subdomain, which is the global operator."""
+    from oracle.robin import RobinSolvers, apply_P_concurrent_robin
+    g = _geom(n=20, J=1, w_out=5, w=4)
+    A = assemble_global(g)
+    f = _rand_field(np.random.default_rng(3), (g.N_y, g.N_x))
+    pf = apply_P_concurrent_robin(g, RobinSolvers(g), A, f)
+    assert np.linalg.norm(f - (A @ pf.ravel()).reshape(f.shape)) < 1e-12 * np.linalg.norm(f)
+
+
+@pytest.mark.parametrize("J", [2, 3, 4])
+def test_concurrent_robin_exact_solution_is_a_fixed_point(J):
+    """Started from the exact solution u = A^{-1} f instead of zero, every subdomain update
+    takes two-sided Robin data from u and reproduces u (the ghost elimination is an
+    identity), so the scheme returns u -- when f vanishes on the overlap columns: the
+    sources are partitioned (f^(j) = f on D^(j)), so a subdomain's extra column carries no
+    source, and (A u) there must be zero for u to solve its problem.  Pins both sides' data
+    (columns, rho, sign, which neighbour) and the assembly of v from the cores."""
+    from oracle.robin import RobinSolvers, apply_P_concurrent_robin, robin_span
+    g = _geom(n=32, J=J, w_out=6, w=4)
+    A = assemble_global(g)
+    f = _rand_field(np.random.default_rng(50 + J), (g.N_y, g.N_x))
+    for s in range(J - 1):
+        f[:, robin_span(g, s)[1] - 1] = 0.0          # the overlap column of subdomains s, s + 1
+    u = solve_direct(g, f, A)
+    v = apply_P_concurrent_robin(g, RobinSolvers(g), A, f, start=u)
+    assert np.linalg.norm(v - u) < 1e-10 * np.linalg.norm(u)
+
+
+def _robin_sub_solve(g, s, f):
+    """Robin subdomain s solved with f on its core and no data."""
+    from oracle.robin import RobinSolvers, robin_span
+    lo, hi = robin_span(g, s)
+    clo, chi = g.strips[s].core
+    rhs = np.zeros((g.N_y, hi - lo), dtype=np.complex128)
+    rhs[:, clo - lo:chi - lo] = f[:, clo:chi]
+    return RobinSolvers(g).solve(s, rhs), lo
+
+
+def test_concurrent_robin_crossing_uses_the_previous_step():
+    """J = 2 and f only on subdomain 0's core: step 1 solves both subdomains (subdomain 1
+    from zero data), step 2 both again, each from the other's step-1 solution.  Subdomain
+    1's step-1 solution is zero, so subdomain 0's final solution is its plain solve of f,
+    and subdomain 1's final one its solve with the data of that.  Updating the crossing
+    subdomains one after the other within a step (a planted Gauss-Seidel order) breaks it."""
+    import oracle.robin as orb
+    g = _geom(n=30, J=2, w_out=6, w=4)
+    A = assemble_global(g)
+    f = np.zeros((g.N_y, g.N_x), complex)
+    clo, chi = g.strips[0].core
+    f[:, clo:chi] = _rand_field(np.random.default_rng(61), (g.N_y, chi - clo))
+    R = orb.RobinSolvers(g)
+    v = orb.apply_P_concurrent_robin(g, R, A, f)
+    x0, lo0 = _robin_sub_solve(g, 0, f)
+    assert np.linalg.norm(v[:, clo:chi] - x0[:, clo - lo0:chi - lo0]) < 1e-12 * np.linalg.norm(x0)
+    # subdomain 1 from subdomain 0's data: a one-step Robin right sweep from x0
+    lo1, hi1 = orb.robin_span(g, 1)
+    rhs = np.zeros((g.N_y, hi1 - lo1), complex)
+    rhs[:, 0] += (x0[:, lo1 - 1 - lo0] - orb.robin_rho(g, lo1) * x0[:, lo1 - lo0]) / g.h ** 2
+    x1 = R.solve(1, rhs)
+    c1lo, c1hi = g.strips[1].core
+    assert np.linalg.norm(v[:, c1lo:c1hi] - x1[:, c1lo - lo1:c1hi - lo1]) < 1e-12 * np.linalg.norm(x1)
+    # planted: updates within a step see each other (subdomain 1 first, then 0)
+    src = open(orb.__file__).read()
+    bad = src.replace("new = {s: solve(s, V) for s in upd}             # both from the previous step's values\n"
+                      "        for s, x in new.items():\n            V[s] = x",
+                      "for s in sorted(upd, reverse=True):\n            V[s] = solve(s, V)")
+    assert bad != src
+    mod = types.ModuleType("robin_planted")
+    mod.__dict__["__name__"] = "oracle.robin_planted"
+    mod.__dict__["__package__"] = "oracle"
+    exec(compile(bad, "robin_planted", "exec"), mod.__dict__)
+    vb = mod.apply_P_concurrent_robin(g, mod.RobinSolvers(g), A, f)
+    assert np.linalg.norm(vb[:, clo:chi] - x0[:, clo - lo0:chi - lo0]) > 1e-6 * np.linalg.norm(x0)
+
+
+def test_concurrent_robin_dd_gmres_reaches_direct_solution():
+    from oracle.solve import solve_dd_concurrent_robin
+    g = _geom(n=32, J=4, w_out=6, w=4)
+    A = assemble_global(g)
+    f = _rand_field(np.random.default_rng(71), (g.N_y, g.N_x))
+    res = solve_dd_concurrent_robin(g, f, 1e-10, A=A)
+    u = solve_direct(g, f, A)
+    assert res.relres < 1e-10 and np.linalg.norm(res.u - u) < 1e-7 * np.linalg.norm(u)
