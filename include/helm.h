@@ -109,8 +109,14 @@ typedef struct {
                            -alpha_x(b) alpha_x(b +- 1/2) rho / h^2, rho = (1 + i k h/2) /
                            (1 - i k h/2) with k at the side's column b, to that column's
                            diagonal and puts the neighbour's data (V_o - rho V_i) / h^2 on
-                           it.  2-D, sweep 0 and HELM_FULL only (else HELM_EINVAL);
-                           pml_iface and pml_iface_s0 are then unused                        */
+                           it.  With sweep 1 the concurrent sweeps of Sec. 3.1 instead: step
+                           n = 1..J solves D^(n) and D^(J+1-n) from f on their cores and
+                           the Robin data of both neighbours' latest solutions (none for a
+                           neighbour not yet solved), both right-hand sides formed before
+                           either solve, so where the chains meet each takes the other's
+                           data from the step before; P f takes every core from its
+                           subdomain's last solution.  2-D and HELM_FULL only (else
+                           HELM_EINVAL); pml_iface and pml_iface_s0 are then unused          */
     int restart;        /* GMRES cycle length (basis vectors kept before a restart); 0
                            (default): 60 in HELM_REDUCED, 30 in HELM_FULL, whose basis
                            vectors are whole fields.  Capped at max_iter                     */

@@ -23,6 +23,15 @@
 using helm::BLK;
 using helm::NSLOT;
 using helm::WP;
+
+namespace helm {
+// concurrent sweeps with Robin transmission (kernels_robin.hip)
+hipError_t launch_robin_rhs(const double2* f, const double2* L, const double2* R, const double2* rho_l,
+                            const double2* rho_r, double2* out, int nrhs, int Nrow, int Nx, int lo, int W,
+                            int c0, int c1, double ih2, hipStream_t st);
+hipError_t launch_parity_pick(const double2* E, const double2* O, const int* par, double2* out, int nrhs,
+                              long Nrow, int Nx, hipStream_t st);
+}  // namespace helm
 using cd = std::complex<double>;
 
 struct Work {
@@ -40,6 +49,8 @@ struct Work {
     // Robin transmission: [2][nrhs][Nrow], a zero half and the data (V_o - rho V_i) / h^2 of
     // the strip being solved (the transmission source is coef * (second half - first half))
     double2* Rob = nullptr;
+    // concurrent Robin sweeps: the right-hand sides of a step's two subdomains, [2][nrhs][Nrow][WP]
+    double2* RobR = nullptr;
     // GMRES.  gnrhs is the right-hand-side capacity of every buffer below and of R, Ut:
     // they are laid out for the nrhs of each call ([k][nrhs][n]) and reallocated when a
     // call brings more right-hand sides than they were sized for
@@ -165,6 +176,7 @@ struct helm_problem {
     unsigned long ap_tick = 0;
     int sweep = 0;              // 0: the double sweep P; 1: the concurrent double sweep P_c
     int trans = 0;              // 0: PML transmission; 1: Robin transmission (Sec. 4.4)
+    int* colpar = nullptr;      // concurrent Robin sweeps: parity of the strip whose core holds each column
     int restart = 0;            // GMRES cycle length (0: by mode)
     int batch_fuse = 0;         // join fused strip-solve launches in helm_solve_batch
     hipStream_t st_c[2] = {};   // concurrent sweep: streams of the downward chain and the z solves
@@ -380,7 +392,7 @@ helm_status upload(helm_t H, void** dptr, const void* src, size_t bytes) {
 void free_work(Work& w) {
     void* ps[] = {w.Yw, w.V, w.G, w.PF, w.Psi, w.Wf, w.Hf, w.Vw, w.Gw, w.Ww, w.Ut, w.R, w.Tup, w.Tdn, w.basis,
                   w.w, w.h1, w.h2, w.nrm, w.partial, w.npartial, w.y, w.red, w.apin, w.basis_old,
-                  w.Yw2, w.Yw3, w.PsiC, w.Rob};
+                  w.Yw2, w.Yw3, w.PsiC, w.Rob, w.RobR};
     for (void* p : ps) dfree(p);
     w = Work();
 }
@@ -409,6 +421,7 @@ helm_status ensure_sweep_ws(helm_t H, int nrhs) {
         const size_t rb = (size_t)2 * nrhs * g.Nrow() * sizeof(double2);
         CHK(dmalloc(H, &w.Rob, rb));
         HIPCHK(hipMemsetAsync(w.Rob, 0, rb, H->st));
+        if (H->sweep == 1) CHK(dmalloc(H, &w.RobR, (size_t)2 * nrhs * g.Nrow() * WP * sizeof(double2)));
     }
     double2** fields[] = {&w.V, &w.G, &w.PF, &w.Psi, &w.Wf, &w.Hf};
     for (double2** f : fields) {
@@ -869,7 +882,67 @@ helm_status conc_setup(helm_t H, int nrhs, const double2* f, double2* ut) {
 }
 
 // the preconditioner of the handle's sweep on whole fields
+// Concurrent sweeps with Robin transmission (Sec. 3.1; conditions of Sec. 4.4): step
+// n = 1..J updates subdomains n and J + 1 - n, each from f on its core and the Robin data
+// of both neighbours' solutions of earlier steps (none for a neighbour not yet solved);
+// where the chains meet, both right-hand sides are formed before either subdomain is
+// solved, so each takes the other's data from the step before.  The latest solutions of
+// even and odd subdomains live in two fields (neighbours' extra columns overlap); v takes
+// every core from its subdomain's field.  A step's two strip solves are one multi-problem
+// launch in complex64.
+helm_status apply_PcR_full(helm_t H, int nrhs, const double2* f, double2* out) {
+    CHK(ensure_sweep_ws(H, nrhs));
+    const auto& g = H->g;
+    Work& w = H->wk;
+    const int J = g.J;
+    const double ih2 = 1.0 / (g.h * g.h);
+    double2* fld[2] = {w.V, w.G};
+    const size_t rstride = (size_t)nrhs * g.Nrow() * WP;
+    std::vector<char> done(J, 0);
+    for (int n = 1; n <= J; ++n) {
+        int upd[2] = {n - 1, J - n};
+        const int nu = upd[0] == upd[1] ? 1 : 2;
+        helm::IOSpec io[2];
+        for (int k = 0; k < nu; ++k) {
+            const int s = upd[k];
+            const auto& S = g.strips[s];
+            const double2* L = s > 0 && done[s - 1] ? fld[(s - 1) & 1] : nullptr;
+            const double2* R = s < J - 1 && done[s + 1] ? fld[(s + 1) & 1] : nullptr;
+            const double2* rl = H->t.rho + (size_t)(s > 0 ? s - 1 : 0) * g.Nrow();
+            const double2* rr = H->t.rho + (size_t)(s < J - 1 ? s : 0) * g.Nrow();
+            double2* rhs = w.RobR + k * rstride;
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_robin_rhs(f, L, R, rl, rr, rhs, nrhs, (int)g.Nrow(), g.Nx, S.a,
+                                                                  S.W, S.core_lo - S.a, S.core_hi - S.a, ih2, H->st)));
+            io[k] = field_io(H, s);
+            io[k].src = rhs; io[k].src_rs = g.Nrow() * S.W; io[k].src_ls = S.W; io[k].src_off = 0;
+            io[k].src_lo = 0; io[k].src_hi = S.W;
+            io[k].dst = fld[s & 1];
+            io[k].o_lo[0] = 0; io[k].o_hi[0] = S.W;
+        }
+        bool fused = false;
+        if (nu == 2 && H->prec == HELM_MIXED_C64 && !H->kt()) {
+            helm::StripJob jb[2];
+            for (int k = 0; k < 2; ++k) {
+                const int s = upd[k];
+                jb[k].t = &H->t; jb[k].g = &H->g; jb[k].ch = &H->ch; jb[k].s = s; jb[k].fs = H->fidx[s];
+                jb[k].f32 = true; jb[k].F = H->F; jb[k].Fc = H->Fc; jb[k].Fs = H->Fs;
+                jb[k].Yw = k == 0 ? w.Yw : w.Yw2; jb[k].nrhs = nrhs; jb[k].io = io[k];
+            }
+            if (helm::strip_jobs_fusable(jb, 2)) {
+                HIPCHK(helm::launch_strip_solve_multi(jb, 2, H->st, nullptr));
+                fused = true;
+            }
+        }
+        if (!fused)
+            for (int k = 0; k < nu; ++k) CHK(strip_solve_any(H, upd[k], nrhs, io[k]));
+        for (int k = 0; k < nu; ++k) done[upd[k]] = 1;
+    }
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_parity_pick(fld[0], fld[1], H->colpar, out, nrhs, g.Nrow(), g.Nx, H->st)));
+    return HELM_OK;
+}
+
 helm_status apply_P_any(helm_t H, int nrhs, const double2* f, double2* out) {
+    if (H->sweep == 1 && H->trans == 1) return apply_PcR_full(H, nrhs, f, out);
     return H->sweep == 1 ? apply_Pc_full(H, nrhs, f, out) : apply_P_full(H, nrhs, f, out);
 }
 
@@ -1567,8 +1640,8 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if (opts->transmission != 0 && opts->transmission != 1)
         return bad("transmission must be 0 (PML) or 1 (Robin)");
     const bool robin = opts->transmission == 1;
-    if (robin && (opts->dim != 2 || opts->sweep != 0 || opts->mode == HELM_REDUCED))
-        return bad("the Robin transmission is built for 2-D problems, the double sweep and the full form");
+    if (robin && (opts->dim != 2 || opts->mode == HELM_REDUCED))
+        return bad("the Robin transmission is built for 2-D problems and the full form");
     if (J > 1 && !robin && opts->pml_iface < 1) return bad("pml_iface must be >= 1");
     double cmax = 0.0;
     for (size_t i = 0; i < (size_t)nx * ny * nz; ++i) {
@@ -1810,6 +1883,12 @@ helm_status helm_setup(const double* c, double omega, double h, const helm_opts*
     if (robin) {
         if ((st = upload(H, (void**)&t.srob, rob.data(), rob.size() * sizeof(double2))) != HELM_OK) return st;
         if ((st = upload(H, (void**)&t.rho, rho.data(), rho.size() * sizeof(double2))) != HELM_OK) return st;
+        if (opts->sweep == 1) {
+            std::vector<int> par(Nx);
+            for (int s = 0; s < J; ++s)
+                for (int x = g.beta[s]; x < g.beta[s + 1]; ++x) par[x] = s & 1;
+            if ((st = upload(H, (void**)&H->colpar, par.data(), par.size() * sizeof(int))) != HELM_OK) return st;
+        }
     }
     H->tf = t;
     if (robin) {

@@ -49,8 +49,9 @@ class Helmholtz:
     sweep      "double" (the paper's P) or "concurrent" (P_c: upward and downward sweeps
                on f at the same time on separate streams)
     transmission  "pml" (the paper's method) or "robin" (the comparison method of Sec. 4.4:
-               unpadded subdomains with first-order absorbing conditions; 2-D, double
-               sweep, full form)
+               unpadded subdomains with first-order absorbing conditions; 2-D, full form;
+               with sweep="concurrent" the concurrent sweeps of Sec. 3.1, step n solving
+               subdomains n and J + 1 - n with two-sided Robin data)
     restart    GMRES cycle length (0 = library default: 60 reduced, 30 full)
     batch_fuse in solve_batch, fuse this problem's strip solves with the other problems
                that set it (lockstep multi-problem launches) instead of its own stream

@@ -99,7 +99,7 @@ def test_robin_one_subdomain_is_the_global_solve():
     H.close()
 
 
-@pytest.mark.parametrize("kw", [dict(mode="reduced"), dict(sweep="concurrent")])
+@pytest.mark.parametrize("kw", [dict(mode="reduced"), dict(mode="reduced", sweep="concurrent")])
 def test_robin_rejects_unsupported_options(kw):
     from paper_1208_3956_amd import Helmholtz
     wl = W.small(n=24, J=2, w_out=6, w=4, nsrc=1)
@@ -142,3 +142,76 @@ def test_table4_robin_column(i):
           f"paper {paper['iterations']})", flush=True)
     assert res.status == 0 and res.relres[0] <= 1e-6
     assert abs(res.iters[0] - row["iterations"]) <= 1
+
+
+# ------------------------------------------------------------ concurrent Robin sweeps
+@pytest.mark.parametrize("J", [4, 5])
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("mixed", 2e-4)])
+def test_concurrent_robin_P(cases, J, prec, tol):
+    """The concurrent sweeps of Sec. 3.1 with Robin transmission (subdomains n and J + 1 - n
+    at step n, two-sided data from the step before) against the oracle, right-hand side by
+    right-hand side; complex64 runs each step's two strip solves as one launch."""
+    from oracle.robin import apply_P_concurrent_robin
+    wl, g, A, R = cases[J]
+    H = _gpu(wl, prec=prec, sweep="concurrent")
+    rng = np.random.default_rng(8)
+    f = _rand(rng, (5, g.N_y, g.N_x))
+    pf = H.apply_P(_t(f)).cpu().numpy()
+    ref = np.stack([apply_P_concurrent_robin(g, R, A, fk) for fk in f])
+    _close(pf, ref, tol, "concurrent P_R")
+    H.close()
+
+
+@pytest.mark.parametrize("prec", ["c128", "mixed"])
+def test_concurrent_robin_solve(cases, prec):
+    from oracle.solve import solve_dd_concurrent_robin
+    wl, g, A, R = cases[4]
+    H = _gpu(wl, prec=prec, sweep="concurrent")
+    f = wl.rhs()
+    res = H.solve(_t(f), tol=1e-6)
+    assert res.status == 0 and max(res.relres) <= 1e-6
+    _close(res.u.cpu().numpy(), solve_direct(g, f, A), 1e-5, "field")
+    if prec == "c128":
+        for k in range(f.shape[0]):
+            ref = solve_dd_concurrent_robin(g, f[k], 1e-6, R=R, A=A)
+            assert abs(res.iters[k] - ref.iters) <= 1, (k, res.iters[k], ref.iters)
+    H.close()
+
+
+def test_concurrent_robin_one_subdomain_is_the_global_solve():
+    wl = W.small(n=24, J=1, w_out=6, w=4, nsrc=2)
+    H = _gpu(wl, chunk=5, sweep="concurrent")
+    res = H.solve(_t(wl.rhs()), tol=1e-10)
+    assert res.iters == [1] * wl.nrhs and max(res.relres) < 1e-10
+    H.close()
+
+
+ORACLE_T4C = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "table4_concurrent_robin_oracle.json")
+
+
+@pytest.mark.parametrize("i", range(4), ids=[f"n{100 * 2 ** i}" for i in range(4)])
+def test_concurrent_robin_table4_problems(i):
+    """Table 4's constant-medium problems (J = n/10) with the concurrent Robin sweeps: the
+    iteration count equals the oracle's within one, and is printed beside the Robin double
+    sweep's.  The concurrent sweeps halve the sequential depth of P but need several times
+    the iterations: each chain's data reach the far side only after it has met the other."""
+    from paper_1208_3956_amd import Helmholtz
+    row = json.load(open(ORACLE_T4C))["rows"][i]
+    n, J = row["n"], row["J"]
+    h = 1.0 / n
+    out = {}
+    for sweep in ("concurrent", "double"):
+        H = Helmholtz(np.ones((n, n)), 2 * math.pi / (10 * h), h, J, pml_outer=10, pml_iface=8,
+                      prec="c128", mode="full", transmission="robin", sweep=sweep, restart=400,
+                      max_iter=400, device=DEV).factor()
+        f = torch.zeros((1, H.N_y, H.N_x), dtype=torch.complex128, device=DEV)
+        f[0, H.N_y // 2, H.N_x // 2] = 1.0 / h ** 2
+        res = H.solve(f, 1e-6)
+        H.close()
+        assert res.status == 0 and res.relres[0] <= 1e-6, sweep
+        out[sweep] = (res.iters[0], res.ms)
+    print(f"Table 4 problem n={n} J={J}: concurrent Robin {out['concurrent'][0]} iterations "
+          f"({out['concurrent'][1]:.0f} ms, oracle {row['iterations']}), Robin double sweep "
+          f"{out['double'][0]} ({out['double'][1]:.0f} ms)", flush=True)
+    assert abs(out["concurrent"][0] - row["iterations"]) <= 1
