@@ -745,11 +745,11 @@ struct SepCtx {
 // local forward chains: zeta_c = a_c - K_c zeta_{c-1} inside group g = blockIdx.y.  First
 // the group's right-hand sides a_c = G'_c r^_c, r^_c = r_s - c_s y_{s-1} - b_s y_{s+1}
 // (s = sep(c)), independent per separator: wave w takes c0 + w, c0 + w + 4, ...
-template <typename T, int D>
+template <typename T, int D, bool SETUP>
 __device__ __forceinline__ void sep_fwd_local(const SolveArgs<T>& a, const Blk& B) {
     SEPK_PROLOGUE
     const int g = B.y, c0 = X.first(g), c1 = X.last(g);
-    {
+    if constexpr (SETUP) {
         const int w = threadIdx.x >> 6;
         for (int c = c0 + w; c <= c1; c += 4) {
             const int sr = X.sep(c);
@@ -801,13 +801,13 @@ __device__ __forceinline__ void sep_fwd_top(const SolveArgs<T>& a, const Blk& B)
                         [&](int k, int b) { return X.yrow(b, X.last(k + 1)); }, okb, vecw, part);
 }
 
-// fix-up of the group's other separators, then its local backward chain
-// xi_c = z'_c - U'_c xi_{c+1} (the group's last separator starts it)
-template <typename T, int D>
+// fix-up of the group's other separators (unless FIX is false: done before, on MFMA), then
+// its local backward chain xi_c = z'_c - U'_c xi_{c+1} (the group's last separator starts it)
+template <typename T, int D, bool FIX>
 __device__ __forceinline__ void sep_fix_bwd_local(const SolveArgs<T>& a, const Blk& B) {
     SEPK_PROLOGUE
     const int g = B.y, c0 = X.first(g), c1 = X.last(g);
-    if (g >= 1) {
+    if (FIX && g >= 1) {
         V vf[RB];
         vecs_at(X.last(g - 1), vf);
         sep_fix<T, RB>(c1 - c0, vf,
@@ -844,13 +844,110 @@ __device__ __forceinline__ void sep_bwd_fix(const SolveArgs<T>& a, const Blk& B)
                    [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw);
 }
 #undef SEPK_PROLOGUE
-template <typename T, int D>
-__global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) { sep_fwd_local<T, D>(a, own_blk()); }
-template <typename T, int D>
+// The separators' independent products for 16 right-hand sides at a time on MFMA (complex64):
+//   MODE 0  a_c = G'_c r^_c for every separator c (the local forward chains' right-hand sides)
+//   MODE 1  z'_c += Phi_c z'_{last g-1} for the separators of group g >= 1 but its last
+//   MODE 2  x_c += Psi_c x_{first g+1} for the separators of group g < G - 1 but its first
+// Grid (separators, right-hand-side groups).  Each workgroup stages its 64 x 16 operand in
+// LDS and forms one (64 x 64) by (64 x 16) product in three real products, so a block is read
+// once per 16 right-hand sides (the per-right-hand-side workgroups of the chains read it once
+// each, which makes these products bound by the CU's load bandwidth).  A workgroup writes only
+// its own separator and reads only separators that no workgroup of the launch writes.
+template <int MODE>
+__device__ __forceinline__ void sep_par_mfma(const SolveArgs<float>& a, const Blk& B) {
+    using V = float2;
+    __shared__ V X[WP][17];
+    const int ns = a.P - 1, c = B.x, g = c / a.q;
+    const int c0 = g * a.q, c1 = min(c0 + a.q, ns) - 1;
+    if (MODE == 1 && (g < 1 || c == c1)) return;
+    if (MODE == 2 && (g >= a.G - 1 || c == c0)) return;
+    const int sr = c * a.m + a.m - 1;                                   // the separator's row
+    const int so = MODE == 1 ? (c0 - 1) * a.m + a.m - 1 : (c1 + 1) * a.m + a.m - 1;   // operand's
+    const V* M = MODE == 0 ? fslot(a, sr, 0) : a.Fs + ((size_t)c * 2 + (MODE == 1 ? 0 : 1)) * BLK;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
+    const int rbase = B.y * 16;
+    // every load of the workgroup is issued before the first use: the A operands, then the
+    // operand tile (four passes of 256 threads; branch-free, clamped addresses)
+    V gA[16];
+    const V* F = M + 16 * w + n;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) gA[s] = F[(4 * s + q4) * WP];
+    constexpr int NP = 16 * WP / NT;
+    RawRhs raw[NP];
+    V ym[NP], yp[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int idx = threadIdx.x + p * NT, q = idx >> 6, k = idx & (WP - 1), r = rbase + q;
+        const V* Yr = a.Yw + (size_t)(r < a.nrhs ? r : a.nrhs - 1) * a.Ny * WP + k;
+        if (MODE == 0) {
+            raw[p] = load_raw(a.io, r, sr, k, a.Ny, a.nrhs, a.W);
+            ym[p] = Yr[(size_t)(sr - 1) * WP];
+            yp[p] = Yr[(size_t)(sr + 1) * WP];
+        } else {
+            ym[p] = Yr[(size_t)so * WP];
+        }
+    }
+    // the fix-ups add to this lane's four entries of the separator
+    const int rn = rbase + n;
+    V* y = a.Yw + ((size_t)(rn < a.nrhs ? rn : a.nrhs - 1) * a.Ny + sr) * WP + 16 * w + 4 * q4;
+    V yold[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) yold[u] = MODE == 0 ? make_float2(0.f, 0.f) : y[u];
+    const double2 cys = a.cy[sr], bys = a.by[sr];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const int idx = threadIdx.x + p * NT, q = idx >> 6, k = idx & (WP - 1);
+        V v = make_float2(0.f, 0.f);
+        if (rbase + q < a.nrhs && k < a.W) {
+            if (MODE == 0) {
+                v = combine<float>(a.io, raw[p]);
+                v = csub(v, cmul(ccast<V>(cys), ym[p]));
+                v = csub(v, cmul(ccast<V>(bys), yp[p]));
+            } else {
+                v = ym[p];
+            }
+        }
+        X[k][q] = v;
+    }
+    __syncthreads();
+    V xb[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) xb[s] = X[4 * s + q4][n];
+    __builtin_amdgcn_sched_barrier(0);
+    mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const V g4 = gA[s];
+        const V x = xb[s];
+        m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.x, x.x, m1, 0, 0, 0);
+        m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.y, x.y, m2, 0, 0, 0);
+        m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.x + g4.y, x.x + x.y, m3, 0, 0, 0);
+    }
+    if (rn >= a.nrhs) return;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const float p1 = m1[u], p2 = m2[u], p3 = m3[u];
+        const V v = make_float2(p1 - p2, p3 - p1 - p2);
+        y[u] = MODE == 0 ? v : cadd(yold[u], v);
+    }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(NT) k_sep_par_mfma(SolveArgs<float> a) { sep_par_mfma<MODE>(a, own_blk()); }
+template <int MODE>
+__global__ void __launch_bounds__(NT) k_sep_par_mfma_multi(MultiArgs<float> m) {
+    int k;
+    Blk b;
+    if (multi_blk(m, k, b)) sep_par_mfma<MODE>(m.a[k], b);
+}
+
+template <typename T, int D, bool SETUP = true>
+__global__ void __launch_bounds__(NT) k_sep_fwd_local(SolveArgs<T> a) { sep_fwd_local<T, D, SETUP>(a, own_blk()); }
+template <typename T, int D, bool SETUP = true>
 __global__ void __launch_bounds__(NT) k_sep_fwd_local_multi(MultiArgs<T> m) {
     int k;
     Blk b;
-    if (multi_blk(m, k, b)) sep_fwd_local<T, D>(m.a[k], b);
+    if (multi_blk(m, k, b)) sep_fwd_local<T, D, SETUP>(m.a[k], b);
 }
 template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_fwd_top(SolveArgs<T> a) { sep_fwd_top<T, D>(a, own_blk()); }
@@ -860,13 +957,13 @@ __global__ void __launch_bounds__(NT) k_sep_fwd_top_multi(MultiArgs<T> m) {
     Blk b;
     if (multi_blk(m, k, b)) sep_fwd_top<T, D>(m.a[k], b);
 }
-template <typename T, int D>
-__global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) { sep_fix_bwd_local<T, D>(a, own_blk()); }
-template <typename T, int D>
+template <typename T, int D, bool FIX = true>
+__global__ void __launch_bounds__(NT) k_sep_fix_bwd_local(SolveArgs<T> a) { sep_fix_bwd_local<T, D, FIX>(a, own_blk()); }
+template <typename T, int D, bool FIX = true>
 __global__ void __launch_bounds__(NT) k_sep_fix_bwd_local_multi(MultiArgs<T> m) {
     int k;
     Blk b;
-    if (multi_blk(m, k, b)) sep_fix_bwd_local<T, D>(m.a[k], b);
+    if (multi_blk(m, k, b)) sep_fix_bwd_local<T, D, FIX>(m.a[k], b);
 }
 template <typename T, int D>
 __global__ void __launch_bounds__(NT) k_sep_bwd_top(SolveArgs<T> a) { sep_bwd_top<T, D>(a, own_blk()); }
@@ -1253,16 +1350,27 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
     if (a.P > 1) {
         if (kt) kt->begin(K_PHASE_B, st);
         if (a.P > 2 && a.G >= 2 && a.Fs) {
-            // the local forward chains form their own right-hand sides a_c
             constexpr int DS = Depth<T>::D;
             const unsigned nr = (unsigned)((a.nrhs + SepRB<T>::RB - 1) / SepRB<T>::RB);
-            hipLaunchKernelGGL((k_sep_fwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
-            hipLaunchKernelGGL((k_sep_fwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
-            hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
-            hipLaunchKernelGGL((k_sep_bwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
-            // complex64 targets-only solves fix the separators up inside phase C
-            if (!(std::is_same<T, float>::value && targets))
+            if constexpr (std::is_same<T, float>::value) {
+                // the independent products on MFMA, the chains one right-hand side per
+                // workgroup; targets-only solves fix the separators up inside phase C
+                const dim3 gp(a.P - 1, (a.nrhs + 15) / 16);
+                hipLaunchKernelGGL(k_sep_par_mfma<0>, gp, dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_fwd_local<T, DS, false>), dim3(nr, a.G), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_fwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL(k_sep_par_mfma<1>, gp, dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS, false>), dim3(nr, a.G), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_bwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
+                if (!targets) hipLaunchKernelGGL(k_sep_par_mfma<2>, gp, dim3(NT), 0, st, a);
+            } else {
+                // the local forward chains form their own right-hand sides a_c
+                hipLaunchKernelGGL((k_sep_fwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_fwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS>), dim3(nr, a.G), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_bwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
                 hipLaunchKernelGGL((k_sep_bwd_fix<T, DS>), dim3(nr, a.G - 1), dim3(NT), 0, st, a);
+            }
         } else {
             hipLaunchKernelGGL((k_phase_b0<T, R>), dim3(a.P - 1, RG), dim3(NT), 0, st, a);
         }
@@ -1393,7 +1501,7 @@ hipError_t launch_strip_solve_multi(const StripJob* jobs, int n, hipStream_t st,
     auto RG = [](const SolveArgs<float>& a) { return (a.nrhs + 15) / 16; };
     auto NR = [](const SolveArgs<float>& a) { return a.nrhs; };     // one right-hand side per block
     auto G = [](const SolveArgs<float>& a) { return a.G; };
-    auto G1 = [](const SolveArgs<float>& a) { return a.G - 1; };
+    auto NS = [](const SolveArgs<float>& a) { return a.P - 1; };      // separators
     auto one = [](const SolveArgs<float>&) { return 1; };
     constexpr int DS = Depth<float>::D;
     dim3 grid;
@@ -1402,17 +1510,21 @@ hipError_t launch_strip_solve_multi(const StripJob* jobs, int n, hipStream_t st,
     hipLaunchKernelGGL(k_phase_a_mfma_multi<2>, grid, dim3(NT), 0, st, m);
     if (kt) kt->end(K_PHASE_A, st);
     if (kt) kt->begin(K_PHASE_B, st);
+    shape(NS, RG, one, grid);
+    hipLaunchKernelGGL(k_sep_par_mfma_multi<0>, grid, dim3(NT), 0, st, m);
     shape(NR, G, one, grid);
-    hipLaunchKernelGGL((k_sep_fwd_local_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    hipLaunchKernelGGL((k_sep_fwd_local_multi<float, DS, false>), grid, dim3(NT), 0, st, m);
     shape(NR, one, one, grid);
     hipLaunchKernelGGL((k_sep_fwd_top_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    shape(NS, RG, one, grid);
+    hipLaunchKernelGGL(k_sep_par_mfma_multi<1>, grid, dim3(NT), 0, st, m);
     shape(NR, G, one, grid);
-    hipLaunchKernelGGL((k_sep_fix_bwd_local_multi<float, DS>), grid, dim3(NT), 0, st, m);
+    hipLaunchKernelGGL((k_sep_fix_bwd_local_multi<float, DS, false>), grid, dim3(NT), 0, st, m);
     shape(NR, one, one, grid);
     hipLaunchKernelGGL((k_sep_bwd_top_multi<float, DS>), grid, dim3(NT), 0, st, m);
     if (!targets) {
-        shape(NR, G1, one, grid);
-        hipLaunchKernelGGL((k_sep_bwd_fix_multi<float, DS>), grid, dim3(NT), 0, st, m);
+        shape(NS, RG, one, grid);
+        hipLaunchKernelGGL(k_sep_par_mfma_multi<2>, grid, dim3(NT), 0, st, m);
     }
     if (kt) kt->end(K_PHASE_B, st);
     if (kt) kt->begin(K_PHASE_C, st);
