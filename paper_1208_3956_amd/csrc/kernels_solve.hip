@@ -1183,10 +1183,12 @@ __global__ void __launch_bounds__(NT) k_phase_c_targets(SolveArgs<T> a) {
 // by tile group 0.
 __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, const Blk& B) {
     using V = float2;
-    __shared__ V X[2 * WP][16];
-    __shared__ V XF[2][WP][16];
+    __shared__ V X[2 * WP][17];
+    __shared__ V XF[2][WP][17];
+    __shared__ int tcs[8];                 // the target columns (the tiles' output addresses)
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
     const int c = B.x, rbase = B.y * 16;
+    if (t < 8) tcs[t] = a.tcol[t];
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
     const int nr = r1 - r0;
@@ -1209,10 +1211,12 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     {
         V xv[8], fv[8];
         bool keepv[8], keepf[8];
+        // element e: right-hand side j = e / 128, k = e % 128 (consecutive lanes read
+        // consecutive columns of one right-hand side's row)
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = t + NT * u;
-            const int k = e >> 4, j = e & 15, r = rbase + j, kk = k & (WP - 1);
+            const int k = e & (2 * WP - 1), j = e >> 7, r = rbase + j, kk = k & (WP - 1);
             const bool above = k < WP;
             keepv[u] = r < a.nrhs && kk < a.W && (above ? has_a : has_b);
             const int row = above ? (has_a ? r0 - 1 : r0) : (has_b ? r1 : r0);
@@ -1220,14 +1224,17 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
             xv[u] = a.Yw[(rr + row) * WP + kk];
             const int side = above ? 0 : 1;
             keepf[u] = keepv[u] && fix[side];
-            const int frow = fix[side] ? sfirst[side] * a.m + a.m - 1 : row;
+            // a dropped value reads row 0: an address the compiler cannot equate with xv's,
+            // which would make it reuse xv behind a wait for every element
+            const int frow = fix[side] ? sfirst[side] * a.m + a.m - 1 : 0;
             fv[u] = a.Yw[(rr + frow) * WP + kk];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = t + NT * u;
-            X[e >> 4][e & 15] = make_float2(keepv[u] ? xv[u].x : 0.f, keepv[u] ? xv[u].y : 0.f);
-            (&XF[0][0][0])[e] = make_float2(keepf[u] ? fv[u].x : 0.f, keepf[u] ? fv[u].y : 0.f);
+            const int k = e & (2 * WP - 1), j = e >> 7;
+            X[k][j] = make_float2(keepv[u] ? xv[u].x : 0.f, keepv[u] ? xv[u].y : 0.f);
+            XF[k >> 6][k & (WP - 1)][j] = make_float2(keepf[u] ? fv[u].x : 0.f, keepf[u] ? fv[u].y : 0.f);
         }
     }
     __syncthreads();
@@ -1240,6 +1247,7 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
             V g[16];
 #pragma unroll
             for (int s4 = 0; s4 < 16; ++s4) g[s4] = Ps[(size_t)(4 * s4 + q4) * WP];
+            __builtin_amdgcn_sched_barrier(0);
             mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
 #pragma unroll
             for (int s4 = 0; s4 < 16; s4 += 2) {
@@ -1264,19 +1272,28 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     }
     const int rn = rbase + n;
     const int nrows = nr * 8, ntile = (nrows + 15) / 16;
-    // the B panel of every tile: [x_above; x_below] in this lane's MFMA layout
+    // k-step s of a side takes the column kc(s) = 8 (s / 2) + 2 q4 + s % 2 in this lane, so
+    // that the lane's two columns of k-steps 2i, 2i + 1 are adjacent and come in one 16-byte
+    // load (each load instruction reads 64 contiguous bytes of 16 compact rows).  The B panel
+    // of every tile, [x_above; x_below], in the same order:
     V vb[32];
 #pragma unroll
-    for (int s4 = 0; s4 < 32; ++s4) vb[s4] = X[4 * s4 + q4][n];
+    for (int s4 = 0; s4 < 32; ++s4) vb[s4] = X[WP * (s4 >> 4) + 8 * ((s4 & 15) >> 1) + 2 * q4 + (s4 & 1)][n];
     for (int tile = w + 4 * B.z; tile < ntile; tile += 4 * B.nz) {
-        // A operands: row rho = 16 tile + n (clamped), k = 4 s + q4
+        // A operands: row rho = 16 tile + n (clamped), columns kc(s) of both sides
         const int rho = min(16 * tile + n, nrows - 1);
         const int l = r0 + (rho >> 3), tt = rho & 7;
-        const V* fa = a.Fc + ((size_t)(l * 2 + 0) * 8 + tt) * WP + q4;
-        const V* fb = a.Fc + ((size_t)(l * 2 + 1) * 8 + tt) * WP + q4;
+        const float4* fa = reinterpret_cast<const float4*>(a.Fc + ((size_t)(l * 2 + 0) * 8 + tt) * WP) + q4;
+        const float4* fb = reinterpret_cast<const float4*>(a.Fc + ((size_t)(l * 2 + 1) * 8 + tt) * WP) + q4;
         V g[32];
 #pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) { g[s4] = fa[4 * s4]; g[16 + s4] = fb[4 * s4]; }
+        for (int i = 0; i < 8; ++i) {
+            const float4 va = fa[4 * i], vb4 = fb[4 * i];
+            g[2 * i] = make_float2(va.x, va.y);
+            g[2 * i + 1] = make_float2(va.z, va.w);
+            g[16 + 2 * i] = make_float2(vb4.x, vb4.y);
+            g[16 + 2 * i + 1] = make_float2(vb4.z, vb4.w);
+        }
         // the y values of this lane's four outputs, loaded before the products (the
         // stores of the outputs below could alias them, so they cannot move up by themselves)
         V y[4];
@@ -1287,11 +1304,12 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
             const int ro = 16 * tile + 4 * q4 + j;
             const int roc = ro < nrows ? ro : nrows - 1;
             lo4[j] = r0 + (roc >> 3);
-            qo[j] = a.tcol[roc & 7];
+            qo[j] = tcs[roc & 7];
             ok[j] = ro < nrows && qo[j] >= 0 && rn < a.nrhs;
             const size_t yi = ((size_t)(rn < a.nrhs ? rn : 0) * a.Ny + lo4[j]) * WP + (qo[j] >= 0 ? qo[j] : 0);
             y[j] = a.Yw[yi];
         }
+        __builtin_amdgcn_sched_barrier(0);       // every operand of the tile in flight first
         mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
 #pragma unroll
         for (int s4 = 0; s4 < 32; s4 += 2) {
@@ -1316,7 +1334,7 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     }
     // the separator row closing this chunk (its x, fixed up above if needed, is in X)
     if (has_b && B.z == 0 && t < 8 * 16) {
-        const int tt = t >> 4, r = rbase + (t & 15), q = a.tcol[tt];
+        const int tt = t >> 4, r = rbase + (t & 15), q = tcs[tt];
         if (q >= 0 && r < a.nrhs) scatter<float>(a, r, r1, q, X[WP + q][t & 15]);
     }
 }
