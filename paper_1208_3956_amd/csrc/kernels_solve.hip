@@ -1188,7 +1188,6 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     __shared__ int tcs[8];                 // the target columns (the tiles' output addresses)
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, n = lane & 15, q4 = lane >> 4;
     const int c = B.x, rbase = B.y * 16;
-    if (t < 8) tcs[t] = a.tcol[t];
     const int r0 = c * a.m;
     const int r1 = (c < a.P - 1) ? c * a.m + a.m - 1 : a.Ny;
     const int nr = r1 - r0;
@@ -1229,6 +1228,8 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
             const int frow = fix[side] ? sfirst[side] * a.m + a.m - 1 : 0;
             fv[u] = a.Yw[(rr + frow) * WP + kk];
         }
+        const int tc = a.tcol[t & 7];          // waited for with the loads above
+        if (t < 8) tcs[t] = tc;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int e = t + NT * u;
@@ -1239,33 +1240,32 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     }
     __syncthreads();
     if (fix[0] || fix[1]) {
-        // X[side] += Psi_s XF[side] (64 x 64 by 64 x 16 on MFMA; wave w: rows 16 w ..)
+        // X[side] += Psi_s XF[side] (64 x 64 by 64 x 16 on MFMA in three real products;
+        // wave w: rows 16 w ..); both sides' blocks are loaded before either product
+        V g[2][16];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const V* Ps = a.Fs + ((size_t)(fix[side] ? sidx[side] : 0) * 2 + 1) * BLK + 16 * w + n;
+#pragma unroll
+            for (int s4 = 0; s4 < 16; ++s4) g[side][s4] = Ps[(size_t)(4 * s4 + q4) * WP];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             if (!fix[side]) continue;
-            const V* Ps = a.Fs + ((size_t)sidx[side] * 2 + 1) * BLK + 16 * w + n;
-            V g[16];
+            mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1;
 #pragma unroll
-            for (int s4 = 0; s4 < 16; ++s4) g[s4] = Ps[(size_t)(4 * s4 + q4) * WP];
-            __builtin_amdgcn_sched_barrier(0);
-            mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
-#pragma unroll
-            for (int s4 = 0; s4 < 16; s4 += 2) {
-                const V g0 = g[s4], g1 = g[s4 + 1];
-                const V v0 = XF[side][4 * s4 + q4][n], v1 = XF[side][4 * s4 + 4 + q4][n];
-                aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
-                aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
-                aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
-                aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.y, aI1, 0, 0, 0);
-                aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g0.y, v0.y, aR0, 0, 0, 0);
-                aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.x, aI0, 0, 0, 0);
-                aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g1.y, v1.y, aR1, 0, 0, 0);
-                aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.x, aI1, 0, 0, 0);
+            for (int s4 = 0; s4 < 16; ++s4) {
+                const V g0 = g[side][s4];
+                const V v0 = XF[side][4 * s4 + q4][n];
+                m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, m1, 0, 0, 0);
+                m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.y, m2, 0, 0, 0);
+                m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x + g0.y, v0.x + v0.y, m3, 0, 0, 0);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 V& xr = X[WP * side + 16 * w + 4 * q4 + j][n];
-                xr = make_float2(xr.x + aR0[j] + aR1[j], xr.y + aI0[j] + aI1[j]);
+                xr = make_float2(xr.x + (m1[j] - m2[j]), xr.y + (m3[j] - m1[j] - m2[j]));
             }
         }
         __syncthreads();
@@ -1277,8 +1277,12 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     // load (each load instruction reads 64 contiguous bytes of 16 compact rows).  The B panel
     // of every tile, [x_above; x_below], in the same order:
     V vb[32];
+    float vs[32];                          // Vr + Vi of the three-product form
 #pragma unroll
-    for (int s4 = 0; s4 < 32; ++s4) vb[s4] = X[WP * (s4 >> 4) + 8 * ((s4 & 15) >> 1) + 2 * q4 + (s4 & 1)][n];
+    for (int s4 = 0; s4 < 32; ++s4) {
+        vb[s4] = X[WP * (s4 >> 4) + 8 * ((s4 & 15) >> 1) + 2 * q4 + (s4 & 1)][n];
+        vs[s4] = vb[s4].x + vb[s4].y;
+    }
     for (int tile = w + 4 * B.z; tile < ntile; tile += 4 * B.nz) {
         // A operands: row rho = 16 tile + n (clamped), columns kc(s) of both sides
         const int rho = min(16 * tile + n, nrows - 1);
@@ -1310,24 +1314,24 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
             y[j] = a.Yw[yi];
         }
         __builtin_amdgcn_sched_barrier(0);       // every operand of the tile in flight first
-        mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
+        // three real products per complex one, two independent sets of accumulators
+        mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1, n1 = m1, n2 = m1, n3 = m1;
 #pragma unroll
         for (int s4 = 0; s4 < 32; s4 += 2) {
             const V g0 = g[s4], g1 = g[s4 + 1];
             const V v0 = vb[s4], v1 = vb[s4 + 1];
-            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
-            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
-            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
-            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.y, aI1, 0, 0, 0);
-            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g0.y, v0.y, aR0, 0, 0, 0);
-            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.x, aI0, 0, 0, 0);
-            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g1.y, v1.y, aR1, 0, 0, 0);
-            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.x, aI1, 0, 0, 0);
+            m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, m1, 0, 0, 0);
+            m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.y, m2, 0, 0, 0);
+            m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x + g0.y, vs[s4], m3, 0, 0, 0);
+            n1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, n1, 0, 0, 0);
+            n2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.y, n2, 0, 0, 0);
+            n3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x + g1.y, vs[s4 + 1], n3, 0, 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (ok[j]) {
-                const V x = make_float2(y[j].x - (aR0[j] + aR1[j]), y[j].y - (aI0[j] + aI1[j]));
+                const float p1 = m1[j] + n1[j], p2 = m2[j] + n2[j], p3 = m3[j] + n3[j];
+                const V x = make_float2(y[j].x - (p1 - p2), y[j].y - (p3 - p1 - p2));
                 scatter<float>(a, rn, lo4[j], qo[j], x);
             }
         }
