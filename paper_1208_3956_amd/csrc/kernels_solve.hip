@@ -849,7 +849,8 @@ __device__ __forceinline__ void sep_bwd_fix(const SolveArgs<T>& a, const Blk& B)
 //   MODE 1  z'_c += Phi_c z'_{last g-1} for the separators of group g >= 1 but its last
 //   MODE 2  x_c += Psi_c x_{first g+1} for the separators of group g < G - 1 but its first
 // Grid (separators, right-hand-side groups).  Each workgroup stages its 64 x 16 operand in
-// LDS and forms one (64 x 64) by (64 x 16) product in three real products, so a block is read
+// LDS and forms one (64 x 64) by (64 x 16) product in four real products (three lose
+// accuracy that the iteration counts of the complex64 solves feel), so a block is read
 // once per 16 right-hand sides (the per-right-hand-side workgroups of the chains read it once
 // each, which makes these products bound by the CU's load bandwidth).  A workgroup writes only
 // its own separator and reads only separators that no workgroup of the launch writes.
@@ -914,20 +915,20 @@ __device__ __forceinline__ void sep_par_mfma(const SolveArgs<float>& a, const Bl
 #pragma unroll
     for (int s = 0; s < 16; ++s) xb[s] = X[4 * s + q4][n];
     __builtin_amdgcn_sched_barrier(0);
-    mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1;
+    mf4 aR = {0.f, 0.f, 0.f, 0.f}, aI = aR;
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
         const V g4 = gA[s];
         const V x = xb[s];
-        m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.x, x.x, m1, 0, 0, 0);
-        m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.y, x.y, m2, 0, 0, 0);
-        m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.x + g4.y, x.x + x.y, m3, 0, 0, 0);
+        aR = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.x, x.x, aR, 0, 0, 0);
+        aI = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.x, x.y, aI, 0, 0, 0);
+        aR = __builtin_amdgcn_mfma_f32_16x16x4f32(-g4.y, x.y, aR, 0, 0, 0);
+        aI = __builtin_amdgcn_mfma_f32_16x16x4f32(g4.y, x.x, aI, 0, 0, 0);
     }
     if (rn >= a.nrhs) return;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const float p1 = m1[u], p2 = m2[u], p3 = m3[u];
-        const V v = make_float2(p1 - p2, p3 - p1 - p2);
+        const V v = make_float2(aR[u], aI[u]);
         y[u] = MODE == 0 ? v : cadd(yold[u], v);
     }
 }
@@ -1240,7 +1241,7 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     }
     __syncthreads();
     if (fix[0] || fix[1]) {
-        // X[side] += Psi_s XF[side] (64 x 64 by 64 x 16 on MFMA in three real products;
+        // X[side] += Psi_s XF[side] (64 x 64 by 64 x 16 on MFMA in four real products;
         // wave w: rows 16 w ..); both sides' blocks are loaded before either product
         V g[2][16];
 #pragma unroll
@@ -1253,19 +1254,20 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             if (!fix[side]) continue;
-            mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1;
+            mf4 aR = {0.f, 0.f, 0.f, 0.f}, aI = aR;
 #pragma unroll
             for (int s4 = 0; s4 < 16; ++s4) {
                 const V g0 = g[side][s4];
                 const V v0 = XF[side][4 * s4 + q4][n];
-                m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, m1, 0, 0, 0);
-                m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.y, m2, 0, 0, 0);
-                m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x + g0.y, v0.x + v0.y, m3, 0, 0, 0);
+                aR = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR, 0, 0, 0);
+                aI = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI, 0, 0, 0);
+                aR = __builtin_amdgcn_mfma_f32_16x16x4f32(-g0.y, v0.y, aR, 0, 0, 0);
+                aI = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.x, aI, 0, 0, 0);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 V& xr = X[WP * side + 16 * w + 4 * q4 + j][n];
-                xr = make_float2(xr.x + (m1[j] - m2[j]), xr.y + (m3[j] - m1[j] - m2[j]));
+                xr = make_float2(xr.x + aR[j], xr.y + aI[j]);
             }
         }
         __syncthreads();
@@ -1277,12 +1279,8 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
     // load (each load instruction reads 64 contiguous bytes of 16 compact rows).  The B panel
     // of every tile, [x_above; x_below], in the same order:
     V vb[32];
-    float vs[32];                          // Vr + Vi of the three-product form
 #pragma unroll
-    for (int s4 = 0; s4 < 32; ++s4) {
-        vb[s4] = X[WP * (s4 >> 4) + 8 * ((s4 & 15) >> 1) + 2 * q4 + (s4 & 1)][n];
-        vs[s4] = vb[s4].x + vb[s4].y;
-    }
+    for (int s4 = 0; s4 < 32; ++s4) vb[s4] = X[WP * (s4 >> 4) + 8 * ((s4 & 15) >> 1) + 2 * q4 + (s4 & 1)][n];
     for (int tile = w + 4 * B.z; tile < ntile; tile += 4 * B.nz) {
         // A operands: row rho = 16 tile + n (clamped), columns kc(s) of both sides
         const int rho = min(16 * tile + n, nrows - 1);
@@ -1314,24 +1312,25 @@ __device__ __forceinline__ void phase_c_targets_mfma(const SolveArgs<float>& a, 
             y[j] = a.Yw[yi];
         }
         __builtin_amdgcn_sched_barrier(0);       // every operand of the tile in flight first
-        // three real products per complex one, two independent sets of accumulators
-        mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1, n1 = m1, n2 = m1, n3 = m1;
+        // four real products per complex one (the three-product form costs accuracy here)
+        mf4 aR0 = {0.f, 0.f, 0.f, 0.f}, aI0 = aR0, aR1 = aR0, aI1 = aR0;
 #pragma unroll
         for (int s4 = 0; s4 < 32; s4 += 2) {
             const V g0 = g[s4], g1 = g[s4 + 1];
             const V v0 = vb[s4], v1 = vb[s4 + 1];
-            m1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, m1, 0, 0, 0);
-            m2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.y, m2, 0, 0, 0);
-            m3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x + g0.y, vs[s4], m3, 0, 0, 0);
-            n1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, n1, 0, 0, 0);
-            n2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.y, n2, 0, 0, 0);
-            n3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x + g1.y, vs[s4 + 1], n3, 0, 0, 0);
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.x, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.x, v0.y, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.y, aI1, 0, 0, 0);
+            aR0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g0.y, v0.y, aR0, 0, 0, 0);
+            aI0 = __builtin_amdgcn_mfma_f32_16x16x4f32(g0.y, v0.x, aI0, 0, 0, 0);
+            aR1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-g1.y, v1.y, aR1, 0, 0, 0);
+            aI1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.x, aI1, 0, 0, 0);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (ok[j]) {
-                const float p1 = m1[j] + n1[j], p2 = m2[j] + n2[j], p3 = m3[j] + n3[j];
-                const V x = make_float2(y[j].x - (p1 - p2), y[j].y - (p3 - p1 - p2));
+                const V x = make_float2(y[j].x - (aR0[j] + aR1[j]), y[j].y - (aI0[j] + aI1[j]));
                 scatter<float>(a, rn, lo4[j], qo[j], x);
             }
         }
