@@ -728,9 +728,9 @@ struct SepCtx {
     __device__ cplx<T>* yrow(int b, int c) const { return a.Yw + ((size_t)rhs(b) * a.Ny + sep(c)) * WP; }
 };
 
-#define SEPK_PROLOGUE                                                     \
+#define SEPK_PROLOGUE_N(RBN)                                              \
     using V = cplx<T>;                                                    \
-    constexpr int RB = SepRB<T>::RB;                                      \
+    constexpr int RB = (RBN);                                             \
     __shared__ V vecw[4][RB][WP];                                         \
     __shared__ V part[2][4][RB][WP];                                      \
     const int i = threadIdx.x & (WP - 1);                                 \
@@ -741,13 +741,18 @@ struct SepCtx {
         for (int b = 0; b < RB; ++b) v[b] = X.yrow(b, c)[i];              \
     };                                                                    \
     (void)i;
+#define SEPK_PROLOGUE SEPK_PROLOGUE_N(SepRB<T>::RB)
+// The local chains without their independent products run 8 groups x the right-hand sides
+// as workgroups: two right-hand sides per workgroup (every block load serves both) keep
+// one workgroup per CU, which measured faster than two workgroups of one.
+template <typename T> struct SepLocalRB { static constexpr int RB = 2; };
 
 // local forward chains: zeta_c = a_c - K_c zeta_{c-1} inside group g = blockIdx.y.  First
 // the group's right-hand sides a_c = G'_c r^_c, r^_c = r_s - c_s y_{s-1} - b_s y_{s+1}
 // (s = sep(c)), independent per separator: wave w takes c0 + w, c0 + w + 4, ...
 template <typename T, int D, bool SETUP>
 __device__ __forceinline__ void sep_fwd_local(const SolveArgs<T>& a, const Blk& B) {
-    SEPK_PROLOGUE
+    SEPK_PROLOGUE_N(SETUP ? SepRB<T>::RB : SepLocalRB<T>::RB)
     const int g = B.y, c0 = X.first(g), c1 = X.last(g);
     if constexpr (SETUP) {
         const int w = threadIdx.x >> 6;
@@ -805,7 +810,7 @@ __device__ __forceinline__ void sep_fwd_top(const SolveArgs<T>& a, const Blk& B)
 // its local backward chain xi_c = z'_c - U'_c xi_{c+1} (the group's last separator starts it)
 template <typename T, int D, bool FIX>
 __device__ __forceinline__ void sep_fix_bwd_local(const SolveArgs<T>& a, const Blk& B) {
-    SEPK_PROLOGUE
+    SEPK_PROLOGUE_N(FIX ? SepRB<T>::RB : SepLocalRB<T>::RB)
     const int g = B.y, c0 = X.first(g), c1 = X.last(g);
     if (FIX && g >= 1) {
         V vf[RB];
@@ -844,6 +849,7 @@ __device__ __forceinline__ void sep_bwd_fix(const SolveArgs<T>& a, const Blk& B)
                    [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw);
 }
 #undef SEPK_PROLOGUE
+#undef SEPK_PROLOGUE_N
 // The separators' independent products for 16 right-hand sides at a time on MFMA (complex64):
 //   MODE 0  a_c = G'_c r^_c for every separator c (the local forward chains' right-hand sides)
 //   MODE 1  z'_c += Phi_c z'_{last g-1} for the separators of group g >= 1 but its last
@@ -1377,11 +1383,12 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
                 // the independent products on MFMA, the chains one right-hand side per
                 // workgroup; targets-only solves fix the separators up inside phase C
                 const dim3 gp(a.P - 1, (a.nrhs + 15) / 16);
+                const unsigned nl = (unsigned)((a.nrhs + SepLocalRB<T>::RB - 1) / SepLocalRB<T>::RB);
                 hipLaunchKernelGGL(k_sep_par_mfma<0>, gp, dim3(NT), 0, st, a);
-                hipLaunchKernelGGL((k_sep_fwd_local<T, DS, false>), dim3(nr, a.G), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_fwd_local<T, DS, false>), dim3(nl, a.G), dim3(NT), 0, st, a);
                 hipLaunchKernelGGL((k_sep_fwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
                 hipLaunchKernelGGL(k_sep_par_mfma<1>, gp, dim3(NT), 0, st, a);
-                hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS, false>), dim3(nr, a.G), dim3(NT), 0, st, a);
+                hipLaunchKernelGGL((k_sep_fix_bwd_local<T, DS, false>), dim3(nl, a.G), dim3(NT), 0, st, a);
                 hipLaunchKernelGGL((k_sep_bwd_top<T, DS>), dim3(nr), dim3(NT), 0, st, a);
                 if (!targets) hipLaunchKernelGGL(k_sep_par_mfma<2>, gp, dim3(NT), 0, st, a);
             } else {
@@ -1521,6 +1528,9 @@ hipError_t launch_strip_solve_multi(const StripJob* jobs, int n, hipStream_t st,
     auto P = [](const SolveArgs<float>& a) { return a.P; };
     auto RG = [](const SolveArgs<float>& a) { return (a.nrhs + 15) / 16; };
     auto NR = [](const SolveArgs<float>& a) { return a.nrhs; };     // one right-hand side per block
+    auto NL = [](const SolveArgs<float>& a) {                       // the local chains' blocks
+        return (a.nrhs + SepLocalRB<float>::RB - 1) / SepLocalRB<float>::RB;
+    };
     auto G = [](const SolveArgs<float>& a) { return a.G; };
     auto NS = [](const SolveArgs<float>& a) { return a.P - 1; };      // separators
     auto one = [](const SolveArgs<float>&) { return 1; };
@@ -1533,13 +1543,13 @@ hipError_t launch_strip_solve_multi(const StripJob* jobs, int n, hipStream_t st,
     if (kt) kt->begin(K_PHASE_B, st);
     shape(NS, RG, one, grid);
     hipLaunchKernelGGL(k_sep_par_mfma_multi<0>, grid, dim3(NT), 0, st, m);
-    shape(NR, G, one, grid);
+    shape(NL, G, one, grid);
     hipLaunchKernelGGL((k_sep_fwd_local_multi<float, DS, false>), grid, dim3(NT), 0, st, m);
     shape(NR, one, one, grid);
     hipLaunchKernelGGL((k_sep_fwd_top_multi<float, DS>), grid, dim3(NT), 0, st, m);
     shape(NS, RG, one, grid);
     hipLaunchKernelGGL(k_sep_par_mfma_multi<1>, grid, dim3(NT), 0, st, m);
-    shape(NR, G, one, grid);
+    shape(NL, G, one, grid);
     hipLaunchKernelGGL((k_sep_fix_bwd_local_multi<float, DS, false>), grid, dim3(NT), 0, st, m);
     shape(NR, one, one, grid);
     hipLaunchKernelGGL((k_sep_bwd_top_multi<float, DS>), grid, dim3(NT), 0, st, m);
