@@ -1007,7 +1007,10 @@ __global__ void __launch_bounds__(NT) k_phase_c(SolveArgs<T> a) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int r = rbase + g + G * u;
-        x[u] = (r < a.nrhs) ? a.Yw[((size_t)r * a.Ny + l) * WP + i] : zero;
+        // clamped load, component-wise select (a select of whole values goes through scratch)
+        const bool rok = r < a.nrhs;
+        const V xl = a.Yw[((size_t)(rok ? r : 0) * a.Ny + l) * WP + i];
+        x[u] = cmk<V>(rok ? xl.x : T(0), rok ? xl.y : T(0));
         V xa = zero, xb = zero;
         if (r < a.nrhs) {
             if (top) xa = a.Yw[((size_t)r * a.Ny + (c * a.m - 1)) * WP + i];
