@@ -138,6 +138,8 @@ struct helm_problem {
     void* F = nullptr;          // factors: double2 (C128) or float2 (MIXED)
     void* Fc = nullptr;         // compact spike rows at the target columns, same precision
     void* Fs = nullptr;         // separator propagators of the two-level separator solve
+    void* Fa = nullptr;         // complex64 2-D: operand-order copies of the factors
+    void* Fw = nullptr;         //   (helm::launch_swizzle_factors)
     double2* F64 = nullptr;     // FP64 factor (the complex64 path's factorisation workspace)
     double2* Fs64 = nullptr;    // FP64 propagators (idem)
     int fac_m = 0;              // rows per chunk the factor buffers were laid out for
@@ -259,6 +261,7 @@ struct Fuser {
             return helm::launch_strip_solve<float>(
                 *j.t, *j.g, *j.ch, j.s, j.fs, static_cast<const float2*>(j.F),
                 static_cast<const float2*>(j.Fc), static_cast<const float2*>(j.Fs),
+                static_cast<const float2*>(j.Fa), static_cast<const float2*>(j.Fw),
                 static_cast<float2*>(j.Yw), j.nrhs, j.io, st, nullptr);
         };
         for (auto& gj : grp)
@@ -482,7 +485,7 @@ helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io, void*
     if (H->fuser && std::is_same<T, float>::value) {
         helm::StripJob j;
         j.t = &H->t; j.g = &H->g; j.ch = &H->ch; j.s = s; j.fs = H->fidx[s]; j.f32 = true;
-        j.F = H->F; j.Fc = H->Fc; j.Fs = H->Fs; j.Yw = yw ? yw : H->wk.Yw;
+        j.F = H->F; j.Fc = H->Fc; j.Fs = H->Fs; j.Fa = H->Fa; j.Fw = H->Fw; j.Yw = yw ? yw : H->wk.Yw;
         j.nrhs = nrhs; j.io = io;
         if (!H->fuse_ev) HIPCHK(hipEventCreateWithFlags(&H->fuse_ev, hipEventDisableTiming));
         HIPCHK(H->fuser->submit(j, H->st, H->fuse_ev));
@@ -491,8 +494,11 @@ helm_status strip_solve(helm_t H, int s, int nrhs, const helm::IOSpec& io, void*
     const auto* F = static_cast<const helm::cplx<T>*>(H->F);
     const auto* Fc = static_cast<const helm::cplx<T>*>(H->Fc);
     const auto* Fs = static_cast<const helm::cplx<T>*>(H->Fs);
+    const auto* Fa = static_cast<const helm::cplx<T>*>(H->Fa);
+    const auto* Fw = static_cast<const helm::cplx<T>*>(H->Fw);
     auto* Yw = static_cast<helm::cplx<T>*>(yw ? yw : H->wk.Yw);
-    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, H->fidx[s], F, Fc, Fs, Yw, nrhs, io, H->st, kt));
+    HIPCHK(helm::launch_strip_solve<T>(H->t, H->g, H->ch, s, H->fidx[s], F, Fc, Fs, Fa, Fw, Yw, nrhs, io,
+                                       H->st, kt));
     return HELM_OK;
 }
 
@@ -926,6 +932,7 @@ helm_status apply_PcR_full(helm_t H, int nrhs, const double2* f, double2* out) {
                 const int s = upd[k];
                 jb[k].t = &H->t; jb[k].g = &H->g; jb[k].ch = &H->ch; jb[k].s = s; jb[k].fs = H->fidx[s];
                 jb[k].f32 = true; jb[k].F = H->F; jb[k].Fc = H->Fc; jb[k].Fs = H->Fs;
+                jb[k].Fa = H->Fa; jb[k].Fw = H->Fw;
                 jb[k].Yw = k == 0 ? w.Yw : w.Yw2; jb[k].nrhs = nrhs; jb[k].io = io[k];
             }
             if (helm::strip_jobs_fusable(jb, 2)) {
@@ -2101,6 +2108,7 @@ helm_status helm_factor(helm_t H) {
         if (single) CHK(dmalloc(H, &H->F, nel * esz));
         else H->F = H->F64;
         CHK(dmalloc(H, &H->Fc, ncomp * esz));
+        if (single) CHK(dmalloc(H, &H->Fa, nel / NSLOT * esz));
         H->fac_m = 0;
     }
     if (H->fac_m != H->ch.m) {
@@ -2110,11 +2118,14 @@ helm_status helm_factor(helm_t H) {
         if (single) HIPCHK(hipMemsetAsync(H->F, 0, nel * esz, H->st));
         if (H->Fs != H->Fs64) dfree(H->Fs);
         dfree(H->Fs64);
+        dfree(H->Fw);
         H->Fs = H->Fs64 = nullptr;
+        H->Fw = nullptr;
         if (nsel) {
             CHK(dmalloc(H, &H->Fs64, nsel * sizeof(double2)));
             if (single) CHK(dmalloc(H, &H->Fs, nsel * esz));
             else H->Fs = H->Fs64;
+            if (single) CHK(dmalloc(H, &H->Fw, nsel * 2 * esz));     // 4 blocks per separator
         }
         H->fac_m = H->ch.m;
     }
@@ -2129,9 +2140,14 @@ helm_status helm_factor(helm_t H) {
         HIPCHK(TIMED(H, helm::K_FACTOR_SEPS,
                      helm::launch_factor_propagators(H->tf, gf, H->ch, F64, H->Fs64,
                                                      single ? static_cast<float2*>(H->Fs) : nullptr, H->st)));
-    if (single)
+    if (single) {
         HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<float2>(F32, static_cast<float2*>(H->Fc),
                                                                            H->tf.tcol, gf, H->ch, H->st)));
+        HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_swizzle_factors(F32, static_cast<const float2*>(H->Fs),
+                                                                   static_cast<float2*>(H->Fa),
+                                                                   static_cast<float2*>(H->Fw), gf, H->ch,
+                                                                   H->nfac, H->st)));
+    }
     else
         HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_extract_targets<double2>(F64, static_cast<double2*>(H->Fc),
                                                                             H->tf.tcol, gf, H->ch, H->st)));
@@ -2541,6 +2557,8 @@ void helm_destroy(helm_t H) {
     dfree(H->F64);
     dfree(H->Fs64);
     dfree(H->Fc);
+    dfree(H->Fa);
+    dfree(H->Fw);
     dfree(H->d_err);
     for (void* p : H->owned) dfree(p);
     delete H;

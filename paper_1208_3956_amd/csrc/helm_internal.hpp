@@ -116,6 +116,8 @@ struct StripJob {
     const void* F = nullptr;
     const void* Fc = nullptr;
     const void* Fs = nullptr;
+    const void* Fa = nullptr;            // operand-order copies (launch_swizzle_factors)
+    const void* Fw = nullptr;
     void* Yw = nullptr;
     int nrhs = 0;
     IOSpec io;
@@ -213,11 +215,24 @@ template <typename V>
 hipError_t launch_extract_targets(const V* F, V* Fc, const int* tcol, const Geom& g,
                                   const Chunks& ch, hipStream_t st);
 
+// Operand-order copies of complex64 factor blocks, for 16-byte loads of two adjacent values
+// per lane (a CU issues loads per instruction, so half the instructions move the same bytes
+// in about half the time).  Fa[slot][row][BLK]: block G_l (slot 0) of every row, laid out as
+// [wave w][pair i][lane][2] holding G_l[16 w + n][8 i + 4 h + q4] (lane = 16 q4 + n, h the
+// half), the A operands of the phase-A products in their k-step order.  Fw[slot][c][4][BLK]:
+// for separator c, the chain blocks (slot 1 and slot 2 at its row) and the propagators (Fs
+// forward, backward), laid out as [wave w][pair j][row i][2] holding M[i][16 w + 2 j + h].
+// Fw is written only when the factor has propagators (two-level separator solve).
+hipError_t launch_swizzle_factors(const float2* F, const float2* Fs, float2* Fa, float2* Fw,
+                                  const Geom& g, const Chunks& ch, int nfac, hipStream_t st);
+
 template <typename T>
-// strip s with its factors in slot fs of F, Fc, Fs (identical strips share a slot)
+// strip s with its factors in slot fs of F, Fc, Fs, and (complex64) the operand-order copies
+// Fa, Fw (identical strips share a slot)
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
-                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
-                              int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt = nullptr);
+                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, const cplx<T>* Fa,
+                              const cplx<T>* Fw, cplx<T>* Yw, int nrhs, const IOSpec& io, hipStream_t st,
+                              KTimer* kt = nullptr);
 
 hipError_t launch_apply_A(const DevTables& t, const Geom& g, int nrhs, const double2* u,
                           const double2* f, double2* out, hipStream_t st);

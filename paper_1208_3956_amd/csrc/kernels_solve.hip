@@ -33,6 +33,8 @@ struct SolveArgs {
     const cplx<T>* Fc;    // compact spike rows of the strip: [Ny][2][8][WP] (reduced phase C)
     const int* tcol;      // 8 strip-local columns of the compact rows (-1 = unused)
     const cplx<T>* Fs;    // separator propagators of the strip: [P-1][2][WP*WP] (two-level solve)
+    const cplx<T>* Fa;    // complex64: G_l in phase-A operand order, [Ny][WP*WP] (see helm_internal.hpp)
+    const cplx<T>* Fw;    // complex64: chain blocks in operand order, [P-1][4][WP*WP]
     cplx<T>* Yw;          // workspace [nrhs][Ny][WP]
     const double2* cy;
     const double2* by;
@@ -331,10 +333,15 @@ __device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Bl
         k = k < nsteps ? k : nsteps - 1;
         return k < nr ? r0 + k : r1 - 2 - (k - nr);
     };
+    // the A operands of k-steps 2i and 2i + 1 come in one 16-byte load (operand-order copy)
     auto load_g = [&](int k, V (&g)[16]) {
-        const V* G = fslot(a, row_of(k), 0) + 16 * w + n;
+        const float4* G = reinterpret_cast<const float4*>(a.Fa + (size_t)row_of(k) * BLK) + w * 8 * 64 + lane;
 #pragma unroll
-        for (int s4 = 0; s4 < 16; ++s4) g[s4] = G[(4 * s4 + q4) * WP];
+        for (int i = 0; i < 8; ++i) {
+            const float4 v = G[i * 64];
+            g[2 * i] = make_float2(v.x, v.y);
+            g[2 * i + 1] = make_float2(v.z, v.w);
+        }
     };
     RawRhs4 raw;
     auto load_rhs = [&](int l) {
@@ -627,7 +634,9 @@ __global__ void __launch_bounds__(NT) k_phase_b(SolveArgs<T> a) {
 // Blocks and inputs of the next D steps are in flight in registers.
 template <typename T> struct SepRB { static constexpr int RB = 1; };
 
-template <typename T, int D, int RB, typename BF, typename RF>
+// SW: blk(k) is an operand-order block of Fw (complex64): the lane's columns 16 w + 2 j,
+// 16 w + 2 j + 1 come in one 16-byte load; otherwise a factor block in its own layout.
+template <typename T, int D, int RB, bool SW = false, typename BF, typename RF>
 __device__ void sep_chain(int n, bool chain, const cplx<T> (&v0)[RB], T sgn, BF blk, RF row,
                           const bool (&okb)[RB], cplx<T> (*vecw)[RB][WP], cplx<T> (*part)[4][RB][WP]) {
     using V = cplx<T>;
@@ -639,9 +648,19 @@ __device__ void sep_chain(int n, bool chain, const cplx<T> (&v0)[RB], T sgn, BF 
     V breg[D][16], ireg[D][RB];
     auto load = [&](int k, V (&bl)[16], V (&x)[RB]) {
         const int kc = k < n ? k : n - 1;
-        const V* M = blk(kc) + (size_t)k0 * WP + i;
+        if constexpr (SW) {
+            const float4* M = reinterpret_cast<const float4*>(blk(kc)) + w * 8 * 64 + i;
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) bl[kk] = M[kk * WP];
+            for (int j = 0; j < 8; ++j) {
+                const float4 v = M[j * 64];
+                bl[2 * j] = make_float2(v.x, v.y);
+                bl[2 * j + 1] = make_float2(v.z, v.w);
+            }
+        } else {
+            const V* M = blk(kc) + (size_t)k0 * WP + i;
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) bl[kk] = M[kk * WP];
+        }
 #pragma unroll
         for (int b = 0; b < RB; ++b) x[b] = row(kc, b)[i];
     };
@@ -790,9 +809,14 @@ __device__ __forceinline__ void sep_fwd_local(const SolveArgs<T>& a, const Blk& 
     }
     V v0[RB];
     vecs_at(c0, v0);
-    sep_chain<T, D, RB>(c1 - c0, true, v0, T(-1),
-                        [&](int k) { return fslot(a, X.sep(c0 + 1 + k), 1); },
-                        [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw, part);
+    if constexpr (!SETUP && std::is_same<T, float>::value)
+        sep_chain<T, D, RB, true>(c1 - c0, true, v0, T(-1),
+                                  [&](int k) { return a.Fw + ((size_t)(c0 + 1 + k) * 4 + 0) * BLK; },
+                                  [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw, part);
+    else
+        sep_chain<T, D, RB>(c1 - c0, true, v0, T(-1),
+                            [&](int k) { return fslot(a, X.sep(c0 + 1 + k), 1); },
+                            [&](int k, int b) { return X.yrow(b, c0 + 1 + k); }, okb, vecw, part);
 }
 
 // chain over the groups' last separators: z'_{last g} = zeta_{last g} + Phi_{last g} z'_{last g-1}
@@ -801,9 +825,14 @@ __device__ __forceinline__ void sep_fwd_top(const SolveArgs<T>& a, const Blk& B)
     SEPK_PROLOGUE
     V v0[RB];
     vecs_at(X.last(0), v0);
-    sep_chain<T, D, RB>(a.G - 1, true, v0, T(1),
-                        [&](int k) { return X.prop(X.last(k + 1), 0); },
-                        [&](int k, int b) { return X.yrow(b, X.last(k + 1)); }, okb, vecw, part);
+    if constexpr (std::is_same<T, float>::value)
+        sep_chain<T, D, RB, true>(a.G - 1, true, v0, T(1),
+                                  [&](int k) { return a.Fw + ((size_t)X.last(k + 1) * 4 + 2) * BLK; },
+                                  [&](int k, int b) { return X.yrow(b, X.last(k + 1)); }, okb, vecw, part);
+    else
+        sep_chain<T, D, RB>(a.G - 1, true, v0, T(1),
+                            [&](int k) { return X.prop(X.last(k + 1), 0); },
+                            [&](int k, int b) { return X.yrow(b, X.last(k + 1)); }, okb, vecw, part);
 }
 
 // fix-up of the group's other separators (unless FIX is false: done before, on MFMA), then
@@ -821,9 +850,14 @@ __device__ __forceinline__ void sep_fix_bwd_local(const SolveArgs<T>& a, const B
     }
     V v0[RB];
     vecs_at(c1, v0);
-    sep_chain<T, D, RB>(c1 - c0, true, v0, T(-1),
-                        [&](int k) { return fslot(a, X.sep(c1 - 1 - k), 2); },
-                        [&](int k, int b) { return X.yrow(b, c1 - 1 - k); }, okb, vecw, part);
+    if constexpr (!FIX && std::is_same<T, float>::value)
+        sep_chain<T, D, RB, true>(c1 - c0, true, v0, T(-1),
+                                  [&](int k) { return a.Fw + ((size_t)(c1 - 1 - k) * 4 + 1) * BLK; },
+                                  [&](int k, int b) { return X.yrow(b, c1 - 1 - k); }, okb, vecw, part);
+    else
+        sep_chain<T, D, RB>(c1 - c0, true, v0, T(-1),
+                            [&](int k) { return fslot(a, X.sep(c1 - 1 - k), 2); },
+                            [&](int k, int b) { return X.yrow(b, c1 - 1 - k); }, okb, vecw, part);
 }
 
 // chain over the groups' first separators: x_{first g} = xi_{first g} + Psi_{first g} x_{first g+1}
@@ -832,9 +866,14 @@ __device__ __forceinline__ void sep_bwd_top(const SolveArgs<T>& a, const Blk& B)
     SEPK_PROLOGUE
     V v0[RB];
     vecs_at(X.first(a.G - 1), v0);
-    sep_chain<T, D, RB>(a.G - 1, true, v0, T(1),
-                        [&](int k) { return X.prop(X.first(a.G - 2 - k), 1); },
-                        [&](int k, int b) { return X.yrow(b, X.first(a.G - 2 - k)); }, okb, vecw, part);
+    if constexpr (std::is_same<T, float>::value)
+        sep_chain<T, D, RB, true>(a.G - 1, true, v0, T(1),
+                                  [&](int k) { return a.Fw + ((size_t)X.first(a.G - 2 - k) * 4 + 3) * BLK; },
+                                  [&](int k, int b) { return X.yrow(b, X.first(a.G - 2 - k)); }, okb, vecw, part);
+    else
+        sep_chain<T, D, RB>(a.G - 1, true, v0, T(1),
+                            [&](int k) { return X.prop(X.first(a.G - 2 - k), 1); },
+                            [&](int k, int b) { return X.yrow(b, X.first(a.G - 2 - k)); }, okb, vecw, part);
 }
 
 // fix-up of the group's other separators: x_c = xi_c + Psi_c x_{first g+1}
@@ -1439,11 +1478,13 @@ hipError_t run(const SolveArgs<T>& a, bool targets, hipStream_t st, KTimer* kt) 
 
 template <typename T>
 SolveArgs<T> solve_args(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
-                        const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
-                        int nrhs, const IOSpec& io) {
+                        const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, const cplx<T>* Fa,
+                        const cplx<T>* Fw, cplx<T>* Yw, int nrhs, const IOSpec& io) {
     SolveArgs<T> a;
     a.F = F + (size_t)fs * g.Ny * NSLOT * BLK;
     a.Fs = Fs ? Fs + (size_t)fs * (ch.P - 1) * 2 * BLK : nullptr;
+    a.Fa = Fa ? Fa + (size_t)fs * g.Ny * BLK : nullptr;
+    a.Fw = Fw ? Fw + (size_t)fs * (ch.P - 1) * 4 * BLK : nullptr;
     a.q = ch.q;
     a.G = ch.G;
     a.Fc = Fc ? Fc + (size_t)fs * g.Ny * 2 * 8 * WP : nullptr;
@@ -1470,9 +1511,15 @@ SolveArgs<T> solve_args(const DevTables& t, const Geom& g, const Chunks& ch, int
 
 template <typename T>
 hipError_t launch_strip_solve(const DevTables& t, const Geom& g, const Chunks& ch, int s, int fs,
-                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, cplx<T>* Yw,
-                              int nrhs, const IOSpec& io, hipStream_t st, KTimer* kt) {
-    const SolveArgs<T> a = solve_args<T>(t, g, ch, s, fs, F, Fc, Fs, Yw, nrhs, io);
+                              const cplx<T>* F, const cplx<T>* Fc, const cplx<T>* Fs, const cplx<T>* Fa,
+                              const cplx<T>* Fw, cplx<T>* Yw, int nrhs, const IOSpec& io, hipStream_t st,
+                              KTimer* kt) {
+    const SolveArgs<T> a = solve_args<T>(t, g, ch, s, fs, F, Fc, Fs, Fa, Fw, Yw, nrhs, io);
+    // complex64 reads the operand-order copies: phase A on MFMA (more than 4 right-hand
+    // sides) and the separator chains of the two-level solve
+    if (std::is_same<T, float>::value &&
+        ((nrhs > 4 && !Fa) || (ch.P > 2 && ch.G >= 2 && Fs && !Fw)))
+        return hipErrorInvalidValue;
     const bool targets = a.io.targets_only != 0;
     if (nrhs <= 4) return run<T, 4>(a, targets, st, kt);
     return run<T, 16>(a, targets, st, kt);
@@ -1482,6 +1529,7 @@ namespace {
 SolveArgs<float> job_args(const StripJob& j) {
     return solve_args<float>(*j.t, *j.g, *j.ch, j.s, j.fs, static_cast<const float2*>(j.F),
                              static_cast<const float2*>(j.Fc), static_cast<const float2*>(j.Fs),
+                             static_cast<const float2*>(j.Fa), static_cast<const float2*>(j.Fw),
                              static_cast<float2*>(j.Yw), j.nrhs, j.io);
 }
 // rows of the full-column phase C per workgroup: about four workgroups per CU
@@ -1502,6 +1550,7 @@ bool strip_jobs_fusable(const StripJob* jobs, int n) {
         const StripJob& j = jobs[k];
         if (!j.f32 || j.g->dim != 2 || j.nrhs <= 4) return false;
         if (!(j.ch->P > 2 && j.ch->G >= 2 && j.Fs)) return false;        // two-level separators
+        if (!j.Fa || !j.Fw) return false;                                // operand-order copies
         const int tk = (j.io.targets_only && j.Fc) ? 1 : 0;
         if (targets >= 0 && tk != targets) return false;
         targets = tk;
@@ -1574,10 +1623,52 @@ hipError_t launch_strip_solve_multi(const StripJob* jobs, int n, hipStream_t st,
 }
 
 template hipError_t launch_strip_solve<float>(const DevTables&, const Geom&, const Chunks&, int, int,
-                                              const float2*, const float2*, const float2*, float2*, int,
-                                              const IOSpec&, hipStream_t, KTimer*);
+                                              const float2*, const float2*, const float2*, const float2*,
+                                              const float2*, float2*, int, const IOSpec&, hipStream_t, KTimer*);
 template hipError_t launch_strip_solve<double>(const DevTables&, const Geom&, const Chunks&, int, int,
-                                               const double2*, const double2*, const double2*, double2*,
-                                               int, const IOSpec&, hipStream_t, KTimer*);
+                                               const double2*, const double2*, const double2*,
+                                               const double2*, const double2*, double2*, int, const IOSpec&,
+                                               hipStream_t, KTimer*);
+
+namespace {
+// Fa[slot][row]: out[((w * 8 + i) * 64 + 16 q4 + n) * 2 + h] = G[16 w + n][8 i + 4 h + q4] of
+// F[slot][row][0] (column-major: element (r, c) at c * WP + r)
+__global__ void __launch_bounds__(NT) k_swizzle_a(const float2* __restrict__ F, float2* __restrict__ Fa) {
+    const size_t blk = blockIdx.x;                       // slot * Ny + row
+    const float2* src = F + blk * NSLOT * BLK;
+    float2* dst = Fa + blk * BLK;
+    for (int o = threadIdx.x; o < BLK; o += NT) {
+        const int h = o & 1, lane = (o >> 1) & 63, i = (o >> 7) & 7, w = o >> 10;
+        const int q4 = lane >> 4, n = lane & 15;
+        dst[o] = src[(8 * i + 4 * h + q4) * WP + 16 * w + n];
+    }
+}
+// Fw[slot][c][kind]: out[((w * 8 + j) * 64 + i) * 2 + h] = M[i][16 w + 2 j + h] for M = the
+// slot-1 / slot-2 block at separator row c m + m - 1 (kind 0 / 1) or the propagator Fs[c][0 / 1]
+// (kind 2 / 3)
+__global__ void __launch_bounds__(NT) k_swizzle_w(const float2* __restrict__ F, const float2* __restrict__ Fs,
+                                                  float2* __restrict__ Fw, int Ny, int m, int ns) {
+    const int kind = blockIdx.x & 3, c = (blockIdx.x >> 2) % ns, slot = (blockIdx.x >> 2) / ns;
+    const int row = c * m + m - 1;
+    const float2* src = kind < 2 ? F + (((size_t)slot * Ny + row) * NSLOT + 1 + kind) * BLK
+                                 : Fs + (((size_t)slot * ns + c) * 2 + (kind - 2)) * BLK;
+    float2* dst = Fw + (size_t)blockIdx.x * BLK;
+    for (int o = threadIdx.x; o < BLK; o += NT) {
+        const int h = o & 1, i = (o >> 1) & 63, j = (o >> 7) & 7, w = o >> 10;
+        dst[o] = src[(16 * w + 2 * j + h) * WP + i];
+    }
+}
+}  // namespace
+
+hipError_t launch_swizzle_factors(const float2* F, const float2* Fs, float2* Fa, float2* Fw,
+                                  const Geom& g, const Chunks& ch, int nfac, hipStream_t st) {
+    if (nfac <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_swizzle_a, dim3((unsigned)(nfac * g.Ny)), dim3(NT), 0, st, F, Fa);
+    const int ns = ch.P - 1;
+    if (Fw && Fs && ns > 0)
+        hipLaunchKernelGGL(k_swizzle_w, dim3((unsigned)(nfac * ns * 4)), dim3(NT), 0, st, F, Fs, Fw, g.Ny,
+                           ch.m, ns);
+    return hipGetLastError();
+}
 
 }  // namespace helm
