@@ -49,7 +49,7 @@ def _case(J):
 
 @pytest.fixture(scope="module")
 def cases():
-    return {J: _case(J) for J in (4, 5)}
+    return {J: _case(J) for J in (2, 3, 4, 5)}
 
 
 def _gpu(wl, prec="c128", chunk=9, **kw):
@@ -145,12 +145,14 @@ def test_table4_robin_column(i):
 
 
 # ------------------------------------------------------------ concurrent Robin sweeps
-@pytest.mark.parametrize("J", [4, 5])
+@pytest.mark.parametrize("J", [2, 3, 4, 5])
 @pytest.mark.parametrize("prec,tol", [("c128", 1e-10), ("mixed", 2e-4)])
 def test_concurrent_robin_P(cases, J, prec, tol):
     """The concurrent sweeps of Sec. 3.1 with Robin transmission (subdomains n and J + 1 - n
     at step n, two-sided data from the step before) against the oracle, right-hand side by
-    right-hand side; complex64 runs each step's two strip solves as one launch."""
+    right-hand side; complex64 runs each step's two strip solves as one launch.  J = 2: the
+    chains meet at once (each subdomain solved twice, the second time with the other's
+    data); J = 3: the middle subdomain is updated once, by a step with a single solve."""
     from oracle.robin import apply_P_concurrent_robin
     wl, g, A, R = cases[J]
     H = _gpu(wl, prec=prec, sweep="concurrent")
