@@ -302,7 +302,11 @@ typedef float mf4 __attribute__((ext_vector_type(4)));
 // (16 values per block, A[16w + n][4s + q4] for k-step s) straight from global memory into
 // a ring of D register blocks, D steps ahead.  Only the right-hand-side panel of a step
 // (64 x 16) goes through LDS, double-buffered, so a step has a single barrier.  Each lane
-// gathers the right-hand-side values of its own four output positions.
+// gathers the right-hand-side values of its own four output positions.  The ring slot a
+// step's products read is refilled inside the product loop, one 16-byte load after the six
+// products that read its pair: the four waves of a workgroup reach their products together
+// after the barrier, and loads issued after the products kept the CU's load path busy
+// while the matrix cores idled (and the stores and right-hand-side loads queued behind).
 template <int D>
 __device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Blk& B) {
     using V = float2;
@@ -334,8 +338,11 @@ __device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Bl
         return k < nr ? r0 + k : r1 - 2 - (k - nr);
     };
     // the A operands of k-steps 2i and 2i + 1 come in one 16-byte load (operand-order copy)
+    auto g_ptr = [&](int k) {
+        return reinterpret_cast<const float4*>(a.Fa + (size_t)row_of(k) * BLK) + w * 8 * 64 + lane;
+    };
     auto load_g = [&](int k, V (&g)[16]) {
-        const float4* G = reinterpret_cast<const float4*>(a.Fa + (size_t)row_of(k) * BLK) + w * 8 * 64 + lane;
+        const float4* G = g_ptr(k);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const float4 v = G[i * 64];
@@ -356,7 +363,9 @@ __device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Bl
 #pragma unroll
     for (int d = 0; d < D; ++d) load_g(d, greg[d]);
 
-    auto mfma_block = [&](const V (&g)[16], const V (*Vb)[R], V (&out)[4]) {
+    // products of block g with the staged panel; g is refilled with block knext meanwhile
+    auto mfma_block = [&](V (&g)[16], const V (*Vb)[R], V (&out)[4], int knext) {
+        const float4* Gn = g_ptr(knext);
         // three real products per complex one: M1 = Gr Vr, M2 = Gi Vi, M3 = (Gr + Gi)(Vr + Vi);
         // Zr = M1 - M2, Zi = M3 - M1 - M2
         mf4 m1 = {0.f, 0.f, 0.f, 0.f}, m2 = m1, m3 = m1, n1 = m1, n2 = m1, n3 = m1;
@@ -374,6 +383,11 @@ __device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Bl
             n1 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x, v1.x, n1, 0, 0, 0);
             n2 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.y, v1.y, n2, 0, 0, 0);
             n3 = __builtin_amdgcn_mfma_f32_16x16x4f32(g1.x + g1.y, v1.x + v1.y, n3, 0, 0, 0);
+            const float4 nv = Gn[(s4 >> 1) * 64];
+            g[s4] = make_float2(nv.x, nv.y);
+            g[s4 + 1] = make_float2(nv.z, nv.w);
+            __builtin_amdgcn_sched_group_barrier(0x008, 6, 0);   // six MFMAs,
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // then the pair's load
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -403,8 +417,7 @@ __device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Bl
         for (int u = 0; u < 4; ++u) Vs[buf][qrow + u][n] = v[u];
         __syncthreads();
         V acc[4];
-        mfma_block(greg[j], Vs[buf], acc);
-        load_g(k + D, greg[j]);
+        mfma_block(greg[j], Vs[buf], acc, k + D);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             z[u] = keep(rn_ok, acc[u]);
@@ -427,8 +440,7 @@ __device__ __forceinline__ void phase_a_mfma(const SolveArgs<float>& a, const Bl
         for (int u = 0; u < 4; ++u) Vs[buf][qrow + u][n] = z[u];
         __syncthreads();
         V acc[4];
-        mfma_block(greg[j], Vs[buf], acc);
-        load_g(k + D, greg[j]);
+        mfma_block(greg[j], Vs[buf], acc, k + D);
         const bool store_y = !a.io.targets_only || l == r0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
