@@ -596,8 +596,11 @@ helm_status sweep_up(helm_t H, int nrhs, const double2* src, int s0, bool full,
             // last two in that of interface s + 1
             const long wrow = (long)(g.J - 1) * helm::IWIN;
             io.dst_rs = g.Nrow() * wrow; io.dst_ls = (int)wrow;
-            io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = io.o_lo[0] + 2;
-            bool in = win_off(g, s, s, S.core_lo, 2, &io.dst_off[0]);
+            bool in = true;
+            if (s > 0) {                       // strip 0 has no interface on its left
+                io.o_lo[0] = S.core_lo - S.a; io.o_hi[0] = io.o_lo[0] + 2;
+                in = win_off(g, s, s, S.core_lo, 2, &io.dst_off[0]);
+            }
             if (s < g.J - 1) {
                 io.o_lo[1] = S.core_hi - 2 - S.a; io.o_hi[1] = S.core_hi - S.a;
                 in = in && win_off(g, s, s + 1, S.core_hi - 2, 2, &io.dst_off[1]);
@@ -696,6 +699,27 @@ helm_status apply_AP_reduced(helm_t H, int nrhs, const double2* psi, double2* ou
     CHK(sweep_down(H, nrhs, w.Ww, false));
     // h = g - A w on the reduced columns; output psi - h
     HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_stencil_win(1, H->t, g, nrhs, w.Ww, psi, w.Gw, out, H->st)));
+    return HELM_OK;
+}
+
+// A restart's reduced right-hand side b = (r - A P r) on the reduced columns for a full field
+// r, with both sweeps of P in the target-only form of Algorithm 3: g = r - A v vanishes off
+// the columns beta_j - 1, beta_j and r - A (v + w) = g - A w off beta_j, beta_j + 1 (Sec. 2.1,
+// exact arithmetic), so the interface windows hold all that b needs.  P r itself is added
+// with the cycle's final application of P, P (r + psi) = P r + P psi.
+helm_status restart_rhs_reduced(helm_t H, int nrhs, const double2* r, double2* b) {
+    CHK(ensure_sweep_ws(H, nrhs));
+    const auto& g = H->g;
+    Work& w = H->wk;
+    if (g.J < 2) return HELM_OK;
+    CHK(sweep_up(H, nrhs, r, 0, false, nullptr));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_stencil_win(3, H->t, g, nrhs, w.Vw, r, w.Gw, nullptr, H->st)));
+    // Algorithm 3's upward sweeps start at the second strip and rely on the first interface's
+    // window of v holding zeros where the first strip would write
+    HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_clear_win_cols(w.Vw, (long)nrhs * g.Nrow(),
+                                                               (long)(g.J - 1) * helm::IWIN, 0, helm::IWIN, H->st)));
+    CHK(sweep_down(H, nrhs, w.Ww, false));
+    HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_stencil_win(4, H->t, g, nrhs, w.Ww, nullptr, w.Gw, b, H->st)));
     return HELM_OK;
 }
 
@@ -1448,6 +1472,9 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
     const long nfull = g.Nrow() * g.Nx;
     const int nred = 2 * (g.J - 1);
     const bool reduced = H->mode == HELM_REDUCED && nred > 0;
+    // restarts of the double sweep with PML transmission take their right-hand side from the
+    // target-only form of P and fold P r into the cycle's final application of P
+    const bool merge = reduced && H->sweep == 0 && H->trans == 0;
     const long n = reduced ? g.Nrow() * nred : nfull;
     CHK(ensure_gmres_ws(H, nrhs, n, std::min(H->max_iter, H->restart > 0 ? H->restart : reduced ? 60 : 30)));
     std::vector<double> fn, rn;
@@ -1502,11 +1529,14 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
                 // iteration (it is counted in the operator applications of helm_get_stats
                 // and against max_iter)
                 H->stat_ap += 1;
-                CHK(apply_P_any(H, nrhs, w.R, w.Ut));
+                if (merge) CHK(restart_rhs_reduced(H, nrhs, w.R, w.red));
+                else CHK(apply_P_any(H, nrhs, w.R, w.Ut));
                 used += 1;
             }
-            HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
-            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, red_cols(H), nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
+            if (cycle == 0 || !merge) {
+                HIPCHK(TIMED(H, helm::K_STENCIL, helm::launch_apply_A(H->t, g, nrhs, w.Ut, w.R, w.Hf, H->st)));
+                HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_gather_cols(w.Hf, red_cols(H), nred, nrhs, g.Nrow(), g.Nx, w.red, H->st)));
+            }
             b = w.red;
             if (cycle > 0 && !prev_aug) CHK(build_aug(H, nrhs, n, w.red, hess, its, aug));
         }
@@ -1544,7 +1574,12 @@ helm_status solve_impl(helm_t H, int nrhs, const double2* f, double2* u, double 
         int kmax = 0;
         for (int r = 0; r < nrhs; ++r) { total[r] += its[r]; kmax = std::max(kmax, its[r]); }
         used += std::max(kmax, 1);
-        if (reduced) {
+        if (reduced && cycle > 0 && merge) {
+            // Algorithm 4 with the restart's P r folded in: u += P (r + psi)
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, red_cols(H), nred, nrhs, g.Nrow(), g.Nx, w.R, H->st, true)));
+            CHK(apply_P_any(H, nrhs, w.R, w.Hf));
+            HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_sum3(u, w.Hf, nullptr, u, nrhs * nfull, H->st)));
+        } else if (reduced) {
             // Algorithm 4: u += P psi + u~   (psi scattered onto the reduced columns of Psi,
             // which is zero everywhere else: nothing but this scatter writes it)
             HIPCHK(TIMED(H, helm::K_OTHER, helm::launch_scatter_cols(w.w, red_cols(H), nred, nrhs, g.Nrow(), g.Nx, w.Psi, H->st)));

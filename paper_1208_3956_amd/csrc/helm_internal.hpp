@@ -246,6 +246,8 @@ hipError_t launch_apply_A_pairs(const DevTables& t, const Geom& g, int nrhs, con
 //   mode 1: out = psi - (g - A u) on beta_j, beta_j + 1
 //   mode 2: out = A (u + psi - g) on beta_j - 1, beta_j (psi, g: window fields too; the
 //           concurrent sweep's v, w' and z)
+//   mode 3: g = psi - A u on beta_j - 1, beta_j with psi a full field
+//   mode 4: out = g - A u on beta_j, beta_j + 1 (g = 0 on beta_j + 1)
 hipError_t launch_stencil_win(int mode, const DevTables& t, const Geom& g, int nrhs, const double2* u,
                               const double2* psi, double2* gw, double2* out, hipStream_t st);
 
@@ -263,8 +265,11 @@ hipError_t launch_lincomb(const double2* V, int nvec, const double2* y, double2*
                           int nrhs, long n, int accumulate, hipStream_t st);
 hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, int nrhs,
                               int Ny, int Nx, double2* red, hipStream_t st);
+// field[.., cols[k]] = red[.., k] (add: +=)
 hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
-                               int Ny, int Nx, double2* field, hipStream_t st);
+                               int Ny, int Nx, double2* field, hipStream_t st, bool add = false);
+// zero entries c0 .. c0 + n - 1 of each row of a window field ([nrows][wrow])
+hipError_t launch_clear_win_cols(double2* win, long nrows, long wrow, int c0, int n, hipStream_t st);
 // zero column cols[k] + shift of every row, k < ncols
 // out = x + y + z; x or z may be null
 hipError_t launch_sum3(const double2* x, const double2* y, const double2* z, double2* out, long n,

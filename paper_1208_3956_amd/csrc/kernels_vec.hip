@@ -127,6 +127,9 @@ __global__ void __launch_bounds__(256) k_apply_A_pairs(StencilArgs s, const int*
 //   MODE 1: out[.., 2 j + k] = psi[.., 2 j + k] - (g[2 + k] - (A u)[2 + k]), k = 0, 1
 //   MODE 2: out[.., 2 j + k] = (A u)[1 + k], k = 0, 1, with u = u + psi - gw (three window
 //           fields: the concurrent sweep's v, w' and z; out on the columns beta_j - 1, beta_j)
+//   MODE 3: MODE 0 with psi a full field [nrhs][Nrow][Nx] (taken at both columns c = 1, 2)
+//   MODE 4: out[.., 2 j + k] = g[2 + k] - (A u)[2 + k], k = 0, 1, with g[3] = 0 (the
+//           residual of the upward sweep vanishes there)
 template <int MODE>
 __global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* __restrict__ bw,
                                                      const double* __restrict__ k2w, int NI, int nrhs,
@@ -141,7 +144,7 @@ __global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* _
     (void)nrhs;
     for (int q = threadIdx.x; q < 2 * NI; q += blockDim.x) {
         const int k = q & 1, j = q >> 1;
-        const int c = (MODE == 1 ? 2 : 1) + k;
+        const int c = (MODE == 1 || MODE == 4 ? 2 : 1) + k;
         const int i = bw[j] + c;
         const size_t b = rr * wrow + (size_t)j * IWIN + c;
         // the field at window offset d from b (MODE 2: the sum v + w' - z of three fields)
@@ -175,8 +178,12 @@ __global__ void __launch_bounds__(128) k_stencil_win(StencilArgs s, const int* _
         if (MODE == 0) {
             const double2 f = c >= 2 ? psi[pr] : cmk<double2>(0, 0);
             gw[b] = csub(f, a);
+        } else if (MODE == 3) {
+            gw[b] = csub(psi[rr * (size_t)s.Nx + i], a);
         } else if (MODE == 1) {
             out[pr] = csub(psi[pr], csub(gw[b], a));
+        } else if (MODE == 4) {
+            out[pr] = csub(c == 2 ? gw[b] : cmk<double2>(0, 0), a);
         } else {
             out[rr * (2 * (size_t)NI) + 2 * (size_t)j + k] = a;
         }
@@ -324,14 +331,22 @@ __global__ void k_gather_cols(const double2* __restrict__ field, const int* __re
 }
 
 __global__ void k_scatter_cols(const double2* __restrict__ red, const int* __restrict__ cols,
-                               int ncols, int nrhs, int Ny, int Nx, double2* __restrict__ field) {
+                               int ncols, int nrhs, int Ny, int Nx, double2* __restrict__ field, int add) {
     const size_t tot = (size_t)nrhs * Ny * ncols;
     for (size_t q = blockIdx.x * (size_t)blockDim.x + threadIdx.x; q < tot;
          q += (size_t)gridDim.x * blockDim.x) {
         const int k = (int)(q % ncols);
         const size_t rl = q / ncols;
-        field[rl * Nx + cols[k]] = red[q];
+        double2* p = field + rl * Nx + cols[k];
+        *p = add ? cadd(*p, red[q]) : red[q];
     }
+}
+
+// entries c0 .. c0 + n - 1 of every row's first window (window fields [nrows][wrow]) set to 0
+__global__ void k_clear_win_cols(double2* __restrict__ win, long nrows, long wrow, int c0, int n) {
+    const long tot = nrows * n;
+    for (long q = blockIdx.x * (long)blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x)
+        win[(q / n) * wrow + c0 + q % n] = cmk<double2>(0, 0);
 }
 
 // out = x + y + z (x or z may be null: treated as zero)
@@ -397,6 +412,10 @@ hipError_t launch_stencil_win(int mode, const DevTables& t, const Geom& g, int n
         hipLaunchKernelGGL(k_stencil_win<0>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
     else if (mode == 1)
         hipLaunchKernelGGL(k_stencil_win<1>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
+    else if (mode == 3)
+        hipLaunchKernelGGL(k_stencil_win<3>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
+    else if (mode == 4)
+        hipLaunchKernelGGL(k_stencil_win<4>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
     else
         hipLaunchKernelGGL(k_stencil_win<2>, grid, dim3(128), 0, st, s, t.bw, t.k2w, NI, nrhs, u, psi, gw, out);
     return hipGetLastError();
@@ -449,10 +468,17 @@ hipError_t launch_gather_cols(const double2* field, const int* cols, int ncols, 
 }
 
 hipError_t launch_scatter_cols(const double2* red, const int* cols, int ncols, int nrhs,
-                               int Ny, int Nx, double2* field, hipStream_t st) {
+                               int Ny, int Nx, double2* field, hipStream_t st, bool add) {
     if (ncols <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_scatter_cols, dim3(grid_for((size_t)nrhs * Ny * ncols)), dim3(256), 0, st,
-                       red, cols, ncols, nrhs, Ny, Nx, field);
+                       red, cols, ncols, nrhs, Ny, Nx, field, add ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_win_cols(double2* win, long nrows, long wrow, int c0, int n, hipStream_t st) {
+    if (nrows <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_win_cols, dim3(grid_for((size_t)nrows * n)), dim3(256), 0, st, win, nrows, wrow,
+                       c0, n);
     return hipGetLastError();
 }
 
