@@ -280,6 +280,17 @@ helm_status helm_apply_P(helm_t H, int nrhs, const void* f, void* out);
 helm_status helm_apply_AP_reduced(helm_t H, int nrhs, const void* psi, void* out);
 
 /*
+ * A GMRES restart's reduced right-hand side in the reduced form: b = (r - A P r) on the
+ * columns beta_j, beta_j + 1 of every internal interface, for a full field r, computed from
+ * both sweeps of P in the target-only form of Algorithm 3 (the support statement of Sec. 2.1:
+ * r - A v vanishes off beta_j - 1, beta_j and r - A P r off beta_j, beta_j + 1).  r: device,
+ * nrhs * N_y * N_x complex128; b: device, nrhs * N_y * 2(J-1) complex128 ordered as in
+ * helm_apply_AP_reduced.  HELM_EINVAL for J = 1, the concurrent sweeps or the Robin
+ * transmission; HELM_ESTATE before helm_factor.
+ */
+helm_status helm_restart_rhs_reduced(helm_t H, int nrhs, const void* r, void* b);
+
+/*
  * The FP64 PML stencil (Sec. 2.2): out = f - A u, or out = A u when f is NULL.
  * u, f, out: device, nrhs * N_y * N_x complex128.
  */

@@ -19,7 +19,7 @@ STATUS_NAMES = {0: "HELM_OK", 1: "HELM_EINVAL", 2: "HELM_ENOMEM", 3: "HELM_EHIP"
 
 # every entry point declared in include/helm.h
 EXPORTS = ["helm_default_opts", "helm_setup", "helm_factor", "helm_solve", "helm_apply_P",
-           "helm_apply_AP_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
+           "helm_apply_AP_reduced", "helm_restart_rhs_reduced", "helm_apply_A", "helm_strip_solve", "helm_get_dims",
            "helm_get_partition", "helm_get_chunks", "helm_get_stats", "helm_set_kernel_timing",
            "helm_get_kernel_times", "helm_last_error", "helm_destroy", "helm_grad",
            "helm_solve_batch", "helm_get_dims3", "helm_autotune", "helm_get_factor_path",
@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
     L.helm_solve.argtypes = [vp, ci, vp, vp, cd, pint, pdbl]
     L.helm_apply_P.argtypes = [vp, ci, vp, vp]
     L.helm_apply_AP_reduced.argtypes = [vp, ci, vp, vp]
+    L.helm_restart_rhs_reduced.argtypes = [vp, ci, vp, vp]
     L.helm_apply_A.argtypes = [vp, ci, vp, vp, vp]
     L.helm_solve_batch.argtypes = [ci, ctypes.POINTER(vp), pint, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                    cd, pint, pdbl]
@@ -166,6 +167,11 @@ def helm_apply_P(hdl, nrhs: int, f_ptr: int, out_ptr: int) -> None:
 def helm_apply_AP_reduced(hdl, nrhs: int, psi_ptr: int, out_ptr: int) -> None:
     check(lib().helm_apply_AP_reduced(hdl, int(nrhs), ctypes.c_void_p(psi_ptr),
                                       ctypes.c_void_p(out_ptr)), hdl)
+
+
+def helm_restart_rhs_reduced(hdl, nrhs: int, r_ptr: int, b_ptr: int) -> None:
+    check(lib().helm_restart_rhs_reduced(hdl, int(nrhs), ctypes.c_void_p(r_ptr),
+                                         ctypes.c_void_p(b_ptr)), hdl)
 
 
 def helm_solve_batch(hdls, nrhs, rhs_ptrs, u_ptrs, tol: float):

@@ -2451,6 +2451,16 @@ helm_status helm_apply_AP_reduced(helm_t H, int nrhs, const void* psi, void* out
     return apply_AP_red(H, nrhs, static_cast<const double2*>(psi), static_cast<double2*>(out));
 }
 
+helm_status helm_restart_rhs_reduced(helm_t H, int nrhs, const void* r, void* b) {
+    if (!H) return HELM_EINVAL;
+    if (!H->factored) return fail(H, HELM_ESTATE, "helm_restart_rhs_reduced before helm_factor");
+    if (H->g.J < 2) return fail(H, HELM_EINVAL, "the reduced space is empty for J = 1");
+    if (nrhs < 1 || !r || !b) return fail(H, HELM_EINVAL, "bad arguments");
+    if (H->trans == 1 || H->sweep == 1)
+        return fail(H, HELM_EINVAL, "the restart right-hand side is built for the double sweep with PML transmission");
+    return restart_rhs_reduced(H, nrhs, static_cast<const double2*>(r), static_cast<double2*>(b));
+}
+
 helm_status helm_apply_A(helm_t H, int nrhs, const void* u, const void* f, void* out) {
     if (!H) return HELM_EINVAL;
     if (!H->t.k2) return fail(H, HELM_ESTATE, "helm_setup did not complete");

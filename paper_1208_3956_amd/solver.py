@@ -253,6 +253,17 @@ class Helmholtz:
         self._end()
         return out
 
+    def restart_rhs_reduced(self, r: torch.Tensor) -> torch.Tensor:
+        """(r - A P r) on the reduced columns, from the target-only sweeps (helm_restart_rhs_reduced)."""
+        r = self._field(r, "r")
+        out = torch.empty((r.shape[0],) + tuple(r.shape[1:-1]) + (2 * (self.J - 1),), dtype=r.dtype,
+                          device=r.device)
+        self._begin()
+        with torch.cuda.device(self.device):
+            L.helm_restart_rhs_reduced(self.h, r.shape[0], r.data_ptr(), out.data_ptr())
+        self._end()
+        return out
+
     def apply_A(self, u: torch.Tensor, f: Optional[torch.Tensor] = None) -> torch.Tensor:
         u = self._field(u, "u")
         if f is not None:

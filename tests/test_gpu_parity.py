@@ -160,6 +160,34 @@ def test_apply_AP_reduced(case, prec, tol):
     H.close()
 
 
+@pytest.mark.parametrize("prec,tol", [("c128", 1e-9), ("mixed", 1e-3)])
+def test_restart_rhs_reduced(case, prec, tol):
+    """A restart's reduced right-hand side from both sweeps in the target-only form (the
+    support statement of Sec. 2.1) against its definition, (r - A P r) on the reduced
+    columns with the oracle's P, for full fields r with nothing zero."""
+    from oracle.dd import to_reduced
+    wl, g, A, S = case
+    H = _gpu(wl, prec=prec, mode="reduced")
+    rng = np.random.default_rng(9)
+    r = _rand(rng, (3, g.N_y, g.N_x))
+    out = H.restart_rhs_reduced(_t(r)).cpu().numpy()
+    ref = np.stack([to_reduced(g, rk - (A @ apply_P(g, S, A, rk).ravel()).reshape(rk.shape)) for rk in r])
+    err = max(np.linalg.norm(out[k] - ref[k]) / np.linalg.norm(ref[k]) for k in range(len(r)))
+    print(f"restart right-hand side ({prec}): relative error {err:.2e}", flush=True)
+    _close(out, ref, tol, "restart right-hand side")
+    H.close()
+
+
+def test_restart_rhs_reduced_rejects_one_strip():
+    from paper_1208_3956_amd import Helmholtz
+    wl = W.small(n=24, J=1, w_out=6, w=4, nsrc=1)
+    H = Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, prec="c128", mode="reduced",
+                  device=DEV).factor()
+    with pytest.raises(Exception, match="J = 1"):
+        H.restart_rhs_reduced(_t(np.zeros((1, H.N_y, H.N_x), dtype=np.complex128)))
+    H.close()
+
+
 @pytest.mark.parametrize("mode", ["full", "reduced"])
 @pytest.mark.parametrize("prec", ["c128", "mixed"])
 def test_solve_matches_direct(case, mode, prec):
