@@ -19,9 +19,9 @@
 // launches (blockIdx.y / gridDim = slab); blocks are padded to Bp (a multiple of 64) with
 // the identity.
 //
-// A solve step is one dense product per plane: G_l (Bp x Bp, column-major) times a panel
-// of right-hand sides ([k][RP], right-hand sides fastest), each workgroup a 16-row x
-// 16-column tile with its four waves splitting the k range.  Operands are read straight
+// A solve step is one dense product per plane: G_l (Bp x Bp) times a panel of right-hand
+// sides ([k][RP], right-hand sides fastest; complex64 in pairs of k), each workgroup a
+// 16-row x 16-column tile with its waves splitting the k range.  Operands are read straight
 // from global memory in the MFMA lane layout.  The right-hand side of the next forward
 // plane (input field, transmission planes, minus c_{l+1} y_l) is formed by the tile that
 // computes y_l, so every element is gathered once.
@@ -386,6 +386,14 @@ __global__ void __launch_bounds__(256) k3_store(const double2* __restrict__ S, i
 }
 
 // ---------------------------------------------------------------- slab solve steps
+// Plane vectors [k][RP]: complex128 stores entry (k, r) at k RP + r; complex64 in pairs of
+// k, at 2 ((k / 2) RP + r) + k % 2, so that a lane's two k of a pair come in one 16-byte load
+// and the 16 lanes of a right-hand-side tile read 256 contiguous bytes.
+template <typename T>
+__device__ inline size_t pidx(int k, int r, int RP) { return (size_t)k * RP + r; }
+template <>
+__device__ inline size_t pidx<float>(int k, int r, int RP) { return 2 * ((size_t)(k >> 1) * RP + r) + (k & 1); }
+
 template <typename T>
 __device__ inline cplx<T> gather3(const Solve3Args<T>& a, int r, int l, int k) {
     const IOSpec& io = a.io;
@@ -427,12 +435,13 @@ __global__ void __launch_bounds__(256) k3_rhs0(Solve3Args<T> a, cplx<T>* __restr
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (size_t)a.Bp * a.RP) return;
     const int i = (int)(e / a.RP), r = (int)(e % a.RP);
-    Tw[e] = (i < a.B && r < a.nrhs) ? gather3<T>(a, r, 0, i) : cmk<cplx<T>>(0, 0);
+    Tw[pidx<T>(i, r, a.RP)] = (i < a.B && r < a.nrhs) ? gather3<T>(a, r, 0, i) : cmk<cplx<T>>(0, 0);
 }
 
 // Z = G X for a 16-row x 16-column tile: G Bp x Bp, column-major (complex128) or in 16-row
-// panels (complex64: entry (i, k) at (i / 16) 16 Bp + 16 k + i % 16, so that the 16 rows of
-// a tile are one contiguous run of 16 Bp entries), X [k][RP].  The k range
+// panels (complex64: entry (i, k) at (i / 16) 16 Bp + 32 (k / 2) + 2 (i % 16) + k % 2, so
+// that the 16 rows of a tile are one contiguous run of 16 Bp entries and each row's pairs of
+// k are adjacent), X a plane vector (pidx).  The k range
 // is cut into blocks of 16; wave w of NW3 takes blocks w, w + NW3, ... (several waves per
 // SIMD hide the load latency; each wave also loads its next block before it multiplies
 // the current one).  The NW3 partial tiles are added through LDS.  Returns, for thread
@@ -451,15 +460,19 @@ __device__ inline float2 tile_product(const float2* __restrict__ G, const float2
     // x3 = sum (Gr + Gi)(Xr + Xi); Re = x1 - x2, Im = x3 - x1 - x2 (two chains of each for
     // independent MFMAs)
     mf4 x1a = {0.f, 0.f, 0.f, 0.f}, x2a = x1a, x3a = x1a, x1b = x1a, x2b = x1a, x3b = x1a;
-    const float2* gp = G + (size_t)(i0 / 16) * 16 * Bp + 16 * q4 + n;
-    const float2* xp = X + (size_t)q4 * RP + r0 + n;
+    // k-step u of block b: lane (n, q4) takes k = 16 b + 4 q4 + u (a permutation of the
+    // block's k, the same for both operands); k-steps 2p, 2p + 1 are one pair of both layouts
+    const float2* gp = G + (size_t)(i0 / 16) * 16 * Bp + 64 * q4 + 2 * n;
+    const float2* xp = X + 2 * ((size_t)(2 * q4) * RP + r0 + n);
     float2 g[4], x[4], gn[4], xn[4];
     auto load = [&](int b, float2 (&gg)[4], float2 (&xx)[4]) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            gg[u] = gp[(size_t)(16 * b + 4 * u) * 16];
-            xx[u] = xp[(size_t)(16 * b + 4 * u) * RP];
-        }
+        const float4* G4 = reinterpret_cast<const float4*>(gp + 256 * (size_t)b);
+        const float4* X4 = reinterpret_cast<const float4*>(xp + 16 * (size_t)b * RP);
+        const float4 g01 = G4[0], g23 = G4[16], x01 = X4[0], x23 = X4[RP];
+        gg[0] = make_float2(g01.x, g01.y); gg[1] = make_float2(g01.z, g01.w);
+        gg[2] = make_float2(g23.x, g23.y); gg[3] = make_float2(g23.z, g23.w);
+        xx[0] = make_float2(x01.x, x01.y); xx[1] = make_float2(x01.z, x01.w);
+        xx[2] = make_float2(x23.x, x23.y); xx[3] = make_float2(x23.z, x23.w);
     };
     if (w < nblk) load(w, g, x);
     for (int b = w; b < nblk; b += NW3) {
@@ -534,7 +547,7 @@ __global__ void __launch_bounds__(NT3) k3_fwd(Solve3Args<T> a, int l, const cplx
     const V y = tile_product(a.F + (size_t)l * a.Bp * a.Bp, Tw, a.Bp, a.RP, i0, r0, red);
     if (threadIdx.x >= 256) return;
     const int i = i0 + (threadIdx.x >> 4), r = r0 + (threadIdx.x & 15);
-    const size_t at = (size_t)i * a.RP + r;
+    const size_t at = pidx<T>(i, r, a.RP);
     a.Yw[(size_t)l * a.Bp * a.RP + at] = y;
     const bool live = i < a.B && r < a.nrhs;
     if (l + 1 < a.Ny) {
@@ -560,7 +573,7 @@ __global__ void __launch_bounds__(NT3) k3_bwd(Solve3Args<T> a, int l) {
                              i0, r0, red);
     if (threadIdx.x >= 256) return;
     const int i = i0 + (threadIdx.x >> 4), r = r0 + (threadIdx.x & 15);
-    V* yl = a.Yw + (size_t)l * plane + (size_t)i * a.RP + r;
+    V* yl = a.Yw + (size_t)l * plane + pidx<T>(i, r, a.RP);
     const V x = csub(*yl, cmul(ccast<V>(a.by[l]), z));
     *yl = x;
     if (i < a.B && r < a.nrhs) scatter3<T>(a, r, l, i, x);
@@ -568,14 +581,15 @@ __global__ void __launch_bounds__(NT3) k3_bwd(Solve3Args<T> a, int l) {
 
 // The complex64 inverses of plane l of the J slots (column-major, slot stride `stride`)
 // written to dst[s][Bp^2] in the 16-row panel layout of the sweeps (destination order:
-// panel, column, row within the panel; the reads are 16-entry runs of a column).
+// panel, pair of columns, row within the panel, column within the pair; the reads are
+// 16-entry runs of two columns).
 __global__ void __launch_bounds__(256) k3_panelize(const float2* __restrict__ F, size_t stride, int l, int Bp,
                                                   float2* __restrict__ dst) {
     const size_t BB = (size_t)Bp * Bp, PW = (size_t)16 * Bp;
     const float2* src = F + blockIdx.y * stride + (size_t)l * BB;
     float2* d = dst + blockIdx.y * BB;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < BB; e += (size_t)gridDim.x * 256) {
-        const size_t p = e / PW, k = (e % PW) / 16, ii = e % 16;
+        const size_t p = e / PW, rem = e % PW, k = 2 * (rem / 32) + rem % 2, ii = (rem % 32) / 2;
         d[e] = src[k * Bp + 16 * p + ii];
     }
 }
