@@ -42,10 +42,11 @@ def lens():
     return wl, g, assemble_global(g)
 
 
-def _H(wl, prec, mode="reduced"):
+def _H(wl, prec, mode="reduced", chunk=0):
     from paper_1208_3956_amd import Helmholtz
     return Helmholtz(wl.c, wl.omega, wl.h, wl.J, wl.w_out, wl.w, wl.pml_power, wl.pml_s0,
-                     pml_iface_s0=wl.pml_iface_s0, prec=prec, mode=mode, device=DEV).factor()
+                     pml_iface_s0=wl.pml_iface_s0, prec=prec, mode=mode, chunk=chunk,
+                     device=DEV).factor()
 
 
 def test_lens_every_strip_has_its_own_factorisation(lens):
@@ -84,17 +85,21 @@ def test_lens_preconditioner_one_rhs(lens):
         H.close()
 
 
-def test_lens_solves_and_iterations(lens):
+@pytest.mark.parametrize("chunk", [0, 8], ids=["default_chunk", "chunk8"])
+def test_lens_solves_and_iterations(lens, chunk):
+    """Both precisions at the default chunk size and at 8 rows (the size the benchmark's
+    autotuner picks for these 16 right-hand sides)."""
     wl, g, A = lens
     f = wl.rhs()
     ft = torch.from_numpy(f).to(DEV)
     res = {}
     for prec in ("c128", "mixed"):
-        H = _H(wl, prec)
+        H = _H(wl, prec, chunk=chunk)
         res[prec] = H.solve(ft, tol=1e-6)
         H.close()
         r = res[prec]
-        print(f"lens {prec}: iterations {r.iters}, restarts {r.restarts}, {r.ms:.0f} ms", flush=True)
+        print(f"lens {prec} chunk {chunk}: iterations {r.iters}, restarts {r.restarts}, {r.ms:.0f} ms",
+              flush=True)
         assert r.status == 0 and max(r.relres) <= 1e-6
         for k in (0, 8, 15):
             u = r.u[k].cpu().numpy()
