@@ -410,6 +410,7 @@ def c128_legs(wl, f, tol, plain_rhs=2):
 
 
 LENS_CHUNKS = (8, 12, 16, 24, 32)
+BATCH_CHUNKS = (16, 24, 32)
 
 
 def lens_leg(tol, reps=2):
@@ -519,6 +520,16 @@ def batch_main(args):
                     pml_iface_s0=wl.pml_iface_s0, prec=args.prec, mode=args.mode, chunk=args.chunk,
                     device=dev, stream=torch.cuda.Stream(dev), batch_fuse=True) for wl in wls]
     pts = sum(f.shape[0] * wl.n_x * wl.n_y for wl, f in zip(wls, fs))
+    tuned = None
+    if args.chunk == 0:
+        # 8 right-hand sides per problem: each handle factors with the chunk size the
+        # autotuner finds fastest for it (before the timed steps), among sizes of 16 rows or
+        # more: timed alone 8-row chunks win, but eight problems at once then run more and
+        # longer separator chains (measured: 534 ms per step with 8 rows, 486 with 16)
+        tuned = [H.autotune(f, candidates=BATCH_CHUNKS, reps=1, cache=None)["chunk_rows"]
+                 for H, f in zip(Hs, fs)]
+        for H, f in zip(Hf, fs):
+            H.autotune(f, candidates=BATCH_CHUNKS, reps=1, cache=None)
 
     solo_ms = [0.0] * len(Hs)
 
@@ -584,7 +595,8 @@ def batch_main(args):
         "vs_baseline": None, "dtype": "c64" if args.prec == "mixed" else "c128", "data": "synthetic",
         "config": {"workload": "layers_uneven_batch", "sizes": [wl.n_x for wl in wls],
                    "J": [wl.J for wl in wls], "nrhs_each": 8, "prec": args.prec, "mode": args.mode,
-                   "step": "helm_factor (each) + helm_solve_batch"},
+                   "step": "helm_factor (each) + helm_solve_batch",
+                   "chunk_rows": tuned if tuned is not None else args.chunk},
         "sequential_value": pts / t_s, "sequential_ms_per_step": t_s * 1e3,
         # each problem's factor + solve alone; the concurrent step cannot be shorter than the
         # slowest of them (the dependency chain of its sweeps and iterations)
